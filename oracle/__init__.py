@@ -1,0 +1,255 @@
+"""FP64 CPU oracle for the semantic Gaussian-splatting rasterizer.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product library
+never does, and this package never imports the product package.
+
+The arithmetic lives in ``sgs_oracle.c`` (plain C, FP64 values, binary32
+decisions); this module builds it with gcc, loads it with ctypes and
+marshals numpy arrays.  ``bruteforce.py`` is a second, independent NumPy
+renderer (no tiles, no boxes) used to pin the C oracle on tiny scenes.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sgs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (gcc, -O2, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _lib.orc_bin.restype = ctypes.c_int64
+        _lib.orc_total_tiles.restype = ctypes.c_int64
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"], "oracle arrays must be contiguous"
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------
+# configuration (readings of what the paper leaves unstated)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Cfg:
+    z_near: float = 0.2
+    blur: float = 0.3
+    guard: float = 1.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    tile: int = 16
+
+    def array(self) -> np.ndarray:
+        amin = float(np.float32(self.alpha_min))
+        kbox = 2.0 * math.log(1.0 / amin)
+        lmin = math.log(amin / (1.0 - amin))
+        return np.array([self.z_near, self.blur, self.guard, self.alpha_min, self.alpha_max,
+                         self.T_min, kbox, lmin], dtype=np.float32)
+
+
+def views_array(views, dtype=np.float32, poses64: Optional[List[np.ndarray]] = None) -> np.ndarray:
+    """[V][18] = W, H, fx, fy, cx, cy, R (row-major), t, from the float32
+    inputs (exactly upcast for dtype=float64).  `poses64` replaces [R|t] by
+    FP64 3x4 matrices (finite differences of the pose)."""
+    rows = []
+    for i, v in enumerate(views):
+        Rt = np.asarray(v.Rt, np.float32).astype(np.float64)
+        if poses64 is not None:
+            Rt = np.asarray(poses64[i], np.float64)[:3, :4]
+        intr = np.float32([v.fx, v.fy, v.cx, v.cy]).astype(np.float64)
+        rows.append(np.concatenate([[v.width, v.height], intr, Rt[:, :3].reshape(-1), Rt[:, 3]]))
+    return np.ascontiguousarray(np.asarray(rows, dtype=np.float64), dtype=dtype)
+
+
+def pixel_counts(views) -> np.ndarray:
+    return np.array([v.width * v.height for v in views], dtype=np.int64)
+
+
+def scene64(scene):
+    """FP64 copy of a scene (exact upcast)."""
+    return {k: np.ascontiguousarray(getattr(scene, k), dtype=np.float64)
+            for k in ("mu", "log_scale", "quat", "logit", "color", "feat")}
+
+
+# ----------------------------------------------------------------------------
+# decisions and binning (binary32)
+# ----------------------------------------------------------------------------
+def decide(scene, views, cfg: Cfg):
+    L = lib()
+    n, V = scene.n, len(views)
+    rect = np.zeros((V, n, 4), np.int32)
+    touched = np.zeros((V, n), np.int32)
+    dbits = np.zeros((V, n), np.uint32)
+    rec32 = np.zeros((V, n, 8), np.float32)
+    c = lambda a: np.ascontiguousarray(a, np.float32)
+    mu, ls, q, lg = c(scene.mu), c(scene.log_scale), c(scene.quat), c(scene.logit)
+    vw, ca = views_array(views), cfg.array()
+    L.orc_decide(ctypes.c_int(n), _p(mu), _p(ls), _p(q), _p(lg), ctypes.c_int(V), _p(vw), _p(ca),
+                 ctypes.c_int(cfg.tile), _p(rect), _p(touched), _p(dbits), _p(rec32))
+    return {"rect": rect, "touched": touched, "dbits": dbits, "rec32": rec32}
+
+
+def total_tiles(views, tile: int) -> int:
+    return int(sum(((v.width + tile - 1) // tile) * ((v.height + tile - 1) // tile) for v in views))
+
+
+def bin_instances(scene, views, cfg: Cfg, dec=None):
+    """Sorted (tile, depth bits, gid) instances: keys (global tile id),
+    gids, ranges[T][2] (start, end) and the count."""
+    L = lib()
+    dec = decide(scene, views, cfg) if dec is None else dec
+    n, V = scene.n, len(views)
+    count = int(dec["touched"].astype(np.int64).sum())
+    T = total_tiles(views, cfg.tile)
+    keys = np.zeros(max(count, 1), np.uint32)
+    gids = np.zeros(max(count, 1), np.int32)
+    ranges = np.zeros((T, 2), np.int32)
+    got = L.orc_bin(ctypes.c_int(n), ctypes.c_int(V), _p(views_array(views)), ctypes.c_int(cfg.tile),
+                    _p(dec["rect"]), _p(dec["touched"]), _p(dec["dbits"]), ctypes.c_int64(max(count, 1)),
+                    _p(keys), _p(gids), _p(ranges))
+    assert got == count
+    return {"keys": keys[:count], "gids": gids[:count], "ranges": ranges, "count": count, "dec": dec}
+
+
+# ----------------------------------------------------------------------------
+# FP64 projection, render, loss, backward
+# ----------------------------------------------------------------------------
+def project64(scene, views, cfg: Cfg, s64=None, poses64=None) -> np.ndarray:
+    L = lib()
+    s64 = scene64(scene) if s64 is None else s64
+    n, V = scene.n, len(views)
+    proj = np.zeros((V, n, 7), np.float64)
+    L.orc_project64(ctypes.c_int(n), _p(s64["mu"]), _p(s64["log_scale"]), _p(s64["quat"]), _p(s64["logit"]),
+                    ctypes.c_int(V), _p(views_array(views, np.float64, poses64)), _p(cfg.array()), _p(proj))
+    return proj
+
+
+def render(scene, views, cfg: Cfg, bins=None, pix_mask=None, s64=None, poses64=None):
+    """FP64 forward render.  Discrete decisions come from the binary32 scene
+    and views; values from `s64` / `poses64` when given (finite differences).
+    Returns out[5+F][P] (R, G, B, depth, opacity, features), Tfinal, last,
+    ncontrib, margin (smallest relative distance to the alpha_min / T_min
+    thresholds met at that pixel)."""
+    L = lib()
+    bins = bin_instances(scene, views, cfg) if bins is None else bins
+    s64 = scene64(scene) if s64 is None else s64
+    proj = project64(scene, views, cfg, s64, poses64)
+    F, n, V = scene.n_feat, scene.n, len(views)
+    P = int(pixel_counts(views).sum())
+    out = np.zeros((5 + F, P), np.float64)
+    Tf = np.zeros(P, np.float64)
+    last = np.zeros(P, np.int32)
+    ncon = np.zeros(P, np.int32)
+    margin = np.full(P, np.inf)
+    gids = np.ascontiguousarray(bins["gids"] if bins["count"] else np.zeros(1, np.int32))
+    pm = None if pix_mask is None else np.ascontiguousarray(pix_mask, np.uint8)
+    L.orc_render(ctypes.c_int(n), ctypes.c_int(F), _p(s64["color"]), _p(s64["feat"]), ctypes.c_int(V),
+                 _p(views_array(views, np.float64, poses64)), _p(cfg.array()), ctypes.c_int(cfg.tile),
+                 _p(np.ascontiguousarray(bins["ranges"])), _p(gids), _p(proj), _p(pm), _p(out), _p(Tf),
+                 _p(last), _p(ncon), _p(margin))
+    return {"out": out, "Tfinal": Tf, "last": last, "ncontrib": ncon, "margin": margin, "bins": bins,
+            "proj": proj}
+
+
+def loss(out: np.ndarray, views, rgb_t, depth_t, labels=None, decoder=None, weights=(0.5, 1.0, 0.0)):
+    """Image-space loss and its gradient d L / d out (FP64)."""
+    L = lib()
+    F = out.shape[0] - 5
+    K = 0 if decoder is None else int(decoder.shape[1])
+    P = out.shape[1]
+    g = np.zeros_like(out)
+    terms = np.zeros(4, np.float64)
+    lab = np.zeros(P, np.int32) if labels is None else np.ascontiguousarray(labels, np.int32)
+    Wd = np.zeros((max(F, 1), 1)) if decoder is None else np.ascontiguousarray(decoder, np.float64)
+    w = np.asarray(weights, np.float64)
+    if K == 0:
+        w = w.copy()
+        w[2] = 0.0
+    L.orc_loss(ctypes.c_int(F), ctypes.c_int(K), ctypes.c_int(len(views)), _p(pixel_counts(views)),
+               _p(np.ascontiguousarray(out, np.float64)), _p(np.ascontiguousarray(rgb_t, np.float64)),
+               _p(np.ascontiguousarray(depth_t, np.float64)), _p(lab), _p(Wd), _p(w), _p(g), _p(terms))
+    return g, terms
+
+
+GRAD_PARAMS = 1
+GRAD_POSE = 2
+
+
+def backward(scene, views, cfg: Cfg, grad_out: np.ndarray, bins=None, flags=GRAD_PARAMS | GRAD_POSE,
+             tile_mask=None, s64=None, poses64=None):
+    """FP64 backward of <grad_out, render> to every parameter and the pose."""
+    L = lib()
+    bins = bin_instances(scene, views, cfg) if bins is None else bins
+    s64 = scene64(scene) if s64 is None else s64
+    proj = project64(scene, views, cfg, s64, poses64)
+    F, n, V = scene.n_feat, scene.n, len(views)
+    vis = np.ascontiguousarray((bins["dec"]["touched"] > 0).astype(np.uint8))
+    r = {
+        "grad2d": np.zeros((V, n, 6)), "gapp": np.zeros((n, 4 + F)),
+        "mu": np.zeros((3, n)), "log_scale": np.zeros((3, n)), "quat": np.zeros((4, n)),
+        "logit": np.zeros(n), "color": np.zeros((3, n)), "feat": np.zeros((F, n)),
+        "gcam": np.zeros((V, n, 3)), "Gcam": np.zeros((V, n, 6)), "twist": np.zeros((V, 6)),
+    }
+    gids = np.ascontiguousarray(bins["gids"] if bins["count"] else np.zeros(1, np.int32))
+    tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
+    L.orc_backward(ctypes.c_int(n), ctypes.c_int(F), _p(s64["mu"]), _p(s64["log_scale"]), _p(s64["quat"]),
+                   _p(s64["logit"]), _p(s64["color"]), _p(s64["feat"]), ctypes.c_int(V),
+                   _p(views_array(views, np.float64, poses64)), _p(cfg.array()), ctypes.c_int(cfg.tile),
+                   _p(np.ascontiguousarray(bins["ranges"])), _p(gids), _p(proj),
+                   _p(np.ascontiguousarray(grad_out, np.float64)), _p(tm), _p(vis), ctypes.c_int(flags),
+                   _p(r["grad2d"]), _p(r["gapp"]), _p(r["mu"]), _p(r["log_scale"]), _p(r["quat"]),
+                   _p(r["logit"]), _p(r["color"]), _p(r["feat"]), _p(r["gcam"]), _p(r["Gcam"]),
+                   _p(r["twist"]))
+    return r
+
+
+def geom(mu, ls, q, logit, view, cfg: Cfg):
+    """FP64 geometry of one pair: dict(p, Sigma, Sigma_c, Sigma2D, R, o)."""
+    L = lib()
+    out = np.zeros(34)
+    vw = views_array([view], np.float64)[0].copy()
+    L.orc_geom(_p(np.asarray(mu, np.float64).copy()), _p(np.asarray(ls, np.float64).copy()),
+               _p(np.asarray(q, np.float64).copy()), ctypes.c_double(float(logit)), _p(vw),
+               _p(cfg.array()), _p(out))
+    return {"p": out[:3], "Sigma": out[3:12].reshape(3, 3), "Sigma_c": out[12:21].reshape(3, 3),
+            "Sigma2D": out[21:24], "R": out[24:33].reshape(3, 3), "o": out[33]}
+
+
+def dec_exp(x: np.ndarray) -> np.ndarray:
+    L = lib()
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.zeros_like(x)
+    L.orc_dec_exp(ctypes.c_int(x.size), _p(x), _p(y))
+    return y
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
