@@ -1,0 +1,263 @@
+/*
+ * sgs.h -- C ABI of the MI355X (gfx950) semantic Gaussian-splatting
+ * rasterizer: forward rendering of colour, depth, cumulative opacity and an
+ * F-channel semantic feature from 3D Gaussians under a camera pose, the
+ * image-space loss gradient, and the backward pass to every Gaussian
+ * parameter and to a 6-DoF pose twist.
+ *
+ * Paper: GS^3LAM, "Gaussian Semantic Splatting SLAM" (ACM MM 2024).
+ *   Sec. 3.2, Eq. (1)-(2)   SG-Field and Sigma = R S S^T R^T
+ *   Sec. 3.2.1, Eq. (3)-(6) EWA projection, alpha, colour and depth blending
+ *   Sec. 3.2.2, Eq. (7)-(8) semantic feature blending and decoding
+ *   Sec. 3.3.1, Eq. (9)     cumulative opacity
+ *   Sec. 3.3.4 / 3.4        colour / depth / semantic losses
+ *   Supp. B.1               Jacobian of the loss with respect to the pose
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is a DEVICE pointer owned by the caller unless
+ *     its comment says "host".  The library allocates no device memory; the
+ *     caller sizes workspaces with the *_workspace queries.
+ *   - Gaussians are float32 structure-of-arrays planes (index i in [0, n)).
+ *   - Images are planar float32 [channel][P_total] where P_total is the sum of
+ *     width*height over the views and view v occupies
+ *     [pixel_offset, pixel_offset + width*height), row-major.  Channel order:
+ *     0,1,2 = R,G,B; 3 = depth; 4 = cumulative opacity; 5.. = features.
+ *   - Pixel (u, v) has centre (u + 1/2, v + 1/2); (cx, cy) is in the same
+ *     continuous image coordinates.
+ *   - All calls are asynchronous on `stream`, never synchronise, never read
+ *     device memory on the host and never allocate, so every call can be
+ *     captured in a HIP graph.  Arguments are validated on the host before
+ *     anything is launched; on an error nothing is launched.
+ *   - Return value: GS_OK, or a negative gs_status.  HIP launch errors are
+ *     reported as GS_EHIP (the HIP error string via gs_last_hip_error()).
+ */
+#ifndef SGS_H
+#define SGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gs_stream; /* a hipStream_t; NULL = default stream */
+
+enum gs_status {
+    GS_OK = 0,
+    GS_EINVAL = -1,        /* bad argument (null pointer, size, layout)          */
+    GS_ECAPACITY = -2,     /* a caller-sized buffer is too small                  */
+    GS_EHIP = -3,          /* a HIP call failed                                   */
+    GS_EUNSUPPORTED = -4   /* valid but not compiled (feature count, tile size)   */
+};
+
+enum gs_flags {
+    GS_GRAD_PARAMS = 1,    /* gradients to the Gaussian parameters (mapping)      */
+    GS_GRAD_POSE = 2       /* per-view 2D gradients kept for the pose twist       */
+};
+
+enum {
+    GS_MAX_VIEWS = 64,
+    GS_MAX_CLASSES = 256
+};
+
+/* The SG-Field of Eq. (1): mean mu, covariance through rotation quat and
+ * log-scales (Eq. 2), opacity o = sigmoid(opacity_logit), colour c and an
+ * n_feat-dimensional semantic feature f.  n_feat must be one of the compiled
+ * values 0, 8, 16, 32 (GS_EUNSUPPORTED otherwise). */
+typedef struct {
+    const float* mu;            /* [3][n]                                   */
+    const float* log_scale;     /* [3][n]                                   */
+    const float* quat;          /* [4][n] (w, x, y, z), normalised inside   */
+    const float* opacity_logit; /* [n]                                      */
+    const float* color;         /* [3][n]                                   */
+    const float* feat;          /* [n_feat][n] (may be NULL if n_feat == 0) */
+    int32_t n;
+    int32_t n_feat;
+} gs_gaussians;
+
+/* Gradients, same planes as gs_gaussians; ACCUMULATED (+=), so per-view calls
+ * and one batched call give the same totals. */
+typedef struct {
+    float* mu;
+    float* log_scale;
+    float* quat;
+    float* opacity_logit;
+    float* color;
+    float* feat;
+} gs_gaussian_grads;
+
+/* A pinhole camera with world->camera transform T_CW = [R|t] (Sec. 3.2.1).
+ * pixel_offset and tile_offset are filled by gs_views_layout. 88 bytes. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float Rt[12];               /* row-major 3x4 [R|t], world -> camera      */
+    int64_t pixel_offset;       /* first pixel of the view in [C][P_total]    */
+    int32_t tile_offset;        /* first global tile id of the view           */
+    int32_t reserved;
+} gs_view;
+
+/* Rasterizer constants.  The paper states none of them; the defaults from
+ * gs_default_config are the readings used throughout:
+ *   z_near 0.2       cull if camera depth <= z_near
+ *   blur 0.3         px^2 added to both diagonal entries of Sigma2D
+ *   guard 1.3        cull if |x/z| > guard * (W/2) / fx (or the same in y)
+ *   alpha_min 1/255  a pair with alpha < alpha_min is skipped
+ *   alpha_max 0.99   alpha is clamped to alpha_max
+ *   T_min 1e-4       stop before a Gaussian that would take T below T_min
+ *   tile             tile side in pixels: 8, 16 or 32
+ *   lds_batch        Gaussians staged in LDS per batch (64, 128 or 256)
+ *   persistent       0: one workgroup per tile; 1: persistent workgroups
+ *                    that pull (view, tile) items from a queue
+ */
+typedef struct {
+    float z_near, blur, guard, alpha_min, alpha_max, T_min;
+    int32_t tile;
+    int32_t lds_batch;
+    int32_t persistent;
+    int32_t reserved;
+} gs_config;
+
+/* Fills *cfg with the defaults listed above (tile 16, lds_batch 256,
+ * persistent 0). */
+int gs_default_config(gs_config* cfg);
+
+/* Host helper: fills pixel_offset / tile_offset of a HOST array of views for
+ * the given tile size and returns the totals.  Every entry point takes the
+ * views twice: `views` (host, for sizes and offsets) and `views_dev`
+ * (device copy of the same array, read by the kernels), which must agree. */
+int gs_views_layout(gs_view* views, int32_t n_views, int32_t tile, int64_t* total_pixels,
+                    int32_t* total_tiles);
+
+/* Floats per Gaussian of the appearance record written by gs_project:
+ * (c0, c1, c2, f0 .. f_{F-1}) padded to a multiple of 4. */
+int32_t gs_app_stride(int32_t n_feat);
+
+/* ---------------------------------------------------------------------------
+ * gs_project -- Eq. (2)-(3) for every (view, Gaussian) pair, one thread each.
+ *   rec[V][n][8]  = (mx, my, A, B, C, o, d, r) : projected mean, conic
+ *                   (Sigma2D^-1, quadratic form A dx^2 + 2B dx dy + C dy^2),
+ *                   opacity, camera depth, and r = the pixel box half-sizes
+ *                   (rx, ry) as two binary16 rounded up.
+ *   rect[V][n][2] = tile rectangle, (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
+ *   tiles_touched[V][n] = number of tiles in rect, 0 if culled
+ *   app[n][gs_app_stride(F)] = colour and feature, gathered per Gaussian by
+ *                   the render kernels (may be NULL to skip).
+ * Culling, the mean, the conic, the depth and the rectangle are computed in
+ * binary32 with one rounding per operation in a fixed order (no contraction),
+ * so that the tile binning and the depth order are reproducible bit for bit.
+ * --------------------------------------------------------------------------- */
+int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+               const gs_config* cfg, float* rec, uint32_t* rect, int32_t* tiles_touched, float* app,
+               gs_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_bin_sort -- tile binning and depth sort (Sec. 3.2.1: tile-based
+ * rasterization of Gaussians sorted in depth order).  Emits one instance per
+ * (view, tile, Gaussian) with the Gaussian's rectangle covering the tile and
+ * sorts them by (global tile id, binary32 depth, Gaussian index) with the
+ * library's own device radix sorts (visible pairs by depth, then instances by
+ * tile, both stable).
+ *   tile_keys[capacity]       global tile id of each sorted instance
+ *   gids[capacity]            Gaussian index of each sorted instance
+ *   tile_ranges[T_total][2]   [start, end) of every global tile
+ *   counts[4] (int64)         [0] instances, [1] visible pairs,
+ *                             [2] 1 if the instance count exceeded capacity
+ *                             (the lists are then truncated: read counts
+ *                             after the stream completes and call again with
+ *                             capacity >= counts[0]), [3] reserved.
+ * ws / ws_bytes: workspace of at least gs_bin_sort_workspace(...) bytes.
+ * --------------------------------------------------------------------------- */
+int gs_bin_sort_workspace(int32_t n, int32_t n_views, int64_t capacity, size_t* bytes);
+int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float* rec, int32_t n,
+                const gs_view* views, const gs_view* views_dev, int32_t n_views, const gs_config* cfg,
+                void* ws, size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* gids,
+                int32_t* tile_ranges, int64_t* counts, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_render_fwd -- front-to-back compositing, Eq. (4), (6), (7), (9):
+ *   alpha_i = min(alpha_max, o_i exp(-q_i / 2)),  q_i = sigma^T conic sigma >= 0
+ *   out_ch  = sum_i x_i,ch alpha_i T_i,  T_i = prod_{j<i} (1 - alpha_j)
+ * over each pixel's tile list in (depth, index) order, skipping alpha <
+ * alpha_min and stopping before T would drop below T_min.  Background 0.
+ *   out[5+F][P_total], T_final[P_total], last[P_total] (number of list
+ *   entries of the pixel's tile up to and including its last contributor).
+ *   queue: >= 4 int32 of device memory, used when cfg->persistent (may be
+ *   NULL otherwise); it is reset inside the call.
+ * --------------------------------------------------------------------------- */
+int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* gids,
+                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev,
+                  int32_t n_views, const gs_config* cfg, float* out, float* T_final, int32_t* last,
+                  int32_t* queue, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_loss_grad -- image-space losses of Sec. 3.3.4 / 3.4 and their gradient:
+ *   per view v (P_v pixels), each term a mean over its pixels,
+ *   L_v = w0 * mean|C - C*| (over 3 P_v) + w1 * mean|D - D*|
+ *       + w2 * mean CE(softmax(W^T F), label)
+ * W is a fixed decoder [n_feat][n_classes] (row-major; the configured linear
+ * stand-in for the paper's F_cnn, Eq. 8); n_classes == 0 drops the CE term.
+ * Writes grad_out[5+F][P_total] = dL/d out (opacity channel 0) and adds the
+ * three summed terms and their total to loss[4] (double, device; the caller
+ * zeroes it; the sum uses atomics, so its last bits may vary run to run --
+ * the gradient does not).  labels in [0, n_classes) (int32).
+ * rgb_target [3][P_total], depth_target [P_total]; weights is a HOST array
+ * of 3 floats (w0, w1, w2).  Views as for the other entry points.
+ * --------------------------------------------------------------------------- */
+int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, const float* depth_target,
+                 const int32_t* labels, const float* decoder, int32_t n_classes, const float* weights,
+                 const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
+                 gs_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_render_bwd -- backward of gs_render_fwd (and of gs_project when
+ * GS_GRAD_PARAMS).  Re-traverses each pixel's list from `last` down,
+ * rebuilding T_i = T_{i+1} / (1 - alpha_i), and forms
+ *   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),
+ *   S_i = sum_{j>i} (g . x_j) alpha_j T_j,
+ * reduces per-Gaussian gradients across each wavefront, then accumulates
+ * with atomics into grad2d:
+ *   grad2d geo [V][n][8]  = dL/d(mx, my, A, B, C, d), 2 unused   (per view)
+ *   grad2d app [n][4+F]   = dL/d(o, c0, c1, c2, f...)            (all views)
+ * (geo first, app right after it; gs_render_bwd_workspace gives the bytes;
+ * the call zeroes it first).  With GS_GRAD_PARAMS the projection backward
+ * then ADDS the gradients of every parameter plane to *grads.  With only
+ * GS_GRAD_POSE (tracking, Sec. 3.4: the field is frozen) colour, feature and
+ * opacity gradients are skipped and grads may be NULL.
+ * --------------------------------------------------------------------------- */
+int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, size_t* bytes);
+int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* gids,
+                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev,
+                  int32_t n_views, const gs_config* cfg, const float* T_final, const int32_t* last,
+                  const float* grad_out, uint32_t flags, float* grad2d, size_t grad2d_bytes,
+                  gs_gaussian_grads* grads, int32_t* queue, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_pose_grad -- Supp. B.1 written as a twist of the left perturbation
+ * T(xi) = Exp(xi) T_CW, xi = (rho, phi):
+ *   dL/drho = sum_i g_i,   dL/dphi = sum_i [p_i x g_i + 2 vex(G_i S_i - S_i G_i)]
+ * with p_i the camera-space mean, S_i its camera-space covariance,
+ * g_i = dL/dp_i and G_i = dL/dS_i obtained from grad2d (of gs_render_bwd)
+ * through the EWA projection.  The view-dependent feature term the paper
+ * drops is zero here because colour and feature are view-independent.
+ *   twist[V][6] (rho, phi), written (not accumulated).
+ *   ws: gs_pose_grad_workspace bytes (per-block partial sums; the final sum
+ *   runs in a fixed order, so the result is deterministic).
+ * --------------------------------------------------------------------------- */
+int gs_pose_grad_workspace(int32_t n, int32_t n_views, size_t* bytes);
+int gs_pose_grad(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                 const gs_config* cfg, const float* grad2d, void* ws, size_t ws_bytes, float* twist,
+                 gs_stream stream);
+
+/* Static description of a status code. */
+const char* gs_error_string(int status);
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char* gs_last_hip_error(void);
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGS_H */

@@ -1,0 +1,52 @@
+// Pieces shared by the forward and backward compositing kernels.
+#pragma once
+
+#include "sgs_common.h"
+
+namespace sgs {
+
+// -1/2 log2(e): the conic is staged pre-scaled so that
+// alpha = o * 2^(A' dx^2 + B2' dx dy + C' dy^2) with A' = kq A, B2' = 2 kq B, C' = kq C.
+constexpr float kQ = -0.72134752044448170f;
+constexpr float kLn2 = 0.69314718055994531f;
+
+template <int F>
+struct AppRec {
+    static constexpr int stride = ((3 + F) + 3) / 4 * 4;  // floats per Gaussian
+    static constexpr int vec = stride / 4;                // float4 per Gaussian
+};
+
+// Staging of one instance into LDS: geometry in two float4
+//   g0 = (mx, my, A', B2'),  g1 = (C', o, d, packed radii)
+__device__ __forceinline__ void stage_geometry(const float4* __restrict__ rec, size_t pair, float4& g0, float4& g1) {
+    const float4 r0 = rec[2 * pair];
+    const float4 r1 = rec[2 * pair + 1];
+    g0 = make_float4(r0.x, r0.y, kQ * r0.z, (2.0f * kQ) * r0.w);
+    g1 = make_float4(kQ * r1.x, r1.y, r1.z, r1.w);
+}
+
+// alpha of one (pixel, Gaussian) pair.  The forward and the backward kernels
+// both call this with the same staged values, so every alpha_min / T_min
+// decision of the backward reproduces the forward exactly.
+//   G = 2^min(q', 0) (the Gaussian factor), returns min(alpha_max, o G).
+__device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, float px, float py, float amax,
+                                            float& dx, float& dy, float& G, bool& unclamped) {
+    dx = px - g0.x;
+    dy = py - g0.y;
+    float q = fmaf(g0.z * dx, dx, dy * fmaf(g0.w, dx, g1.x * dy));
+    q = fminf(q, 0.0f);
+    G = __builtin_amdgcn_exp2f(q);
+    const float a = g1.y * G;
+    unclamped = a < amax;
+    return unclamped ? a : amax;
+}
+
+// Conservative wavefront-level test: can the Gaussian reach any pixel centre
+// of the 8x8 block whose first centre is (x0, y0)?  Only prunes; a Gaussian
+// outside its box has alpha < alpha_min at every pixel centre.
+__device__ __forceinline__ bool box_misses(const float4& g0, const float4& g1, float x0, float y0) {
+    const float2 r = unpack_radii(g1.w);
+    return (g0.x + r.x < x0) || (g0.x - r.x > x0 + 7.0f) || (g0.y + r.y < y0) || (g0.y - r.y > y0 + 7.0f);
+}
+
+}  // namespace sgs

@@ -1,0 +1,330 @@
+// Backward of the compositing (GS^3LAM Sec. 3.2.1-3.2.2, differentiated for
+// the gradient-descent updates of Sec. 3.3.4 and 3.4).
+//
+// Same launch shape as the forward.  Each pixel starts from T_final and its
+// `last` count and walks its tile list from the back, rebuilding the
+// transmittance before every contributor by division, T_i = T_{i+1}/(1-a_i),
+// instead of storing it.  With g the pixel's upstream gradient (5+F
+// channels) and x_i the Gaussian's channel values (colour, depth, 1, f),
+//   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),
+//   S_i = sum_{j>i} (g . x_j) alpha_j T_j      (one scalar per pixel),
+// then through alpha = min(alpha_max, o 2^q'), q' = A'dx^2 + B2'dx dy + C'dy^2,
+// to the projected mean, the conic, the opacity, and linearly to colour,
+// depth and feature.  The 10+F per-Gaussian values of the 64 pixels of a
+// wavefront are summed with a transposing butterfly (each exchange halves
+// the values a lane keeps, so after log2 steps every lane holds a different
+// total) and one atomic instruction per wavefront and Gaussian writes them.
+// Wavefronts with no contributing pixel skip the reduction.
+#include "raster_common.h"
+
+namespace sgs {
+
+// One butterfly step at xor distance D over the first CNT values.
+template <int NV>
+struct Butterfly {
+    // After the call, the lane holds in v[0] the wavefront total of value
+    // index slot(lane) (the first log2(NV) lane bits, reversed).
+    __device__ __forceinline__ static float reduce(float (&v)[NV], int lane) {
+        int cnt = NV;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            if (cnt > 1) {
+                const int half = cnt >> 1;
+                const bool up = (lane & d) != 0;
+#pragma unroll
+                for (int k = 0; k < NV / 2; ++k) {
+                    if (k < half) {
+                        const float send = up ? v[k] : v[k + half];
+                        const float keep = up ? v[k + half] : v[k];
+                        v[k] = keep + __shfl_xor(send, d, kWave);
+                    }
+                }
+                cnt = half;
+            } else {
+                v[0] += __shfl_xor(v[0], d, kWave);
+            }
+        }
+        return v[0];
+    }
+    __device__ __forceinline__ static int slot(int lane) {
+        int s = 0, cnt = NV;
+#pragma unroll
+        for (int b = 0; (1 << b) < NV; ++b) {
+            cnt >>= 1;
+            if (lane & (1 << b)) s += cnt;
+        }
+        return s;
+    }
+    static constexpr int lanes_log2() {
+        int b = 0;
+        while ((1 << b) < NV) ++b;
+        return b;
+    }
+};
+
+template <int N>
+struct Pow2 {
+    static constexpr int value = N <= 1 ? 1 : 2 * Pow2<(N + 1) / 2>::value;
+};
+template <>
+struct Pow2<1> {
+    static constexpr int value = 1;
+};
+
+template <int TS, int F, int B, bool PARAMS>
+__device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, const float4* __restrict__ app, int n,
+                                         const int32_t* __restrict__ gids, const int2* __restrict__ ranges,
+                                         const gs_view* __restrict__ views, int n_views, int64_t P,
+                                         const RasterConst& c, const float* __restrict__ T_final,
+                                         const int32_t* __restrict__ last, const float* __restrict__ grad_out,
+                                         float* __restrict__ grad_geo, float* __restrict__ grad_app, float4* s_g0,
+                                         float4* s_g1, float4* s_app, int* s_max) {
+    constexpr int NT = TS * TS;
+    constexpr int AV = AppRec<F>::vec;
+    constexpr int NREAL = PARAMS ? 10 + F : 6;
+    constexpr int NV = Pow2<NREAL>::value;
+    constexpr int GA = 4 + F;  // per-Gaussian appearance gradient record
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    constexpr int WPR = TS / 8;
+    const int sbx = (wave % WPR) * 8, sby = (wave / WPR) * 8;
+
+    const int v = view_of_tile(views, n_views, t);
+    const gs_view& vw = views[v];
+    const int tiles_x = ceil_div(vw.width, TS);
+    const int lt = t - vw.tile_offset;
+    const int tx = lt % tiles_x, ty = lt / tiles_x;
+    const int x = tx * TS + sbx + (lane & 7);
+    const int y = ty * TS + sby + (lane >> 3);
+    const bool inside = x < vw.width && y < vw.height;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float wx0 = (float)(tx * TS + sbx) + 0.5f, wy0 = (float)(ty * TS + sby) + 0.5f;
+    const size_t vbase = (size_t)v * n;
+    const int2 rg = ranges[t];
+
+    const int64_t p = inside ? vw.pixel_offset + (int64_t)y * vw.width + x : 0;
+    float T = inside ? T_final[p] : 1.0f;
+    const int lastp = inside ? last[p] : 0;
+    float g[5 + F];
+#pragma unroll
+    for (int ch = 0; ch < 5 + F; ++ch) g[ch] = inside ? grad_out[ch * P + p] : 0.0f;
+    float Sg = 0.0f;
+    const float amin = c.alpha_min, amax = c.alpha_max;
+
+    if (tid == 0) *s_max = 0;
+    __syncthreads();
+    if (lastp > 0) atomicMax(s_max, lastp);
+    __syncthreads();
+    const int end = rg.x + *s_max;
+
+    // per-slot scale: dmx, dmy <- -ln2; dA, dC <- -1/2; dB <- -1; others 1
+    const int my_slot = Butterfly<NV>::slot(lane);
+    const bool writer = (lane >> Butterfly<NV>::lanes_log2()) == 0 && my_slot < NREAL;
+    float scale = 1.0f;
+    if (my_slot < 2) scale = -kLn2;
+    else if (my_slot == 2 || my_slot == 4) scale = -0.5f;
+    else if (my_slot == 3) scale = -1.0f;
+
+    for (int bend = end; bend > rg.x; bend -= B) {
+        const int bstart = max(rg.x, bend - B);
+        const int nb = bend - bstart;
+        __syncthreads();
+        for (int k = tid; k < nb; k += NT) {
+            const int gid = gids[bstart + k];
+            float4 a0, a1;
+            stage_geometry(rec, vbase + gid, a0, a1);
+            s_g0[k] = a0;
+            s_g1[k] = a1;
+#pragma unroll
+            for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
+        }
+        __syncthreads();
+        for (int j = nb - 1; j >= 0; --j) {
+            const float4 g0 = s_g0[j];
+            const float4 g1 = s_g1[j];
+            if (box_misses(g0, g1, wx0, wy0)) continue;
+            const int jl = bstart + j - rg.x;
+            float dx = 0.f, dy = 0.f, G = 0.f;
+            bool unc = false;
+            bool contrib = jl < lastp;
+            float a = 0.0f;
+            if (contrib) {
+                a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
+                contrib = a >= amin;
+            }
+            if (!__any(contrib)) continue;
+            float val[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) val[k] = 0.0f;
+            if (contrib) {
+                const float* ap = reinterpret_cast<const float*>(&s_app[j * AV]);
+                const float ra = 1.0f / (1.0f - a);
+                T = T * ra;  // transmittance before this Gaussian
+                const float w = a * T;
+                float gx = fmaf(g[0], ap[0], fmaf(g[1], ap[1], fmaf(g[2], ap[2], fmaf(g[3], g1.z, g[4]))));
+#pragma unroll
+                for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], ap[3 + f], gx);
+                const float dA = fmaf(T, gx, -Sg * ra);
+                Sg = fmaf(gx, w, Sg);
+                const float h = unc ? dA * a : 0.0f;
+                val[0] = h * fmaf(2.0f * g0.z, dx, g0.w * dy);
+                val[1] = h * fmaf(g0.w, dx, 2.0f * g1.x * dy);
+                val[2] = h * dx * dx;
+                val[3] = h * dx * dy;
+                val[4] = h * dy * dy;
+                val[5] = g[3] * w;
+                if (PARAMS) {
+                    val[6] = unc ? dA * G : 0.0f;
+                    val[7] = g[0] * w;
+                    val[8] = g[1] * w;
+                    val[9] = g[2] * w;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) val[10 + f] = g[5 + f] * w;
+                }
+            }
+            const float tot = Butterfly<NV>::reduce(val, lane);
+            if (writer) {
+                const int gid = gids[bstart + j];
+                if (my_slot < 6) {
+                    atomicAdd(&grad_geo[(vbase + gid) * 8 + my_slot], tot * scale);
+                } else {
+                    atomicAdd(&grad_app[(size_t)gid * GA + (my_slot - 6)], tot);
+                }
+            }
+        }
+    }
+}
+
+template <int TS, int F, int B, bool PARAMS>
+__global__ void __launch_bounds__(TS* TS) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
+                                                       int n, const int32_t* __restrict__ gids,
+                                                       const int2* __restrict__ ranges,
+                                                       const gs_view* __restrict__ views, int n_views,
+                                                       int total_tiles, int64_t P, RasterConst c,
+                                                       const float* __restrict__ T_final,
+                                                       const int32_t* __restrict__ last,
+                                                       const float* __restrict__ grad_out,
+                                                       float* __restrict__ grad_geo, float* __restrict__ grad_app,
+                                                       int32_t* queue, int persistent) {
+    constexpr int AV = AppRec<F>::vec;
+    __shared__ float4 s_g0[B];
+    __shared__ float4 s_g1[B];
+    __shared__ float4 s_app[B * AV];
+    __shared__ int s_tile;
+    __shared__ int s_max;
+    if (!persistent) {
+        bwd_tile<TS, F, B, PARAMS>(blockIdx.x, rec, app, n, gids, ranges, views, n_views, P, c, T_final, last,
+                                   grad_out, grad_geo, grad_app, s_g0, s_g1, s_app, &s_max);
+        return;
+    }
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = atomicAdd(queue + 1, 1);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= total_tiles) break;
+        bwd_tile<TS, F, B, PARAMS>(t, rec, app, n, gids, ranges, views, n_views, P, c, T_final, last, grad_out,
+                                   grad_geo, grad_app, s_g0, s_g1, s_app, &s_max);
+    }
+}
+
+__global__ void k_reset_queue_bwd(int32_t* q) {
+    if (threadIdx.x < 4) q[threadIdx.x] = 0;
+}
+
+template <int TS, int F, int B, bool PARAMS>
+hipError_t launch_bwd_t(const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
+                        const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
+                        int persistent, const float* T_final, const int32_t* last, const float* grad_out,
+                        float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+    auto kern = k_render_bwd<TS, F, B, PARAMS>;
+    unsigned grid = (unsigned)total_tiles;
+    if (persistent) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TS * TS, 0);
+        if (per_cu < 1) per_cu = 1;
+        const unsigned cap = (unsigned)(cus * per_cu);
+        grid = cap < grid ? cap : grid;
+        hipLaunchKernelGGL(k_reset_queue_bwd, dim3(1), dim3(64), 0, s, queue);
+    }
+    if (grid == 0) return hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TS * TS), 0, s, reinterpret_cast<const float4*>(rec),
+                       reinterpret_cast<const float4*>(app), n, gids, reinterpret_cast<const int2*>(ranges), views,
+                       n_views, total_tiles, P, c, T_final, last, grad_out, grad_geo, grad_app, queue, persistent);
+    return hipGetLastError();
+}
+
+template <int TS, int F, bool PARAMS>
+hipError_t launch_bwd_b(int B, const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
+                        const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
+                        int persistent, const float* T_final, const int32_t* last, const float* grad_out,
+                        float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+    switch (B) {
+        case 64:
+            return launch_bwd_t<TS, F, 64, PARAMS>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
+                                                   persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+        case 128:
+            return launch_bwd_t<TS, F, 128, PARAMS>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
+                                                    persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+        default:
+            return launch_bwd_t<TS, F, 256, PARAMS>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
+                                                    persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+    }
+}
+
+template <int F, bool PARAMS>
+hipError_t launch_bwd_ts(int TS, int B, const float* rec, const float* app, int n, const int32_t* gids,
+                         const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
+                         const RasterConst& c, int persistent, const float* T_final, const int32_t* last,
+                         const float* grad_out, float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+    switch (TS) {
+        case 8:
+            return launch_bwd_b<8, F, PARAMS>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
+                                              persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+        case 32:
+            return launch_bwd_b<32, F, PARAMS>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
+                                               persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+        default:
+            return launch_bwd_b<16, F, PARAMS>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
+                                               persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+    }
+}
+
+template <int F>
+hipError_t launch_bwd_f(bool params, int TS, int B, const float* rec, const float* app, int n, const int32_t* gids,
+                        const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
+                        const RasterConst& c, int persistent, const float* T_final, const int32_t* last,
+                        const float* grad_out, float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+    if (params)
+        return launch_bwd_ts<F, true>(TS, B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                      T_final, last, grad_out, grad_geo, grad_app, queue, s);
+    return launch_bwd_ts<F, false>(TS, B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                   T_final, last, grad_out, grad_geo, grad_app, queue, s);
+}
+
+hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
+                             const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
+                             int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
+                             const float* T_final, const int32_t* last, const float* grad_out, bool params,
+                             float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+    const int TS = c.tile;
+    switch (n_feat) {
+        case 0:
+            return launch_bwd_f<0>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+                                   total_pixels, c, persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+        case 8:
+            return launch_bwd_f<8>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+                                   total_pixels, c, persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+        case 32:
+            return launch_bwd_f<32>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views,
+                                    total_tiles, total_pixels, c, persistent, T_final, last, grad_out, grad_geo,
+                                    grad_app, queue, s);
+        default:
+            return launch_bwd_f<16>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views,
+                                    total_tiles, total_pixels, c, persistent, T_final, last, grad_out, grad_geo,
+                                    grad_app, queue, s);
+    }
+}
+
+}  // namespace sgs

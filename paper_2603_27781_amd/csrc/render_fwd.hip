@@ -1,0 +1,227 @@
+// Forward compositing, GS^3LAM Sec. 3.2.1 Eq. (4)-(6), Sec. 3.2.2 Eq. (7),
+// Sec. 3.3.1 Eq. (9):
+//   out_ch(p) = sum_i x_i,ch alpha_i T_i,   T_i = prod_{j<i} (1 - alpha_j)
+// for colour (3), depth (1) and the F semantic feature channels, with the
+// cumulative opacity written as 1 - T_final (equal to sum_i alpha_i T_i).
+//
+// Launch shape: one workgroup of TS*TS threads per (view, tile); each
+// wavefront owns an 8x8 block of pixels (compact, so that a small splat
+// touches few wavefronts).  The tile's depth-sorted list is walked in
+// batches of B instances that the whole workgroup stages into LDS (geometry
+// as two float4, appearance as (3+F) floats padded to float4); every
+// wavefront then reads them as broadcasts.  A wavefront skips a Gaussian
+// whose pixel box misses its 8x8 block (uniform branch, no exp), a pixel
+// stops when T would fall below T_min, a wavefront stops when all of its
+// pixels stopped and the workgroup stops when every wavefront did.
+//
+// persistent = 1 launches ~one wave of workgroups that pull tile indices
+// from a device counter (all views share one queue), so views of uneven
+// size are balanced inside one launch.
+#include "raster_common.h"
+
+namespace sgs {
+
+template <int TS, int F, int B>
+__device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, const float4* __restrict__ app, int n,
+                                         const int32_t* __restrict__ gids, const int2* __restrict__ ranges,
+                                         const gs_view* __restrict__ views, int n_views, int64_t P,
+                                         const RasterConst& c, float* __restrict__ out, float* __restrict__ T_final,
+                                         int32_t* __restrict__ last, float4* s_g0, float4* s_g1, float4* s_app) {
+    constexpr int NT = TS * TS;
+    constexpr int AV = AppRec<F>::vec;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    constexpr int WPR = TS / 8;
+    const int sbx = (wave % WPR) * 8, sby = (wave / WPR) * 8;
+
+    const int v = view_of_tile(views, n_views, t);
+    const gs_view& vw = views[v];
+    const int tiles_x = ceil_div(vw.width, TS);
+    const int lt = t - vw.tile_offset;
+    const int tx = lt % tiles_x, ty = lt / tiles_x;
+    const int x = tx * TS + sbx + (lane & 7);
+    const int y = ty * TS + sby + (lane >> 3);
+    const bool inside = x < vw.width && y < vw.height;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float wx0 = (float)(tx * TS + sbx) + 0.5f, wy0 = (float)(ty * TS + sby) + 0.5f;
+    const size_t vbase = (size_t)v * n;
+    const int2 rg = ranges[t];
+
+    float acc[4 + F];
+#pragma unroll
+    for (int k = 0; k < 4 + F; ++k) acc[k] = 0.0f;
+    float T = 1.0f;
+    int lastj = 0;
+    bool done = !inside;
+    const float amin = c.alpha_min, amax = c.alpha_max, tmin = c.T_min;
+
+    for (int b0 = rg.x; b0 < rg.y; b0 += B) {
+        if (__syncthreads_and(done)) break;
+        const int nb = min(B, rg.y - b0);
+        for (int k = tid; k < nb; k += NT) {
+            const int gid = gids[b0 + k];
+            float4 a0, a1;
+            stage_geometry(rec, vbase + gid, a0, a1);
+            s_g0[k] = a0;
+            s_g1[k] = a1;
+#pragma unroll
+            for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
+        }
+        __syncthreads();
+        if (!__all(done)) {
+            for (int j = 0; j < nb; ++j) {
+                const float4 g0 = s_g0[j];
+                const float4 g1 = s_g1[j];
+                if (box_misses(g0, g1, wx0, wy0)) continue;
+                if (!done) {
+                    float dx, dy, G;
+                    bool unc;
+                    const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
+                    if (a >= amin) {
+                        const float Tn = T * (1.0f - a);
+                        if (Tn < tmin) {
+                            done = true;
+                        } else {
+                            const float w = a * T;
+                            const float* ap = reinterpret_cast<const float*>(&s_app[j * AV]);
+                            acc[0] = fmaf(w, ap[0], acc[0]);
+                            acc[1] = fmaf(w, ap[1], acc[1]);
+                            acc[2] = fmaf(w, ap[2], acc[2]);
+                            acc[3] = fmaf(w, g1.z, acc[3]);
+#pragma unroll
+                            for (int f = 0; f < F; ++f) acc[4 + f] = fmaf(w, ap[3 + f], acc[4 + f]);
+                            T = Tn;
+                            lastj = b0 - rg.x + j + 1;
+                        }
+                    }
+                }
+                if (__all(done)) break;
+            }
+        }
+    }
+    if (inside) {
+        const int64_t p = vw.pixel_offset + (int64_t)y * vw.width + x;
+        out[p] = acc[0];
+        out[P + p] = acc[1];
+        out[2 * P + p] = acc[2];
+        out[3 * P + p] = acc[3];
+        out[4 * P + p] = 1.0f - T;
+#pragma unroll
+        for (int f = 0; f < F; ++f) out[(5 + f) * P + p] = acc[4 + f];
+        T_final[p] = T;
+        last[p] = lastj;
+    }
+}
+
+template <int TS, int F, int B>
+__global__ void __launch_bounds__(TS* TS) k_render_fwd(const float4* __restrict__ rec, const float4* __restrict__ app,
+                                                       int n, const int32_t* __restrict__ gids,
+                                                       const int2* __restrict__ ranges,
+                                                       const gs_view* __restrict__ views, int n_views,
+                                                       int total_tiles, int64_t P, RasterConst c,
+                                                       float* __restrict__ out, float* __restrict__ T_final,
+                                                       int32_t* __restrict__ last, int32_t* queue, int persistent) {
+    constexpr int AV = AppRec<F>::vec;
+    __shared__ float4 s_g0[B];
+    __shared__ float4 s_g1[B];
+    __shared__ float4 s_app[B * AV];
+    __shared__ int s_tile;
+    if (!persistent) {
+        fwd_tile<TS, F, B>(blockIdx.x, rec, app, n, gids, ranges, views, n_views, P, c, out, T_final, last, s_g0,
+                           s_g1, s_app);
+        return;
+    }
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= total_tiles) break;
+        fwd_tile<TS, F, B>(t, rec, app, n, gids, ranges, views, n_views, P, c, out, T_final, last, s_g0, s_g1,
+                           s_app);
+    }
+}
+
+__global__ void k_reset_queue(int32_t* q) {
+    if (threadIdx.x < 4) q[threadIdx.x] = 0;
+}
+
+template <int TS, int F, int B>
+hipError_t launch_fwd_t(const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
+                        const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
+                        int persistent, float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s) {
+    auto kern = k_render_fwd<TS, F, B>;
+    unsigned grid = (unsigned)total_tiles;
+    if (persistent) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TS * TS, 0);
+        if (per_cu < 1) per_cu = 1;
+        unsigned cap = (unsigned)(cus * per_cu);
+        grid = cap < grid ? cap : grid;
+        hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, queue);
+    }
+    if (grid == 0) return hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TS * TS), 0, s, reinterpret_cast<const float4*>(rec),
+                       reinterpret_cast<const float4*>(app), n, gids, reinterpret_cast<const int2*>(ranges), views,
+                       n_views, total_tiles, P, c, out, T_final, last, queue, persistent);
+    return hipGetLastError();
+}
+
+template <int TS, int F>
+hipError_t launch_fwd_b(int B, const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
+                        const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
+                        int persistent, float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s) {
+    switch (B) {
+        case 64:
+            return launch_fwd_t<TS, F, 64>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                           out, T_final, last, queue, s);
+        case 128:
+            return launch_fwd_t<TS, F, 128>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                            out, T_final, last, queue, s);
+        default:
+            return launch_fwd_t<TS, F, 256>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                            out, T_final, last, queue, s);
+    }
+}
+
+template <int F>
+hipError_t launch_fwd_f(int TS, int B, const float* rec, const float* app, int n, const int32_t* gids,
+                        const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
+                        const RasterConst& c, int persistent, float* out, float* T_final, int32_t* last,
+                        int32_t* queue, hipStream_t s) {
+    switch (TS) {
+        case 8:
+            return launch_fwd_b<8, F>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                      out, T_final, last, queue, s);
+        case 32:
+            return launch_fwd_b<32, F>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                       out, T_final, last, queue, s);
+        default:
+            return launch_fwd_b<16, F>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+                                       out, T_final, last, queue, s);
+    }
+}
+
+hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
+                             const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
+                             int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent, float* out,
+                             float* T_final, int32_t* last, int32_t* queue, hipStream_t s) {
+    const int TS = c.tile;
+    switch (n_feat) {
+        case 0:
+            return launch_fwd_f<0>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+                                   total_pixels, c, persistent, out, T_final, last, queue, s);
+        case 8:
+            return launch_fwd_f<8>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+                                   total_pixels, c, persistent, out, T_final, last, queue, s);
+        case 32:
+            return launch_fwd_f<32>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+                                    total_pixels, c, persistent, out, T_final, last, queue, s);
+        default:
+            return launch_fwd_f<16>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+                                    total_pixels, c, persistent, out, T_final, last, queue, s);
+    }
+}
+
+}  // namespace sgs

@@ -1,0 +1,298 @@
+// Host side of the C ABI declared in include/sgs.h: argument validation,
+// derived constants, workspace carving and kernel launches.  Nothing here
+// allocates device memory, synchronises or reads device memory.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "sgs_common.h"
+
+using namespace sgs;
+
+namespace {
+
+thread_local char g_hip_err[256] = {0};
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return GS_OK;
+    std::snprintf(g_hip_err, sizeof(g_hip_err), "%s", hipGetErrorString(e));
+    return GS_EHIP;
+}
+
+bool pow2_tile(int t) { return t == 8 || t == 16 || t == 32; }
+
+int check_config(const gs_config* c) {
+    if (!c) return GS_EINVAL;
+    if (!pow2_tile(c->tile)) return GS_EUNSUPPORTED;
+    if (c->lds_batch != 64 && c->lds_batch != 128 && c->lds_batch != 256) return GS_EUNSUPPORTED;
+    if (!(c->alpha_min > 0.0f && c->alpha_min < 1.0f)) return GS_EINVAL;
+    if (!(c->alpha_max > c->alpha_min && c->alpha_max < 1.0f)) return GS_EINVAL;
+    if (!(c->T_min > 0.0f && c->T_min < 1.0f)) return GS_EINVAL;
+    if (!(c->z_near > 0.0f) || !(c->blur >= 0.0f) || !(c->guard > 0.0f)) return GS_EINVAL;
+    if (c->persistent != 0 && c->persistent != 1) return GS_EINVAL;
+    return GS_OK;
+}
+
+RasterConst make_const(const gs_config* c) {
+    RasterConst k;
+    k.z_near = c->z_near;
+    k.blur = c->blur;
+    k.guard = c->guard;
+    k.alpha_min = c->alpha_min;
+    k.alpha_max = c->alpha_max;
+    k.T_min = c->T_min;
+    const double am = (double)c->alpha_min;
+    k.kbox = (float)(2.0 * std::log(1.0 / am));
+    k.logit_min = (float)std::log(am / (1.0 - am));
+    k.tile = c->tile;
+    return k;
+}
+
+// Views must be laid out back to back (as gs_views_layout does).
+int check_views(const gs_view* views, const gs_view* views_dev, int n_views, int tile, int64_t* total_pixels,
+                int* total_tiles) {
+    if (!views || !views_dev) return GS_EINVAL;
+    if (n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+    int64_t px = 0;
+    int64_t tl = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gs_view& w = views[v];
+        if (w.width <= 0 || w.height <= 0 || w.width > 65535 * 8 || w.height > 65535 * 8) return GS_EINVAL;
+        if (!(w.fx > 0.0f) || !(w.fy > 0.0f)) return GS_EINVAL;
+        if (w.pixel_offset != px) return GS_EINVAL;
+        if (tile > 0 && w.tile_offset != tl) return GS_EINVAL;
+        px += (int64_t)w.width * w.height;
+        if (tile > 0) tl += (int64_t)ceil_div(w.width, tile) * ceil_div(w.height, tile);
+    }
+    if (tl >= (1ll << 31) || px >= (1ll << 31)) return GS_EINVAL;
+    if (total_pixels) *total_pixels = px;
+    if (total_tiles) *total_tiles = (int)tl;
+    return GS_OK;
+}
+
+int check_gauss(const gs_gaussians* g, bool need_app) {
+    if (!g) return GS_EINVAL;
+    if (g->n < 1) return GS_EINVAL;
+    if (!g->mu || !g->log_scale || !g->quat || !g->opacity_logit) return GS_EINVAL;
+    if (!feat_supported(g->n_feat)) return GS_EUNSUPPORTED;
+    if (need_app && (!g->color || (g->n_feat > 0 && !g->feat))) return GS_EINVAL;
+    return GS_OK;
+}
+
+GaussPtrs gauss_ptrs(const gs_gaussians* g) {
+    GaussPtrs p;
+    p.mu = g->mu;
+    p.log_scale = g->log_scale;
+    p.quat = g->quat;
+    p.logit = g->opacity_logit;
+    p.color = g->color;
+    p.feat = g->feat;
+    p.n = g->n;
+    p.n_feat = g->n_feat;
+    return p;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+size_t grad2d_bytes(int n, int n_feat, int n_views) {
+    return ((size_t)n_views * n * 8 + (size_t)n * (4 + n_feat)) * sizeof(float);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_default_config(gs_config* cfg) {
+    if (!cfg) return GS_EINVAL;
+    cfg->z_near = 0.2f;
+    cfg->blur = 0.3f;
+    cfg->guard = 1.3f;
+    cfg->alpha_min = 1.0f / 255.0f;
+    cfg->alpha_max = 0.99f;
+    cfg->T_min = 1e-4f;
+    cfg->tile = 16;
+    cfg->lds_batch = 256;
+    cfg->persistent = 0;
+    cfg->reserved = 0;
+    return GS_OK;
+}
+
+int gs_views_layout(gs_view* views, int32_t n_views, int32_t tile, int64_t* total_pixels, int32_t* total_tiles) {
+    if (!views || n_views < 1 || n_views > GS_MAX_VIEWS || !pow2_tile(tile)) return GS_EINVAL;
+    int64_t px = 0, tl = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (views[v].width <= 0 || views[v].height <= 0) return GS_EINVAL;
+        views[v].pixel_offset = px;
+        views[v].tile_offset = (int32_t)tl;
+        views[v].reserved = 0;
+        px += (int64_t)views[v].width * views[v].height;
+        tl += (int64_t)ceil_div(views[v].width, tile) * ceil_div(views[v].height, tile);
+    }
+    if (tl >= (1ll << 31)) return GS_EINVAL;
+    if (total_pixels) *total_pixels = px;
+    if (total_tiles) *total_tiles = (int32_t)tl;
+    return GS_OK;
+}
+
+int32_t gs_app_stride(int32_t n_feat) { return n_feat < 0 ? -1 : (int32_t)app_stride(n_feat); }
+
+int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+               const gs_config* cfg, float* rec, uint32_t* rect, int32_t* tiles_touched, float* app,
+               gs_stream stream) {
+    int st = check_gauss(g, app != nullptr);
+    if (st) return st;
+    if ((st = check_config(cfg))) return st;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, nullptr))) return st;
+    if (!rec || !rect || !tiles_touched) return GS_EINVAL;
+    if (!aligned16(rec) || (app && !aligned16(app))) return GS_EINVAL;
+    if ((int64_t)g->n * n_views >= (1ll << 31)) return GS_EINVAL;
+    return hip_status(launch_project(gauss_ptrs(g), views_dev, n_views, make_const(cfg), rec, rect, tiles_touched,
+                                     app, app_stride(g->n_feat), reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_bin_sort_workspace(int32_t n, int32_t n_views, int64_t capacity, size_t* bytes) {
+    if (!bytes || n < 1 || n_views < 1 || n_views > GS_MAX_VIEWS || capacity < 0) return GS_EINVAL;
+    if ((int64_t)n * n_views >= (1ll << 31) || capacity >= (1ll << 31)) return GS_EINVAL;
+    *bytes = binsort_workspace_bytes(n, n_views, capacity);
+    return GS_OK;
+}
+
+int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float* rec, int32_t n,
+                const gs_view* views, const gs_view* views_dev, int32_t n_views, const gs_config* cfg, void* ws,
+                size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* gids, int32_t* tile_ranges,
+                int64_t* counts, gs_stream stream) {
+    int st = check_config(cfg);
+    if (st) return st;
+    int total_tiles = 0;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, &total_tiles))) return st;
+    if (!rect || !tiles_touched || !rec || !ws || !tile_ranges || !counts) return GS_EINVAL;
+    if (capacity > 0 && (!tile_keys || !gids)) return GS_EINVAL;
+    if (n < 1 || capacity < 0 || capacity >= (1ll << 31) || (int64_t)n * n_views >= (1ll << 31)) return GS_EINVAL;
+    if (ws_bytes < binsort_workspace_bytes(n, n_views, capacity)) return GS_ECAPACITY;
+    if (!aligned16(rec) || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return GS_EINVAL;
+    return hip_status(launch_binsort(rect, tiles_touched, rec, n, views_dev, n_views, total_tiles, cfg->tile, ws,
+                                     capacity, tile_keys, gids, tile_ranges, counts,
+                                     reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* gids,
+                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                  const gs_config* cfg, float* out, float* T_final, int32_t* last, int32_t* queue,
+                  gs_stream stream) {
+    int st = check_config(cfg);
+    if (st) return st;
+    int64_t P = 0;
+    int total_tiles = 0;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, &P, &total_tiles))) return st;
+    if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
+    if (n < 1 || !rec || !app || !gids || !tile_ranges || !out || !T_final || !last) return GS_EINVAL;
+    if (cfg->persistent && !queue) return GS_EINVAL;
+    if (!aligned16(rec) || !aligned16(app)) return GS_EINVAL;
+    return hip_status(launch_render_fwd(rec, app, n, n_feat, gids, tile_ranges, views_dev, n_views, total_tiles, P,
+                                        make_const(cfg), cfg->lds_batch, cfg->persistent, out, T_final, last, queue,
+                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, const float* depth_target,
+                 const int32_t* labels, const float* decoder, int32_t n_classes, const float* weights,
+                  const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
+                  gs_stream stream) {
+    if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
+    int64_t P = 0;
+    int st = check_views(views, views_dev, n_views, 0, &P, nullptr);
+    if (st) return st;
+    if (!out || !rgb_target || !depth_target || !weights || !grad_out || !loss) return GS_EINVAL;
+    if (n_classes < 0 || n_classes > GS_MAX_CLASSES) return GS_EINVAL;
+    if (n_classes > 0 && n_feat > 0 && (!labels || !decoder)) return GS_EINVAL;
+    return hip_status(launch_loss(out, n_feat, rgb_target, depth_target, labels, decoder, n_feat > 0 ? n_classes : 0,
+                                  weights, views_dev, n_views, P, grad_out, loss,
+                                  reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, size_t* bytes) {
+    if (!bytes || n < 1 || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+    if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
+    *bytes = grad2d_bytes(n, n_feat, n_views);
+    return GS_OK;
+}
+
+int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* gids,
+                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                  const gs_config* cfg, const float* T_final, const int32_t* last, const float* grad_out,
+                  uint32_t flags, float* grad2d, size_t grad2d_bytes_, gs_gaussian_grads* grads, int32_t* queue,
+                  gs_stream stream) {
+    const bool params = (flags & GS_GRAD_PARAMS) != 0;
+    int st = check_gauss(g, false);
+    if (st) return st;
+    if ((st = check_config(cfg))) return st;
+    int64_t P = 0;
+    int total_tiles = 0;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, &P, &total_tiles))) return st;
+    if ((flags & ~(uint32_t)(GS_GRAD_PARAMS | GS_GRAD_POSE)) != 0 || flags == 0) return GS_EINVAL;
+    if (!rec || !app || !gids || !tile_ranges || !T_final || !last || !grad_out || !grad2d) return GS_EINVAL;
+    if (cfg->persistent && !queue) return GS_EINVAL;
+    if (grad2d_bytes_ < grad2d_bytes(g->n, g->n_feat, n_views)) return GS_ECAPACITY;
+    if (!aligned16(rec) || !aligned16(app) || !aligned16(grad2d)) return GS_EINVAL;
+    if (params) {
+        if (!grads || !grads->mu || !grads->log_scale || !grads->quat || !grads->opacity_logit || !grads->color ||
+            (g->n_feat > 0 && !grads->feat))
+            return GS_EINVAL;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float* geo = grad2d;
+    float* appg = grad2d + (size_t)n_views * g->n * 8;
+    hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (int64_t)(grad2d_bytes(g->n, g->n_feat, n_views) / 4), s);
+    if (e != hipSuccess) return hip_status(e);
+    const RasterConst c = make_const(cfg);
+    e = launch_render_bwd(rec, app, g->n, g->n_feat, gids, tile_ranges, views_dev, n_views, total_tiles, P, c,
+                          cfg->lds_batch, cfg->persistent, T_final, last, grad_out, params, geo, appg, queue, s);
+    if (e != hipSuccess) return hip_status(e);
+    if (params) {
+        GradPtrs o;
+        o.mu = grads->mu;
+        o.log_scale = grads->log_scale;
+        o.quat = grads->quat;
+        o.logit = grads->opacity_logit;
+        o.color = grads->color;
+        o.feat = grads->feat;
+        e = launch_project_bwd(gauss_ptrs(g), views_dev, n_views, c, geo, appg, o, s);
+    }
+    return hip_status(e);
+}
+
+int gs_pose_grad_workspace(int32_t n, int32_t n_views, size_t* bytes) {
+    if (!bytes || n < 1 || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+    *bytes = pose_workspace_bytes(n, n_views);
+    return GS_OK;
+}
+
+int gs_pose_grad(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                 const gs_config* cfg, const float* grad2d, void* ws, size_t ws_bytes, float* twist,
+                 gs_stream stream) {
+    int st = check_gauss(g, false);
+    if (st) return st;
+    if ((st = check_config(cfg))) return st;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, nullptr))) return st;
+    if (!grad2d || !ws || !twist) return GS_EINVAL;
+    if (ws_bytes < pose_workspace_bytes(g->n, n_views)) return GS_ECAPACITY;
+    if (!aligned16(grad2d) || (reinterpret_cast<uintptr_t>(ws) & 15u) != 0) return GS_EINVAL;
+    return hip_status(launch_pose_grad(gauss_ptrs(g), views_dev, n_views, make_const(cfg), grad2d, ws, twist,
+                                       reinterpret_cast<hipStream_t>(stream)));
+}
+
+const char* gs_error_string(int status) {
+    switch (status) {
+        case GS_OK: return "ok";
+        case GS_EINVAL: return "invalid argument";
+        case GS_ECAPACITY: return "buffer too small";
+        case GS_EHIP: return "HIP error";
+        case GS_EUNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char* gs_last_hip_error(void) { return g_hip_err; }
+
+int32_t gs_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal definitions shared by the HIP translation units of libsgs.
+// Every kernel here targets gfx950 (CDNA4, wave64) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "../../include/sgs.h"
+
+namespace sgs {
+
+constexpr int kWave = 64;
+
+// Constants of the rasterizer derived on the host from gs_config.
+struct RasterConst {
+    float z_near, blur, guard, alpha_min, alpha_max, T_min;
+    float kbox;       // (float)(2 ln(1/alpha_min)): squared box radius in std-devs
+    float logit_min;  // (float)ln(alpha_min / (1 - alpha_min)): opacity cull
+    int32_t tile;
+};
+
+// Plain-pointer view of the Gaussian planes, passed by value to kernels.
+struct GaussPtrs {
+    const float* mu;
+    const float* log_scale;
+    const float* quat;
+    const float* logit;
+    const float* color;
+    const float* feat;
+    int32_t n, n_feat;
+};
+
+struct GradPtrs {
+    float* mu;
+    float* log_scale;
+    float* quat;
+    float* logit;
+    float* color;
+    float* feat;
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Index of the view owning global tile t (views sorted by tile_offset).
+__device__ inline int view_of_tile(const gs_view* views, int n_views, int t) {
+    int v = 0;
+    while (v + 1 < n_views && views[v + 1].tile_offset <= t) ++v;
+    return v;
+}
+
+// Pack two non-negative radii as binary16, rounded up (a conservative box).
+__device__ inline float pack_radii(float rx, float ry) {
+    __half hx = __float2half_ru(rx);
+    __half hy = __float2half_ru(ry);
+    uint32_t bits = (uint32_t)__half_as_ushort(hx) | ((uint32_t)__half_as_ushort(hy) << 16);
+    return __uint_as_float(bits);
+}
+
+__device__ inline float2 unpack_radii(float packed) {
+    uint32_t bits = __float_as_uint(packed);
+    return make_float2(__half2float(__ushort_as_half((unsigned short)(bits & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(bits >> 16))));
+}
+
+// Fill kernel (used instead of hipMemsetAsync so that calls stay correct
+// when captured in a HIP graph and replayed).
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count);
+
+hipError_t fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// launchers (each defined in the translation unit of its kernels)
+// ---------------------------------------------------------------------------
+hipError_t launch_project(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
+                          float* rec, uint32_t* rect, int32_t* touched, float* app, int app_stride,
+                          hipStream_t s);
+
+size_t binsort_workspace_bytes(int n, int n_views, int64_t capacity);
+hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const float* rec, int n,
+                          const gs_view* views_dev, int n_views, int total_tiles, int tile, void* ws,
+                          int64_t capacity, uint32_t* tile_keys, int32_t* gids, int32_t* ranges,
+                          int64_t* counts, hipStream_t s);
+
+hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
+                             const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
+                             int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
+                             float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s);
+
+hipError_t launch_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t,
+                       const int32_t* labels, const float* decoder, int n_classes, const float* weights,
+                       const gs_view* views_dev, int n_views, int64_t total_pixels, float* grad_out,
+                       double* loss, hipStream_t s);
+
+hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
+                             const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
+                             int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
+                             const float* T_final, const int32_t* last, const float* grad_out, bool params,
+                             float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s);
+
+hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
+                              const float* grad_geo, const float* grad_app, const GradPtrs& out,
+                              hipStream_t s);
+
+size_t pose_workspace_bytes(int n, int n_views);
+hipError_t launch_pose_grad(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
+                            const float* grad_geo, void* ws, float* twist, hipStream_t s);
+
+// Feature counts compiled into the render kernels.
+inline bool feat_supported(int f) { return f == 0 || f == 8 || f == 16 || f == 32; }
+inline int app_stride(int f) { return ((3 + f) + 3) / 4 * 4; }
+
+}  // namespace sgs

@@ -1,0 +1,287 @@
+"""Torch-facing driver of the HIP rasterizer.
+
+PyTorch provides device memory and the stream; every step of the path runs
+in libsgs kernels called through the C ABI (see include/sgs.h).  A
+`Rasterizer` owns the buffers of one workload shape (n Gaussians, F feature
+channels, a fixed set of view sizes) so that a whole fwd+bwd step can be
+captured once in a HIP graph and replayed; poses can change between replays
+through `set_poses`.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GsConfig, GsGaussianGrads, GsGaussians, GsView, check
+
+VIEW_WORDS = ctypes.sizeof(GsView) // 4  # 22 x 32-bit words per view
+
+
+@dataclasses.dataclass
+class Config:
+    z_near: float = 0.2
+    blur: float = 0.3
+    guard: float = 1.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    tile: int = 16
+    lds_batch: int = 256
+    persistent: int = 0
+
+    def c(self) -> GsConfig:
+        return GsConfig(self.z_near, self.blur, self.guard, self.alpha_min, self.alpha_max, self.T_min, self.tile,
+                        self.lds_batch, self.persistent, 0)
+
+
+@dataclasses.dataclass
+class Gaussians:
+    """FP32 structure-of-arrays planes on the GPU (GS^3LAM Eq. 1)."""
+    mu: torch.Tensor         # [3][n]
+    log_scale: torch.Tensor  # [3][n]
+    quat: torch.Tensor       # [4][n]
+    logit: torch.Tensor      # [n]
+    color: torch.Tensor      # [3][n]
+    feat: torch.Tensor       # [F][n]
+
+    @property
+    def n(self) -> int:
+        return int(self.mu.shape[1])
+
+    @property
+    def n_feat(self) -> int:
+        return int(self.feat.shape[0])
+
+    @staticmethod
+    def from_numpy(scene, device="cuda") -> "Gaussians":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return Gaussians(t(scene.mu), t(scene.log_scale), t(scene.quat), t(scene.logit), t(scene.color),
+                         t(scene.feat))
+
+    def tensors(self):
+        return [self.mu, self.log_scale, self.quat, self.logit, self.color, self.feat]
+
+    def c(self) -> GsGaussians:
+        for t in self.tensors():
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), "Gaussian planes: contiguous fp32 cuda"
+        return GsGaussians(self.mu.data_ptr(), self.log_scale.data_ptr(), self.quat.data_ptr(), self.logit.data_ptr(),
+                           self.color.data_ptr(), self.feat.data_ptr() if self.n_feat > 0 else None, self.n,
+                           self.n_feat)
+
+    def zeros_like(self) -> "Gaussians":
+        return Gaussians(*(torch.zeros_like(t) for t in self.tensors()))
+
+
+def _grads_c(gr: Gaussians) -> GsGaussianGrads:
+    return GsGaussianGrads(gr.mu.data_ptr(), gr.log_scale.data_ptr(), gr.quat.data_ptr(), gr.logit.data_ptr(),
+                           gr.color.data_ptr(), gr.feat.data_ptr() if gr.n_feat > 0 else None)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Views:
+    """Host and device copies of the gs_view array (back-to-back layout)."""
+
+    def __init__(self, views: Sequence, tile: int, device="cuda"):
+        L = _lib.load()
+        V = len(views)
+        self.n = V
+        self.tile = tile
+        self.host = (GsView * V)()
+        for i, v in enumerate(views):
+            h = self.host[i]
+            h.width, h.height = int(v.width), int(v.height)
+            h.fx, h.fy, h.cx, h.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
+            Rt = np.asarray(v.Rt, np.float32).reshape(-1)
+            for k in range(12):
+                h.Rt[k] = float(Rt[k])
+        tp, tt = ctypes.c_int64(0), ctypes.c_int32(0)
+        check(L.gs_views_layout(self.host, V, tile, ctypes.byref(tp), ctypes.byref(tt)), "gs_views_layout")
+        self.total_pixels = int(tp.value)
+        self.total_tiles = int(tt.value)
+        raw = np.frombuffer(bytes(self.host), dtype=np.int32).reshape(V, VIEW_WORDS).copy()
+        self.dev = torch.from_numpy(raw).to(device)
+        self.sizes = [(int(v.width), int(v.height)) for v in views]
+
+    def set_poses(self, Rts: torch.Tensor) -> None:
+        """Overwrite the device poses ([V][3][4] float32, on the GPU) in place:
+        graph-safe (a device copy into the buffer the captured kernels read)."""
+        self.dev.view(torch.float32)[:, 6:18].copy_(Rts.reshape(self.n, 12))
+
+    def dev_ptr(self):
+        return ctypes.c_void_p(self.dev.data_ptr())
+
+
+class Rasterizer:
+    """Buffers and calls of one fwd+bwd pass for a fixed workload shape."""
+
+    def __init__(self, n: int, n_feat: int, views: Views, cfg: Config, capacity: Optional[int] = None,
+                 device="cuda"):
+        L = _lib.load()
+        self.L, self.n, self.F, self.views, self.cfg, self.device = L, n, n_feat, views, cfg, device
+        self.cc = cfg.c()
+        V, P = views.n, views.total_pixels
+        self.AS = int(L.gs_app_stride(n_feat))
+        dev = dict(device=device)
+        self.rec = torch.empty(V * n * 8, dtype=torch.float32, **dev)
+        self.rect = torch.empty(V * n * 2, dtype=torch.int32, **dev)
+        self.touched = torch.empty(V * n, dtype=torch.int32, **dev)
+        self.app = torch.empty(n * self.AS, dtype=torch.float32, **dev)
+        self.counts = torch.zeros(4, dtype=torch.int64, **dev)
+        self.ranges = torch.empty(views.total_tiles * 2, dtype=torch.int32, **dev)
+        self.out = torch.empty(5 + n_feat, P, dtype=torch.float32, **dev)
+        self.T_final = torch.empty(P, dtype=torch.float32, **dev)
+        self.last = torch.empty(P, dtype=torch.int32, **dev)
+        self.queue = torch.zeros(8, dtype=torch.int32, **dev)
+        b = ctypes.c_size_t(0)
+        check(L.gs_render_bwd_workspace(n, n_feat, V, ctypes.byref(b)), "gs_render_bwd_workspace")
+        self.grad2d = torch.empty(b.value // 4, dtype=torch.float32, **dev)
+        check(L.gs_pose_grad_workspace(n, V, ctypes.byref(b)), "gs_pose_grad_workspace")
+        self.pose_ws = torch.empty(max(b.value, 16) // 8 + 1, dtype=torch.float64, **dev)
+        self.twist = torch.zeros(V, 6, dtype=torch.float32, **dev)
+        self.loss = torch.zeros(4, dtype=torch.float64, **dev)
+        self.grad_out = torch.empty_like(self.out)
+        self.capacity = 0
+        self.set_capacity(capacity if capacity is not None else max(4 * V * n, 1 << 16))
+
+    # ------------------------------------------------------------------ buffers
+    def set_capacity(self, capacity: int) -> None:
+        capacity = int(capacity)
+        if capacity == self.capacity:
+            return
+        b = ctypes.c_size_t(0)
+        check(self.L.gs_bin_sort_workspace(self.n, self.views.n, capacity, ctypes.byref(b)), "gs_bin_sort_workspace")
+        self.ws = torch.empty(b.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + b.value]
+        self.keys = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+        self.gids = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+        self.capacity = capacity
+
+    def instance_counts(self):
+        """(instances, visible pairs, overflow) -- synchronises."""
+        c = self.counts.cpu().tolist()
+        return int(c[0]), int(c[1]), bool(c[2])
+
+    def ensure_capacity(self, g: Gaussians, slack: float = 1.25) -> int:
+        """Run projection + binning once and grow the instance buffers if
+        needed (one host synchronisation; call before capturing a graph)."""
+        self.project(g)
+        self.bin_sort()
+        inst, _, over = self.instance_counts()
+        if over or inst > self.capacity:
+            self.set_capacity(int(inst * slack) + 1024)
+            self.project(g)
+            self.bin_sort()
+        return inst
+
+    # -------------------------------------------------------------------- calls
+    def project(self, g: Gaussians) -> None:
+        check(self.L.gs_project(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
+                                ctypes.byref(self.cc), self.rec.data_ptr(), self.rect.data_ptr(),
+                                self.touched.data_ptr(), self.app.data_ptr(), _stream()), "gs_project")
+
+    def bin_sort(self) -> None:
+        check(self.L.gs_bin_sort(self.rect.data_ptr(), self.touched.data_ptr(), self.rec.data_ptr(), self.n,
+                                 self.views.host, self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc),
+                                 self.ws_view.data_ptr(), self.ws_view.numel(), self.capacity, self.keys.data_ptr(),
+                                 self.gids.data_ptr(), self.ranges.data_ptr(), self.counts.data_ptr(), _stream()),
+              "gs_bin_sort")
+
+    def render_fwd(self) -> None:
+        check(self.L.gs_render_fwd(self.rec.data_ptr(), self.app.data_ptr(), self.n, self.F, self.gids.data_ptr(),
+                                   self.ranges.data_ptr(), self.views.host, self.views.dev_ptr(), self.views.n,
+                                   ctypes.byref(self.cc), self.out.data_ptr(), self.T_final.data_ptr(),
+                                   self.last.data_ptr(), self.queue.data_ptr(), _stream()), "gs_render_fwd")
+
+    def forward(self, g: Gaussians) -> torch.Tensor:
+        self.project(g)
+        self.bin_sort()
+        self.render_fwd()
+        return self.out
+
+    def loss_grad(self, rgb_t, depth_t, labels=None, decoder=None, weights=(0.5, 1.0, 0.0),
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """L1 colour + L1 depth + CE(W^T F) per view; writes self.grad_out and
+        adds the loss terms to self.loss (zero it first for a fresh value)."""
+        out = self.out if out is None else out
+        K = 0 if decoder is None else int(decoder.shape[1])
+        w = (ctypes.c_float * 3)(*[float(x) for x in weights])
+        check(self.L.gs_loss_grad(out.data_ptr(), self.F, rgb_t.data_ptr(), depth_t.data_ptr(),
+                                  labels.data_ptr() if labels is not None else None,
+                                  decoder.data_ptr() if decoder is not None else None, K, w, self.views.host,
+                                  self.views.dev_ptr(), self.views.n, self.grad_out.data_ptr(),
+                                  self.loss.data_ptr(), _stream()), "gs_loss_grad")
+        return self.grad_out
+
+    def render_bwd(self, g: Gaussians, grad_out: torch.Tensor, flags: int, grads: Optional[Gaussians]) -> None:
+        gc = _grads_c(grads) if grads is not None else None
+        check(self.L.gs_render_bwd(ctypes.byref(g.c()), self.rec.data_ptr(), self.app.data_ptr(),
+                                   self.gids.data_ptr(), self.ranges.data_ptr(), self.views.host,
+                                   self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc),
+                                   self.T_final.data_ptr(), self.last.data_ptr(), grad_out.data_ptr(), flags,
+                                   self.grad2d.data_ptr(), self.grad2d.numel() * 4,
+                                   ctypes.byref(gc) if gc is not None else None, self.queue.data_ptr(), _stream()),
+              "gs_render_bwd")
+
+    def pose_grad(self, g: Gaussians) -> torch.Tensor:
+        check(self.L.gs_pose_grad(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
+                                  ctypes.byref(self.cc), self.grad2d.data_ptr(), self.pose_ws.data_ptr(),
+                                  self.pose_ws.numel() * 8, self.twist.data_ptr(), _stream()), "gs_pose_grad")
+        return self.twist
+
+    # ------------------------------------------------------------ views of state
+    @property
+    def grad_geo(self) -> torch.Tensor:
+        return self.grad2d[: self.views.n * self.n * 8].view(self.views.n, self.n, 8)
+
+    @property
+    def grad_app(self) -> torch.Tensor:
+        o = self.views.n * self.n * 8
+        return self.grad2d[o: o + self.n * (4 + self.F)].view(self.n, 4 + self.F)
+
+    def n_instances_dev(self) -> torch.Tensor:
+        return self.counts[0]
+
+
+class RasterizeFunction(torch.autograd.Function):
+    """Autograd wrapper: inputs (xi, mu, log_scale, quat, logit, color, feat),
+    output the planar image [5+F][P].  `xi` is a [V][6] twist placeholder
+    whose value is not applied (render at the poses held by the rasterizer's
+    views; update them between steps with Views.set_poses); its gradient is
+    the twist gradient of the left perturbation Exp(xi) T_CW at xi = 0."""
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, xi, mu, log_scale, quat, logit, color, feat):
+        g = Gaussians(mu.detach().contiguous(), log_scale.detach().contiguous(), quat.detach().contiguous(),
+                      logit.detach().contiguous(), color.detach().contiguous(), feat.detach().contiguous())
+        rast.forward(g)
+        ctx.rast = rast
+        ctx.g = g
+        ctx.want_pose = xi is not None and xi.requires_grad
+        return rast.out.clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        rast, g = ctx.rast, ctx.g
+        need_params = any(ctx.needs_input_grad[2:8])
+        flags = (_lib.GS_GRAD_PARAMS if need_params else 0) | (_lib.GS_GRAD_POSE if ctx.want_pose else 0)
+        if flags == 0:
+            return (None,) * 8
+        grads = g.zeros_like() if need_params else None
+        rast.render_bwd(g, grad_out.contiguous(), flags, grads)
+        gxi = rast.pose_grad(g).clone() if ctx.want_pose else None
+        if grads is None:
+            return (None, gxi) + (None,) * 6
+        return (None, gxi, grads.mu, grads.log_scale, grads.quat, grads.logit, grads.color, grads.feat)
+
+
+def rasterize(rast: Rasterizer, xi, mu, log_scale, quat, logit, color, feat) -> torch.Tensor:
+    return RasterizeFunction.apply(rast, xi, mu, log_scale, quat, logit, color, feat)

@@ -1,0 +1,95 @@
+"""The C-ABI library loads and exports every symbol include/sgs.h declares;
+host-only helpers and argument validation (no GPU needed: nothing launches)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2603_27781_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sgs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declarations_are_exported():
+    L = _lib.load()
+    decl = _declared()
+    assert len(decl) >= 14
+    assert sorted(_lib.EXPORTS) == decl
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(_lib.GsView) == 88
+    assert ctypes.sizeof(_lib.GsConfig) == 40
+    assert ctypes.sizeof(_lib.GsGaussians) == 56
+
+
+def test_default_config_and_layout():
+    L = _lib.load()
+    c = _lib.GsConfig()
+    assert L.gs_default_config(ctypes.byref(c)) == 0
+    assert (c.tile, c.lds_batch, c.persistent) == (16, 256, 0)
+    assert c.alpha_min == pytest.approx(1 / 255) and c.T_min == pytest.approx(1e-4)
+    V = (_lib.GsView * 3)()
+    for i, (w, h) in enumerate([(1200, 680), (640, 480), (33, 17)]):
+        V[i].width, V[i].height, V[i].fx, V[i].fy = w, h, 500.0, 500.0
+    tp, tt = ctypes.c_int64(), ctypes.c_int32()
+    assert L.gs_views_layout(V, 3, 16, ctypes.byref(tp), ctypes.byref(tt)) == 0
+    assert [V[i].pixel_offset for i in range(3)] == [0, 816000, 816000 + 307200]
+    assert [V[i].tile_offset for i in range(3)] == [0, 75 * 43, 75 * 43 + 40 * 30]
+    assert tt.value == 75 * 43 + 40 * 30 + 3 * 2 and tp.value == 816000 + 307200 + 33 * 17
+    assert L.gs_views_layout(V, 3, 12, ctypes.byref(tp), ctypes.byref(tt)) == _lib.GS_EINVAL
+    assert [L.gs_app_stride(f) for f in (0, 8, 16, 32)] == [4, 12, 20, 36]
+
+
+def test_workspace_queries():
+    L = _lib.load()
+    b = ctypes.c_size_t()
+    assert L.gs_render_bwd_workspace(1000, 16, 2, ctypes.byref(b)) == 0
+    assert b.value == (2 * 1000 * 8 + 1000 * 20) * 4
+    assert L.gs_render_bwd_workspace(1000, 12, 2, ctypes.byref(b)) == _lib.GS_EUNSUPPORTED
+    assert L.gs_bin_sort_workspace(1000, 2, 5000, ctypes.byref(b)) == 0 and b.value > 5 * 2000 * 4
+    assert L.gs_bin_sort_workspace(0, 2, 5000, ctypes.byref(b)) == _lib.GS_EINVAL
+    assert L.gs_pose_grad_workspace(1000, 2, ctypes.byref(b)) == 0 and b.value == 4 * 2 * 6 * 8
+
+
+def test_validation_rejects_before_any_launch():
+    """Invalid arguments are rejected on the host; the dummy pointers below
+    are never dereferenced (no GPU is touched)."""
+    L = _lib.load()
+    cfg = _lib.GsConfig()
+    L.gs_default_config(ctypes.byref(cfg))
+    V = (_lib.GsView * 1)()
+    V[0].width, V[0].height, V[0].fx, V[0].fy = 64, 64, 64.0, 64.0
+    L.gs_views_layout(V, 1, 16, None, None)
+    dummy = 1 << 20
+    g = _lib.GsGaussians(dummy, dummy, dummy, dummy, dummy, dummy, 100, 16)
+    bad = _lib.GsConfig.from_buffer_copy(cfg)
+    bad.tile = 12
+    assert L.gs_project(ctypes.byref(g), V, dummy, 1, ctypes.byref(bad), dummy, dummy, dummy, dummy,
+                        None) == _lib.GS_EUNSUPPORTED
+    g12 = _lib.GsGaussians(dummy, dummy, dummy, dummy, dummy, dummy, 100, 12)
+    assert L.gs_project(ctypes.byref(g12), V, dummy, 1, ctypes.byref(cfg), dummy, dummy, dummy, dummy,
+                        None) == _lib.GS_EUNSUPPORTED
+    assert L.gs_project(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), None, dummy, dummy, dummy,
+                        None) == _lib.GS_EINVAL
+    assert L.gs_project(ctypes.byref(g), V, None, 1, ctypes.byref(cfg), dummy, dummy, dummy, dummy,
+                        None) == _lib.GS_EINVAL
+    V[0].pixel_offset = 7  # not the back-to-back layout
+    assert L.gs_project(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, dummy, dummy, dummy,
+                        None) == _lib.GS_EINVAL
+    L.gs_views_layout(V, 1, 16, None, None)
+    assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, V, dummy, 1, ctypes.byref(cfg), dummy,
+                           dummy, dummy, 0, dummy, 1 << 30, None, dummy, None) == _lib.GS_EINVAL
+    assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, V, dummy, 1, ctypes.byref(cfg), dummy,
+                           dummy, dummy, 1, dummy, 16, None, dummy, None) == _lib.GS_ECAPACITY
+    assert L.gs_error_string(_lib.GS_ECAPACITY) == b"buffer too small"
+    assert L.gs_version() >= 100

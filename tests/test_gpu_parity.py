@@ -1,0 +1,307 @@
+"""GPU parity: every C-ABI entry point against the FP64 CPU oracle on the
+same seeded inputs.  Bit-exact for the integer work (culling, tile
+rectangles, instance lists, sorted order, ranges); stated tolerances for
+floating point."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_27781_amd import workloads as wl
+from gpu_common import (MARGIN, TOL_GRAD, compare_render, gpu_setup, oracle_cfg, rel_err)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _multi_view_tiny(seed=61, n=300, F=16):
+    w = wl.tiny_scene(seed, n, F=F, W=53, H=37, f=40.0)
+    v2 = wl.make_view(29, 21, 25.0, wl.se3_exp(np.array([0.02, -0.01, 0.03, 0.01, 0.03, -0.02])))
+    v3 = wl.make_view(64, 48, 50.0, wl.se3_exp(np.array([-0.05, 0.02, 0.0, -0.02, 0.01, 0.04])))
+    return w.scene, w.views + [v2, v3]
+
+
+CASES = {
+    "tiny3views-F16": lambda: _multi_view_tiny(),
+    "cfg1-64x64-2k": lambda: (wl.config1().scene, wl.config1().views),
+    "cfg2-160x120-20k-F16": lambda: (lambda w: (w.scene, w.views))(wl.config2(n=20_000, width=160, height=120)),
+    "tiny-F8": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(62, 200, F=8, W=40, H=40, f=35.0)),
+    "tiny-F32": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(63, 200, F=32, W=40, H=24, f=35.0)),
+}
+
+
+def _project(name, tile):
+    scene, views = CASES[name]()
+    r, g, cfg = gpu_setup(scene, views, {"tile": tile})
+    r.project(g)
+    torch.cuda.synchronize()
+    dec = oracle.decide(scene, views, oracle_cfg(cfg))
+    return scene, views, r, g, cfg, dec
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("tile", [8, 16])
+def test_project_bit_exact(name, tile):
+    scene, views, r, g, cfg, dec = _project(name, tile)
+    V, n = len(views), scene.n
+    rec = r.rec.view(V, n, 8).cpu().numpy()
+    touched = r.touched.view(V, n).cpu().numpy()
+    rect = r.rect.view(V, n, 2).cpu().numpy().view(np.uint32)
+    assert np.array_equal(touched, dec["touched"])
+    vis = touched > 0
+    assert vis.sum() > 0
+    r32 = dec["rec32"]
+    # mean, conic, depth: the binary32 decision path, bit for bit
+    for k_gpu, k_orc in ((0, 0), (1, 1), (2, 2), (3, 3), (4, 4), (6, 5)):
+        assert np.array_equal(rec[..., k_gpu][vis].view(np.uint32), r32[..., k_orc][vis].view(np.uint32)), k_gpu
+    # rectangles
+    ro = dec["rect"]
+    x0 = (rect[..., 0] & 0xFFFF).astype(np.int32)
+    y0 = (rect[..., 0] >> 16).astype(np.int32)
+    x1 = (rect[..., 1] & 0xFFFF).astype(np.int32)
+    y1 = (rect[..., 1] >> 16).astype(np.int32)
+    for a, k in ((x0, 0), (y0, 1), (x1, 2), (y1, 3)):
+        assert np.array_equal(a[vis], ro[..., k][vis])
+    # opacity (value path) and the conservative binary16 radii
+    proj = oracle.project64(scene, views, oracle_cfg(cfg))
+    assert np.max(np.abs(rec[..., 5][vis] - proj[..., 5][vis])) < 1e-6
+    bits = rec[..., 7].view(np.uint32)
+    rx = (bits & 0xFFFF).astype(np.uint16).view(np.float16).astype(np.float32)
+    ry = (bits >> 16).astype(np.uint16).view(np.float16).astype(np.float32)
+    assert np.all(rx[vis] >= r32[..., 6][vis]) and np.all(ry[vis] >= r32[..., 7][vis])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_bin_sort_bit_exact(name, tile):
+    scene, views, r, g, cfg, dec = _project(name, tile)
+    r.bin_sort()
+    inst, nvis, over = r.instance_counts()
+    ref = oracle.bin_instances(scene, views, oracle_cfg(cfg), dec=dec)
+    assert not over
+    assert inst == ref["count"]
+    assert nvis == int((dec["touched"] > 0).sum())
+    assert np.array_equal(r.keys[:inst].cpu().numpy().view(np.uint32), ref["keys"])
+    assert np.array_equal(r.gids[:inst].cpu().numpy(), ref["gids"])
+    assert np.array_equal(r.ranges.view(-1, 2).cpu().numpy(), ref["ranges"])
+
+
+def test_bin_sort_capacity_overflow_is_reported():
+    scene, views = CASES["cfg1-64x64-2k"]()
+    r, g, cfg = gpu_setup(scene, views, {"tile": 16}, capacity=1000)
+    r.project(g)
+    r.bin_sort()
+    inst, _, over = r.instance_counts()
+    assert over and inst > 1000
+    assert r.ensure_capacity(g) == inst
+    r.bin_sort()
+    assert r.instance_counts()[2] is False
+
+
+def _render(name, tile, lds_batch=256, persistent=0):
+    scene, views = CASES[name]()
+    r, g, cfg = gpu_setup(scene, views, {"tile": tile, "lds_batch": lds_batch, "persistent": persistent})
+    r.ensure_capacity(g)
+    r.forward(g)
+    torch.cuda.synchronize()
+    return scene, views, r, g, cfg
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("tile,lds_batch,persistent", [(16, 256, 0), (8, 64, 0), (32, 128, 1)])
+def test_render_fwd_parity(name, tile, lds_batch, persistent):
+    scene, views, r, g, cfg = _render(name, tile, lds_batch, persistent)
+    ref = oracle.render(scene, views, oracle_cfg(cfg))
+    flagged, rep = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref)
+    print(name, tile, "flagged", flagged, rep)
+    assert flagged <= max(2, 1e-3 * ref["out"].shape[1])
+
+
+@pytest.mark.parametrize("name", ["cfg1-64x64-2k", "tiny3views-F16"])
+def test_render_is_tile_size_invariant(name):
+    outs = []
+    for tile, lb in ((8, 64), (16, 256), (32, 128)):
+        _, _, r, _, _ = _render(name, tile, lb)
+        outs.append(r.out.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
+def test_persistent_forward_is_bit_identical():
+    _, _, r0, _, _ = _render("tiny3views-F16", 16, 256, 0)
+    _, _, r1, _, _ = _render("tiny3views-F16", 16, 256, 1)
+    assert np.array_equal(r0.out.cpu().numpy(), r1.out.cpu().numpy())
+    assert np.array_equal(r0.last.cpu().numpy(), r1.last.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", ["tiny3views-F16", "cfg2-160x120-20k-F16", "tiny-F32"])
+def test_loss_grad_parity(name):
+    scene, views, r, g, cfg = _render(name, 16)
+    F = scene.n_feat
+    rng = np.random.default_rng(7)
+    P = r.views.total_pixels
+    out32 = r.out.cpu().numpy()
+    rgb_t = rng.uniform(0, 1, size=(3, P)).astype(np.float32)
+    dep_t = rng.uniform(1, 4, size=P).astype(np.float32)
+    K = 20
+    lab = rng.integers(0, K, size=P).astype(np.int32)
+    W = wl.decoder_matrix(rng, F, K)
+    wts = (0.5, 1.0, 0.01)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    r.loss.zero_()
+    r.loss_grad(dev(rgb_t), dev(dep_t), dev(lab), dev(W), wts)
+    go = r.grad_out.cpu().numpy()
+    gref, terms = oracle.loss(out32.astype(np.float64), views, rgb_t, dep_t, lab, W.astype(np.float64), wts)
+    assert np.array_equal(np.sign(go[0:4]), np.sign(gref[0:4]))
+    assert np.max(np.abs(go[0:4] - gref[0:4])) <= 1e-6 * np.max(np.abs(gref[0:4]))
+    assert rel_err(go[5:], gref[5:]) <= 1e-5
+    assert np.all(go[4] == 0)
+    loss = r.loss.cpu().numpy()
+    assert loss[3] == pytest.approx(terms[3], rel=1e-5)
+
+
+def _backward_case(name, tile=16, flags=3, persistent=0, lds_batch=256, seed=11):
+    scene, views, r, g, cfg = _render(name, tile, lds_batch, persistent)
+    rng = np.random.default_rng(seed)
+    go = rng.normal(size=r.out.shape).astype(np.float32) * 1e-2
+    grads = g.zeros_like()
+    r.render_bwd(g, torch.from_numpy(go).cuda(), flags, grads if flags & 1 else None)
+    tw = r.pose_grad(g).cpu().numpy() if flags & 2 else None
+    torch.cuda.synchronize()
+    ref = oracle.backward(scene, views, oracle_cfg(cfg), go.astype(np.float64), flags=flags)
+    return scene, views, r, grads, tw, ref
+
+
+def _check_grads(scene, views, r, grads, tw, ref, flags):
+    V, n, F = len(views), scene.n, scene.n_feat
+    geo = r.grad_geo.cpu().numpy()
+    errs = {}
+    for k, nm in enumerate(["mx", "my", "A", "B", "C", "d"]):
+        errs[nm] = rel_err(geo[..., k], ref["grad2d"][..., k])
+    if flags & 1:
+        app = r.grad_app.cpu().numpy()
+        errs["o"] = rel_err(app[:, 0], ref["gapp"][:, 0])
+        errs["c"] = rel_err(app[:, 1:4], ref["gapp"][:, 1:4])
+        if F:
+            errs["f"] = rel_err(app[:, 4:], ref["gapp"][:, 4:])
+        for nm in ["mu", "log_scale", "quat", "logit", "color", "feat"]:
+            if nm == "feat" and F == 0:
+                continue
+            errs["d" + nm] = rel_err(getattr(grads, "logit" if nm == "logit" else nm).cpu().numpy(), ref[nm])
+    if flags & 2:
+        for v in range(V):
+            errs[f"twist{v}"] = rel_err(tw[v], ref["twist"][v])
+    print(errs)
+    bad = {k: e for k, e in errs.items() if e > TOL_GRAD}
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_render_bwd_and_pose_parity(name):
+    out = _backward_case(name)
+    _check_grads(*out, flags=3)
+
+
+@pytest.mark.parametrize("tile,lds_batch,persistent", [(8, 64, 1), (32, 128, 0)])
+def test_backward_launch_shapes(tile, lds_batch, persistent):
+    out = _backward_case("tiny3views-F16", tile=tile, persistent=persistent, lds_batch=lds_batch)
+    _check_grads(*out, flags=3)
+
+
+def test_pose_only_backward():
+    """Tracking mode (GS_GRAD_POSE only): the field is frozen, only the 2D
+    geometric gradients and the twist are produced."""
+    out = _backward_case("cfg1-64x64-2k", flags=2)
+    _check_grads(*out, flags=2)
+
+
+def test_batched_equals_sum_of_single_views():
+    scene, views = CASES["tiny3views-F16"]()
+    rng = np.random.default_rng(3)
+    P = sum(v.width * v.height for v in views)
+    go = (rng.normal(size=(5 + scene.n_feat, P)) * 1e-2).astype(np.float32)
+    r, g, cfg = gpu_setup(scene, views, {"tile": 16})
+    r.ensure_capacity(g)
+    r.forward(g)
+    gb = g.zeros_like()
+    r.render_bwd(g, torch.from_numpy(go).cuda(), 3, gb)
+    twb = r.pose_grad(g).cpu().numpy()
+    outb = r.out.cpu().numpy()
+    acc = g.zeros_like()
+    off = 0
+    for vi, v in enumerate(views):
+        rv, gv, _ = gpu_setup(scene, [v], {"tile": 16})
+        rv.ensure_capacity(gv)
+        rv.forward(gv)
+        Pv = v.width * v.height
+        assert np.array_equal(rv.out.cpu().numpy(), outb[:, off:off + Pv])
+        rv.render_bwd(gv, torch.from_numpy(np.ascontiguousarray(go[:, off:off + Pv])).cuda(), 3, acc)
+        twv = rv.pose_grad(gv).cpu().numpy()
+        assert rel_err(twv[0], twb[vi]) <= 1e-4
+        off += Pv
+    for a, b in zip(acc.tensors(), gb.tensors()):
+        assert rel_err(a.cpu().numpy(), b.cpu().numpy().astype(np.float64)) <= 1e-4
+
+
+def test_autograd_function_matches_direct_calls():
+    from paper_2603_27781_amd import raster
+    scene, views = CASES["tiny3views-F16"]()
+    r, g, cfg = gpu_setup(scene, views, {"tile": 16})
+    r.ensure_capacity(g)
+    params = [t.clone().requires_grad_(True) for t in g.tensors()]
+    xi = torch.zeros(len(views), 6, device="cuda", requires_grad=True)
+    out = raster.rasterize(r, xi, *params)
+    wgt = torch.randn_like(out)
+    (out * wgt).sum().backward()
+    direct = g.zeros_like()
+    r.forward(g)
+    r.render_bwd(g, wgt.contiguous(), 3, direct)
+    tw = r.pose_grad(g)
+    for p, d in zip(params, direct.tensors()):
+        assert torch.allclose(p.grad, d, rtol=1e-4, atol=1e-6 * float(d.abs().max()))
+    assert torch.allclose(xi.grad, tw, rtol=1e-4, atol=1e-6 * float(tw.abs().max()))
+
+
+def test_edge_cases_empty_and_single():
+    # every Gaussian behind the camera: nothing visible, background 0, T = 1
+    w = wl.tiny_scene(71, 50, F=8)
+    sc = w.scene.copy()
+    sc.mu[2] = -5.0
+    r, g, cfg = gpu_setup(sc, w.views, {"tile": 16})
+    r.forward(g)
+    torch.cuda.synchronize()
+    assert r.instance_counts()[0] == 0
+    assert float(r.out.abs().max()) == 0.0 and float(r.T_final.min()) == 1.0
+    grads = g.zeros_like()
+    r.render_bwd(g, torch.ones_like(r.out), 3, grads)
+    assert all(float(t.abs().max()) == 0.0 for t in grads.tensors())
+    # a single Gaussian
+    s1 = w.scene.subset(np.array([3]))
+    out = _single(s1, w.views)
+    assert out
+
+
+def _single(scene, views):
+    r, g, cfg = gpu_setup(scene, views, {"tile": 8, "lds_batch": 64})
+    r.ensure_capacity(g)
+    r.forward(g)
+    ref = oracle.render(scene, views, oracle_cfg(cfg))
+    compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref)
+    return True
+
+
+def test_abi_rejects_bad_arguments_without_launching():
+    from paper_2603_27781_amd import _lib, raster
+    scene, views = CASES["tiny-F8"]()
+    r, g, cfg = gpu_setup(scene, views, {"tile": 16})
+    L = _lib.load()
+    bad = raster.Config(tile=12).c()
+    import ctypes
+    st = L.gs_project(ctypes.byref(g.c()), r.views.host, r.views.dev_ptr(), 1, ctypes.byref(bad), r.rec.data_ptr(),
+                      r.rect.data_ptr(), r.touched.data_ptr(), r.app.data_ptr(), None)
+    assert st == _lib.GS_EUNSUPPORTED
+    st = L.gs_project(ctypes.byref(g.c()), r.views.host, r.views.dev_ptr(), 1, ctypes.byref(r.cc), None,
+                      r.rect.data_ptr(), r.touched.data_ptr(), r.app.data_ptr(), None)
+    assert st == _lib.GS_EINVAL
+    st = L.gs_bin_sort(r.rect.data_ptr(), r.touched.data_ptr(), r.rec.data_ptr(), r.n, r.views.host,
+                       r.views.dev_ptr(), 1, ctypes.byref(r.cc), r.ws_view.data_ptr(), 16, r.capacity,
+                       r.keys.data_ptr(), r.gids.data_ptr(), r.ranges.data_ptr(), r.counts.data_ptr(), None)
+    assert st == _lib.GS_ECAPACITY
