@@ -198,40 +198,54 @@ int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat,
  *       + w2 * mean CE(softmax(W^T F), label)
  * W is a fixed decoder [n_feat][n_classes] (row-major; the configured linear
  * stand-in for the paper's F_cnn, Eq. 8); n_classes == 0 drops the CE term.
- * Writes grad_out[5+F][P_total] = dL/d out (opacity channel 0) and adds the
- * three summed terms and their total to loss[4] (double, device; the caller
- * zeroes it; the sum uses atomics, so its last bits may vary run to run --
- * the gradient does not).  labels in [0, n_classes) (int32).
+ * Writes grad_out[5+F][P_total] = dL/d out (opacity channel 0) and WRITES
+ * loss[4] (double, device) = (colour term, depth term, semantic term,
+ * total), each summed over the views; the per-block partial sums go to ws
+ * (gs_loss_grad_workspace bytes) and are added in a fixed order, so the
+ * value is deterministic.  labels in [0, n_classes) (int32).
  * rgb_target [3][P_total], depth_target [P_total]; weights is a HOST array
  * of 3 floats (w0, w1, w2).  Views as for the other entry points.
  * --------------------------------------------------------------------------- */
+int gs_loss_grad_workspace(int64_t total_pixels, size_t* bytes);
 int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, const float* depth_target,
                  const int32_t* labels, const float* decoder, int32_t n_classes, const float* weights,
                  const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
-                 gs_stream stream);
+                 void* ws, size_t ws_bytes, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
- * gs_render_bwd -- backward of gs_render_fwd (and of gs_project when
- * GS_GRAD_PARAMS).  Re-traverses each pixel's list from `last` down,
- * rebuilding T_i = T_{i+1} / (1 - alpha_i), and forms
+ * gs_render_bwd -- backward of gs_render_fwd.  Re-traverses each pixel's list
+ * from `last` down, rebuilding T_i = T_{i+1} / (1 - alpha_i), and forms
  *   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),
  *   S_i = sum_{j>i} (g . x_j) alpha_j T_j,
- * reduces per-Gaussian gradients across each wavefront, then accumulates
- * with atomics into grad2d:
+ * with g the pixel's upstream gradient grad_out[5+F][P_total] and x_i the
+ * Gaussian's channel values (colour, depth, 1, feature); reduces the
+ * per-Gaussian gradients across each wavefront, then ACCUMULATES (+=, with
+ * atomics) into grad2d, which the caller zeroes before the first call:
  *   grad2d geo [V][n][8]  = dL/d(mx, my, A, B, C, d), 2 unused   (per view)
  *   grad2d app [n][4+F]   = dL/d(o, c0, c1, c2, f...)            (all views)
- * (geo first, app right after it; gs_render_bwd_workspace gives the bytes;
- * the call zeroes it first).  With GS_GRAD_PARAMS the projection backward
- * then ADDS the gradients of every parameter plane to *grads.  With only
- * GS_GRAD_POSE (tracking, Sec. 3.4: the field is frozen) colour, feature and
- * opacity gradients are skipped and grads may be NULL.
+ * (geo first, app right after it; gs_render_bwd_workspace gives the bytes).
+ * flags: GS_GRAD_PARAMS fills geo and app; GS_GRAD_POSE alone (tracking,
+ * Sec. 3.4: the field is frozen) fills geo only and skips colour, feature
+ * and opacity.
  * --------------------------------------------------------------------------- */
 int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, size_t* bytes);
 int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* gids,
                   const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev,
                   int32_t n_views, const gs_config* cfg, const float* T_final, const int32_t* last,
                   const float* grad_out, uint32_t flags, float* grad2d, size_t grad2d_bytes,
-                  gs_gaussian_grads* grads, int32_t* queue, gs_stream stream);
+                  int32_t* queue, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_project_bwd -- backward of gs_project (Eq. 2-3) for the mapping step:
+ * from grad2d of gs_render_bwd (GS_GRAD_PARAMS) to every parameter plane,
+ * one thread per Gaussian summing its views in registers (no atomics):
+ *   conic = Sigma2D^-1, Sigma2D = (J R_CW M)(J R_CW M)^T + bI, M = R(q) diag(e^s),
+ *   mean2d = pi(R_CW mu + t), depth = (R_CW mu + t)_z, o = sigmoid(logit).
+ * ADDS the gradients to *grads.
+ * --------------------------------------------------------------------------- */
+int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                   const gs_config* cfg, const float* grad2d, size_t grad2d_bytes, gs_gaussian_grads* grads,
+                   gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_pose_grad -- Supp. B.1 written as a twist of the left perturbation

@@ -152,31 +152,53 @@ def project64(scene, views, cfg: Cfg, s64=None, poses64=None) -> np.ndarray:
     return proj
 
 
-def render(scene, views, cfg: Cfg, bins=None, pix_mask=None, s64=None, poses64=None):
+def project32(scene, views, cfg: Cfg, dec=None) -> np.ndarray:
+    """[V][n][7] projection whose mean, conic and depth are the binary32
+    decision-path values (upcast exactly) and whose opacity is FP64: the
+    geometry the discrete alpha_min / T_min decisions of a binary32
+    implementation are taken on."""
+    dec = decide(scene, views, cfg) if dec is None else dec
+    r = dec["rec32"].astype(np.float64)
+    o = 1.0 / (1.0 + np.exp(-np.asarray(scene.logit, np.float32).astype(np.float64)))
+    proj = np.zeros(r.shape[:2] + (7,))
+    proj[..., 0:5] = r[..., 0:5]
+    proj[..., 5] = o[None, :]
+    proj[..., 6] = r[..., 5]
+    return np.ascontiguousarray(proj)
+
+
+def render(scene, views, cfg: Cfg, bins=None, pix_mask=None, s64=None, poses64=None, geometry="fp64"):
     """FP64 forward render.  Discrete decisions come from the binary32 scene
     and views; values from `s64` / `poses64` when given (finite differences).
+    geometry="fp32" takes the projected mean, conic and depth from the
+    binary32 decision path instead of the FP64 projection (used to compare a
+    binary32 implementation away from threshold ties).
     Returns out[5+F][P] (R, G, B, depth, opacity, features), Tfinal, last,
-    ncontrib, margin (smallest relative distance to the alpha_min / T_min
-    thresholds met at that pixel)."""
+    ncontrib, margin_a / margin_t (smallest relative distance to the
+    alpha_min / T_min thresholds met at that pixel) and margin (their min)."""
     L = lib()
     bins = bin_instances(scene, views, cfg) if bins is None else bins
     s64 = scene64(scene) if s64 is None else s64
-    proj = project64(scene, views, cfg, s64, poses64)
+    if geometry == "fp32":
+        proj = project32(scene, views, cfg, bins["dec"])
+    else:
+        proj = project64(scene, views, cfg, s64, poses64)
     F, n, V = scene.n_feat, scene.n, len(views)
     P = int(pixel_counts(views).sum())
     out = np.zeros((5 + F, P), np.float64)
     Tf = np.zeros(P, np.float64)
     last = np.zeros(P, np.int32)
     ncon = np.zeros(P, np.int32)
-    margin = np.full(P, np.inf)
+    ma = np.full(P, np.inf)
+    mt = np.full(P, np.inf)
     gids = np.ascontiguousarray(bins["gids"] if bins["count"] else np.zeros(1, np.int32))
     pm = None if pix_mask is None else np.ascontiguousarray(pix_mask, np.uint8)
     L.orc_render(ctypes.c_int(n), ctypes.c_int(F), _p(s64["color"]), _p(s64["feat"]), ctypes.c_int(V),
                  _p(views_array(views, np.float64, poses64)), _p(cfg.array()), ctypes.c_int(cfg.tile),
                  _p(np.ascontiguousarray(bins["ranges"])), _p(gids), _p(proj), _p(pm), _p(out), _p(Tf),
-                 _p(last), _p(ncon), _p(margin))
-    return {"out": out, "Tfinal": Tf, "last": last, "ncontrib": ncon, "margin": margin, "bins": bins,
-            "proj": proj}
+                 _p(last), _p(ncon), _p(ma), _p(mt))
+    return {"out": out, "Tfinal": Tf, "last": last, "ncontrib": ncon, "margin_a": ma, "margin_t": mt,
+            "margin": np.minimum(ma, mt), "bins": bins, "proj": proj}
 
 
 def loss(out: np.ndarray, views, rgb_t, depth_t, labels=None, decoder=None, weights=(0.5, 1.0, 0.0)):

@@ -422,7 +422,7 @@ static double feat_of(const scene_ctx* s, int ch, int gid) {
 }
 
 static void pixel_forward(const scene_ctx* s, int v, int u, int w_, double* out, double* Tfinal,
-                          int32_t* last, int32_t* ncontrib, double* margin) {
+                          int32_t* last, int32_t* ncontrib, double* margin_a, double* margin_t) {
     const double* vw = s->views + (size_t)v * VSTRIDE;
     const int W = (int)vw[0];
     const int tx = (W + s->tile - 1) / s->tile;
@@ -431,7 +431,7 @@ static void pixel_forward(const scene_ctx* s, int v, int u, int w_, double* out,
     const double amin = s->cfg[C_AMIN], amax = s->cfg[C_AMAX], tmin = s->cfg[C_TMIN];
     const int NC = 5 + s->F;
     const double px = u + 0.5, py = w_ + 0.5;
-    double T = 1.0, mg = INFINITY;
+    double T = 1.0, mga = INFINITY, mgt = INFINITY;
     int lst = 0, cnt = 0;
     for (int ch = 0; ch < NC; ++ch) out[ch] = 0.0;
     for (int32_t k = beg; k < end; ++k) {
@@ -441,11 +441,11 @@ static void pixel_forward(const scene_ctx* s, int v, int u, int w_, double* out,
         int qc;
         double a = pair_alpha(pr, px, py, amax, &raw, &G, &dx, &dy, &qc);
         double m1 = fabs(a - amin) / amin;
-        if (m1 < mg) mg = m1;
+        if (m1 < mga) mga = m1;
         if (a < amin) continue;
         double Tn = T * (1.0 - a);
         double m2 = fabs(Tn - tmin) / tmin;
-        if (m2 < mg) mg = m2;
+        if (m2 < mgt) mgt = m2;
         if (Tn < tmin) break;
         double wgt = a * T;
         for (int ch = 0; ch < NC; ++ch) {
@@ -459,7 +459,8 @@ static void pixel_forward(const scene_ctx* s, int v, int u, int w_, double* out,
     *Tfinal = T;
     *last = lst;
     *ncontrib = cnt;
-    *margin = mg;
+    *margin_a = mga;
+    *margin_t = mgt;
 }
 
 static void setup_ctx(scene_ctx* s, int n, int F, const double* color, const double* feat, int V,
@@ -487,11 +488,13 @@ static void free_ctx(scene_ctx* s) {
 
 /* Forward render of every pixel (or of the pixels with pix_mask[p] != 0).
  * proj[V][n][7] from orc_project64; out[5+F][P]: R, G, B, depth, opacity,
- * features; Tfinal[P], last[P], ncontrib[P], margin[P]. */
+ * features; Tfinal[P], last[P], ncontrib[P], and the smallest relative
+ * distance of any alpha to alpha_min (margin_a[P]) and of any T (1 - alpha)
+ * to T_min (margin_t[P]) met at the pixel. */
 void orc_render(int n, int F, const double* color, const double* feat, int V, const double* views,
                 const float* cfg, int tile, const int32_t* ranges, const int32_t* gids,
                 const double* proj, const uint8_t* pix_mask, double* out, double* Tfinal,
-                int32_t* last, int32_t* ncontrib, double* margin) {
+                int32_t* last, int32_t* ncontrib, double* margin_a, double* margin_t) {
     scene_ctx s;
     setup_ctx(&s, n, F, color, feat, V, views, cfg, tile, ranges, gids, (const proj_t*)proj);
     const int64_t P = s.pix_base[V];
@@ -504,7 +507,7 @@ void orc_render(int n, int F, const double* color, const double* feat, int V, co
             for (int x = 0; x < W; ++x) {
                 const int64_t p = s.pix_base[v] + (int64_t)y * W + x;
                 if (pix_mask && !pix_mask[p]) continue;
-                pixel_forward(&s, v, x, y, acc, &Tfinal[p], &last[p], &ncontrib[p], &margin[p]);
+                pixel_forward(&s, v, x, y, acc, &Tfinal[p], &last[p], &ncontrib[p], &margin_a[p], &margin_t[p]);
                 for (int ch = 0; ch < NC; ++ch) out[(size_t)ch * P + p] = acc[ch];
             }
         }

@@ -7,7 +7,9 @@
 // One thread per pixel: the F feature channels stay in registers, the
 // decoder sits in LDS (broadcast reads), and the softmax is evaluated with
 // a running maximum (one pass for the log-sum-exp, one for the gradient) so
-// no per-class array is needed.
+// no per-class array is needed.  The loss value is reduced per block into a
+// partial-sum array and then summed in a fixed order by one block (no
+// same-address atomics, deterministic).
 #include "sgs_common.h"
 
 namespace sgs {
@@ -18,7 +20,7 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ out, int
                                               const int32_t* __restrict__ labels, const float* __restrict__ decoder,
                                               int K, float w0, float w1, float w2,
                                               const gs_view* __restrict__ views, int n_views,
-                                              float* __restrict__ grad_out, double* __restrict__ loss) {
+                                              float* __restrict__ grad_out, double* __restrict__ partials) {
     __shared__ float sW[(F > 0 ? F : 1) * GS_MAX_CLASSES];
     __shared__ double s_red[3][256 / kWave];
     const int tid = threadIdx.x;
@@ -85,7 +87,7 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ out, int
         ld *= (double)w1 / (double)Pv;
         ls *= (double)w2 / (double)Pv;
     }
-    // block reduction of the three terms, one atomic per term per block
+    // block reduction of the three terms into this block's partial sums
     const int lane = tid & (kWave - 1), wave = tid / kWave;
     for (int d = kWave / 2; d > 0; d >>= 1) {
         lc += __shfl_xor(lc, d, kWave);
@@ -98,46 +100,66 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ out, int
         s_red[2][wave] = ls;
     }
     __syncthreads();
-    if (tid == 0) {
-        double a = 0, b = 0, e = 0;
-        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-            a += s_red[0][w];
-            b += s_red[1][w];
-            e += s_red[2][w];
-        }
-        atomicAdd(&loss[0], a);
-        atomicAdd(&loss[1], b);
-        atomicAdd(&loss[2], e);
-        atomicAdd(&loss[3], a + b + e);
+    if (tid < 3) {
+        double a = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) a += s_red[tid][w];
+        partials[3 * (size_t)blockIdx.x + tid] = a;
     }
 }
+
+// Fixed-order sum of the per-block partials: loss = (colour, depth, semantic, total).
+__global__ void __launch_bounds__(256) k_loss_final(const double* __restrict__ partials, int nblk,
+                                                    double* __restrict__ loss) {
+    __shared__ double s[3][256];
+    double acc[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int k = 0; k < 3; ++k) acc[k] += partials[3 * (size_t)b + k];
+    for (int k = 0; k < 3; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int d = blockDim.x / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d)
+            for (int k = 0; k < 3; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss[0] = s[0][0];
+        loss[1] = s[1][0];
+        loss[2] = s[2][0];
+        loss[3] = s[0][0] + s[1][0] + s[2][0];
+    }
+}
+
+size_t loss_workspace_bytes(int64_t P) { return (size_t)((P + 255) / 256) * 3 * sizeof(double) + 16; }
 
 template <int F>
 hipError_t launch_loss_t(const float* out, const float* rgb_t, const float* depth_t, const int32_t* labels,
                          const float* decoder, int K, const float* w, const gs_view* views, int n_views, int64_t P,
-                         float* grad_out, double* loss, hipStream_t s) {
+                         float* grad_out, double* loss, void* ws, hipStream_t s) {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_loss<F>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, out, P, rgb_t, depth_t, labels,
-                       decoder, K, w[0], w[1], w[2], views, n_views, grad_out, loss);
+    const int nblk = (int)((P + 255) / 256);
+    double* partials = static_cast<double*>(ws);
+    hipLaunchKernelGGL(k_loss<F>, dim3((unsigned)nblk), dim3(256), 0, s, out, P, rgb_t, depth_t, labels, decoder, K,
+                       w[0], w[1], w[2], views, n_views, grad_out, partials);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, partials, nblk, loss);
     return hipGetLastError();
 }
 
 hipError_t launch_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t, const int32_t* labels,
                        const float* decoder, int n_classes, const float* weights, const gs_view* views_dev,
-                       int n_views, int64_t total_pixels, float* grad_out, double* loss, hipStream_t s) {
+                       int n_views, int64_t total_pixels, float* grad_out, double* loss, void* ws, hipStream_t s) {
     switch (n_feat) {
         case 0:
             return launch_loss_t<0>(out, rgb_t, depth_t, labels, decoder, n_classes, weights, views_dev, n_views,
-                                    total_pixels, grad_out, loss, s);
+                                    total_pixels, grad_out, loss, ws, s);
         case 8:
             return launch_loss_t<8>(out, rgb_t, depth_t, labels, decoder, n_classes, weights, views_dev, n_views,
-                                    total_pixels, grad_out, loss, s);
+                                    total_pixels, grad_out, loss, ws, s);
         case 32:
             return launch_loss_t<32>(out, rgb_t, depth_t, labels, decoder, n_classes, weights, views_dev, n_views,
-                                     total_pixels, grad_out, loss, s);
+                                     total_pixels, grad_out, loss, ws, s);
         default:
             return launch_loss_t<16>(out, rgb_t, depth_t, labels, decoder, n_classes, weights, views_dev, n_views,
-                                     total_pixels, grad_out, loss, s);
+                                     total_pixels, grad_out, loss, ws, s);
     }
 }
 

@@ -13,37 +13,51 @@
 // depth and feature.  The 10+F per-Gaussian values of the 64 pixels of a
 // wavefront are summed with a transposing butterfly (each exchange halves
 // the values a lane keeps, so after log2 steps every lane holds a different
-// total) and one atomic instruction per wavefront and Gaussian writes them.
+// total); one LDS atomic instruction per wavefront and Gaussian adds them to
+// the batch's per-Gaussian accumulator, and after the batch the workgroup
+// flushes each touched Gaussian once with global atomics.  (Flushing every
+// wavefront straight to global memory made the four wavefronts of a tile
+// hit the same cache lines at the same time and serialised in L2.)
 // Wavefronts with no contributing pixel skip the reduction.
 #include "raster_common.h"
 
 namespace sgs {
 
-// One butterfly step at xor distance D over the first CNT values.
+// Transposing butterfly over NV (a power of two) values per lane.  Step D
+// (xor distance D = 1, 2, 4, ...) halves the CNT values a lane keeps: a lane
+// with bit D set keeps the upper half and sends the lower half to its
+// partner, which does the opposite, and both add what they receive.  After
+// log2(NV) steps each lane holds one partial total, the remaining steps
+// finish the sum across the wavefront.  Every index is a compile-time
+// constant (template recursion), so the values stay in registers.
+template <int NV, int CNT, int D>
+struct BflyStep {
+    __device__ __forceinline__ static void run(float (&v)[NV], int lane) {
+        if constexpr (D < kWave) {
+            if constexpr (CNT > 1) {
+                constexpr int HALF = CNT / 2;
+                const bool up = (lane & D) != 0;
+#pragma unroll
+                for (int k = 0; k < HALF; ++k) {
+                    const float send = up ? v[k] : v[k + HALF];
+                    const float keep = up ? v[k + HALF] : v[k];
+                    v[k] = keep + __shfl_xor(send, D, kWave);
+                }
+                BflyStep<NV, HALF, 2 * D>::run(v, lane);
+            } else {
+                v[0] += __shfl_xor(v[0], D, kWave);
+                BflyStep<NV, 1, 2 * D>::run(v, lane);
+            }
+        }
+    }
+};
+
 template <int NV>
 struct Butterfly {
     // After the call, the lane holds in v[0] the wavefront total of value
     // index slot(lane) (the first log2(NV) lane bits, reversed).
     __device__ __forceinline__ static float reduce(float (&v)[NV], int lane) {
-        int cnt = NV;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            if (cnt > 1) {
-                const int half = cnt >> 1;
-                const bool up = (lane & d) != 0;
-#pragma unroll
-                for (int k = 0; k < NV / 2; ++k) {
-                    if (k < half) {
-                        const float send = up ? v[k] : v[k + half];
-                        const float keep = up ? v[k + half] : v[k];
-                        v[k] = keep + __shfl_xor(send, d, kWave);
-                    }
-                }
-                cnt = half;
-            } else {
-                v[0] += __shfl_xor(v[0], d, kWave);
-            }
-        }
+        BflyStep<NV, NV, 1>::run(v, lane);
         return v[0];
     }
     __device__ __forceinline__ static int slot(int lane) {
@@ -78,12 +92,13 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                                          const RasterConst& c, const float* __restrict__ T_final,
                                          const int32_t* __restrict__ last, const float* __restrict__ grad_out,
                                          float* __restrict__ grad_geo, float* __restrict__ grad_app, float4* s_g0,
-                                         float4* s_g1, float4* s_app, int* s_max) {
+                                         float4* s_g1, float4* s_app, int* s_max, float* s_acc, int* s_used) {
     constexpr int NT = TS * TS;
     constexpr int AV = AppRec<F>::vec;
     constexpr int NREAL = PARAMS ? 10 + F : 6;
     constexpr int NV = Pow2<NREAL>::value;
     constexpr int GA = 4 + F;  // per-Gaussian appearance gradient record
+    constexpr int AST = NREAL + 1;  // accumulator stride (odd: spreads LDS banks)
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     constexpr int WPR = TS / 8;
     const int sbx = (wave % WPR) * 8, sby = (wave / WPR) * 8;
@@ -136,7 +151,9 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             s_g1[k] = a1;
 #pragma unroll
             for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
+            s_used[k] = 0;
         }
+        for (int k = tid; k < nb * AST; k += NT) s_acc[k] = 0.0f;
         __syncthreads();
         for (int j = nb - 1; j >= 0; --j) {
             const float4 g0 = s_g0[j];
@@ -182,13 +199,21 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 }
             }
             const float tot = Butterfly<NV>::reduce(val, lane);
-            if (writer) {
-                const int gid = gids[bstart + j];
-                if (my_slot < 6) {
-                    atomicAdd(&grad_geo[(vbase + gid) * 8 + my_slot], tot * scale);
-                } else {
-                    atomicAdd(&grad_app[(size_t)gid * GA + (my_slot - 6)], tot);
-                }
+            if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
+            if (lane == 0) s_used[j] = 1;
+        }
+        __syncthreads();
+        // flush: one global atomic per value and touched Gaussian of the batch
+        for (int k = tid; k < nb; k += NT) {
+            if (!s_used[k]) continue;
+            const int gid = gids[bstart + k];
+            float* gg = grad_geo + (vbase + gid) * 8;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) atomicAdd(&gg[q], s_acc[k * AST + q]);
+            if (PARAMS) {
+                float* ga = grad_app + (size_t)gid * GA;
+#pragma unroll
+                for (int q = 0; q < 4 + F; ++q) atomicAdd(&ga[q], s_acc[k * AST + 6 + q]);
             }
         }
     }
@@ -211,9 +236,12 @@ __global__ void __launch_bounds__(TS* TS) k_render_bwd(const float4* __restrict_
     __shared__ float4 s_app[B * AV];
     __shared__ int s_tile;
     __shared__ int s_max;
+    constexpr int NREAL = PARAMS ? 10 + F : 6;
+    __shared__ float s_acc[B * (NREAL + 1)];
+    __shared__ int s_used[B];
     if (!persistent) {
         bwd_tile<TS, F, B, PARAMS>(blockIdx.x, rec, app, n, gids, ranges, views, n_views, P, c, T_final, last,
-                                   grad_out, grad_geo, grad_app, s_g0, s_g1, s_app, &s_max);
+                                   grad_out, grad_geo, grad_app, s_g0, s_g1, s_app, &s_max, s_acc, s_used);
         return;
     }
     for (;;) {
@@ -223,7 +251,7 @@ __global__ void __launch_bounds__(TS* TS) k_render_bwd(const float4* __restrict_
         const int t = s_tile;
         if (t >= total_tiles) break;
         bwd_tile<TS, F, B, PARAMS>(t, rec, app, n, gids, ranges, views, n_views, P, c, T_final, last, grad_out,
-                                   grad_geo, grad_app, s_g0, s_g1, s_app, &s_max);
+                                   grad_geo, grad_app, s_g0, s_g1, s_app, &s_max, s_acc, s_used);
     }
 }
 

@@ -193,19 +193,27 @@ int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat,
                                         reinterpret_cast<hipStream_t>(stream)));
 }
 
+int gs_loss_grad_workspace(int64_t total_pixels, size_t* bytes) {
+    if (!bytes || total_pixels < 1) return GS_EINVAL;
+    *bytes = loss_workspace_bytes(total_pixels);
+    return GS_OK;
+}
+
 int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, const float* depth_target,
                  const int32_t* labels, const float* decoder, int32_t n_classes, const float* weights,
-                  const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
-                  gs_stream stream) {
+                 const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
+                 void* ws, size_t ws_bytes, gs_stream stream) {
     if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
     int64_t P = 0;
     int st = check_views(views, views_dev, n_views, 0, &P, nullptr);
     if (st) return st;
-    if (!out || !rgb_target || !depth_target || !weights || !grad_out || !loss) return GS_EINVAL;
+    if (!out || !rgb_target || !depth_target || !weights || !grad_out || !loss || !ws) return GS_EINVAL;
     if (n_classes < 0 || n_classes > GS_MAX_CLASSES) return GS_EINVAL;
     if (n_classes > 0 && n_feat > 0 && (!labels || !decoder)) return GS_EINVAL;
+    if (ws_bytes < loss_workspace_bytes(P)) return GS_ECAPACITY;
+    if ((reinterpret_cast<uintptr_t>(ws) & 15u) != 0) return GS_EINVAL;
     return hip_status(launch_loss(out, n_feat, rgb_target, depth_target, labels, decoder, n_feat > 0 ? n_classes : 0,
-                                  weights, views_dev, n_views, P, grad_out, loss,
+                                  weights, views_dev, n_views, P, grad_out, loss, ws,
                                   reinterpret_cast<hipStream_t>(stream)));
 }
 
@@ -219,8 +227,7 @@ int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, size_t* 
 int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* gids,
                   const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev, int32_t n_views,
                   const gs_config* cfg, const float* T_final, const int32_t* last, const float* grad_out,
-                  uint32_t flags, float* grad2d, size_t grad2d_bytes_, gs_gaussian_grads* grads, int32_t* queue,
-                  gs_stream stream) {
+                  uint32_t flags, float* grad2d, size_t grad2d_bytes_, int32_t* queue, gs_stream stream) {
     const bool params = (flags & GS_GRAD_PARAMS) != 0;
     int st = check_gauss(g, false);
     if (st) return st;
@@ -233,31 +240,37 @@ int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, con
     if (cfg->persistent && !queue) return GS_EINVAL;
     if (grad2d_bytes_ < grad2d_bytes(g->n, g->n_feat, n_views)) return GS_ECAPACITY;
     if (!aligned16(rec) || !aligned16(app) || !aligned16(grad2d)) return GS_EINVAL;
-    if (params) {
-        if (!grads || !grads->mu || !grads->log_scale || !grads->quat || !grads->opacity_logit || !grads->color ||
-            (g->n_feat > 0 && !grads->feat))
-            return GS_EINVAL;
-    }
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float* geo = grad2d;
     float* appg = grad2d + (size_t)n_views * g->n * 8;
-    hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (int64_t)(grad2d_bytes(g->n, g->n_feat, n_views) / 4), s);
-    if (e != hipSuccess) return hip_status(e);
-    const RasterConst c = make_const(cfg);
-    e = launch_render_bwd(rec, app, g->n, g->n_feat, gids, tile_ranges, views_dev, n_views, total_tiles, P, c,
-                          cfg->lds_batch, cfg->persistent, T_final, last, grad_out, params, geo, appg, queue, s);
-    if (e != hipSuccess) return hip_status(e);
-    if (params) {
-        GradPtrs o;
-        o.mu = grads->mu;
-        o.log_scale = grads->log_scale;
-        o.quat = grads->quat;
-        o.logit = grads->opacity_logit;
-        o.color = grads->color;
-        o.feat = grads->feat;
-        e = launch_project_bwd(gauss_ptrs(g), views_dev, n_views, c, geo, appg, o, s);
-    }
-    return hip_status(e);
+    return hip_status(launch_render_bwd(rec, app, g->n, g->n_feat, gids, tile_ranges, views_dev, n_views,
+                                        total_tiles, P, make_const(cfg), cfg->lds_batch, cfg->persistent, T_final,
+                                        last, grad_out, params, geo, appg, queue,
+                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                   const gs_config* cfg, const float* grad2d, size_t grad2d_bytes_, gs_gaussian_grads* grads,
+                   gs_stream stream) {
+    int st = check_gauss(g, false);
+    if (st) return st;
+    if ((st = check_config(cfg))) return st;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, nullptr))) return st;
+    if (!grad2d || !grads || !grads->mu || !grads->log_scale || !grads->quat || !grads->opacity_logit ||
+        !grads->color || (g->n_feat > 0 && !grads->feat))
+        return GS_EINVAL;
+    if (grad2d_bytes_ < grad2d_bytes(g->n, g->n_feat, n_views)) return GS_ECAPACITY;
+    if (!aligned16(grad2d)) return GS_EINVAL;
+    GradPtrs o;
+    o.mu = grads->mu;
+    o.log_scale = grads->log_scale;
+    o.quat = grads->quat;
+    o.logit = grads->opacity_logit;
+    o.color = grads->color;
+    o.feat = grads->feat;
+    const float* geo = grad2d;
+    const float* appg = grad2d + (size_t)n_views * g->n * 8;
+    return hip_status(launch_project_bwd(gauss_ptrs(g), views_dev, n_views, make_const(cfg), geo, appg, o,
+                                         reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_pose_grad_workspace(int32_t n, int32_t n_views, size_t* bytes) {

@@ -87,10 +87,11 @@ hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_fe
                              int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
                              float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s);
 
+size_t loss_workspace_bytes(int64_t P);
 hipError_t launch_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t,
                        const int32_t* labels, const float* decoder, int n_classes, const float* weights,
                        const gs_view* views_dev, int n_views, int64_t total_pixels, float* grad_out,
-                       double* loss, hipStream_t s);
+                       double* loss, void* ws, hipStream_t s);
 
 hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
                              const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,

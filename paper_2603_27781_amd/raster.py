@@ -147,6 +147,8 @@ class Rasterizer:
         self.pose_ws = torch.empty(max(b.value, 16) // 8 + 1, dtype=torch.float64, **dev)
         self.twist = torch.zeros(V, 6, dtype=torch.float32, **dev)
         self.loss = torch.zeros(4, dtype=torch.float64, **dev)
+        check(L.gs_loss_grad_workspace(P, ctypes.byref(b)), "gs_loss_grad_workspace")
+        self.loss_ws = torch.empty(b.value // 8 + 2, dtype=torch.float64, **dev)
         self.grad_out = torch.empty_like(self.out)
         self.capacity = 0
         self.set_capacity(capacity if capacity is not None else max(4 * V * n, 1 << 16))
@@ -171,13 +173,15 @@ class Rasterizer:
         return int(c[0]), int(c[1]), bool(c[2])
 
     def ensure_capacity(self, g: Gaussians, slack: float = 1.25) -> int:
-        """Run projection + binning once and grow the instance buffers if
-        needed (one host synchronisation; call before capturing a graph)."""
+        """Run projection + binning once and size the instance buffers to the
+        measured count times `slack` (one host synchronisation; call before
+        capturing a graph, and again if the scene changes a lot)."""
         self.project(g)
         self.bin_sort()
         inst, _, over = self.instance_counts()
-        if over or inst > self.capacity:
-            self.set_capacity(int(inst * slack) + 1024)
+        want = int(inst * slack) + 1024
+        if over or inst > self.capacity or self.capacity > 2 * want:
+            self.set_capacity(want)
             self.project(g)
             self.bin_sort()
         return inst
@@ -210,7 +214,7 @@ class Rasterizer:
     def loss_grad(self, rgb_t, depth_t, labels=None, decoder=None, weights=(0.5, 1.0, 0.0),
                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """L1 colour + L1 depth + CE(W^T F) per view; writes self.grad_out and
-        adds the loss terms to self.loss (zero it first for a fresh value)."""
+        the loss terms (colour, depth, semantic, total) to self.loss."""
         out = self.out if out is None else out
         K = 0 if decoder is None else int(decoder.shape[1])
         w = (ctypes.c_float * 3)(*[float(x) for x in weights])
@@ -218,18 +222,31 @@ class Rasterizer:
                                   labels.data_ptr() if labels is not None else None,
                                   decoder.data_ptr() if decoder is not None else None, K, w, self.views.host,
                                   self.views.dev_ptr(), self.views.n, self.grad_out.data_ptr(),
-                                  self.loss.data_ptr(), _stream()), "gs_loss_grad")
+                                  self.loss.data_ptr(), self.loss_ws.data_ptr(), self.loss_ws.numel() * 8,
+                                  _stream()), "gs_loss_grad")
         return self.grad_out
 
     def render_bwd(self, g: Gaussians, grad_out: torch.Tensor, flags: int, grads: Optional[Gaussians]) -> None:
-        gc = _grads_c(grads) if grads is not None else None
+        """Backward of the compositing into the 2D gradient buffer (zeroed
+        here) and, with GS_GRAD_PARAMS, of the projection into `grads` (+=)."""
+        self.grad2d.zero_()
+        self.render_bwd_2d(g, grad_out, flags)
+        if flags & _lib.GS_GRAD_PARAMS:
+            self.project_bwd(g, grads)
+
+    def render_bwd_2d(self, g: Gaussians, grad_out: torch.Tensor, flags: int) -> None:
         check(self.L.gs_render_bwd(ctypes.byref(g.c()), self.rec.data_ptr(), self.app.data_ptr(),
                                    self.gids.data_ptr(), self.ranges.data_ptr(), self.views.host,
                                    self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc),
                                    self.T_final.data_ptr(), self.last.data_ptr(), grad_out.data_ptr(), flags,
-                                   self.grad2d.data_ptr(), self.grad2d.numel() * 4,
-                                   ctypes.byref(gc) if gc is not None else None, self.queue.data_ptr(), _stream()),
-              "gs_render_bwd")
+                                   self.grad2d.data_ptr(), self.grad2d.numel() * 4, self.queue.data_ptr(),
+                                   _stream()), "gs_render_bwd")
+
+    def project_bwd(self, g: Gaussians, grads: Gaussians) -> None:
+        gc = _grads_c(grads)
+        check(self.L.gs_project_bwd(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
+                                    ctypes.byref(self.cc), self.grad2d.data_ptr(), self.grad2d.numel() * 4,
+                                    ctypes.byref(gc), _stream()), "gs_project_bwd")
 
     def pose_grad(self, g: Gaussians) -> torch.Tensor:
         check(self.L.gs_pose_grad(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,

@@ -13,9 +13,18 @@ from paper_2603_27781_amd import workloads as wl
 TOL_RGB = 1e-5
 TOL_REL_DF = 1e-4
 TOL_GRAD = 1e-3
-# a pixel whose alpha_min / T_min decisions lie within this relative margin
-# of the threshold may legitimately decide differently in binary32 and FP64
-MARGIN = 1e-3
+# A pixel whose alpha_min / T_min decisions lie within these relative
+# margins of the threshold may legitimately decide differently in binary32
+# and FP64; it is left out of the value comparison and counted.
+#  - against the oracle on the binary32 projected geometry (mean, conic,
+#    depth as the decision path computes them): only the kernel's binary32
+#    alpha and transmittance arithmetic differs,
+MARGIN_A32, MARGIN_T32 = 2e-5, 2e-4
+#  - against the oracle on the FP64 geometry: the binary32 mean alone is
+#    off by up to half an ulp of ~1e3 px, i.e. ~3e-5 px, so alpha can differ
+#    by ~1e-4 relatively near the box edge.
+MARGIN_A64, MARGIN_T64 = 1e-3, 1e-3
+MARGIN = MARGIN_A64
 
 
 def gpu_setup(scene, views, cfg_kw=None, capacity=None):
@@ -33,12 +42,13 @@ def oracle_cfg(cfg) -> oracle.Cfg:
                       alpha_max=cfg.alpha_max, T_min=cfg.T_min, tile=cfg.tile)
 
 
-def compare_render(out_gpu, T_gpu, last_gpu, ref, sel=None):
+def compare_render(out_gpu, T_gpu, last_gpu, ref, sel=None, geometry="fp32"):
     """Returns (n_flagged, report dict); asserts the tolerances on the
     unflagged pixels of `sel` (a boolean pixel mask, default all)."""
     P = ref["out"].shape[1]
     sel = np.ones(P, bool) if sel is None else sel
-    ok = sel & (ref["margin"] >= MARGIN)
+    ma, mt = (MARGIN_A32, MARGIN_T32) if geometry == "fp32" else (MARGIN_A64, MARGIN_T64)
+    ok = sel & (ref["margin_a"] >= ma) & (ref["margin_t"] >= mt)
     flagged = int((sel & ~ok).sum())
     o, g = ref["out"][:, ok], out_gpu[:, ok].astype(np.float64)
     rep = {}

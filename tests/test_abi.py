@@ -88,8 +88,10 @@ def test_validation_rejects_before_any_launch():
                         None) == _lib.GS_EINVAL
     L.gs_views_layout(V, 1, 16, None, None)
     assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, V, dummy, 1, ctypes.byref(cfg), dummy,
-                           dummy, dummy, 0, dummy, 1 << 30, None, dummy, None) == _lib.GS_EINVAL
+                           dummy, dummy, 0, dummy, 1 << 30, dummy, None) == _lib.GS_EINVAL
     assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, V, dummy, 1, ctypes.byref(cfg), dummy,
-                           dummy, dummy, 1, dummy, 16, None, dummy, None) == _lib.GS_ECAPACITY
+                           dummy, dummy, 1, dummy, 16, dummy, None) == _lib.GS_ECAPACITY
+    assert L.gs_project_bwd(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, 1 << 30, None,
+                            None) == _lib.GS_EINVAL
     assert L.gs_error_string(_lib.GS_ECAPACITY) == b"buffer too small"
     assert L.gs_version() >= 100

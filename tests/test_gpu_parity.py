@@ -109,11 +109,25 @@ def _render(name, tile, lds_batch=256, persistent=0):
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("tile,lds_batch,persistent", [(16, 256, 0), (8, 64, 0), (32, 128, 1)])
 def test_render_fwd_parity(name, tile, lds_batch, persistent):
+    """Against the oracle on the binary32 projected geometry: pixels within
+    2e-5 (alpha) / 2e-4 (T) of a threshold are counted, at most 2e-4 P."""
     scene, views, r, g, cfg = _render(name, tile, lds_batch, persistent)
-    ref = oracle.render(scene, views, oracle_cfg(cfg))
+    ref = oracle.render(scene, views, oracle_cfg(cfg), geometry="fp32")
     flagged, rep = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref)
     print(name, tile, "flagged", flagged, rep)
-    assert flagged <= max(2, 1e-3 * ref["out"].shape[1])
+    assert flagged <= max(2, 2e-4 * ref["out"].shape[1])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_render_fwd_parity_fp64_geometry(name):
+    """Against the all-FP64 oracle: same value tolerances, wider threshold
+    margins (the binary32 mean is ~3e-5 px off), at most 2% of pixels."""
+    scene, views, r, g, cfg = _render(name, 16)
+    ref = oracle.render(scene, views, oracle_cfg(cfg), geometry="fp64")
+    flagged, rep = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref,
+                                  geometry="fp64")
+    print(name, "flagged", flagged, rep)
+    assert flagged <= 0.02 * ref["out"].shape[1]
 
 
 @pytest.mark.parametrize("name", ["cfg1-64x64-2k", "tiny3views-F16"])
@@ -146,7 +160,6 @@ def test_loss_grad_parity(name):
     W = wl.decoder_matrix(rng, F, K)
     wts = (0.5, 1.0, 0.01)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    r.loss.zero_()
     r.loss_grad(dev(rgb_t), dev(dep_t), dev(lab), dev(W), wts)
     go = r.grad_out.cpu().numpy()
     gref, terms = oracle.loss(out32.astype(np.float64), views, rgb_t, dep_t, lab, W.astype(np.float64), wts)
@@ -283,9 +296,9 @@ def _single(scene, views):
     r, g, cfg = gpu_setup(scene, views, {"tile": 8, "lds_batch": 64})
     r.ensure_capacity(g)
     r.forward(g)
-    ref = oracle.render(scene, views, oracle_cfg(cfg))
-    compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref)
-    return True
+    ref = oracle.render(scene, views, oracle_cfg(cfg), geometry="fp32")
+    flagged, _ = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref)
+    return flagged <= 2
 
 
 def test_abi_rejects_bad_arguments_without_launching():
