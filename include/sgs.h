@@ -154,26 +154,33 @@ int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views
 
 /* ---------------------------------------------------------------------------
  * gs_bin_sort -- tile binning and depth sort (Sec. 3.2.1: tile-based
- * rasterization of Gaussians sorted in depth order).  Emits one instance per
- * (view, tile, Gaussian) with the Gaussian's rectangle covering the tile and
- * sorts them by (global tile id, binary32 depth, Gaussian index) with the
- * library's own device radix sorts (visible pairs by depth, then instances by
- * tile, both stable).
- *   tile_keys[capacity]       global tile id of each sorted instance
- *   gids[capacity]            Gaussian index of each sorted instance
- *   tile_ranges[T_total][2]   [start, end) of every global tile
- *   counts[4] (int64)         [0] instances, [1] visible pairs,
- *                             [2] 1 if the instance count exceeded capacity
- *                             (the lists are then truncated: read counts
- *                             after the stream completes and call again with
- *                             capacity >= counts[0]), [3] reserved.
- * ws / ws_bytes: workspace of at least gs_bin_sort_workspace(...) bytes.
+ * rasterization of Gaussians sorted in depth order).  Every visible
+ * (view, Gaussian) pair emits one instance per tile of its rectangle; the
+ * instances are sorted by (global tile id, binary32 depth, Gaussian index)
+ * with the library's own device radix sorts (visible pairs by depth, then
+ * instances by tile, both stable).
+ * An instance is identified by its emission index e (pairs in depth order,
+ * each pair's tiles row by row), so the instances of one pair occupy the
+ * contiguous range [pair_first[pair], pair_first[pair] + tiles_touched[pair]).
+ *   tile_keys[capacity]     global tile id of each sorted instance
+ *   inst[capacity]          emission index of each sorted instance
+ *   inst_gid[capacity]      Gaussian index of each emission index
+ *                           (so inst_gid[inst[k]] is the k-th sorted Gaussian)
+ *   pair_first[V][n]        first emission index of each visible pair
+ *   tile_ranges[T_total][2] [start, end) of every global tile in the sorted list
+ *   counts[4] (int64)       [0] instances, [1] visible pairs,
+ *                           [2] 1 if the instance count exceeded capacity
+ *                           (the lists are then truncated: read counts after
+ *                           the stream completes and call again with
+ *                           capacity >= counts[0]), [3] reserved.
+ * ws / ws_bytes: workspace of at least gs_bin_sort_workspace(...) bytes,
+ * 256-byte aligned.  Instance counts must stay below 2^31.
  * --------------------------------------------------------------------------- */
 int gs_bin_sort_workspace(int32_t n, int32_t n_views, int64_t capacity, size_t* bytes);
 int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float* rec, int32_t n,
                 const gs_view* views, const gs_view* views_dev, int32_t n_views, const gs_config* cfg,
-                void* ws, size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* gids,
-                int32_t* tile_ranges, int64_t* counts, gs_stream stream);
+                void* ws, size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* inst,
+                int32_t* inst_gid, int32_t* pair_first, int32_t* tile_ranges, int64_t* counts, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_render_fwd -- front-to-back compositing, Eq. (4), (6), (7), (9):
@@ -181,15 +188,16 @@ int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float*
  *   out_ch  = sum_i x_i,ch alpha_i T_i,  T_i = prod_{j<i} (1 - alpha_j)
  * over each pixel's tile list in (depth, index) order, skipping alpha <
  * alpha_min and stopping before T would drop below T_min.  Background 0.
+ *   inst, inst_gid, tile_ranges from gs_bin_sort; rec, app from gs_project.
  *   out[5+F][P_total], T_final[P_total], last[P_total] (number of list
  *   entries of the pixel's tile up to and including its last contributor).
  *   queue: >= 4 int32 of device memory, used when cfg->persistent (may be
  *   NULL otherwise); it is reset inside the call.
  * --------------------------------------------------------------------------- */
-int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* gids,
-                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev,
-                  int32_t n_views, const gs_config* cfg, float* out, float* T_final, int32_t* last,
-                  int32_t* queue, gs_stream stream);
+int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* inst,
+                  const int32_t* inst_gid, const int32_t* tile_ranges, const gs_view* views,
+                  const gs_view* views_dev, int32_t n_views, const gs_config* cfg, float* out, float* T_final,
+                  int32_t* last, int32_t* queue, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_loss_grad -- image-space losses of Sec. 3.3.4 / 3.4 and their gradient:
@@ -218,22 +226,28 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
  *   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),
  *   S_i = sum_{j>i} (g . x_j) alpha_j T_j,
  * with g the pixel's upstream gradient grad_out[5+F][P_total] and x_i the
- * Gaussian's channel values (colour, depth, 1, feature); reduces the
- * per-Gaussian gradients across each wavefront, then ACCUMULATES (+=, with
- * atomics) into grad2d, which the caller zeroes before the first call:
- *   grad2d geo [V][n][8]  = dL/d(mx, my, A, B, C, d), 2 unused   (per view)
+ * Gaussian's channel values (colour, depth, 1, feature).  Per-Gaussian sums
+ * are reduced across each wavefront and tile, written as one record per
+ * instance into ws (no atomics), then summed per (view, Gaussian) pair in a
+ * fixed order, so the result is deterministic.  WRITES grad2d:
+ *   grad2d geo [V][n][8]  = dL/d(mx, my, A, B, C, d), 2 unused   (per view,
+ *                           zero for pairs that are not visible)
  *   grad2d app [n][4+F]   = dL/d(o, c0, c1, c2, f...)            (all views)
- * (geo first, app right after it; gs_render_bwd_workspace gives the bytes).
- * flags: GS_GRAD_PARAMS fills geo and app; GS_GRAD_POSE alone (tracking,
- * Sec. 3.4: the field is frozen) fills geo only and skips colour, feature
- * and opacity.
+ * (geo first, app right after it).  flags: GS_GRAD_PARAMS fills geo and app;
+ * GS_GRAD_POSE alone (tracking, Sec. 3.4: the field is frozen) fills geo
+ * only and skips colour, feature and opacity (app is left untouched).
+ * inst, inst_gid, pair_first, tile_ranges, capacity: as given to / written by
+ * gs_bin_sort; tiles_touched from gs_project.
+ * gs_render_bwd_workspace gives grad2d_bytes and ws_bytes (capacity records).
  * --------------------------------------------------------------------------- */
-int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, size_t* bytes);
-int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* gids,
-                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev,
+int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags,
+                            size_t* grad2d_bytes, size_t* ws_bytes);
+int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* inst,
+                  const int32_t* inst_gid, const int32_t* pair_first, const int32_t* tiles_touched,
+                  int64_t capacity, const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev,
                   int32_t n_views, const gs_config* cfg, const float* T_final, const int32_t* last,
-                  const float* grad_out, uint32_t flags, float* grad2d, size_t grad2d_bytes,
-                  int32_t* queue, gs_stream stream);
+                  const float* grad_out, uint32_t flags, float* grad2d, size_t grad2d_bytes, void* ws,
+                  size_t ws_bytes, int32_t* queue, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_project_bwd -- backward of gs_project (Eq. 2-3) for the mapping step:

@@ -77,16 +77,17 @@ def load() -> ctypes.CDLL:
                              c_void_p, c_void_p, c_void_p]
     L.gs_bin_sort_workspace.argtypes = [c_int32, c_int32, c_int64, P(c_size_t)]
     L.gs_bin_sort.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, P(GsView), c_void_p, c_int32, P(GsConfig),
-                              c_void_p, c_size_t, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
-    L.gs_render_fwd.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, P(GsView), c_void_p,
-                                c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+                              c_void_p, c_size_t, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p]
+    L.gs_render_fwd.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, P(GsView),
+                                c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.gs_loss_grad_workspace.argtypes = [c_int64, P(c_size_t)]
     L.gs_loss_grad.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, P(c_float),
                                P(GsView), c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
-    L.gs_render_bwd_workspace.argtypes = [c_int32, c_int32, c_int32, P(c_size_t)]
-    L.gs_render_bwd.argtypes = [P(GsGaussians), c_void_p, c_void_p, c_void_p, c_void_p, P(GsView), c_void_p,
-                                c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p, c_uint32, c_void_p, c_size_t,
-                                c_void_p, c_void_p]
+    L.gs_render_bwd_workspace.argtypes = [c_int32, c_int32, c_int32, c_int64, c_uint32, P(c_size_t), P(c_size_t)]
+    L.gs_render_bwd.argtypes = [P(GsGaussians), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
+                                c_void_p, P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p,
+                                c_uint32, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p]
     L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_size_t,
                                  P(GsGaussianGrads), c_void_p]
     L.gs_pose_grad_workspace.argtypes = [c_int32, c_int32, P(c_size_t)]

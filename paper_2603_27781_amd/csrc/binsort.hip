@@ -271,9 +271,16 @@ __global__ void k_counts(const int64_t* n_inst, const int64_t* n_vis, int64_t ca
     *n_clamped = I < capacity ? I : capacity;
 }
 
+// Emission: the visible pair at depth-sorted position i writes one instance
+// per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1:
+// key = global tile id, value = the emission index itself.  inst_gid[e] keeps
+// the Gaussian of emission index e, pair_first[pair] the first emission index
+// of the pair, so that the instances of one (view, Gaussian) pair stay
+// contiguous in emission space after the tile sort has reordered them.
 __global__ void k_emit(const uint32_t* __restrict__ vis_vals, const uint32_t* __restrict__ offs, const int64_t* n_vis,
                        const uint2* __restrict__ rect, const gs_view* __restrict__ views, int n, int tile,
-                       int64_t capacity, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                       int64_t capacity, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                       int32_t* __restrict__ inst_gid, int32_t* __restrict__ pair_first) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= *n_vis) return;
     const uint32_t pair = vis_vals[i];
@@ -284,11 +291,13 @@ __global__ void k_emit(const uint32_t* __restrict__ vis_vals, const uint32_t* __
     const int tx = ceil_div(views[v].width, tile);
     const uint32_t tbase = (uint32_t)views[v].tile_offset;
     int64_t o = offs[i];
+    pair_first[pair] = (int32_t)o;
     for (int y = y0; y <= y1; ++y)
         for (int x = x0; x <= x1; ++x) {
             if (o < capacity) {
                 keys[o] = tbase + (uint32_t)(y * tx + x);
-                vals[o] = gid;
+                vals[o] = (uint32_t)o;
+                inst_gid[o] = (int32_t)gid;
             }
             ++o;
         }
@@ -337,8 +346,8 @@ size_t binsort_workspace_bytes(int n, int n_views, int64_t capacity) { return ws
 
 hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const float* rec, int n,
                           const gs_view* views_dev, int n_views, int total_tiles, int tile, void* ws,
-                          int64_t capacity, uint32_t* tile_keys, int32_t* gids, int32_t* ranges, int64_t* counts,
-                          hipStream_t s) {
+                          int64_t capacity, uint32_t* tile_keys, int32_t* inst, int32_t* inst_gid,
+                          int32_t* pair_first, int32_t* ranges, int64_t* counts, hipStream_t s) {
     const WsLayout L = ws_layout(n, n_views, capacity);
     char* w = static_cast<char*>(ws);
     uint32_t* vis_k0 = reinterpret_cast<uint32_t*>(w + L.vis_k0);
@@ -373,12 +382,13 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     while ((1ll << bits) < (int64_t)total_tiles) ++bits;
     const int passes = (bits + 7) / 8;
     uint32_t* ek = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(tile_keys) : ik2;
-    uint32_t* ev = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(gids) : iv2;
+    uint32_t* ev = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(inst) : iv2;
     uint32_t* ok = (passes % 2 == 0) ? ik2 : reinterpret_cast<uint32_t*>(tile_keys);
-    uint32_t* ov = (passes % 2 == 0) ? iv2 : reinterpret_cast<uint32_t*>(gids);
+    uint32_t* ov = (passes % 2 == 0) ? iv2 : reinterpret_cast<uint32_t*>(inst);
     if (vn > 0) {
         hipLaunchKernelGGL(k_emit, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, vis_v0, pos, &cnt[0],
-                           reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, ev);
+                           reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, ev, inst_gid,
+                           pair_first);
     }
     e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, bsum, s);
     if (e != hipSuccess) return e;

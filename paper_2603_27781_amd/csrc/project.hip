@@ -1,7 +1,8 @@
 // Projection of every (view, Gaussian) pair: GS^3LAM Sec. 3.2, Eq. (2)-(3).
 //
-// One thread per pair, grid (ceil(n/256), V): the Gaussian planes are read
-// as coalesced structure-of-arrays loads and each block works on one view.
+// One thread per Gaussian (grid ceil(n/256)): the Gaussian planes are read
+// once as coalesced structure-of-arrays loads, and the thread projects the
+// Gaussian into every view.
 //
 // Everything that decides an integer downstream -- culling, the projected
 // mean, the conic, the depth key and the tile rectangle -- is evaluated in
@@ -34,17 +35,18 @@ __device__ __forceinline__ float dec_exp(float x) {
     return ldexpf(p, (int)n);
 }
 
-__global__ void __launch_bounds__(256) k_project(GaussPtrs g, const gs_view* __restrict__ views,
+// One thread per Gaussian: the view-independent part (opacity cull, unit
+// quaternion, rotation, scales, M = R S) is evaluated once, then every view
+// is projected in turn; each view's outputs are written as coalesced rows.
+__global__ void __launch_bounds__(256) k_project(GaussPtrs g, const gs_view* __restrict__ views, int n_views,
                                                  RasterConst c, float4* __restrict__ rec,
                                                  uint2* __restrict__ rect, int32_t* __restrict__ touched,
                                                  float* __restrict__ app, int app_stride) {
     const int n = g.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y;
     if (i >= n) return;
-    const gs_view& vw = views[v];
 
-    if (app != nullptr && v == 0) {
+    if (app != nullptr) {
         // appearance record (c, f) gathered per instance by the render kernels
         float* a = app + (size_t)i * app_stride;
         a[0] = g.color[i];
@@ -54,34 +56,18 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, const gs_view* __r
         for (int k = 3 + g.n_feat; k < app_stride; ++k) a[k] = 0.0f;
     }
 
-    const size_t o = (size_t)v * n + i;
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint2 rc = make_uint2(0xffffffffu, 0xffffffffu);
-    int32_t cnt = 0;
-
     const float logit = g.logit[i];
     const float m0 = g.mu[i], m1 = g.mu[(size_t)n + i], m2 = g.mu[2 * (size_t)n + i];
-    const float* R = vw.Rt;  // row-major [R|t]: R[0..2] t at [3], [7], [11]
-    bool vis = logit > c.logit_min;
-    const float p0 = ((R[0] * m0 + R[1] * m1) + R[2] * m2) + R[3];
-    const float p1 = ((R[4] * m0 + R[5] * m1) + R[6] * m2) + R[7];
-    const float p2 = ((R[8] * m0 + R[9] * m1) + R[10] * m2) + R[11];
-    vis = vis && (p2 > c.z_near);
-    const float xn = p0 / p2, yn = p1 / p2;
-    const float limx = (c.guard * (0.5f * (float)vw.width)) / vw.fx;
-    const float limy = (c.guard * (0.5f * (float)vw.height)) / vw.fy;
-    vis = vis && (fabsf(xn) <= limx) && (fabsf(yn) <= limy);
-    const float mx = vw.fx * xn + vw.cx;
-    const float my = vw.fy * yn + vw.cy;
-
     const float q0 = g.quat[i], q1 = g.quat[(size_t)n + i], q2 = g.quat[2 * (size_t)n + i],
                 q3 = g.quat[3 * (size_t)n + i];
     const float n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
-    vis = vis && (n2 > 0.0f) && (n2 < INFINITY);
-    if (vis) {
+    const bool alive = (logit > c.logit_min) && (n2 > 0.0f) && (n2 < INFINITY);
+    // rotation of the unit quaternion and M = R S (Eq. 2)
+    float M00 = 0.f, M01 = 0.f, M02 = 0.f, M10 = 0.f, M11 = 0.f, M12 = 0.f, M20 = 0.f, M21 = 0.f, M22 = 0.f;
+    float op = 0.f;
+    if (alive) {
         const float nrm = sqrtf(n2);
         const float w = q0 / nrm, x = q1 / nrm, y = q2 / nrm, z = q3 / nrm;
-        // rotation of the unit quaternion (Eq. 2)
         const float r00 = 1.0f - 2.0f * (y * y + z * z);
         const float r01 = 2.0f * (x * y - w * z);
         const float r02 = 2.0f * (x * z + w * y);
@@ -94,58 +80,78 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, const gs_view* __r
         const float s0 = dec_exp(g.log_scale[i]);
         const float s1 = dec_exp(g.log_scale[(size_t)n + i]);
         const float s2 = dec_exp(g.log_scale[2 * (size_t)n + i]);
-        // M = R S (columns scaled)
-        const float M00 = r00 * s0, M01 = r01 * s1, M02 = r02 * s2;
-        const float M10 = r10 * s0, M11 = r11 * s1, M12 = r12 * s2;
-        const float M20 = r20 * s0, M21 = r21 * s1, M22 = r22 * s2;
-        // EWA (Eq. 3): J = d(pi)/dp, T = J R_CW, U = T M, Sigma2D = U U^T + b I
-        const float j00 = vw.fx / p2, j11 = vw.fy / p2;
-        const float j02 = -(j00 * xn), j12 = -(j11 * yn);
-        const float T00 = j00 * R[0] + j02 * R[8];
-        const float T01 = j00 * R[1] + j02 * R[9];
-        const float T02 = j00 * R[2] + j02 * R[10];
-        const float T10 = j11 * R[4] + j12 * R[8];
-        const float T11 = j11 * R[5] + j12 * R[9];
-        const float T12 = j11 * R[6] + j12 * R[10];
-        const float U00 = (T00 * M00 + T01 * M10) + T02 * M20;
-        const float U01 = (T00 * M01 + T01 * M11) + T02 * M21;
-        const float U02 = (T00 * M02 + T01 * M12) + T02 * M22;
-        const float U10 = (T10 * M00 + T11 * M10) + T12 * M20;
-        const float U11 = (T10 * M01 + T11 * M11) + T12 * M21;
-        const float U12 = (T10 * M02 + T11 * M12) + T12 * M22;
-        const float a = ((U00 * U00 + U01 * U01) + U02 * U02) + c.blur;
-        const float b = (U00 * U10 + U01 * U11) + U02 * U12;
-        const float cc = ((U10 * U10 + U11 * U11) + U12 * U12) + c.blur;
-        const float det = a * cc - b * b;
-        vis = (det > 0.0f) && (det < INFINITY);
+        M00 = r00 * s0; M01 = r01 * s1; M02 = r02 * s2;
+        M10 = r10 * s0; M11 = r11 * s1; M12 = r12 * s2;
+        M20 = r20 * s0; M21 = r21 * s1; M22 = r22 * s2;
+        // value path: activated opacity (hardware exp is fine here)
+        op = 1.0f / (1.0f + __expf(-logit));
+    }
+
+    for (int v = 0; v < n_views; ++v) {
+        const gs_view& vw = views[v];
+        const size_t o = (size_t)v * n + i;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint2 rc = make_uint2(0xffffffffu, 0xffffffffu);
+        int32_t cnt = 0;
+        const float* R = vw.Rt;  // row-major [R|t]: R[0..2] t at [3], [7], [11]
+        const float p0 = ((R[0] * m0 + R[1] * m1) + R[2] * m2) + R[3];
+        const float p1 = ((R[4] * m0 + R[5] * m1) + R[6] * m2) + R[7];
+        const float p2 = ((R[8] * m0 + R[9] * m1) + R[10] * m2) + R[11];
+        bool vis = alive && (p2 > c.z_near);
+        const float xn = p0 / p2, yn = p1 / p2;
+        const float limx = (c.guard * (0.5f * (float)vw.width)) / vw.fx;
+        const float limy = (c.guard * (0.5f * (float)vw.height)) / vw.fy;
+        vis = vis && (fabsf(xn) <= limx) && (fabsf(yn) <= limy);
         if (vis) {
-            const float rx = sqrtf(c.kbox * a) * 0x1.004p+0f;
-            const float ry = sqrtf(c.kbox * cc) * 0x1.004p+0f;
-            // tile rectangle (inclusive); tile is a power of two so the scale is exact
-            const float inv = 1.0f / (float)c.tile;
-            const int tx = ceil_div(vw.width, c.tile), ty = ceil_div(vw.height, c.tile);
-            float fx0 = floorf((mx - rx) * inv), fx1 = floorf((mx + rx) * inv);
-            float fy0 = floorf((my - ry) * inv), fy1 = floorf((my + ry) * inv);
-            vis = (fx1 >= 0.0f) && (fx0 <= (float)(tx - 1)) && (fy1 >= 0.0f) && (fy0 <= (float)(ty - 1));
+            const float mx = vw.fx * xn + vw.cx;
+            const float my = vw.fy * yn + vw.cy;
+            // EWA (Eq. 3): J = d(pi)/dp, T = J R_CW, U = T M, Sigma2D = U U^T + b I
+            const float j00 = vw.fx / p2, j11 = vw.fy / p2;
+            const float j02 = -(j00 * xn), j12 = -(j11 * yn);
+            const float T00 = j00 * R[0] + j02 * R[8];
+            const float T01 = j00 * R[1] + j02 * R[9];
+            const float T02 = j00 * R[2] + j02 * R[10];
+            const float T10 = j11 * R[4] + j12 * R[8];
+            const float T11 = j11 * R[5] + j12 * R[9];
+            const float T12 = j11 * R[6] + j12 * R[10];
+            const float U00 = (T00 * M00 + T01 * M10) + T02 * M20;
+            const float U01 = (T00 * M01 + T01 * M11) + T02 * M21;
+            const float U02 = (T00 * M02 + T01 * M12) + T02 * M22;
+            const float U10 = (T10 * M00 + T11 * M10) + T12 * M20;
+            const float U11 = (T10 * M01 + T11 * M11) + T12 * M21;
+            const float U12 = (T10 * M02 + T11 * M12) + T12 * M22;
+            const float a = ((U00 * U00 + U01 * U01) + U02 * U02) + c.blur;
+            const float b = (U00 * U10 + U01 * U11) + U02 * U12;
+            const float cc = ((U10 * U10 + U11 * U11) + U12 * U12) + c.blur;
+            const float det = a * cc - b * b;
+            vis = (det > 0.0f) && (det < INFINITY);
             if (vis) {
-                fx0 = fx0 < 0.0f ? 0.0f : fx0;
-                fy0 = fy0 < 0.0f ? 0.0f : fy0;
-                fx1 = fx1 > (float)(tx - 1) ? (float)(tx - 1) : fx1;
-                fy1 = fy1 > (float)(ty - 1) ? (float)(ty - 1) : fy1;
-                const int ix0 = (int)fx0, iy0 = (int)fy0, ix1 = (int)fx1, iy1 = (int)fy1;
-                cnt = (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
-                rc = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
-                // value path: activated opacity (hardware exp is fine here)
-                const float op = 1.0f / (1.0f + __expf(-logit));
-                r0 = make_float4(mx, my, cc / det, -b / det);
-                r1 = make_float4(a / det, op, p2, pack_radii(rx, ry));
+                const float rx = sqrtf(c.kbox * a) * 0x1.004p+0f;
+                const float ry = sqrtf(c.kbox * cc) * 0x1.004p+0f;
+                // tile rectangle (inclusive); tile is a power of two so the scale is exact
+                const float inv = 1.0f / (float)c.tile;
+                const int tx = ceil_div(vw.width, c.tile), ty = ceil_div(vw.height, c.tile);
+                float fx0 = floorf((mx - rx) * inv), fx1 = floorf((mx + rx) * inv);
+                float fy0 = floorf((my - ry) * inv), fy1 = floorf((my + ry) * inv);
+                vis = (fx1 >= 0.0f) && (fx0 <= (float)(tx - 1)) && (fy1 >= 0.0f) && (fy0 <= (float)(ty - 1));
+                if (vis) {
+                    fx0 = fx0 < 0.0f ? 0.0f : fx0;
+                    fy0 = fy0 < 0.0f ? 0.0f : fy0;
+                    fx1 = fx1 > (float)(tx - 1) ? (float)(tx - 1) : fx1;
+                    fy1 = fy1 > (float)(ty - 1) ? (float)(ty - 1) : fy1;
+                    const int ix0 = (int)fx0, iy0 = (int)fy0, ix1 = (int)fx1, iy1 = (int)fy1;
+                    cnt = (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
+                    rc = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
+                    r0 = make_float4(mx, my, cc / det, -b / det);
+                    r1 = make_float4(a / det, op, p2, pack_radii(rx, ry));
+                }
             }
         }
+        rec[2 * o] = r0;
+        rec[2 * o + 1] = r1;
+        rect[o] = rc;
+        touched[o] = cnt;
     }
-    rec[2 * o] = r0;
-    rec[2 * o + 1] = r1;
-    rect[o] = rc;
-    touched[o] = cnt;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
@@ -166,9 +172,8 @@ hipError_t launch_project(const GaussPtrs& g, const gs_view* views_dev, int n_vi
                           float* rec, uint32_t* rect, int32_t* touched, float* app, int app_stride_,
                           hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    dim3 grid((unsigned)ceil_div(g.n, 256), (unsigned)n_views);
-    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, g, views_dev, c, reinterpret_cast<float4*>(rec),
-                       reinterpret_cast<uint2*>(rect), touched, app, app_stride_);
+    hipLaunchKernelGGL(k_project, dim3((unsigned)ceil_div(g.n, 256)), dim3(256), 0, s, g, views_dev, n_views, c,
+                       reinterpret_cast<float4*>(rec), reinterpret_cast<uint2*>(rect), touched, app, app_stride_);
     return hipGetLastError();
 }
 

@@ -41,6 +41,24 @@ __device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, 
     return unclamped ? a : amax;
 }
 
+// Value of `x` held by lane (lane ^ D) of the wavefront.  D = 1, 2: DPP
+// quad permutation (a VALU operand modifier, no LDS traffic); D = 4 .. 16:
+// ds_swizzle in xor mode (within 32-lane halves); D = 32: ds_bpermute.
+template <int D>
+__device__ __forceinline__ float xor_lane(float x) {
+    const int v = __float_as_int(x);
+    if constexpr (D == 1) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+    } else if constexpr (D == 2) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+    } else if constexpr (D < 32) {
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(v, (D << 10) | 0x1F));  // xor_mask D, and_mask 31
+    } else {
+        const int lane = __lane_id();
+        return __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ D) << 2, v));
+    }
+}
+
 // Conservative wavefront-level test: can the Gaussian reach any pixel centre
 // of the 8x8 block whose first centre is (x0, y0)?  Only prunes; a Gaussian
 // outside its box has alpha < alpha_min at every pixel centre.

@@ -14,11 +14,16 @@
 // wavefront are summed with a transposing butterfly (each exchange halves
 // the values a lane keeps, so after log2 steps every lane holds a different
 // total); one LDS atomic instruction per wavefront and Gaussian adds them to
-// the batch's per-Gaussian accumulator, and after the batch the workgroup
-// flushes each touched Gaussian once with global atomics.  (Flushing every
-// wavefront straight to global memory made the four wavefronts of a tile
-// hit the same cache lines at the same time and serialised in L2.)
+// the batch's per-instance accumulator (the four wavefronts of the tile).
 // Wavefronts with no contributing pixel skip the reduction.
+//
+// No global atomics: every (view, tile, Gaussian) instance belongs to exactly
+// one tile, so after each batch the workgroup writes the instance's totals as
+// one contiguous record at its emission index.  The instances of a (view,
+// Gaussian) pair are contiguous in emission order, so k_reduce_records then
+// sums each pair's records in a fixed order: the gradients are
+// deterministic, and the scattered read-modify-write traffic of atomics
+// (which dominated this kernel) is replaced by streaming writes and reads.
 #include "raster_common.h"
 
 namespace sgs {
@@ -41,11 +46,11 @@ struct BflyStep {
                 for (int k = 0; k < HALF; ++k) {
                     const float send = up ? v[k] : v[k + HALF];
                     const float keep = up ? v[k + HALF] : v[k];
-                    v[k] = keep + __shfl_xor(send, D, kWave);
+                    v[k] = keep + xor_lane<D>(send);
                 }
                 BflyStep<NV, HALF, 2 * D>::run(v, lane);
             } else {
-                v[0] += __shfl_xor(v[0], D, kWave);
+                v[0] += xor_lane<D>(v[0]);
                 BflyStep<NV, 1, 2 * D>::run(v, lane);
             }
         }
@@ -87,18 +92,18 @@ struct Pow2<1> {
 
 template <int TS, int F, int B, bool PARAMS>
 __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, const float4* __restrict__ app, int n,
-                                         const int32_t* __restrict__ gids, const int2* __restrict__ ranges,
-                                         const gs_view* __restrict__ views, int n_views, int64_t P,
-                                         const RasterConst& c, const float* __restrict__ T_final,
-                                         const int32_t* __restrict__ last, const float* __restrict__ grad_out,
-                                         float* __restrict__ grad_geo, float* __restrict__ grad_app, float4* s_g0,
-                                         float4* s_g1, float4* s_app, int* s_max, float* s_acc, int* s_used) {
+                                         const int32_t* __restrict__ inst, const int32_t* __restrict__ inst_gid,
+                                         const int2* __restrict__ ranges, const gs_view* __restrict__ views,
+                                         int n_views, int64_t P, const RasterConst& c,
+                                         const float* __restrict__ T_final, const int32_t* __restrict__ last,
+                                         const float* __restrict__ grad_out, float* __restrict__ records,
+                                         float4* s_g0, float4* s_g1, float4* s_app, int* s_max, float* s_acc) {
     constexpr int NT = TS * TS;
     constexpr int AV = AppRec<F>::vec;
     constexpr int NREAL = PARAMS ? 10 + F : 6;
     constexpr int NV = Pow2<NREAL>::value;
-    constexpr int GA = 4 + F;  // per-Gaussian appearance gradient record
-    constexpr int AST = NREAL + 1;  // accumulator stride (odd: spreads LDS banks)
+    constexpr int RS = (NREAL + 3) / 4 * 4;  // record stride (floats), float4-aligned
+    constexpr int AST = NREAL + 1;           // accumulator stride (odd: spreads LDS banks)
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     constexpr int WPR = TS / 8;
     const int sbx = (wave % WPR) * 8, sby = (wave / WPR) * 8;
@@ -131,6 +136,14 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     __syncthreads();
     const int end = rg.x + *s_max;
 
+    // instances past every pixel's last contributor: zero records
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = end + tid; k < rg.y; k += NT) {
+        float4* r4 = reinterpret_cast<float4*>(records + (size_t)inst[k] * RS);
+#pragma unroll
+        for (int q = 0; q < RS / 4; ++q) r4[q] = z4;
+    }
+
     // per-slot scale: dmx, dmy <- -ln2; dA, dC <- -1/2; dB <- -1; others 1
     const int my_slot = Butterfly<NV>::slot(lane);
     const bool writer = (lane >> Butterfly<NV>::lanes_log2()) == 0 && my_slot < NREAL;
@@ -144,14 +157,13 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
         const int nb = bend - bstart;
         __syncthreads();
         for (int k = tid; k < nb; k += NT) {
-            const int gid = gids[bstart + k];
+            const int gid = inst_gid[inst[bstart + k]];
             float4 a0, a1;
             stage_geometry(rec, vbase + gid, a0, a1);
             s_g0[k] = a0;
             s_g1[k] = a1;
 #pragma unroll
             for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
-            s_used[k] = 0;
         }
         for (int k = tid; k < nb * AST; k += NT) s_acc[k] = 0.0f;
         __syncthreads();
@@ -200,20 +212,17 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             }
             const float tot = Butterfly<NV>::reduce(val, lane);
             if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
-            if (lane == 0) s_used[j] = 1;
         }
         __syncthreads();
-        // flush: one global atomic per value and touched Gaussian of the batch
+        // one contiguous record per instance of the batch (zeros if untouched)
         for (int k = tid; k < nb; k += NT) {
-            if (!s_used[k]) continue;
-            const int gid = gids[bstart + k];
-            float* gg = grad_geo + (vbase + gid) * 8;
+            float4* r4 = reinterpret_cast<float4*>(records + (size_t)inst[bstart + k] * RS);
+            const float* a = s_acc + k * AST;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) atomicAdd(&gg[q], s_acc[k * AST + q]);
-            if (PARAMS) {
-                float* ga = grad_app + (size_t)gid * GA;
-#pragma unroll
-                for (int q = 0; q < 4 + F; ++q) atomicAdd(&ga[q], s_acc[k * AST + 6 + q]);
+            for (int q = 0; q < RS / 4; ++q) {
+                const int b = 4 * q;
+                r4[q] = make_float4(b < NREAL ? a[b] : 0.f, b + 1 < NREAL ? a[b + 1] : 0.f,
+                                    b + 2 < NREAL ? a[b + 2] : 0.f, b + 3 < NREAL ? a[b + 3] : 0.f);
             }
         }
     }
@@ -221,27 +230,26 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 
 template <int TS, int F, int B, bool PARAMS>
 __global__ void __launch_bounds__(TS* TS) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
-                                                       int n, const int32_t* __restrict__ gids,
+                                                       int n, const int32_t* __restrict__ inst,
+                                                       const int32_t* __restrict__ inst_gid,
                                                        const int2* __restrict__ ranges,
                                                        const gs_view* __restrict__ views, int n_views,
                                                        int total_tiles, int64_t P, RasterConst c,
                                                        const float* __restrict__ T_final,
                                                        const int32_t* __restrict__ last,
                                                        const float* __restrict__ grad_out,
-                                                       float* __restrict__ grad_geo, float* __restrict__ grad_app,
-                                                       int32_t* queue, int persistent) {
+                                                       float* __restrict__ records, int32_t* queue, int persistent) {
     constexpr int AV = AppRec<F>::vec;
+    constexpr int NREAL = PARAMS ? 10 + F : 6;
     __shared__ float4 s_g0[B];
     __shared__ float4 s_g1[B];
     __shared__ float4 s_app[B * AV];
+    __shared__ float s_acc[B * (NREAL + 1)];
     __shared__ int s_tile;
     __shared__ int s_max;
-    constexpr int NREAL = PARAMS ? 10 + F : 6;
-    __shared__ float s_acc[B * (NREAL + 1)];
-    __shared__ int s_used[B];
     if (!persistent) {
-        bwd_tile<TS, F, B, PARAMS>(blockIdx.x, rec, app, n, gids, ranges, views, n_views, P, c, T_final, last,
-                                   grad_out, grad_geo, grad_app, s_g0, s_g1, s_app, &s_max, s_acc, s_used);
+        bwd_tile<TS, F, B, PARAMS>(blockIdx.x, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, T_final,
+                                   last, grad_out, records, s_g0, s_g1, s_app, &s_max, s_acc);
         return;
     }
     for (;;) {
@@ -250,8 +258,63 @@ __global__ void __launch_bounds__(TS* TS) k_render_bwd(const float4* __restrict_
         __syncthreads();
         const int t = s_tile;
         if (t >= total_tiles) break;
-        bwd_tile<TS, F, B, PARAMS>(t, rec, app, n, gids, ranges, views, n_views, P, c, T_final, last, grad_out,
-                                   grad_geo, grad_app, s_g0, s_g1, s_app, &s_max, s_acc, s_used);
+        bwd_tile<TS, F, B, PARAMS>(t, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, T_final, last,
+                                   grad_out, records, s_g0, s_g1, s_app, &s_max, s_acc);
+    }
+}
+
+// Sum of the records of every (view, Gaussian) pair (contiguous emission
+// indices, fixed order), one thread per Gaussian looping over the views:
+// grad_geo[V][n][8] <- (dmx, dmy, dA, dB, dC, dd, 0, 0), zero where the pair
+// is not visible; grad_app[n][4+F] <- the appearance part summed over views.
+template <int F, bool PARAMS>
+__global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict__ records,
+                                                        const int32_t* __restrict__ pair_first,
+                                                        const int32_t* __restrict__ touched, int n, int n_views,
+                                                        int64_t capacity, float* __restrict__ grad_geo,
+                                                        float* __restrict__ grad_app) {
+    constexpr int NREAL = PARAMS ? 10 + F : 6;
+    constexpr int RS = (NREAL + 3) / 4 * 4;
+    constexpr int NA = PARAMS ? 4 + F : 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float appacc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) appacc[q] = 0.0f;
+    for (int v = 0; v < n_views; ++v) {
+        const size_t pair = (size_t)v * n + i;
+        const int cnt = touched[pair];
+        float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (cnt > 0) {
+            const int64_t first = pair_first[pair];
+            const int64_t stop = first + cnt < capacity ? first + cnt : capacity;  // truncated lists
+            for (int64_t e = first; e < stop; ++e) {
+                const float4* r4 = reinterpret_cast<const float4*>(records + (size_t)e * RS);
+                float r[RS];
+#pragma unroll
+                for (int q = 0; q < RS / 4; ++q) {
+                    const float4 a = r4[q];
+                    r[4 * q] = a.x;
+                    r[4 * q + 1] = a.y;
+                    r[4 * q + 2] = a.z;
+                    r[4 * q + 3] = a.w;
+                }
+#pragma unroll
+                for (int q = 0; q < 6; ++q) geo[q] += r[q];
+                if (PARAMS) {
+#pragma unroll
+                    for (int q = 0; q < NA; ++q) appacc[q] += r[6 + q];
+                }
+            }
+        }
+        float4* gg = reinterpret_cast<float4*>(grad_geo + pair * 8);
+        gg[0] = make_float4(geo[0], geo[1], geo[2], geo[3]);
+        gg[1] = make_float4(geo[4], geo[5], 0.f, 0.f);
+    }
+    if (PARAMS) {
+        float* ga = grad_app + (size_t)i * (4 + F);
+#pragma unroll
+        for (int q = 0; q < NA; ++q) ga[q] = appacc[q];
     }
 }
 
@@ -260,17 +323,17 @@ __global__ void k_reset_queue_bwd(int32_t* q) {
 }
 
 template <int TS, int F, int B, bool PARAMS>
-hipError_t launch_bwd_t(const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
-                        const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
-                        int persistent, const float* T_final, const int32_t* last, const float* grad_out,
-                        float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+hipError_t launch_bwd_t(const float* rec, const float* app, int n, const int32_t* inst, const int32_t* inst_gid,
+                        const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
+                        const RasterConst& c, int persistent, const float* T_final, const int32_t* last,
+                        const float* grad_out, float* records, int32_t* queue, hipStream_t s) {
     auto kern = k_render_bwd<TS, F, B, PARAMS>;
     unsigned grid = (unsigned)total_tiles;
     if (persistent) {
         int dev = 0, cus = 0, per_cu = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TS * TS, 0);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TS * TS, 0);
         if (per_cu < 1) per_cu = 1;
         const unsigned cap = (unsigned)(cus * per_cu);
         grid = cap < grid ? cap : grid;
@@ -278,80 +341,104 @@ hipError_t launch_bwd_t(const float* rec, const float* app, int n, const int32_t
     }
     if (grid == 0) return hipGetLastError();
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TS * TS), 0, s, reinterpret_cast<const float4*>(rec),
-                       reinterpret_cast<const float4*>(app), n, gids, reinterpret_cast<const int2*>(ranges), views,
-                       n_views, total_tiles, P, c, T_final, last, grad_out, grad_geo, grad_app, queue, persistent);
+                       reinterpret_cast<const float4*>(app), n, inst, inst_gid, reinterpret_cast<const int2*>(ranges),
+                       views, n_views, total_tiles, P, c, T_final, last, grad_out, records, queue, persistent);
     return hipGetLastError();
 }
 
 template <int TS, int F, bool PARAMS>
-hipError_t launch_bwd_b(int B, const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
-                        const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
-                        int persistent, const float* T_final, const int32_t* last, const float* grad_out,
-                        float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+hipError_t launch_bwd_b(int B, const float* rec, const float* app, int n, const int32_t* inst, const int32_t* inst_gid,
+                        const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
+                        const RasterConst& c, int persistent, const float* T_final, const int32_t* last,
+                        const float* grad_out, float* records, int32_t* queue, hipStream_t s) {
     switch (B) {
         case 64:
-            return launch_bwd_t<TS, F, 64, PARAMS>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
-                                                   persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+            return launch_bwd_t<TS, F, 64, PARAMS>(rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles,
+                                                   P, c, persistent, T_final, last, grad_out, records, queue, s);
         case 128:
-            return launch_bwd_t<TS, F, 128, PARAMS>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
-                                                    persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+            return launch_bwd_t<TS, F, 128, PARAMS>(rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles,
+                                                    P, c, persistent, T_final, last, grad_out, records, queue, s);
         default:
-            return launch_bwd_t<TS, F, 256, PARAMS>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
-                                                    persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+            return launch_bwd_t<TS, F, 256, PARAMS>(rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles,
+                                                    P, c, persistent, T_final, last, grad_out, records, queue, s);
     }
 }
 
 template <int F, bool PARAMS>
-hipError_t launch_bwd_ts(int TS, int B, const float* rec, const float* app, int n, const int32_t* gids,
-                         const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
-                         const RasterConst& c, int persistent, const float* T_final, const int32_t* last,
-                         const float* grad_out, float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+hipError_t launch_bwd_ts(int TS, int B, const float* rec, const float* app, int n, const int32_t* inst,
+                         const int32_t* inst_gid, const int32_t* ranges, const gs_view* views, int n_views,
+                         int total_tiles, int64_t P, const RasterConst& c, int persistent, const float* T_final,
+                         const int32_t* last, const float* grad_out, float* records, int32_t* queue, hipStream_t s) {
     switch (TS) {
         case 8:
-            return launch_bwd_b<8, F, PARAMS>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
-                                              persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+            return launch_bwd_b<8, F, PARAMS>(B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P,
+                                              c, persistent, T_final, last, grad_out, records, queue, s);
         case 32:
-            return launch_bwd_b<32, F, PARAMS>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
-                                               persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+            return launch_bwd_b<32, F, PARAMS>(B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P,
+                                               c, persistent, T_final, last, grad_out, records, queue, s);
         default:
-            return launch_bwd_b<16, F, PARAMS>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c,
-                                               persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
+            return launch_bwd_b<16, F, PARAMS>(B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P,
+                                               c, persistent, T_final, last, grad_out, records, queue, s);
     }
 }
 
 template <int F>
-hipError_t launch_bwd_f(bool params, int TS, int B, const float* rec, const float* app, int n, const int32_t* gids,
-                        const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
-                        const RasterConst& c, int persistent, const float* T_final, const int32_t* last,
-                        const float* grad_out, float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+hipError_t launch_bwd_f(bool params, int TS, int B, const float* rec, const float* app, int n, const int32_t* inst,
+                        const int32_t* inst_gid, const int32_t* ranges, const gs_view* views, int n_views,
+                        int total_tiles, int64_t P, const RasterConst& c, int persistent, const float* T_final,
+                        const int32_t* last, const float* grad_out, float* records, int32_t* queue, hipStream_t s) {
     if (params)
-        return launch_bwd_ts<F, true>(TS, B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
-                                      T_final, last, grad_out, grad_geo, grad_app, queue, s);
-    return launch_bwd_ts<F, false>(TS, B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
-                                   T_final, last, grad_out, grad_geo, grad_app, queue, s);
+        return launch_bwd_ts<F, true>(TS, B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c,
+                                      persistent, T_final, last, grad_out, records, queue, s);
+    return launch_bwd_ts<F, false>(TS, B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c,
+                                   persistent, T_final, last, grad_out, records, queue, s);
 }
 
-hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
-                             const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
-                             int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
-                             const float* T_final, const int32_t* last, const float* grad_out, bool params,
-                             float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s) {
+int bwd_record_floats(int n_feat, bool params) {
+    const int nreal = params ? 10 + n_feat : 6;
+    return (nreal + 3) / 4 * 4;
+}
+
+hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_feat, const int32_t* inst,
+                             const int32_t* inst_gid, const int32_t* ranges, const gs_view* views_dev, int n_views,
+                             int total_tiles, int64_t total_pixels, const RasterConst& c, int lds_batch,
+                             int persistent, const float* T_final, const int32_t* last, const float* grad_out,
+                             bool params, float* records, int32_t* queue, hipStream_t s) {
     const int TS = c.tile;
+#define SGS_BWD_CASE(FF)                                                                                            \
+    return launch_bwd_f<FF>(params, TS, lds_batch, rec, app, n, inst, inst_gid, ranges, views_dev, n_views,         \
+                            total_tiles, total_pixels, c, persistent, T_final, last, grad_out, records, queue, s)
     switch (n_feat) {
-        case 0:
-            return launch_bwd_f<0>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
-                                   total_pixels, c, persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
-        case 8:
-            return launch_bwd_f<8>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
-                                   total_pixels, c, persistent, T_final, last, grad_out, grad_geo, grad_app, queue, s);
-        case 32:
-            return launch_bwd_f<32>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views,
-                                    total_tiles, total_pixels, c, persistent, T_final, last, grad_out, grad_geo,
-                                    grad_app, queue, s);
-        default:
-            return launch_bwd_f<16>(params, TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views,
-                                    total_tiles, total_pixels, c, persistent, T_final, last, grad_out, grad_geo,
-                                    grad_app, queue, s);
+        case 0: SGS_BWD_CASE(0);
+        case 8: SGS_BWD_CASE(8);
+        case 32: SGS_BWD_CASE(32);
+        default: SGS_BWD_CASE(16);
+    }
+#undef SGS_BWD_CASE
+}
+
+template <int F>
+hipError_t launch_reduce_t(bool params, const float* records, const int32_t* pair_first, const int32_t* touched,
+                           int n, int n_views, int64_t capacity, float* grad_geo, float* grad_app, hipStream_t s) {
+    const dim3 grid((unsigned)ceil_div(n, 256));
+    if (params)
+        hipLaunchKernelGGL((k_reduce_records<F, true>), grid, dim3(256), 0, s, records, pair_first, touched, n, n_views,
+                           capacity, grad_geo, grad_app);
+    else
+        hipLaunchKernelGGL((k_reduce_records<F, false>), grid, dim3(256), 0, s, records, pair_first, touched, n,
+                           n_views, capacity, grad_geo, grad_app);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_records(const float* records, const int32_t* pair_first, const int32_t* touched, int n,
+                                 int n_feat, int n_views, int64_t capacity, bool params, float* grad_geo,
+                                 float* grad_app, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    switch (n_feat) {
+        case 0: return launch_reduce_t<0>(params, records, pair_first, touched, n, n_views, capacity, grad_geo, grad_app, s);
+        case 8: return launch_reduce_t<8>(params, records, pair_first, touched, n, n_views, capacity, grad_geo, grad_app, s);
+        case 32: return launch_reduce_t<32>(params, records, pair_first, touched, n, n_views, capacity, grad_geo, grad_app, s);
+        default: return launch_reduce_t<16>(params, records, pair_first, touched, n, n_views, capacity, grad_geo, grad_app, s);
     }
 }
 

@@ -23,7 +23,8 @@ namespace sgs {
 
 template <int TS, int F, int B>
 __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, const float4* __restrict__ app, int n,
-                                         const int32_t* __restrict__ gids, const int2* __restrict__ ranges,
+                                         const int32_t* __restrict__ inst, const int32_t* __restrict__ inst_gid,
+                                         const int2* __restrict__ ranges,
                                          const gs_view* __restrict__ views, int n_views, int64_t P,
                                          const RasterConst& c, float* __restrict__ out, float* __restrict__ T_final,
                                          int32_t* __restrict__ last, float4* s_g0, float4* s_g1, float4* s_app) {
@@ -58,7 +59,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
         if (__syncthreads_and(done)) break;
         const int nb = min(B, rg.y - b0);
         for (int k = tid; k < nb; k += NT) {
-            const int gid = gids[b0 + k];
+            const int gid = inst_gid[inst[b0 + k]];
             float4 a0, a1;
             stage_geometry(rec, vbase + gid, a0, a1);
             s_g0[k] = a0;
@@ -114,7 +115,8 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
 
 template <int TS, int F, int B>
 __global__ void __launch_bounds__(TS* TS) k_render_fwd(const float4* __restrict__ rec, const float4* __restrict__ app,
-                                                       int n, const int32_t* __restrict__ gids,
+                                                       int n, const int32_t* __restrict__ inst,
+                                                       const int32_t* __restrict__ inst_gid,
                                                        const int2* __restrict__ ranges,
                                                        const gs_view* __restrict__ views, int n_views,
                                                        int total_tiles, int64_t P, RasterConst c,
@@ -126,7 +128,7 @@ __global__ void __launch_bounds__(TS* TS) k_render_fwd(const float4* __restrict_
     __shared__ float4 s_app[B * AV];
     __shared__ int s_tile;
     if (!persistent) {
-        fwd_tile<TS, F, B>(blockIdx.x, rec, app, n, gids, ranges, views, n_views, P, c, out, T_final, last, s_g0,
+        fwd_tile<TS, F, B>(blockIdx.x, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, out, T_final, last, s_g0,
                            s_g1, s_app);
         return;
     }
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(TS* TS) k_render_fwd(const float4* __restrict_
         __syncthreads();
         const int t = s_tile;
         if (t >= total_tiles) break;
-        fwd_tile<TS, F, B>(t, rec, app, n, gids, ranges, views, n_views, P, c, out, T_final, last, s_g0, s_g1,
+        fwd_tile<TS, F, B>(t, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, out, T_final, last, s_g0, s_g1,
                            s_app);
     }
 }
@@ -146,7 +148,8 @@ __global__ void k_reset_queue(int32_t* q) {
 }
 
 template <int TS, int F, int B>
-hipError_t launch_fwd_t(const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
+hipError_t launch_fwd_t(const float* rec, const float* app, int n, const int32_t* inst, const int32_t* inst_gid,
+                        const int32_t* ranges,
                         const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
                         int persistent, float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s) {
     auto kern = k_render_fwd<TS, F, B>;
@@ -163,63 +166,64 @@ hipError_t launch_fwd_t(const float* rec, const float* app, int n, const int32_t
     }
     if (grid == 0) return hipGetLastError();
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TS * TS), 0, s, reinterpret_cast<const float4*>(rec),
-                       reinterpret_cast<const float4*>(app), n, gids, reinterpret_cast<const int2*>(ranges), views,
+                       reinterpret_cast<const float4*>(app), n, inst, inst_gid, reinterpret_cast<const int2*>(ranges), views,
                        n_views, total_tiles, P, c, out, T_final, last, queue, persistent);
     return hipGetLastError();
 }
 
 template <int TS, int F>
-hipError_t launch_fwd_b(int B, const float* rec, const float* app, int n, const int32_t* gids, const int32_t* ranges,
+hipError_t launch_fwd_b(int B, const float* rec, const float* app, int n, const int32_t* inst, const int32_t* inst_gid,
+                        const int32_t* ranges,
                         const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
                         int persistent, float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s) {
     switch (B) {
         case 64:
-            return launch_fwd_t<TS, F, 64>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+            return launch_fwd_t<TS, F, 64>(rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c, persistent,
                                            out, T_final, last, queue, s);
         case 128:
-            return launch_fwd_t<TS, F, 128>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+            return launch_fwd_t<TS, F, 128>(rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c, persistent,
                                             out, T_final, last, queue, s);
         default:
-            return launch_fwd_t<TS, F, 256>(rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+            return launch_fwd_t<TS, F, 256>(rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c, persistent,
                                             out, T_final, last, queue, s);
     }
 }
 
 template <int F>
-hipError_t launch_fwd_f(int TS, int B, const float* rec, const float* app, int n, const int32_t* gids,
-                        const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
+hipError_t launch_fwd_f(int TS, int B, const float* rec, const float* app, int n, const int32_t* inst,
+                        const int32_t* inst_gid, const int32_t* ranges, const gs_view* views, int n_views, int total_tiles, int64_t P,
                         const RasterConst& c, int persistent, float* out, float* T_final, int32_t* last,
                         int32_t* queue, hipStream_t s) {
     switch (TS) {
         case 8:
-            return launch_fwd_b<8, F>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+            return launch_fwd_b<8, F>(B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c, persistent,
                                       out, T_final, last, queue, s);
         case 32:
-            return launch_fwd_b<32, F>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+            return launch_fwd_b<32, F>(B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c, persistent,
                                        out, T_final, last, queue, s);
         default:
-            return launch_fwd_b<16, F>(B, rec, app, n, gids, ranges, views, n_views, total_tiles, P, c, persistent,
+            return launch_fwd_b<16, F>(B, rec, app, n, inst, inst_gid, ranges, views, n_views, total_tiles, P, c, persistent,
                                        out, T_final, last, queue, s);
     }
 }
 
-hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
-                             const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
+hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_feat, const int32_t* inst,
+                             const int32_t* inst_gid, const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
                              int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent, float* out,
                              float* T_final, int32_t* last, int32_t* queue, hipStream_t s) {
     const int TS = c.tile;
     switch (n_feat) {
         case 0:
-            return launch_fwd_f<0>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+            return launch_fwd_f<0>(TS, lds_batch, rec, app, n, inst, inst_gid, ranges, views_dev, n_views, total_tiles,
                                    total_pixels, c, persistent, out, T_final, last, queue, s);
         case 8:
-            return launch_fwd_f<8>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+            return launch_fwd_f<8>(TS, lds_batch, rec, app, n, inst, inst_gid, ranges, views_dev, n_views, total_tiles,
                                    total_pixels, c, persistent, out, T_final, last, queue, s);
         case 32:
-            return launch_fwd_f<32>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+            return launch_fwd_f<32>(TS, lds_batch, rec, app, n, inst, inst_gid, ranges, views_dev, n_views, total_tiles,
                                     total_pixels, c, persistent, out, T_final, last, queue, s);
         default:
-            return launch_fwd_f<16>(TS, lds_batch, rec, app, n, gids, ranges, views_dev, n_views, total_tiles,
+            return launch_fwd_f<16>(TS, lds_batch, rec, app, n, inst, inst_gid, ranges, views_dev, n_views, total_tiles,
                                     total_pixels, c, persistent, out, T_final, last, queue, s);
     }
 }

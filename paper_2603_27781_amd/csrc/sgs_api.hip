@@ -159,38 +159,38 @@ int gs_bin_sort_workspace(int32_t n, int32_t n_views, int64_t capacity, size_t* 
 
 int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float* rec, int32_t n,
                 const gs_view* views, const gs_view* views_dev, int32_t n_views, const gs_config* cfg, void* ws,
-                size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* gids, int32_t* tile_ranges,
-                int64_t* counts, gs_stream stream) {
+                size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* inst, int32_t* inst_gid,
+                int32_t* pair_first, int32_t* tile_ranges, int64_t* counts, gs_stream stream) {
     int st = check_config(cfg);
     if (st) return st;
     int total_tiles = 0;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, &total_tiles))) return st;
-    if (!rect || !tiles_touched || !rec || !ws || !tile_ranges || !counts) return GS_EINVAL;
-    if (capacity > 0 && (!tile_keys || !gids)) return GS_EINVAL;
+    if (!rect || !tiles_touched || !rec || !ws || !tile_ranges || !counts || !pair_first) return GS_EINVAL;
+    if (capacity > 0 && (!tile_keys || !inst || !inst_gid)) return GS_EINVAL;
     if (n < 1 || capacity < 0 || capacity >= (1ll << 31) || (int64_t)n * n_views >= (1ll << 31)) return GS_EINVAL;
     if (ws_bytes < binsort_workspace_bytes(n, n_views, capacity)) return GS_ECAPACITY;
     if (!aligned16(rec) || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return GS_EINVAL;
     return hip_status(launch_binsort(rect, tiles_touched, rec, n, views_dev, n_views, total_tiles, cfg->tile, ws,
-                                     capacity, tile_keys, gids, tile_ranges, counts,
+                                     capacity, tile_keys, inst, inst_gid, pair_first, tile_ranges, counts,
                                      reinterpret_cast<hipStream_t>(stream)));
 }
 
-int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* gids,
-                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev, int32_t n_views,
-                  const gs_config* cfg, float* out, float* T_final, int32_t* last, int32_t* queue,
-                  gs_stream stream) {
+int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* inst,
+                  const int32_t* inst_gid, const int32_t* tile_ranges, const gs_view* views,
+                  const gs_view* views_dev, int32_t n_views, const gs_config* cfg, float* out, float* T_final,
+                  int32_t* last, int32_t* queue, gs_stream stream) {
     int st = check_config(cfg);
     if (st) return st;
     int64_t P = 0;
     int total_tiles = 0;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, &P, &total_tiles))) return st;
     if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
-    if (n < 1 || !rec || !app || !gids || !tile_ranges || !out || !T_final || !last) return GS_EINVAL;
+    if (n < 1 || !rec || !app || !inst || !inst_gid || !tile_ranges || !out || !T_final || !last) return GS_EINVAL;
     if (cfg->persistent && !queue) return GS_EINVAL;
     if (!aligned16(rec) || !aligned16(app)) return GS_EINVAL;
-    return hip_status(launch_render_fwd(rec, app, n, n_feat, gids, tile_ranges, views_dev, n_views, total_tiles, P,
-                                        make_const(cfg), cfg->lds_batch, cfg->persistent, out, T_final, last, queue,
-                                        reinterpret_cast<hipStream_t>(stream)));
+    return hip_status(launch_render_fwd(rec, app, n, n_feat, inst, inst_gid, tile_ranges, views_dev, n_views,
+                                        total_tiles, P, make_const(cfg), cfg->lds_batch, cfg->persistent, out,
+                                        T_final, last, queue, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_loss_grad_workspace(int64_t total_pixels, size_t* bytes) {
@@ -217,35 +217,52 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
                                   reinterpret_cast<hipStream_t>(stream)));
 }
 
-int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, size_t* bytes) {
-    if (!bytes || n < 1 || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags,
+                            size_t* grad2d_bytes_out, size_t* ws_bytes) {
+    if (!grad2d_bytes_out || !ws_bytes || n < 1 || n_views < 1 || n_views > GS_MAX_VIEWS || capacity < 0)
+        return GS_EINVAL;
     if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
-    *bytes = grad2d_bytes(n, n_feat, n_views);
+    *grad2d_bytes_out = grad2d_bytes(n, n_feat, n_views);
+    *ws_bytes = (size_t)(capacity > 0 ? capacity : 1) * bwd_record_floats(n_feat, (flags & GS_GRAD_PARAMS) != 0) *
+                sizeof(float);
     return GS_OK;
 }
 
-int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* gids,
+int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* inst,
+                  const int32_t* inst_gid, const int32_t* pair_first, const int32_t* tiles_touched, int64_t capacity,
                   const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev, int32_t n_views,
                   const gs_config* cfg, const float* T_final, const int32_t* last, const float* grad_out,
-                  uint32_t flags, float* grad2d, size_t grad2d_bytes_, int32_t* queue, gs_stream stream) {
+                  uint32_t flags, float* grad2d, size_t grad2d_bytes_, void* ws, size_t ws_bytes, int32_t* queue,
+                  gs_stream stream) {
     const bool params = (flags & GS_GRAD_PARAMS) != 0;
-    int st = check_gauss(g, false);
+    if (!g) return GS_EINVAL;
+    if (g->n < 1) return GS_EINVAL;
+    if (!feat_supported(g->n_feat)) return GS_EUNSUPPORTED;
+    int st = check_config(cfg);
     if (st) return st;
-    if ((st = check_config(cfg))) return st;
     int64_t P = 0;
     int total_tiles = 0;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, &P, &total_tiles))) return st;
     if ((flags & ~(uint32_t)(GS_GRAD_PARAMS | GS_GRAD_POSE)) != 0 || flags == 0) return GS_EINVAL;
-    if (!rec || !app || !gids || !tile_ranges || !T_final || !last || !grad_out || !grad2d) return GS_EINVAL;
+    if (!rec || !app || !inst || !inst_gid || !pair_first || !tiles_touched || !tile_ranges || !T_final || !last ||
+        !grad_out || !grad2d || !ws)
+        return GS_EINVAL;
+    if (capacity < 0 || capacity >= (1ll << 31)) return GS_EINVAL;
     if (cfg->persistent && !queue) return GS_EINVAL;
     if (grad2d_bytes_ < grad2d_bytes(g->n, g->n_feat, n_views)) return GS_ECAPACITY;
-    if (!aligned16(rec) || !aligned16(app) || !aligned16(grad2d)) return GS_EINVAL;
+    const size_t rec_bytes = (size_t)(capacity > 0 ? capacity : 1) * bwd_record_floats(g->n_feat, params) * sizeof(float);
+    if (ws_bytes < rec_bytes) return GS_ECAPACITY;
+    if (!aligned16(rec) || !aligned16(app) || !aligned16(grad2d) || !aligned16(ws)) return GS_EINVAL;
     float* geo = grad2d;
     float* appg = grad2d + (size_t)n_views * g->n * 8;
-    return hip_status(launch_render_bwd(rec, app, g->n, g->n_feat, gids, tile_ranges, views_dev, n_views,
-                                        total_tiles, P, make_const(cfg), cfg->lds_batch, cfg->persistent, T_final,
-                                        last, grad_out, params, geo, appg, queue,
-                                        reinterpret_cast<hipStream_t>(stream)));
+    float* records = static_cast<float*>(ws);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_render_bwd(rec, app, g->n, g->n_feat, inst, inst_gid, tile_ranges, views_dev, n_views,
+                                     total_tiles, P, make_const(cfg), cfg->lds_batch, cfg->persistent, T_final, last,
+                                     grad_out, params, records, queue, s);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(launch_reduce_records(records, pair_first, tiles_touched, g->n, g->n_feat, n_views, capacity,
+                                            params, geo, appg, s));
 }
 
 int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,

@@ -79,10 +79,11 @@ hipError_t launch_project(const GaussPtrs& g, const gs_view* views_dev, int n_vi
 size_t binsort_workspace_bytes(int n, int n_views, int64_t capacity);
 hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const float* rec, int n,
                           const gs_view* views_dev, int n_views, int total_tiles, int tile, void* ws,
-                          int64_t capacity, uint32_t* tile_keys, int32_t* gids, int32_t* ranges,
-                          int64_t* counts, hipStream_t s);
+                          int64_t capacity, uint32_t* tile_keys, int32_t* inst, int32_t* inst_gid,
+                          int32_t* pair_first, int32_t* ranges, int64_t* counts, hipStream_t s);
 
-hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
+hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_feat, const int32_t* inst,
+                             const int32_t* inst_gid,
                              const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
                              int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
                              float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s);
@@ -93,11 +94,15 @@ hipError_t launch_loss(const float* out, int n_feat, const float* rgb_t, const f
                        const gs_view* views_dev, int n_views, int64_t total_pixels, float* grad_out,
                        double* loss, void* ws, hipStream_t s);
 
-hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_feat, const int32_t* gids,
-                             const int32_t* ranges, const gs_view* views_dev, int n_views, int total_tiles,
-                             int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
-                             const float* T_final, const int32_t* last, const float* grad_out, bool params,
-                             float* grad_geo, float* grad_app, int32_t* queue, hipStream_t s);
+int bwd_record_floats(int n_feat, bool params);
+hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_feat, const int32_t* inst,
+                             const int32_t* inst_gid, const int32_t* ranges, const gs_view* views_dev, int n_views,
+                             int total_tiles, int64_t total_pixels, const RasterConst& c, int lds_batch,
+                             int persistent, const float* T_final, const int32_t* last, const float* grad_out,
+                             bool params, float* records, int32_t* queue, hipStream_t s);
+hipError_t launch_reduce_records(const float* records, const int32_t* pair_first, const int32_t* touched, int n,
+                                 int n_feat, int n_views, int64_t capacity, bool params, float* grad_geo,
+                                 float* grad_app, hipStream_t s);
 
 hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
                               const float* grad_geo, const float* grad_app, const GradPtrs& out,

@@ -140,9 +140,11 @@ class Rasterizer:
         self.T_final = torch.empty(P, dtype=torch.float32, **dev)
         self.last = torch.empty(P, dtype=torch.int32, **dev)
         self.queue = torch.zeros(8, dtype=torch.int32, **dev)
-        b = ctypes.c_size_t(0)
-        check(L.gs_render_bwd_workspace(n, n_feat, V, ctypes.byref(b)), "gs_render_bwd_workspace")
+        b, b2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(L.gs_render_bwd_workspace(n, n_feat, V, 1, _lib.GS_GRAD_PARAMS, ctypes.byref(b), ctypes.byref(b2)),
+              "gs_render_bwd_workspace")
         self.grad2d = torch.empty(b.value // 4, dtype=torch.float32, **dev)
+        self.pair_first = torch.empty(V * n, dtype=torch.int32, **dev)
         check(L.gs_pose_grad_workspace(n, V, ctypes.byref(b)), "gs_pose_grad_workspace")
         self.pose_ws = torch.empty(max(b.value, 16) // 8 + 1, dtype=torch.float64, **dev)
         self.twist = torch.zeros(V, 6, dtype=torch.float32, **dev)
@@ -164,8 +166,17 @@ class Rasterizer:
         off = (-self.ws.data_ptr()) % 256
         self.ws_view = self.ws[off:off + b.value]
         self.keys = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
-        self.gids = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+        self.inst = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+        self.inst_gid = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+        g2, rb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(self.L.gs_render_bwd_workspace(self.n, self.F, self.views.n, capacity, _lib.GS_GRAD_PARAMS,
+                                             ctypes.byref(g2), ctypes.byref(rb)), "gs_render_bwd_workspace")
+        self.records = torch.empty(rb.value // 4, dtype=torch.float32, device=self.device)
         self.capacity = capacity
+
+    def sorted_gids(self, count: int) -> torch.Tensor:
+        """Gaussian index of each of the first `count` sorted instances."""
+        return self.inst_gid[self.inst[:count].long()]
 
     def instance_counts(self):
         """(instances, visible pairs, overflow) -- synchronises."""
@@ -196,12 +207,12 @@ class Rasterizer:
         check(self.L.gs_bin_sort(self.rect.data_ptr(), self.touched.data_ptr(), self.rec.data_ptr(), self.n,
                                  self.views.host, self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc),
                                  self.ws_view.data_ptr(), self.ws_view.numel(), self.capacity, self.keys.data_ptr(),
-                                 self.gids.data_ptr(), self.ranges.data_ptr(), self.counts.data_ptr(), _stream()),
-              "gs_bin_sort")
+                                 self.inst.data_ptr(), self.inst_gid.data_ptr(), self.pair_first.data_ptr(),
+                                 self.ranges.data_ptr(), self.counts.data_ptr(), _stream()), "gs_bin_sort")
 
     def render_fwd(self) -> None:
-        check(self.L.gs_render_fwd(self.rec.data_ptr(), self.app.data_ptr(), self.n, self.F, self.gids.data_ptr(),
-                                   self.ranges.data_ptr(), self.views.host, self.views.dev_ptr(), self.views.n,
+        check(self.L.gs_render_fwd(self.rec.data_ptr(), self.app.data_ptr(), self.n, self.F, self.inst.data_ptr(),
+                                   self.inst_gid.data_ptr(), self.ranges.data_ptr(), self.views.host, self.views.dev_ptr(), self.views.n,
                                    ctypes.byref(self.cc), self.out.data_ptr(), self.T_final.data_ptr(),
                                    self.last.data_ptr(), self.queue.data_ptr(), _stream()), "gs_render_fwd")
 
@@ -227,20 +238,20 @@ class Rasterizer:
         return self.grad_out
 
     def render_bwd(self, g: Gaussians, grad_out: torch.Tensor, flags: int, grads: Optional[Gaussians]) -> None:
-        """Backward of the compositing into the 2D gradient buffer (zeroed
-        here) and, with GS_GRAD_PARAMS, of the projection into `grads` (+=)."""
-        self.grad2d.zero_()
+        """Backward of the compositing into the 2D gradient buffer and, with
+        GS_GRAD_PARAMS, of the projection into `grads` (+=)."""
         self.render_bwd_2d(g, grad_out, flags)
         if flags & _lib.GS_GRAD_PARAMS:
             self.project_bwd(g, grads)
 
     def render_bwd_2d(self, g: Gaussians, grad_out: torch.Tensor, flags: int) -> None:
         check(self.L.gs_render_bwd(ctypes.byref(g.c()), self.rec.data_ptr(), self.app.data_ptr(),
-                                   self.gids.data_ptr(), self.ranges.data_ptr(), self.views.host,
+                                   self.inst.data_ptr(), self.inst_gid.data_ptr(), self.pair_first.data_ptr(),
+                                   self.touched.data_ptr(), self.capacity, self.ranges.data_ptr(), self.views.host,
                                    self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc),
                                    self.T_final.data_ptr(), self.last.data_ptr(), grad_out.data_ptr(), flags,
-                                   self.grad2d.data_ptr(), self.grad2d.numel() * 4, self.queue.data_ptr(),
-                                   _stream()), "gs_render_bwd")
+                                   self.grad2d.data_ptr(), self.grad2d.numel() * 4, self.records.data_ptr(),
+                                   self.records.numel() * 4, self.queue.data_ptr(), _stream()), "gs_render_bwd")
 
     def project_bwd(self, g: Gaussians, grads: Gaussians) -> None:
         gc = _grads_c(grads)

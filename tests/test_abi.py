@@ -53,9 +53,12 @@ def test_default_config_and_layout():
 def test_workspace_queries():
     L = _lib.load()
     b = ctypes.c_size_t()
-    assert L.gs_render_bwd_workspace(1000, 16, 2, ctypes.byref(b)) == 0
-    assert b.value == (2 * 1000 * 8 + 1000 * 20) * 4
-    assert L.gs_render_bwd_workspace(1000, 12, 2, ctypes.byref(b)) == _lib.GS_EUNSUPPORTED
+    b2 = ctypes.c_size_t()
+    assert L.gs_render_bwd_workspace(1000, 16, 2, 5000, 1, ctypes.byref(b), ctypes.byref(b2)) == 0
+    assert b.value == (2 * 1000 * 8 + 1000 * 20) * 4 and b2.value == 5000 * 28 * 4
+    assert L.gs_render_bwd_workspace(1000, 16, 2, 5000, 2, ctypes.byref(b), ctypes.byref(b2)) == 0
+    assert b2.value == 5000 * 8 * 4
+    assert L.gs_render_bwd_workspace(1000, 12, 2, 5000, 1, ctypes.byref(b), ctypes.byref(b2)) == _lib.GS_EUNSUPPORTED
     assert L.gs_bin_sort_workspace(1000, 2, 5000, ctypes.byref(b)) == 0 and b.value > 5 * 2000 * 4
     assert L.gs_bin_sort_workspace(0, 2, 5000, ctypes.byref(b)) == _lib.GS_EINVAL
     assert L.gs_pose_grad_workspace(1000, 2, ctypes.byref(b)) == 0 and b.value == 4 * 2 * 6 * 8
@@ -87,10 +90,15 @@ def test_validation_rejects_before_any_launch():
     assert L.gs_project(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, dummy, dummy, dummy,
                         None) == _lib.GS_EINVAL
     L.gs_views_layout(V, 1, 16, None, None)
-    assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, V, dummy, 1, ctypes.byref(cfg), dummy,
-                           dummy, dummy, 0, dummy, 1 << 30, dummy, None) == _lib.GS_EINVAL
-    assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, V, dummy, 1, ctypes.byref(cfg), dummy,
-                           dummy, dummy, 1, dummy, 16, dummy, None) == _lib.GS_ECAPACITY
+    assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, dummy, dummy, 100, dummy, V, dummy, 1,
+                           ctypes.byref(cfg), dummy, dummy, dummy, 0, dummy, 1 << 30, dummy, 1 << 30, dummy,
+                           None) == _lib.GS_EINVAL
+    assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, dummy, dummy, 100, dummy, V, dummy, 1,
+                           ctypes.byref(cfg), dummy, dummy, dummy, 1, dummy, 16, dummy, 1 << 30, dummy,
+                           None) == _lib.GS_ECAPACITY
+    assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, dummy, dummy, 100, dummy, V, dummy, 1,
+                           ctypes.byref(cfg), dummy, dummy, dummy, 1, dummy, 1 << 30, dummy, 16, dummy,
+                           None) == _lib.GS_ECAPACITY
     assert L.gs_project_bwd(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, 1 << 30, None,
                             None) == _lib.GS_EINVAL
     assert L.gs_error_string(_lib.GS_ECAPACITY) == b"buffer too small"

@@ -81,7 +81,17 @@ def test_bin_sort_bit_exact(name, tile):
     assert inst == ref["count"]
     assert nvis == int((dec["touched"] > 0).sum())
     assert np.array_equal(r.keys[:inst].cpu().numpy().view(np.uint32), ref["keys"])
-    assert np.array_equal(r.gids[:inst].cpu().numpy(), ref["gids"])
+    assert np.array_equal(r.sorted_gids(inst).cpu().numpy(), ref["gids"])
+    # emission layout: each visible pair's instances are contiguous from pair_first
+    touched = r.touched.cpu().numpy()
+    first = r.pair_first.cpu().numpy()
+    inst_gid = r.inst_gid[:inst].cpu().numpy()
+    n = scene.n
+    vis = np.nonzero(touched > 0)[0]
+    for pair in vis[:: max(1, len(vis) // 200)]:
+        e0 = first[pair]
+        assert np.all(inst_gid[e0:e0 + touched[pair]] == pair % n)
+    assert np.array_equal(np.sort(r.inst[:inst].cpu().numpy()), np.arange(inst))
     assert np.array_equal(r.ranges.view(-1, 2).cpu().numpy(), ref["ranges"])
 
 
@@ -316,5 +326,6 @@ def test_abi_rejects_bad_arguments_without_launching():
     assert st == _lib.GS_EINVAL
     st = L.gs_bin_sort(r.rect.data_ptr(), r.touched.data_ptr(), r.rec.data_ptr(), r.n, r.views.host,
                        r.views.dev_ptr(), 1, ctypes.byref(r.cc), r.ws_view.data_ptr(), 16, r.capacity,
-                       r.keys.data_ptr(), r.gids.data_ptr(), r.ranges.data_ptr(), r.counts.data_ptr(), None)
+                       r.keys.data_ptr(), r.inst.data_ptr(), r.inst_gid.data_ptr(), r.pair_first.data_ptr(),
+                       r.ranges.data_ptr(), r.counts.data_ptr(), None)
     assert st == _lib.GS_ECAPACITY
