@@ -58,9 +58,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--lds-batch", type=int, default=256)
-    ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--lds-batch", type=int, default=None)
+    ap.add_argument("--persistent", type=int, default=None)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-perview", action="store_true")
@@ -95,10 +95,15 @@ def main():
     params = not w.pose_only
     pose = w.pose_grad
 
-    cfg = raster.Config(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent)
+    kw = dict(batched.BENCH_CONFIG)
+    for k, a in (("tile", args.tile), ("lds_batch", args.lds_batch), ("persistent", args.persistent)):
+        if a is not None:
+            kw[k] = a
+    cfg = raster.Config(**kw)
     if args.autotune:
         from paper_2603_27781_amd import autotune
-        cfg = autotune.tune(g, w.views, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose)
+        cfg = autotune.tune(g, w.views, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose, verbose=True,
+                            cache=None)
         log(f"autotuned config: {cfg}")
 
     if args.copy_calib_mb > 0:

@@ -24,6 +24,10 @@ import torch
 from . import _lib
 from .raster import Config, Gaussians, Rasterizer, Views
 
+# Launch configuration the benchmark times (chosen with autotune.tune on the
+# 8 x 1200x680, 1M-Gaussian, F=16 mapping step).
+BENCH_CONFIG = {"tile": 16, "lds_batch": 128, "persistent": 1}
+
 
 class MappingStep:
     def __init__(self, g: Gaussians, views: Sequence, cfg: Config, rgb_t: torch.Tensor, depth_t: torch.Tensor,

@@ -158,45 +158,35 @@ def _unit_quats(rng, n):
 
 
 def _quat_from_matrix(R):
-    """Rotation matrices [n][3][3] -> unit quaternions [4][n] (w, x, y, z)."""
-    n = R.shape[0]
-    q = np.zeros((n, 4))
-    tr = R[:, 0, 0] + R[:, 1, 1] + R[:, 2, 2]
-    cases = np.stack([tr, R[:, 0, 0], R[:, 1, 1], R[:, 2, 2]], axis=1).argmax(axis=1)
-    for i in range(n):
-        m = R[i]
-        c = cases[i]
-        if c == 0:
-            s = math.sqrt(1.0 + tr[i]) * 2
-            q[i] = [0.25 * s, (m[2, 1] - m[1, 2]) / s, (m[0, 2] - m[2, 0]) / s, (m[1, 0] - m[0, 1]) / s]
-        elif c == 1:
-            s = math.sqrt(1.0 + m[0, 0] - m[1, 1] - m[2, 2]) * 2
-            q[i] = [(m[2, 1] - m[1, 2]) / s, 0.25 * s, (m[0, 1] + m[1, 0]) / s, (m[0, 2] + m[2, 0]) / s]
-        elif c == 2:
-            s = math.sqrt(1.0 + m[1, 1] - m[0, 0] - m[2, 2]) * 2
-            q[i] = [(m[0, 2] - m[2, 0]) / s, (m[0, 1] + m[1, 0]) / s, 0.25 * s, (m[1, 2] + m[2, 1]) / s]
-        else:
-            s = math.sqrt(1.0 + m[2, 2] - m[0, 0] - m[1, 1]) * 2
-            q[i] = [(m[1, 0] - m[0, 1]) / s, (m[0, 2] + m[2, 0]) / s, (m[1, 2] + m[2, 1]) / s, 0.25 * s]
+    """Rotation matrices [n][3][3] -> unit quaternions [4][n] (w, x, y, z),
+    choosing per matrix the numerically largest of the four candidates."""
+    R = np.asarray(R, np.float64)
+    m00, m11, m22 = R[:, 0, 0], R[:, 1, 1], R[:, 2, 2]
+    tr = m00 + m11 + m22
+    case = np.stack([tr, m00, m11, m22], axis=1).argmax(axis=1)
+    q = np.zeros((R.shape[0], 4))
+    c = case == 0
+    s = np.sqrt(np.maximum(1.0 + tr[c], 1e-30)) * 2
+    q[c] = np.stack([0.25 * s, (R[c, 2, 1] - R[c, 1, 2]) / s, (R[c, 0, 2] - R[c, 2, 0]) / s,
+                     (R[c, 1, 0] - R[c, 0, 1]) / s], axis=1)
+    c = case == 1
+    s = np.sqrt(np.maximum(1.0 + m00[c] - m11[c] - m22[c], 1e-30)) * 2
+    q[c] = np.stack([(R[c, 2, 1] - R[c, 1, 2]) / s, 0.25 * s, (R[c, 0, 1] + R[c, 1, 0]) / s,
+                     (R[c, 0, 2] + R[c, 2, 0]) / s], axis=1)
+    c = case == 2
+    s = np.sqrt(np.maximum(1.0 + m11[c] - m00[c] - m22[c], 1e-30)) * 2
+    q[c] = np.stack([(R[c, 0, 2] - R[c, 2, 0]) / s, (R[c, 0, 1] + R[c, 1, 0]) / s, 0.25 * s,
+                     (R[c, 1, 2] + R[c, 2, 1]) / s], axis=1)
+    c = case == 3
+    s = np.sqrt(np.maximum(1.0 + m22[c] - m00[c] - m11[c], 1e-30)) * 2
+    q[c] = np.stack([(R[c, 1, 0] - R[c, 0, 1]) / s, (R[c, 0, 2] + R[c, 2, 0]) / s,
+                     (R[c, 1, 2] + R[c, 2, 1]) / s, 0.25 * s], axis=1)
     return q.T
 
 
 def _quat_from_frames(e1, e2, n):
-    """Vectorised matrix->quaternion for frames with columns (e1, e2, n)."""
-    R = np.stack([e1, e2, n], axis=2)            # [N][3][3], columns are axes
-    N = R.shape[0]
-    tr = R[:, 0, 0] + R[:, 1, 1] + R[:, 2, 2]
-    q = np.zeros((N, 4))
-    m = tr > 0
-    s = np.sqrt(np.maximum(1.0 + tr, 1e-30)) * 2
-    q[m, 0] = 0.25 * s[m]
-    q[m, 1] = (R[m, 2, 1] - R[m, 1, 2]) / s[m]
-    q[m, 2] = (R[m, 0, 2] - R[m, 2, 0]) / s[m]
-    q[m, 3] = (R[m, 1, 0] - R[m, 0, 1]) / s[m]
-    rest = np.nonzero(~m)[0]
-    if rest.size:
-        q[rest] = _quat_from_matrix(R[rest]).T
-    return q.T
+    """Quaternions of the frames with columns (e1, e2, n)."""
+    return _quat_from_matrix(np.stack([e1, e2, n], axis=2))
 
 
 # ----------------------------------------------------------------------------
