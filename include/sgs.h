@@ -9,8 +9,8 @@
  *   Sec. 3.2, Eq. (1)-(2)   SG-Field and Sigma = R S S^T R^T
  *   Sec. 3.2.1, Eq. (3)-(6) EWA projection, alpha, colour and depth blending
  *   Sec. 3.2.2, Eq. (7)-(8) semantic feature blending and decoding
- *   Sec. 3.3.1, Eq. (9)     cumulative opacity
- *   Sec. 3.3.4 / 3.4        colour / depth / semantic losses
+ *   Sec. 3.3.1, Eq. (10)    cumulative opacity
+ *   Sec. 3.3.4, Eq. (15)-(18); Sec. 3.4, Eq. (21)  losses
  *   Supp. B.1               Jacobian of the loss with respect to the pose
  *
  * Conventions shared by every entry point:
@@ -183,7 +183,7 @@ int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float*
                 int32_t* inst_gid, int32_t* pair_first, int32_t* tile_ranges, int64_t* counts, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
- * gs_render_fwd -- front-to-back compositing, Eq. (4), (6), (7), (9):
+ * gs_render_fwd -- front-to-back compositing, Eq. (4), (6), (7), (10):
  *   alpha_i = min(alpha_max, o_i exp(-q_i / 2)),  q_i = sigma^T conic sigma >= 0
  *   out_ch  = sum_i x_i,ch alpha_i T_i,  T_i = prod_{j<i} (1 - alpha_j)
  * over each pixel's tile list in (depth, index) order, skipping alpha <

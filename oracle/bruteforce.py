@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY -- an independent second implementation used to pin
 the C oracle on tiny scenes.  It has no tiles and no bounding boxes: every
 pixel considers every Gaussian that survives culling, in (binary32 depth,
 index) order, and composites front to back (GS^3LAM Sec. 3.2.1 Eq. (4)-(7),
-Sec. 3.3.1 Eq. (9)).  Gradients come from torch.autograd, not from any
+Sec. 3.3.1 Eq. (10)).  Gradients come from torch.autograd, not from any
 hand-derived chain rule, so they pin the oracle's analytic backward.
 
 The discrete decisions (culling, alpha_min skip, T_min stop) are taken on

@@ -9,7 +9,7 @@
  *   - Eq. (3)  Sigma2D = J R_CW Sigma R_CW^T J^T (EWA splatting) plus a
  *              low-pass dilation b*I, its inverse (the conic),
  *   - Eq. (5)  alpha = o * exp(-1/2 sigma^T Sigma2D^-1 sigma),
- *   - Eq. (4), (6), (7), (9): front-to-back compositing of colour, depth,
+ *   - Eq. (4), (6), (7), (10): front-to-back compositing of colour, depth,
  *              semantic feature and cumulative opacity in depth order,
  *   - the image-space loss gradients of Sec. 3.3.4 / 3.4 (L1 colour, L1
  *     depth, cross-entropy through a fixed linear decoder),

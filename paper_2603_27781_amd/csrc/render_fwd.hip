@@ -1,5 +1,5 @@
 // Forward compositing, GS^3LAM Sec. 3.2.1 Eq. (4)-(6), Sec. 3.2.2 Eq. (7),
-// Sec. 3.3.1 Eq. (9):
+// Sec. 3.3.1 Eq. (10):
 //   out_ch(p) = sum_i x_i,ch alpha_i T_i,   T_i = prod_{j<i} (1 - alpha_j)
 // for colour (3), depth (1) and the F semantic feature channels, with the
 // cumulative opacity written as 1 - T_final (equal to sum_i alpha_i T_i).

@@ -1,7 +1,7 @@
 """Pins of the FP64 CPU oracle against facts fixed by the paper and by
 mathematics (closed forms, invariants, brute force, finite differences).
 
-Paper: GS^3LAM, Sec. 3.2 (Eq. 1-7), Sec. 3.3.1 (Eq. 9), Supp. B.1.
+Paper: GS^3LAM, Sec. 3.2 (Eq. 1-7), Sec. 3.3.1 (Eq. 10), Supp. B.1.
 """
 import json
 import math
