@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--lds-batch", type=int, default=None)
+    ap.add_argument("--lds-batch-bwd", type=int, default=None)
     ap.add_argument("--persistent", type=int, default=None)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -96,7 +97,8 @@ def main():
     pose = w.pose_grad
 
     kw = dict(batched.BENCH_CONFIG)
-    for k, a in (("tile", args.tile), ("lds_batch", args.lds_batch), ("persistent", args.persistent)):
+    for k, a in (("tile", args.tile), ("lds_batch", args.lds_batch), ("persistent", args.persistent),
+                 ("lds_batch_bwd", args.lds_batch_bwd)):
         if a is not None:
             kw[k] = a
     cfg = raster.Config(**kw)
@@ -211,7 +213,8 @@ def main():
                    "resolution": sorted({f"{v.width}x{v.height}" for v in w.views}), "feat": F, "classes": K,
                    "pixels_per_step": P, "instances": n_inst, "visible_pairs": n_vis,
                    "grad": ("params" if params else "") + ("+pose" if pose else ""), "mode": "batched hipGraph",
-                   "tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent},
+                   "tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
+                   "lds_batch_bwd": cfg.lds_batch_bwd},
         "per_view": per_view, "entry_us": {k: round(v, 2) for k, v in kern_us.items()},
         "roofline": roofline, "cpu_baseline": cpu,
     }

@@ -110,17 +110,19 @@ typedef struct {
  *   lds_batch        Gaussians staged in LDS per batch (64, 128 or 256)
  *   persistent       0: one workgroup per tile; 1: persistent workgroups
  *                    that pull (view, tile) items from a queue
+ *   lds_batch_bwd    Gaussians staged per batch by the render backward
+ *                    (64, 128 or 256; 0 = the same as lds_batch)
  */
 typedef struct {
     float z_near, blur, guard, alpha_min, alpha_max, T_min;
     int32_t tile;
     int32_t lds_batch;
     int32_t persistent;
-    int32_t reserved;
+    int32_t lds_batch_bwd;
 } gs_config;
 
 /* Fills *cfg with the defaults listed above (tile 16, lds_batch 256,
- * persistent 0). */
+ * persistent 0, lds_batch_bwd 0). */
 int gs_default_config(gs_config* cfg);
 
 /* Host helper: fills pixel_offset / tile_offset of a HOST array of views for
@@ -142,6 +144,8 @@ int32_t gs_app_stride(int32_t n_feat);
  *                   (rx, ry) as two binary16 rounded up.
  *   rect[V][n][2] = tile rectangle, (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
  *   tiles_touched[V][n] = number of tiles in rect, 0 if culled
+ *                   (rec and rect are written only for pairs with
+ *                   tiles_touched > 0; other entries are left as they were)
  *   app[n][gs_app_stride(F)] = colour and feature, gathered per Gaussian by
  *                   the render kernels (may be NULL to skip).
  * Culling, the mean, the conic, the depth and the rectangle are computed in
@@ -230,8 +234,8 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
  * are reduced across each wavefront and tile, written as one record per
  * instance into ws (no atomics), then summed per (view, Gaussian) pair in a
  * fixed order, so the result is deterministic.  WRITES grad2d:
- *   grad2d geo [V][n][8]  = dL/d(mx, my, A, B, C, d), 2 unused   (per view,
- *                           zero for pairs that are not visible)
+ *   grad2d geo [V][n][8]  = dL/d(mx, my, A, B, C, d), 2 unused   (per view;
+ *                           written only for visible pairs, tiles_touched > 0)
  *   grad2d app [n][4+F]   = dL/d(o, c0, c1, c2, f...)            (all views)
  * (geo first, app right after it).  flags: GS_GRAD_PARAMS fills geo and app;
  * GS_GRAD_POSE alone (tracking, Sec. 3.4: the field is frozen) fills geo
@@ -255,11 +259,11 @@ int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, con
  * one thread per Gaussian summing its views in registers (no atomics):
  *   conic = Sigma2D^-1, Sigma2D = (J R_CW M)(J R_CW M)^T + bI, M = R(q) diag(e^s),
  *   mean2d = pi(R_CW mu + t), depth = (R_CW mu + t)_z, o = sigmoid(logit).
- * ADDS the gradients to *grads.
+ * Pairs with tiles_touched == 0 are skipped.  ADDS the gradients to *grads.
  * --------------------------------------------------------------------------- */
 int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
-                   const gs_config* cfg, const float* grad2d, size_t grad2d_bytes, gs_gaussian_grads* grads,
-                   gs_stream stream);
+                   const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, size_t grad2d_bytes,
+                   gs_gaussian_grads* grads, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_pose_grad -- Supp. B.1 written as a twist of the left perturbation
@@ -267,7 +271,8 @@ int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* v
  *   dL/drho = sum_i g_i,   dL/dphi = sum_i [p_i x g_i + 2 vex(G_i S_i - S_i G_i)]
  * with p_i the camera-space mean, S_i its camera-space covariance,
  * g_i = dL/dp_i and G_i = dL/dS_i obtained from grad2d (of gs_render_bwd)
- * through the EWA projection.  The view-dependent feature term the paper
+ * through the EWA projection (pairs with tiles_touched == 0 are skipped).
+ * The view-dependent feature term the paper
  * drops is zero here because colour and feature are view-independent.
  *   twist[V][6] (rho, phi), written (not accumulated).
  *   ws: gs_pose_grad_workspace bytes (per-block partial sums; the final sum
@@ -275,8 +280,8 @@ int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* v
  * --------------------------------------------------------------------------- */
 int gs_pose_grad_workspace(int32_t n, int32_t n_views, size_t* bytes);
 int gs_pose_grad(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
-                 const gs_config* cfg, const float* grad2d, void* ws, size_t ws_bytes, float* twist,
-                 gs_stream stream);
+                 const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, void* ws,
+                 size_t ws_bytes, float* twist, gs_stream stream);
 
 /* Static description of a status code. */
 const char* gs_error_string(int status);

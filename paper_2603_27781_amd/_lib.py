@@ -47,7 +47,7 @@ class GsView(ctypes.Structure):
 class GsConfig(ctypes.Structure):
     _fields_ = [("z_near", c_float), ("blur", c_float), ("guard", c_float), ("alpha_min", c_float),
                 ("alpha_max", c_float), ("T_min", c_float), ("tile", c_int32), ("lds_batch", c_int32),
-                ("persistent", c_int32), ("reserved", c_int32)]
+                ("persistent", c_int32), ("lds_batch_bwd", c_int32)]
 
 
 assert ctypes.sizeof(GsView) == 88 and ctypes.sizeof(GsConfig) == 40
@@ -88,11 +88,11 @@ def load() -> ctypes.CDLL:
     L.gs_render_bwd.argtypes = [P(GsGaussians), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                 c_void_p, P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p,
                                 c_uint32, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p]
-    L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_size_t,
-                                 P(GsGaussianGrads), c_void_p]
+    L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
+                                 c_size_t, P(GsGaussianGrads), c_void_p]
     L.gs_pose_grad_workspace.argtypes = [c_int32, c_int32, P(c_size_t)]
     L.gs_pose_grad.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
-                               c_size_t, c_void_p, c_void_p]
+                               c_void_p, c_size_t, c_void_p, c_void_p]
     L.gs_error_string.argtypes = [ctypes.c_int]
     L.gs_error_string.restype = ctypes.c_char_p
     L.gs_last_hip_error.restype = ctypes.c_char_p

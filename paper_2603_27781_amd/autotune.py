@@ -3,7 +3,8 @@
 Tries tile side (8, 16, 32) x Gaussians staged per LDS batch (64, 128, 256)
 x launch mode (one workgroup per tile, or persistent workgroups pulling
 (view, tile) items from a queue), times a few eager steps of the real
-workload for each and keeps the fastest.  Results are cached in a JSON file
+workload for each and keeps the fastest; then, for the winner, tries the
+other batch sizes for the render backward alone.  Results are cached in a JSON file
 keyed by device name and workload shape (Gaussian count, feature count,
 view sizes, gradient mode), so later runs skip the sweep.
 """
@@ -44,8 +45,8 @@ def tune(g, views: Sequence, rgb_t, dep_t, lab, W, weights, params=True, pose=Fa
         except (OSError, ValueError):
             pass
     best, best_ms, results = None, float("inf"), []
-    for tile, batch, persistent in (candidates or CANDIDATES):
-        cfg = Config(tile=tile, lds_batch=batch, persistent=persistent)
+
+    def trial(cfg):
         st = MappingStep(g, views, cfg, rgb_t, dep_t, lab, W, weights, params=params, pose=pose)
         st.ensure_capacity()
         st.run()
@@ -59,13 +60,27 @@ def tune(g, views: Sequence, rgb_t, dep_t, lab, W, weights, params=True, pose=Fa
             torch.cuda.synchronize()
             times.append(a.elapsed_time(b))
         ms = float(np.median(times))
-        results.append({"tile": tile, "lds_batch": batch, "persistent": persistent, "ms": ms})
+        results.append({"tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
+                        "lds_batch_bwd": cfg.lds_batch_bwd, "ms": ms})
         if verbose:
-            print(f"[autotune] tile {tile} batch {batch} persistent {persistent}: {ms:.3f} ms", flush=True)
-        if ms < best_ms:
-            best, best_ms = cfg, ms
+            print(f"[autotune] tile {cfg.tile} batch {cfg.lds_batch}/{cfg.lds_batch_bwd} "
+                  f"persistent {cfg.persistent}: {ms:.3f} ms", flush=True)
         del st
         torch.cuda.empty_cache()
+        return ms
+
+    for tile, batch, persistent in (candidates or CANDIDATES):
+        cfg = Config(tile=tile, lds_batch=batch, persistent=persistent)
+        ms = trial(cfg)
+        if ms < best_ms:
+            best, best_ms = cfg, ms
+    for bb in (64, 128, 256):
+        if bb == best.lds_batch or (best.tile == 8 and bb == 256):
+            continue
+        cfg = dataclasses.replace(best, lds_batch_bwd=bb)
+        ms = trial(cfg)
+        if ms < best_ms:
+            best, best_ms = cfg, ms
     if cache:
         try:
             os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -47,13 +47,17 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, const gs_view* __r
     if (i >= n) return;
 
     if (app != nullptr) {
-        // appearance record (c, f) gathered per instance by the render kernels
-        float* a = app + (size_t)i * app_stride;
-        a[0] = g.color[i];
-        a[1] = g.color[(size_t)n + i];
-        a[2] = g.color[2 * (size_t)n + i];
-        for (int f = 0; f < g.n_feat; ++f) a[3 + f] = g.feat[(size_t)f * n + i];
-        for (int k = 3 + g.n_feat; k < app_stride; ++k) a[k] = 0.0f;
+        // appearance record (c, f, 0...) gathered per instance by the render
+        // kernels, written as float4 (app_stride is a multiple of 4)
+        float4* a4 = reinterpret_cast<float4*>(app + (size_t)i * app_stride);
+        const int F = g.n_feat;
+        auto val = [&](int k) -> float {
+            if (k < 3) return g.color[(size_t)k * n + i];
+            if (k < 3 + F) return g.feat[(size_t)(k - 3) * n + i];
+            return 0.0f;
+        };
+        for (int q = 0; q < app_stride / 4; ++q)
+            a4[q] = make_float4(val(4 * q), val(4 * q + 1), val(4 * q + 2), val(4 * q + 3));
     }
 
     const float logit = g.logit[i];
@@ -90,8 +94,6 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, const gs_view* __r
     for (int v = 0; v < n_views; ++v) {
         const gs_view& vw = views[v];
         const size_t o = (size_t)v * n + i;
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint2 rc = make_uint2(0xffffffffu, 0xffffffffu);
         int32_t cnt = 0;
         const float* R = vw.Rt;  // row-major [R|t]: R[0..2] t at [3], [7], [11]
         const float p0 = ((R[0] * m0 + R[1] * m1) + R[2] * m2) + R[3];
@@ -141,15 +143,14 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, const gs_view* __r
                     fy1 = fy1 > (float)(ty - 1) ? (float)(ty - 1) : fy1;
                     const int ix0 = (int)fx0, iy0 = (int)fy0, ix1 = (int)fx1, iy1 = (int)fy1;
                     cnt = (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
-                    rc = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
-                    r0 = make_float4(mx, my, cc / det, -b / det);
-                    r1 = make_float4(a / det, op, p2, pack_radii(rx, ry));
+                    // the record and rectangle of a pair are only read when it is visible
+                    rec[2 * o] = make_float4(mx, my, cc / det, -b / det);
+                    rec[2 * o + 1] = make_float4(a / det, op, p2, pack_radii(rx, ry));
+                    rect[o] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16),
+                                         (uint32_t)ix1 | ((uint32_t)iy1 << 16));
                 }
             }
         }
-        rec[2 * o] = r0;
-        rec[2 * o + 1] = r1;
-        rect[o] = rc;
         touched[o] = cnt;
     }
 }

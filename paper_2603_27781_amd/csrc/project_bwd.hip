@@ -126,7 +126,8 @@ __device__ __forceinline__ bool nonzero(const float4 a, const float4 b) {
 // Parameter gradients, one thread per Gaussian, looping over the views (no
 // atomics: every view's contribution is summed in registers).
 __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const gs_view* __restrict__ views, int n_views,
-                                                     float blur, const float4* __restrict__ grad_geo,
+                                                     float blur, const int32_t* __restrict__ touched,
+                                                     const float4* __restrict__ grad_geo,
                                                      const float* __restrict__ grad_app, GradPtrs out) {
     const int n = g.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,6 +141,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const gs_view*
     bool any = false;
     for (int v = 0; v < n_views; ++v) {
         const size_t o = (size_t)v * n + i;
+        if (touched[o] <= 0) continue;
         const float4 g0 = grad_geo[2 * o], g1 = grad_geo[2 * o + 1];
         if (!nonzero(g0, g1)) continue;
         any = true;
@@ -185,6 +187,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const gs_view*
 
 // Twist contributions per (view, Gaussian), reduced per block in FP64.
 __global__ void __launch_bounds__(256) k_pose_partial(GaussPtrs g, const gs_view* __restrict__ views, float blur,
+                                                      const int32_t* __restrict__ touched,
                                                       const float4* __restrict__ grad_geo,
                                                       double* __restrict__ partials, int nblk) {
     __shared__ double s_red[6][256 / kWave];
@@ -192,7 +195,7 @@ __global__ void __launch_bounds__(256) k_pose_partial(GaussPtrs g, const gs_view
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
     double tw[6] = {0, 0, 0, 0, 0, 0};
-    if (i < n) {
+    if (i < n && touched[(size_t)v * n + i] > 0) {
         const size_t o = (size_t)v * n + i;
         const float4 g0 = grad_geo[2 * o], g1 = grad_geo[2 * o + 1];
         if (nonzero(g0, g1)) {
@@ -266,10 +269,11 @@ __global__ void __launch_bounds__(256) k_pose_final(const double* __restrict__ p
 }
 
 hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
-                              const float* grad_geo, const float* grad_app, const GradPtrs& out, hipStream_t s) {
+                              const int32_t* touched, const float* grad_geo, const float* grad_app,
+                              const GradPtrs& out, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)ceil_div(g.n, 256)), dim3(256), 0, s, g, views_dev, n_views,
-                       c.blur, reinterpret_cast<const float4*>(grad_geo), grad_app, out);
+                       c.blur, touched, reinterpret_cast<const float4*>(grad_geo), grad_app, out);
     return hipGetLastError();
 }
 
@@ -279,11 +283,11 @@ size_t pose_workspace_bytes(int n, int n_views) {
 }
 
 hipError_t launch_pose_grad(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
-                            const float* grad_geo, void* ws, float* twist, hipStream_t s) {
+                            const int32_t* touched, const float* grad_geo, void* ws, float* twist, hipStream_t s) {
     const int nblk = ceil_div(g.n > 0 ? g.n : 1, 256);
     double* partials = static_cast<double*>(ws);
     hipLaunchKernelGGL(k_pose_partial, dim3((unsigned)nblk, (unsigned)n_views), dim3(256), 0, s, g, views_dev,
-                       c.blur, reinterpret_cast<const float4*>(grad_geo), partials, nblk);
+                       c.blur, touched, reinterpret_cast<const float4*>(grad_geo), partials, nblk);
     hipLaunchKernelGGL(k_pose_final, dim3((unsigned)n_views), dim3(256), 0, s, partials, nblk, twist);
     return hipGetLastError();
 }

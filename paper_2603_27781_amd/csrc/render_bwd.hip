@@ -265,8 +265,9 @@ __global__ void __launch_bounds__(TS* TS) k_render_bwd(const float4* __restrict_
 
 // Sum of the records of every (view, Gaussian) pair (contiguous emission
 // indices, fixed order), one thread per Gaussian looping over the views:
-// grad_geo[V][n][8] <- (dmx, dmy, dA, dB, dC, dd, 0, 0), zero where the pair
-// is not visible; grad_app[n][4+F] <- the appearance part summed over views.
+// grad_geo[V][n][8] <- (dmx, dmy, dA, dB, dC, dd, 0, 0) for visible pairs
+// (others are not written); grad_app[n][4+F] <- the appearance part summed
+// over views.
 template <int F, bool PARAMS>
 __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict__ records,
                                                         const int32_t* __restrict__ pair_first,
@@ -284,8 +285,9 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
     for (int v = 0; v < n_views; ++v) {
         const size_t pair = (size_t)v * n + i;
         const int cnt = touched[pair];
+        if (cnt <= 0) continue;
         float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (cnt > 0) {
+        {
             const int64_t first = pair_first[pair];
             const int64_t stop = first + cnt < capacity ? first + cnt : capacity;  // truncated lists
             for (int64_t e = first; e < stop; ++e) {

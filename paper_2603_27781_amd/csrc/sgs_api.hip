@@ -25,6 +25,8 @@ int check_config(const gs_config* c) {
     if (!c) return GS_EINVAL;
     if (!pow2_tile(c->tile)) return GS_EUNSUPPORTED;
     if (c->lds_batch != 64 && c->lds_batch != 128 && c->lds_batch != 256) return GS_EUNSUPPORTED;
+    if (c->lds_batch_bwd != 0 && c->lds_batch_bwd != 64 && c->lds_batch_bwd != 128 && c->lds_batch_bwd != 256)
+        return GS_EUNSUPPORTED;
     if (!(c->alpha_min > 0.0f && c->alpha_min < 1.0f)) return GS_EINVAL;
     if (!(c->alpha_max > c->alpha_min && c->alpha_max < 1.0f)) return GS_EINVAL;
     if (!(c->T_min > 0.0f && c->T_min < 1.0f)) return GS_EINVAL;
@@ -113,7 +115,7 @@ int gs_default_config(gs_config* cfg) {
     cfg->tile = 16;
     cfg->lds_batch = 256;
     cfg->persistent = 0;
-    cfg->reserved = 0;
+    cfg->lds_batch_bwd = 0;
     return GS_OK;
 }
 
@@ -257,8 +259,9 @@ int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, con
     float* appg = grad2d + (size_t)n_views * g->n * 8;
     float* records = static_cast<float*>(ws);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int batch = cfg->lds_batch_bwd ? cfg->lds_batch_bwd : cfg->lds_batch;
     hipError_t e = launch_render_bwd(rec, app, g->n, g->n_feat, inst, inst_gid, tile_ranges, views_dev, n_views,
-                                     total_tiles, P, make_const(cfg), cfg->lds_batch, cfg->persistent, T_final, last,
+                                     total_tiles, P, make_const(cfg), batch, cfg->persistent, T_final, last,
                                      grad_out, params, records, queue, s);
     if (e != hipSuccess) return hip_status(e);
     return hip_status(launch_reduce_records(records, pair_first, tiles_touched, g->n, g->n_feat, n_views, capacity,
@@ -266,13 +269,13 @@ int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, con
 }
 
 int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
-                   const gs_config* cfg, const float* grad2d, size_t grad2d_bytes_, gs_gaussian_grads* grads,
-                   gs_stream stream) {
+                   const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, size_t grad2d_bytes_,
+                   gs_gaussian_grads* grads, gs_stream stream) {
     int st = check_gauss(g, false);
     if (st) return st;
     if ((st = check_config(cfg))) return st;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, nullptr))) return st;
-    if (!grad2d || !grads || !grads->mu || !grads->log_scale || !grads->quat || !grads->opacity_logit ||
+    if (!tiles_touched || !grad2d || !grads || !grads->mu || !grads->log_scale || !grads->quat || !grads->opacity_logit ||
         !grads->color || (g->n_feat > 0 && !grads->feat))
         return GS_EINVAL;
     if (grad2d_bytes_ < grad2d_bytes(g->n, g->n_feat, n_views)) return GS_ECAPACITY;
@@ -286,8 +289,8 @@ int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* v
     o.feat = grads->feat;
     const float* geo = grad2d;
     const float* appg = grad2d + (size_t)n_views * g->n * 8;
-    return hip_status(launch_project_bwd(gauss_ptrs(g), views_dev, n_views, make_const(cfg), geo, appg, o,
-                                         reinterpret_cast<hipStream_t>(stream)));
+    return hip_status(launch_project_bwd(gauss_ptrs(g), views_dev, n_views, make_const(cfg), tiles_touched, geo, appg,
+                                         o, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_pose_grad_workspace(int32_t n, int32_t n_views, size_t* bytes) {
@@ -297,17 +300,17 @@ int gs_pose_grad_workspace(int32_t n, int32_t n_views, size_t* bytes) {
 }
 
 int gs_pose_grad(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
-                 const gs_config* cfg, const float* grad2d, void* ws, size_t ws_bytes, float* twist,
-                 gs_stream stream) {
+                 const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, void* ws, size_t ws_bytes,
+                 float* twist, gs_stream stream) {
     int st = check_gauss(g, false);
     if (st) return st;
     if ((st = check_config(cfg))) return st;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, nullptr))) return st;
-    if (!grad2d || !ws || !twist) return GS_EINVAL;
+    if (!tiles_touched || !grad2d || !ws || !twist) return GS_EINVAL;
     if (ws_bytes < pose_workspace_bytes(g->n, n_views)) return GS_ECAPACITY;
     if (!aligned16(grad2d) || (reinterpret_cast<uintptr_t>(ws) & 15u) != 0) return GS_EINVAL;
-    return hip_status(launch_pose_grad(gauss_ptrs(g), views_dev, n_views, make_const(cfg), grad2d, ws, twist,
-                                       reinterpret_cast<hipStream_t>(stream)));
+    return hip_status(launch_pose_grad(gauss_ptrs(g), views_dev, n_views, make_const(cfg), tiles_touched, grad2d, ws,
+                                       twist, reinterpret_cast<hipStream_t>(stream)));
 }
 
 const char* gs_error_string(int status) {

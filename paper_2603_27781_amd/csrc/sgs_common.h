@@ -105,12 +105,12 @@ hipError_t launch_reduce_records(const float* records, const int32_t* pair_first
                                  float* grad_app, hipStream_t s);
 
 hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
-                              const float* grad_geo, const float* grad_app, const GradPtrs& out,
-                              hipStream_t s);
+                              const int32_t* touched, const float* grad_geo, const float* grad_app,
+                              const GradPtrs& out, hipStream_t s);
 
 size_t pose_workspace_bytes(int n, int n_views);
 hipError_t launch_pose_grad(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
-                            const float* grad_geo, void* ws, float* twist, hipStream_t s);
+                            const int32_t* touched, const float* grad_geo, void* ws, float* twist, hipStream_t s);
 
 // Feature counts compiled into the render kernels.
 inline bool feat_supported(int f) { return f == 0 || f == 8 || f == 16 || f == 32; }

@@ -33,10 +33,11 @@ class Config:
     tile: int = 16
     lds_batch: int = 256
     persistent: int = 0
+    lds_batch_bwd: int = 0   # 0: same as lds_batch
 
     def c(self) -> GsConfig:
         return GsConfig(self.z_near, self.blur, self.guard, self.alpha_min, self.alpha_max, self.T_min, self.tile,
-                        self.lds_batch, self.persistent, 0)
+                        self.lds_batch, self.persistent, self.lds_batch_bwd)
 
 
 @dataclasses.dataclass
@@ -256,19 +257,24 @@ class Rasterizer:
     def project_bwd(self, g: Gaussians, grads: Gaussians) -> None:
         gc = _grads_c(grads)
         check(self.L.gs_project_bwd(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
-                                    ctypes.byref(self.cc), self.grad2d.data_ptr(), self.grad2d.numel() * 4,
-                                    ctypes.byref(gc), _stream()), "gs_project_bwd")
+                                    ctypes.byref(self.cc), self.touched.data_ptr(), self.grad2d.data_ptr(),
+                                    self.grad2d.numel() * 4, ctypes.byref(gc), _stream()), "gs_project_bwd")
 
     def pose_grad(self, g: Gaussians) -> torch.Tensor:
         check(self.L.gs_pose_grad(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
-                                  ctypes.byref(self.cc), self.grad2d.data_ptr(), self.pose_ws.data_ptr(),
-                                  self.pose_ws.numel() * 8, self.twist.data_ptr(), _stream()), "gs_pose_grad")
+                                  ctypes.byref(self.cc), self.touched.data_ptr(), self.grad2d.data_ptr(),
+                                  self.pose_ws.data_ptr(), self.pose_ws.numel() * 8, self.twist.data_ptr(),
+                                  _stream()), "gs_pose_grad")
         return self.twist
 
     # ------------------------------------------------------------ views of state
     @property
     def grad_geo(self) -> torch.Tensor:
-        return self.grad2d[: self.views.n * self.n * 8].view(self.views.n, self.n, 8)
+        """[V][n][8] 2D gradients; entries of pairs that are not visible are
+        zeroed here (the library leaves them unwritten)."""
+        geo = self.grad2d[: self.views.n * self.n * 8].view(self.views.n, self.n, 8)
+        vis = self.touched[: self.views.n * self.n].view(self.views.n, self.n, 1) > 0
+        return torch.where(vis, geo, torch.zeros((), dtype=geo.dtype, device=geo.device))
 
     @property
     def grad_app(self) -> torch.Tensor:

@@ -36,7 +36,7 @@ def test_default_config_and_layout():
     L = _lib.load()
     c = _lib.GsConfig()
     assert L.gs_default_config(ctypes.byref(c)) == 0
-    assert (c.tile, c.lds_batch, c.persistent) == (16, 256, 0)
+    assert (c.tile, c.lds_batch, c.persistent, c.lds_batch_bwd) == (16, 256, 0, 0)
     assert c.alpha_min == pytest.approx(1 / 255) and c.T_min == pytest.approx(1e-4)
     V = (_lib.GsView * 3)()
     for i, (w, h) in enumerate([(1200, 680), (640, 480), (33, 17)]):
@@ -99,7 +99,7 @@ def test_validation_rejects_before_any_launch():
     assert L.gs_render_bwd(ctypes.byref(g), dummy, dummy, dummy, dummy, dummy, dummy, 100, dummy, V, dummy, 1,
                            ctypes.byref(cfg), dummy, dummy, dummy, 1, dummy, 1 << 30, dummy, 16, dummy,
                            None) == _lib.GS_ECAPACITY
-    assert L.gs_project_bwd(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, 1 << 30, None,
+    assert L.gs_project_bwd(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, dummy, 1 << 30, None,
                             None) == _lib.GS_EINVAL
     assert L.gs_error_string(_lib.GS_ECAPACITY) == b"buffer too small"
     assert L.gs_version() >= 100

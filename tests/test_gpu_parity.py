@@ -107,9 +107,10 @@ def test_bin_sort_capacity_overflow_is_reported():
     assert r.instance_counts()[2] is False
 
 
-def _render(name, tile, lds_batch=256, persistent=0):
+def _render(name, tile, lds_batch=256, persistent=0, lds_batch_bwd=0):
     scene, views = CASES[name]()
-    r, g, cfg = gpu_setup(scene, views, {"tile": tile, "lds_batch": lds_batch, "persistent": persistent})
+    r, g, cfg = gpu_setup(scene, views, {"tile": tile, "lds_batch": lds_batch, "persistent": persistent,
+                                         "lds_batch_bwd": lds_batch_bwd})
     r.ensure_capacity(g)
     r.forward(g)
     torch.cuda.synchronize()
@@ -181,8 +182,8 @@ def test_loss_grad_parity(name):
     assert loss[3] == pytest.approx(terms[3], rel=1e-5)
 
 
-def _backward_case(name, tile=16, flags=3, persistent=0, lds_batch=256, seed=11):
-    scene, views, r, g, cfg = _render(name, tile, lds_batch, persistent)
+def _backward_case(name, tile=16, flags=3, persistent=0, lds_batch=256, seed=11, lds_batch_bwd=0):
+    scene, views, r, g, cfg = _render(name, tile, lds_batch, persistent, lds_batch_bwd)
     rng = np.random.default_rng(seed)
     go = rng.normal(size=r.out.shape).astype(np.float32) * 1e-2
     grads = g.zeros_like()
@@ -223,9 +224,11 @@ def test_render_bwd_and_pose_parity(name):
     _check_grads(*out, flags=3)
 
 
-@pytest.mark.parametrize("tile,lds_batch,persistent", [(8, 64, 1), (32, 128, 0)])
-def test_backward_launch_shapes(tile, lds_batch, persistent):
-    out = _backward_case("tiny3views-F16", tile=tile, persistent=persistent, lds_batch=lds_batch)
+@pytest.mark.parametrize("tile,lds_batch,persistent,lds_batch_bwd",
+                         [(8, 64, 1, 0), (32, 128, 0, 0), (16, 256, 1, 64), (16, 64, 0, 256)])
+def test_backward_launch_shapes(tile, lds_batch, persistent, lds_batch_bwd):
+    out = _backward_case("tiny3views-F16", tile=tile, persistent=persistent, lds_batch=lds_batch,
+                         lds_batch_bwd=lds_batch_bwd)
     _check_grads(*out, flags=3)
 
 
