@@ -42,8 +42,10 @@ __device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, 
 }
 
 // Value of `x` held by lane (lane ^ D) of the wavefront.  D = 1, 2: DPP
-// quad permutation (a VALU operand modifier, no LDS traffic); D = 4 .. 16:
-// ds_swizzle in xor mode (within 32-lane halves); D = 32: ds_bpermute.
+// quad permutation; D = 8: DPP row rotation by 8 (within a row of 16 lanes
+// that is lane ^ 8); all three are VALU operand modifiers, no LDS traffic.
+// D = 4, 16: ds_swizzle in xor mode (within 32-lane halves); D = 32:
+// ds_bpermute.
 template <int D>
 __device__ __forceinline__ float xor_lane(float x) {
     const int v = __float_as_int(x);
@@ -51,11 +53,31 @@ __device__ __forceinline__ float xor_lane(float x) {
         return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
     } else if constexpr (D == 2) {
         return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+    } else if constexpr (D == 8) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));  // row_ror:8
     } else if constexpr (D < 32) {
         return __int_as_float(__builtin_amdgcn_ds_swizzle(v, (D << 10) | 0x1F));  // xor_mask D, and_mask 31
     } else {
         const int lane = __lane_id();
         return __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ D) << 2, v));
+    }
+}
+
+// One exchange of the transposing butterfly across lane bit log2(D) for
+// D = 16, 32 (gfx950 permlane swaps): returns, in every lane, the pair total
+// of lo (lanes with the bit clear) or of hi (lanes with the bit set).  The
+// swap moves the upper lanes of `lo` and the lower lanes of `hi` across, so
+// one swap and one add replace two selects, a permute and an add.
+template <int D>
+__device__ __forceinline__ float swap_halves_add(float lo, float hi) {
+    static_assert(D == 16 || D == 32, "swap exchange is for lane bits 4 and 5");
+    const unsigned a = __float_as_uint(lo), b = __float_as_uint(hi);
+    if constexpr (D == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 }
 

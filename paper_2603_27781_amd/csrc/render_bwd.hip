@@ -28,30 +28,40 @@
 
 namespace sgs {
 
-// Transposing butterfly over NV (a power of two) values per lane.  Step D
-// (xor distance D = 1, 2, 4, ...) halves the CNT values a lane keeps: a lane
-// with bit D set keeps the upper half and sends the lower half to its
-// partner, which does the opposite, and both add what they receive.  After
-// log2(NV) steps each lane holds one partial total, the remaining steps
-// finish the sum across the wavefront.  Every index is a compile-time
-// constant (template recursion), so the values stay in registers.
-template <int NV, int CNT, int D>
+// Transposing butterfly over NV (a power of two) values per lane.  Each
+// halving step, across one lane bit, halves the CNT values a lane keeps: a
+// lane with the bit set keeps the upper half and receives its partner's
+// upper half, the partner the opposite, and both add.  Lane bits are taken
+// in the order 5, 4 (permlane swaps: one swap + one add per pair), then 0, 1
+// (DPP), 2 (swizzle), 3 (DPP): after log2(NV) halving steps each lane holds
+// one partial total, and the remaining bits finish the sum across the
+// wavefront.  Every index is a compile-time constant (template recursion),
+// so the values stay in registers.
+__host__ __device__ constexpr int bfly_bit(int s) { return s == 0 ? 5 : (s == 1 ? 4 : s - 2); }
+
+template <int NV, int CNT, int S>
 struct BflyStep {
     __device__ __forceinline__ static void run(float (&v)[NV], int lane) {
-        if constexpr (D < kWave) {
+        if constexpr (S < 6) {
+            constexpr int D = 1 << bfly_bit(S);
             if constexpr (CNT > 1) {
                 constexpr int HALF = CNT / 2;
-                const bool up = (lane & D) != 0;
+                if constexpr (D >= 16) {
 #pragma unroll
-                for (int k = 0; k < HALF; ++k) {
-                    const float send = up ? v[k] : v[k + HALF];
-                    const float keep = up ? v[k + HALF] : v[k];
-                    v[k] = keep + xor_lane<D>(send);
+                    for (int k = 0; k < HALF; ++k) v[k] = swap_halves_add<D>(v[k], v[k + HALF]);
+                } else {
+                    const bool up = (lane & D) != 0;
+#pragma unroll
+                    for (int k = 0; k < HALF; ++k) {
+                        const float send = up ? v[k] : v[k + HALF];
+                        const float keep = up ? v[k + HALF] : v[k];
+                        v[k] = keep + xor_lane<D>(send);
+                    }
                 }
-                BflyStep<NV, HALF, 2 * D>::run(v, lane);
+                BflyStep<NV, HALF, S + 1>::run(v, lane);
             } else {
                 v[0] += xor_lane<D>(v[0]);
-                BflyStep<NV, 1, 2 * D>::run(v, lane);
+                BflyStep<NV, 1, S + 1>::run(v, lane);
             }
         }
     }
@@ -59,25 +69,32 @@ struct BflyStep {
 
 template <int NV>
 struct Butterfly {
+    static constexpr int steps() {
+        int b = 0;
+        while ((1 << b) < NV) ++b;
+        return b;
+    }
     // After the call, the lane holds in v[0] the wavefront total of value
-    // index slot(lane) (the first log2(NV) lane bits, reversed).
+    // index slot(lane).
     __device__ __forceinline__ static float reduce(float (&v)[NV], int lane) {
-        BflyStep<NV, NV, 1>::run(v, lane);
+        BflyStep<NV, NV, 0>::run(v, lane);
         return v[0];
     }
     __device__ __forceinline__ static int slot(int lane) {
         int s = 0, cnt = NV;
 #pragma unroll
-        for (int b = 0; (1 << b) < NV; ++b) {
+        for (int st = 0; st < steps(); ++st) {
             cnt >>= 1;
-            if (lane & (1 << b)) s += cnt;
+            if (lane & (1 << bfly_bit(st))) s += cnt;
         }
         return s;
     }
-    static constexpr int lanes_log2() {
-        int b = 0;
-        while ((1 << b) < NV) ++b;
-        return b;
+    // Lane bits summed over after the halving steps; lanes with all of them
+    // clear hold one copy of each slot total.
+    static constexpr int reduced_mask() {
+        int m = 0;
+        for (int st = steps(); st < 6; ++st) m |= 1 << bfly_bit(st);
+        return m;
     }
 };
 
@@ -146,7 +163,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 
     // per-slot scale: dmx, dmy <- -ln2; dA, dC <- -1/2; dB <- -1; others 1
     const int my_slot = Butterfly<NV>::slot(lane);
-    const bool writer = (lane >> Butterfly<NV>::lanes_log2()) == 0 && my_slot < NREAL;
+    const bool writer = (lane & Butterfly<NV>::reduced_mask()) == 0 && my_slot < NREAL;
     float scale = 1.0f;
     if (my_slot < 2) scale = -kLn2;
     else if (my_slot == 2 || my_slot == 4) scale = -0.5f;
@@ -172,44 +189,43 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             const float4 g1 = s_g1[j];
             if (box_misses(g0, g1, wx0, wy0)) continue;
             const int jl = bstart + j - rg.x;
-            float dx = 0.f, dy = 0.f, G = 0.f;
-            bool unc = false;
-            bool contrib = jl < lastp;
-            float a = 0.0f;
-            if (contrib) {
-                a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
-                contrib = a >= amin;
-            }
+            float dx, dy, G;
+            bool unc;
+            const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
+            const bool contrib = jl < lastp && a >= amin;
             if (!__any(contrib)) continue;
+            // Branch-free over the wavefront: lanes without a contribution
+            // take alpha = 0 (T unchanged, exact since rcp(1) = 1, w = 0) and
+            // zero multipliers for the geometric terms.
+            const float ac = contrib ? a : 0.0f;
+            const float* ap = reinterpret_cast<const float*>(&s_app[j * AV]);
+            const float ra = __builtin_amdgcn_rcpf(1.0f - ac);
+            T = T * ra;  // transmittance before this Gaussian
+            const float w = ac * T;
+            float gx = fmaf(g[0], ap[0], fmaf(g[1], ap[1], fmaf(g[2], ap[2], fmaf(g[3], g1.z, g[4]))));
+#pragma unroll
+            for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], ap[3 + f], gx);
+            const float dA = fmaf(T, gx, -Sg * ra);
+            Sg = fmaf(gx, w, Sg);
+            const float hm = (contrib && unc) ? dA : 0.0f;
+            const float h = hm * a;
             float val[NV];
+            val[0] = h * fmaf(2.0f * g0.z, dx, g0.w * dy);
+            val[1] = h * fmaf(g0.w, dx, 2.0f * g1.x * dy);
+            val[2] = h * dx * dx;
+            val[3] = h * dx * dy;
+            val[4] = h * dy * dy;
+            val[5] = g[3] * w;
+            if (PARAMS) {
+                val[6] = hm * G;
+                val[7] = g[0] * w;
+                val[8] = g[1] * w;
+                val[9] = g[2] * w;
 #pragma unroll
-            for (int k = 0; k < NV; ++k) val[k] = 0.0f;
-            if (contrib) {
-                const float* ap = reinterpret_cast<const float*>(&s_app[j * AV]);
-                const float ra = 1.0f / (1.0f - a);
-                T = T * ra;  // transmittance before this Gaussian
-                const float w = a * T;
-                float gx = fmaf(g[0], ap[0], fmaf(g[1], ap[1], fmaf(g[2], ap[2], fmaf(g[3], g1.z, g[4]))));
-#pragma unroll
-                for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], ap[3 + f], gx);
-                const float dA = fmaf(T, gx, -Sg * ra);
-                Sg = fmaf(gx, w, Sg);
-                const float h = unc ? dA * a : 0.0f;
-                val[0] = h * fmaf(2.0f * g0.z, dx, g0.w * dy);
-                val[1] = h * fmaf(g0.w, dx, 2.0f * g1.x * dy);
-                val[2] = h * dx * dx;
-                val[3] = h * dx * dy;
-                val[4] = h * dy * dy;
-                val[5] = g[3] * w;
-                if (PARAMS) {
-                    val[6] = unc ? dA * G : 0.0f;
-                    val[7] = g[0] * w;
-                    val[8] = g[1] * w;
-                    val[9] = g[2] * w;
-#pragma unroll
-                    for (int f = 0; f < F; ++f) val[10 + f] = g[5 + f] * w;
-                }
+                for (int f = 0; f < F; ++f) val[10 + f] = g[5 + f] * w;
             }
+#pragma unroll
+            for (int k = NREAL; k < NV; ++k) val[k] = 0.0f;
             const float tot = Butterfly<NV>::reduce(val, lane);
             if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
         }
