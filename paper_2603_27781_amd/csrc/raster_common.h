@@ -63,6 +63,14 @@ __device__ __forceinline__ float xor_lane(float x) {
     }
 }
 
+// Value of `x` held by lane 7 - (lane & 7) of the same group of 8 (DPP
+// row_half_mirror): the partner differs in lane bit 2, and also in bits 0
+// and 1, so it serves as the bit-2 exchange of a butterfly only while the
+// values do not yet depend on bits 0 and 1.
+__device__ __forceinline__ float mirror8_lane(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x141, 0xF, 0xF, false));
+}
+
 // One exchange of the transposing butterfly across lane bit log2(D) for
 // D = 16, 32 (gfx950 permlane swaps): returns, in every lane, the pair total
 // of lo (lanes with the bit clear) or of hi (lanes with the bit set).  The

@@ -32,12 +32,20 @@ namespace sgs {
 // halving step, across one lane bit, halves the CNT values a lane keeps: a
 // lane with the bit set keeps the upper half and receives its partner's
 // upper half, the partner the opposite, and both add.  Lane bits are taken
-// in the order 5, 4 (permlane swaps: one swap + one add per pair), then 0, 1
-// (DPP), 2 (swizzle), 3 (DPP): after log2(NV) halving steps each lane holds
-// one partial total, and the remaining bits finish the sum across the
-// wavefront.  Every index is a compile-time constant (template recursion),
-// so the values stay in registers.
-__host__ __device__ constexpr int bfly_bit(int s) { return s == 0 ? 5 : (s == 1 ? 4 : s - 2); }
+// in the order 5, 4 (permlane swaps: one swap + one add per pair), 2 (DPP
+// half-row mirror, valid because bits 0 and 1 are still unused), 0, 1 (DPP
+// quad permutations), 3 (DPP row rotation): after log2(NV) halving steps
+// each lane holds one partial total, and the remaining bits finish the sum
+// across the wavefront.  No step goes through LDS.  Every index is a
+// compile-time constant (template recursion), so the values stay in
+// registers.
+__host__ __device__ constexpr int bfly_bit(int s) { return s == 0 ? 5 : (s == 1 ? 4 : (s == 2 ? 2 : (s == 3 ? 0 : (s == 4 ? 1 : 3)))); }
+
+template <int D>
+__device__ __forceinline__ float bfly_partner(float x) {
+    if constexpr (D == 4) return mirror8_lane(x);
+    else return xor_lane<D>(x);
+}
 
 template <int NV, int CNT, int S>
 struct BflyStep {
@@ -55,12 +63,15 @@ struct BflyStep {
                     for (int k = 0; k < HALF; ++k) {
                         const float send = up ? v[k] : v[k + HALF];
                         const float keep = up ? v[k + HALF] : v[k];
-                        v[k] = keep + xor_lane<D>(send);
+                        v[k] = keep + bfly_partner<D>(send);
                     }
                 }
                 BflyStep<NV, HALF, S + 1>::run(v, lane);
             } else {
-                v[0] += xor_lane<D>(v[0]);
+                // full reduction across this bit; the mirror partner is only
+                // valid while bits 0 and 1 are unused, which holds here since
+                // bit 2 comes before them in the order
+                v[0] += bfly_partner<D>(v[0]);
                 BflyStep<NV, 1, S + 1>::run(v, lane);
             }
         }
@@ -121,6 +132,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     constexpr int NV = Pow2<NREAL>::value;
     constexpr int RS = (NREAL + 3) / 4 * 4;  // record stride (floats), float4-aligned
     constexpr int AST = NREAL + 1;           // accumulator stride (odd: spreads LDS banks)
+    constexpr int NQ = B / 64;               // 64-bit candidate masks per batch
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     constexpr int WPR = TS / 8;
     const int sbx = (wave % WPR) * 8, sby = (wave / WPR) * 8;
@@ -152,6 +164,10 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     if (lastp > 0) atomicMax(s_max, lastp);
     __syncthreads();
     const int end = rg.x + *s_max;
+    // the wavefront's own bound: no lane contributes from position wlast on
+    int wlast = lastp;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) wlast = max(wlast, __shfl_xor(wlast, d, kWave));
 
     // instances past every pixel's last contributor: zero records
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -184,50 +200,81 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
         }
         for (int k = tid; k < nb * AST; k += NT) s_acc[k] = 0.0f;
         __syncthreads();
-        for (int j = nb - 1; j >= 0; --j) {
-            const float4 g0 = s_g0[j];
-            const float4 g1 = s_g1[j];
-            if (box_misses(g0, g1, wx0, wy0)) continue;
-            const int jl = bstart + j - rg.x;
-            float dx, dy, G;
-            bool unc;
-            const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
-            const bool contrib = jl < lastp && a >= amin;
-            if (!__any(contrib)) continue;
-            // Branch-free over the wavefront: lanes without a contribution
-            // take alpha = 0 (T unchanged, exact since rcp(1) = 1, w = 0) and
-            // zero multipliers for the geometric terms.
-            const float ac = contrib ? a : 0.0f;
-            const float* ap = reinterpret_cast<const float*>(&s_app[j * AV]);
-            const float ra = __builtin_amdgcn_rcpf(1.0f - ac);
-            T = T * ra;  // transmittance before this Gaussian
-            const float w = ac * T;
-            float gx = fmaf(g[0], ap[0], fmaf(g[1], ap[1], fmaf(g[2], ap[2], fmaf(g[3], g1.z, g[4]))));
+        // Candidates of this wavefront: Gaussians of the batch before its
+        // last contributor whose box reaches its 8x8 block, one bit each
+        // (lane k tests Gaussian 64 q + k).  The loop below visits only
+        // these, from the back, with the next candidate's geometry already
+        // in flight.
+        uint64_t cand[NQ];
 #pragma unroll
-            for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], ap[3 + f], gx);
-            const float dA = fmaf(T, gx, -Sg * ra);
-            Sg = fmaf(gx, w, Sg);
-            const float hm = (contrib && unc) ? dA : 0.0f;
-            const float h = hm * a;
-            float val[NV];
-            val[0] = h * fmaf(2.0f * g0.z, dx, g0.w * dy);
-            val[1] = h * fmaf(g0.w, dx, 2.0f * g1.x * dy);
-            val[2] = h * dx * dx;
-            val[3] = h * dx * dy;
-            val[4] = h * dy * dy;
-            val[5] = g[3] * w;
-            if (PARAMS) {
-                val[6] = hm * G;
-                val[7] = g[0] * w;
-                val[8] = g[1] * w;
-                val[9] = g[2] * w;
+        for (int q = 0; q < NQ; ++q) {
+            const int k = 64 * q + lane;
+            bool ok = false;
+            if (k < nb && bstart + k - rg.x < wlast) ok = !box_misses(s_g0[k], s_g1[k], wx0, wy0);
+            cand[q] = __ballot(ok);
+        }
 #pragma unroll
-                for (int f = 0; f < F; ++f) val[10 + f] = g[5 + f] * w;
+        for (int q = NQ - 1; q >= 0; --q) {
+            uint64_t m = cand[q];
+            if (m == 0) continue;
+            int j = 64 * q + 63 - __builtin_clzll(m);
+            float4 g0 = s_g0[j], g1 = s_g1[j];
+            for (;;) {
+                m &= ~(1ull << (j - 64 * q));
+                const int jn = m ? 64 * q + 63 - __builtin_clzll(m) : -1;
+                // unconditional load (index clamped): a conditional one is
+                // folded into a pointer select that leaves LDS addressing
+                const int jp = jn >= 0 ? jn : j;
+                const float4 g0n = s_g0[jp], g1n = s_g1[jp];
+                float4 av[AV];
+#pragma unroll
+                for (int qq = 0; qq < AV; ++qq) av[qq] = s_app[j * AV + qq];
+                const int jl = bstart + j - rg.x;
+                float dx, dy, G;
+                bool unc;
+                const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
+                const bool contrib = jl < lastp && a >= amin;
+                if (__any(contrib)) {
+                    // Branch-free over the wavefront: lanes without a
+                    // contribution take alpha = 0 (T unchanged, exact since
+                    // rcp(1) = 1, w = 0) and zero multipliers.
+                    const float ac = contrib ? a : 0.0f;
+                    const float* ap = reinterpret_cast<const float*>(av);
+                    const float ra = __builtin_amdgcn_rcpf(1.0f - ac);
+                    T = T * ra;  // transmittance before this Gaussian
+                    const float w = ac * T;
+                    float gx = fmaf(g[0], ap[0], fmaf(g[1], ap[1], fmaf(g[2], ap[2], fmaf(g[3], g1.z, g[4]))));
+#pragma unroll
+                    for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], ap[3 + f], gx);
+                    const float dA = fmaf(T, gx, -Sg * ra);
+                    Sg = fmaf(gx, w, Sg);
+                    const float hm = (contrib && unc) ? dA : 0.0f;
+                    const float h = hm * a;
+                    float val[NV];
+                    val[0] = h * fmaf(2.0f * g0.z, dx, g0.w * dy);
+                    val[1] = h * fmaf(g0.w, dx, 2.0f * g1.x * dy);
+                    val[2] = h * dx * dx;
+                    val[3] = h * dx * dy;
+                    val[4] = h * dy * dy;
+                    val[5] = g[3] * w;
+                    if (PARAMS) {
+                        val[6] = hm * G;
+                        val[7] = g[0] * w;
+                        val[8] = g[1] * w;
+                        val[9] = g[2] * w;
+#pragma unroll
+                        for (int f = 0; f < F; ++f) val[10 + f] = g[5 + f] * w;
+                    }
+#pragma unroll
+                    for (int k = NREAL; k < NV; ++k) val[k] = 0.0f;
+                    const float tot = Butterfly<NV>::reduce(val, lane);
+                    if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
+                }
+                if (jn < 0) break;
+                j = jn;
+                g0 = g0n;
+                g1 = g1n;
             }
-#pragma unroll
-            for (int k = NREAL; k < NV; ++k) val[k] = 0.0f;
-            const float tot = Butterfly<NV>::reduce(val, lane);
-            if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
         }
         __syncthreads();
         // one contiguous record per instance of the batch (zeros if untouched)
@@ -244,8 +291,11 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     }
 }
 
+// Occupancy: the kernel is latency-bound (LDS reads and cross-lane steps on
+// every Gaussian), so with up to 16 feature channels the register budget is
+// capped at five wavefronts per SIMD (the values fit without spills).
 template <int TS, int F, int B, bool PARAMS>
-__global__ void __launch_bounds__(TS* TS) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
+__global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <= 16 ? 5 : 1, 8))) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
                                                        int n, const int32_t* __restrict__ inst,
                                                        const int32_t* __restrict__ inst_gid,
                                                        const int2* __restrict__ ranges,

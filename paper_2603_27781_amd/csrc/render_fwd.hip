@@ -9,10 +9,12 @@
 // touches few wavefronts).  The tile's depth-sorted list is walked in
 // batches of B instances that the whole workgroup stages into LDS (geometry
 // as two float4, appearance as (3+F) floats padded to float4); every
-// wavefront then reads them as broadcasts.  A wavefront skips a Gaussian
-// whose pixel box misses its 8x8 block (uniform branch, no exp), a pixel
-// stops when T would fall below T_min, a wavefront stops when all of its
-// pixels stopped and the workgroup stops when every wavefront did.
+// wavefront then reads them as broadcasts.  Per batch, each wavefront
+// ballots which Gaussians' pixel boxes reach its 8x8 block (one bit per
+// Gaussian) and visits only those, with the next one's geometry already in
+// flight; a pixel stops when T would fall below T_min, a wavefront stops
+// when all of its pixels stopped and the workgroup stops when every
+// wavefront did.
 //
 // persistent = 1 launches ~one wave of workgroups that pull tile indices
 // from a device counter (all views share one queue), so views of uneven
@@ -30,6 +32,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                                          int32_t* __restrict__ last, float4* s_g0, float4* s_g1, float4* s_app) {
     constexpr int NT = TS * TS;
     constexpr int AV = AppRec<F>::vec;
+    constexpr int NQ = B / 64;  // 64-bit candidate masks per batch
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     constexpr int WPR = TS / 8;
     const int sbx = (wave % WPR) * 8, sby = (wave / WPR) * 8;
@@ -69,33 +72,58 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
         }
         __syncthreads();
         if (!__all(done)) {
-            for (int j = 0; j < nb; ++j) {
-                const float4 g0 = s_g0[j];
-                const float4 g1 = s_g1[j];
-                if (box_misses(g0, g1, wx0, wy0)) continue;
-                if (!done) {
+            uint64_t cand[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int k = 64 * q + lane;
+                cand[q] = __ballot(k < nb && !box_misses(s_g0[k], s_g1[k], wx0, wy0));
+            }
+            bool wdone = false;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                uint64_t m = cand[q];
+                if (m == 0 || wdone) continue;
+                int j = 64 * q + __builtin_ctzll(m);
+                float4 g0 = s_g0[j], g1 = s_g1[j];
+                for (;;) {
+                    m &= m - 1;
+                    const int jn = m ? 64 * q + __builtin_ctzll(m) : -1;
+                    // unconditional load (index clamped): a conditional one is
+                    // folded into a pointer select that leaves LDS addressing
+                    const int jp = jn >= 0 ? jn : j;
+                    const float4 g0n = s_g0[jp], g1n = s_g1[jp];
+                    float4 av[AV];
+#pragma unroll
+                    for (int qq = 0; qq < AV; ++qq) av[qq] = s_app[j * AV + qq];
                     float dx, dy, G;
                     bool unc;
                     const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
-                    if (a >= amin) {
-                        const float Tn = T * (1.0f - a);
-                        if (Tn < tmin) {
-                            done = true;
-                        } else {
-                            const float w = a * T;
-                            const float* ap = reinterpret_cast<const float*>(&s_app[j * AV]);
-                            acc[0] = fmaf(w, ap[0], acc[0]);
-                            acc[1] = fmaf(w, ap[1], acc[1]);
-                            acc[2] = fmaf(w, ap[2], acc[2]);
-                            acc[3] = fmaf(w, g1.z, acc[3]);
+                    const bool ok = !done && a >= amin;
+                    const float Tn = T * (1.0f - a);
+                    const bool use = ok && !(Tn < tmin);
+                    if (__any(use)) {
+                        // lanes not contributing add exactly 0 * x
+                        const float w = use ? a * T : 0.0f;
+                        const float* ap = reinterpret_cast<const float*>(av);
+                        acc[0] = fmaf(w, ap[0], acc[0]);
+                        acc[1] = fmaf(w, ap[1], acc[1]);
+                        acc[2] = fmaf(w, ap[2], acc[2]);
+                        acc[3] = fmaf(w, g1.z, acc[3]);
 #pragma unroll
-                            for (int f = 0; f < F; ++f) acc[4 + f] = fmaf(w, ap[3 + f], acc[4 + f]);
-                            T = Tn;
-                            lastj = b0 - rg.x + j + 1;
-                        }
+                        for (int f = 0; f < F; ++f) acc[4 + f] = fmaf(w, ap[3 + f], acc[4 + f]);
+                        T = use ? Tn : T;
+                        lastj = use ? b0 - rg.x + j + 1 : lastj;
                     }
+                    done = done || (ok && Tn < tmin);
+                    if (__all(done)) {
+                        wdone = true;
+                        break;
+                    }
+                    if (jn < 0) break;
+                    j = jn;
+                    g0 = g0n;
+                    g1 = g1n;
                 }
-                if (__all(done)) break;
             }
         }
     }
