@@ -4,30 +4,98 @@
 // each averaged over the pixels of its view, weighted by (w0, w1, w2).
 // W is the fixed linear decoder standing in for F_cnn (Sec. 3.2.2, Eq. 8).
 //
-// One thread per pixel: the F feature channels stay in registers, the
-// decoder sits in LDS (broadcast reads), and the softmax is evaluated with
-// a running maximum (one pass for the log-sum-exp, one for the gradient) so
-// no per-class array is needed.  The loss value is reduced per block into a
-// partial-sum array and then summed in a fixed order by one block (no
-// same-address atomics, deterministic).
+// One thread per pixel: the F feature channels stay in registers.  The
+// decoder is first copied transposed (one row of F floats per class) into
+// the workspace, so that in the pixel kernel a class row is one
+// wavefront-uniform scalar load whose values feed the FMAs directly.  With
+// at most KC classes the logits z_k = sum_f W[f][k] F_f are kept in
+// registers: one pass computes them and their maximum, a second forms the
+// softmax weights and dCE/dF_f = sum_k W[f][k] softmax_k - W[f][label].
+// More classes recompute z in the second pass.  The loss value is reduced
+// per block into a partial-sum array and then summed in a fixed order by
+// one block (no same-address atomics, deterministic).
 #include "sgs_common.h"
 
 namespace sgs {
 
-template <int F>
-__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ out, int64_t P,
-                                              const float* __restrict__ rgb_t, const float* __restrict__ depth_t,
-                                              const int32_t* __restrict__ labels, const float* __restrict__ decoder,
-                                              int K, float w0, float w1, float w2,
-                                              const gs_view* __restrict__ views, int n_views,
-                                              float* __restrict__ grad_out, double* __restrict__ partials) {
-    __shared__ float sW[(F > 0 ? F : 1) * GS_MAX_CLASSES];
-    __shared__ double s_red[3][256 / kWave];
-    const int tid = threadIdx.x;
-    if (F > 0) {
-        for (int k = tid; k < F * K; k += blockDim.x) sW[k] = decoder[k];
+constexpr int kLossThreads = 256;
+constexpr int kLossKC = 64;  // classes whose logits are kept in registers
+
+__global__ void k_transpose_decoder(const float* __restrict__ W, int F, int K, float* __restrict__ Wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F * K) return;
+    const int f = i / K, k = i - f * K;
+    Wt[k * F + f] = W[i];
+}
+
+template <int F, bool CACHED>
+__device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], const float* __restrict__ Wt, int K,
+                                             int lab, float (&gf)[F > 0 ? F : 1]) {
+    float m = -INFINITY, zl = 0.0f, se = 0.0f;
+    float ga[F > 0 ? F : 1];
+#pragma unroll
+    for (int f = 0; f < F; ++f) ga[f] = 0.0f;
+    if constexpr (CACHED) {
+        float z[kLossKC];
+#pragma unroll
+        for (int k = 0; k < kLossKC; ++k) {
+            if (k < K) {
+                const float* wr = Wt + k * F;
+                float acc = 0.0f;
+#pragma unroll
+                for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
+                z[k] = acc;
+                m = fmaxf(m, acc);
+                zl = k == lab ? acc : zl;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kLossKC; ++k) {
+            if (k < K) {
+                const float* wr = Wt + k * F;
+                const float e = __expf(z[k] - m);
+                se += e;
+#pragma unroll
+                for (int f = 0; f < F; ++f) ga[f] = fmaf(wr[f], e, ga[f]);
+            }
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            const float* wr = Wt + k * F;
+            float acc = 0.0f;
+#pragma unroll
+            for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
+            m = fmaxf(m, acc);
+            zl = k == lab ? acc : zl;
+        }
+        for (int k = 0; k < K; ++k) {
+            const float* wr = Wt + k * F;
+            float acc = 0.0f;
+#pragma unroll
+            for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
+            const float e = __expf(acc - m);
+            se += e;
+#pragma unroll
+            for (int f = 0; f < F; ++f) ga[f] = fmaf(wr[f], e, ga[f]);
+        }
     }
-    __syncthreads();
+    const float inv = 1.0f / se;
+    const bool lab_ok = lab >= 0 && lab < K;
+#pragma unroll
+    for (int f = 0; f < F; ++f) gf[f] = ga[f] * inv - (lab_ok ? Wt[lab * F + f] : 0.0f);
+    return (m + __logf(se)) - zl;
+}
+
+template <int F, bool CACHED>
+__global__ void __launch_bounds__(kLossThreads) k_loss(const float* __restrict__ out, int64_t P,
+                                                       const float* __restrict__ rgb_t,
+                                                       const float* __restrict__ depth_t,
+                                                       const int32_t* __restrict__ labels,
+                                                       const float* __restrict__ Wt, int K, float w0, float w1,
+                                                       float w2, const gs_view* __restrict__ views, int n_views,
+                                                       float* __restrict__ grad_out, double* __restrict__ partials) {
+    __shared__ double s_red[3][kLossThreads / kWave];
+    const int tid = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + tid;
     double lc = 0.0, ld = 0.0, ls = 0.0;
     if (p < P) {
@@ -52,34 +120,7 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ out, int
             float gf[F > 0 ? F : 1];
 #pragma unroll
             for (int f = 0; f < F; ++f) gf[f] = 0.0f;
-            if (K > 0 && w2 != 0.0f) {
-                const int lab = labels[p];
-                // pass 1: running log-sum-exp of z_k = sum_f W[f][k] F_f
-                float m = -INFINITY, se = 0.0f, zl = 0.0f;
-                for (int k = 0; k < K; ++k) {
-                    float z = 0.0f;
-#pragma unroll
-                    for (int f = 0; f < F; ++f) z = fmaf(sW[f * K + k], fv[f], z);
-                    if (k == lab) zl = z;
-                    if (z > m) {
-                        se = se * __expf(m - z) + 1.0f;
-                        m = z;
-                    } else {
-                        se += __expf(z - m);
-                    }
-                }
-                const float inv = 1.0f / se;
-                ls += (double)((m + __logf(se)) - zl);
-                // pass 2: dCE/dF_f = sum_k W[f][k] (softmax_k - [k == label])
-                for (int k = 0; k < K; ++k) {
-                    float z = 0.0f;
-#pragma unroll
-                    for (int f = 0; f < F; ++f) z = fmaf(sW[f * K + k], fv[f], z);
-                    const float e = __expf(z - m) * inv - (k == lab ? 1.0f : 0.0f);
-#pragma unroll
-                    for (int f = 0; f < F; ++f) gf[f] = fmaf(sW[f * K + k], e, gf[f]);
-                }
-            }
+            if (K > 0 && w2 != 0.0f) ls += (double)semantic_ce<F, CACHED>(fv, Wt, K, labels[p], gf);
 #pragma unroll
             for (int f = 0; f < F; ++f) grad_out[(5 + f) * P + p] = gs * gf[f];
         }
@@ -107,21 +148,33 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ out, int
     }
 }
 
-// Fixed-order sum of the per-block partials: loss = (colour, depth, semantic, total).
-__global__ void __launch_bounds__(256) k_loss_final(const double* __restrict__ partials, int nblk,
-                                                    double* __restrict__ loss) {
-    __shared__ double s[3][256];
-    double acc[3] = {0, 0, 0};
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-        for (int k = 0; k < 3; ++k) acc[k] += partials[3 * (size_t)b + k];
-    for (int k = 0; k < 3; ++k) s[k][threadIdx.x] = acc[k];
+// Fixed-order sum of the per-block partials: loss = (colour, depth, semantic,
+// total).  Thread t sums partials t, t + 1024, ... (four independent chains
+// per term), then a fixed tree over the threads.
+__global__ void __launch_bounds__(1024) k_loss_final(const double* __restrict__ partials, int nblk,
+                                                     double* __restrict__ loss) {
+    __shared__ double s[3][1024];
+    const int t = threadIdx.x;
+    double acc[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    int b = t;
+    for (; b + 3 * 1024 < nblk; b += 4 * 1024)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k][u] += partials[3 * (size_t)(b + u * 1024) + k];
+    for (int u = 0; b < nblk; b += 1024, ++u)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k][u & 3] += partials[3 * (size_t)b + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[k][t] = (acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3]);
     __syncthreads();
-    for (int d = blockDim.x / 2; d > 0; d >>= 1) {
-        if ((int)threadIdx.x < d)
-            for (int k = 0; k < 3; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + d];
+    for (int d = 512; d > 0; d >>= 1) {
+        if (t < d)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s[k][t] += s[k][t + d];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         loss[0] = s[0][0];
         loss[1] = s[1][0];
         loss[2] = s[2][0];
@@ -129,18 +182,33 @@ __global__ void __launch_bounds__(256) k_loss_final(const double* __restrict__ p
     }
 }
 
-size_t loss_workspace_bytes(int64_t P) { return (size_t)((P + 255) / 256) * 3 * sizeof(double) + 16; }
+// workspace: per-block partials (3 doubles each), then the transposed decoder
+static size_t loss_partials_bytes(int64_t P) {
+    return ((size_t)((P + kLossThreads - 1) / kLossThreads) * 3 * sizeof(double) + 255) / 256 * 256;
+}
+size_t loss_workspace_bytes(int64_t P) {
+    return loss_partials_bytes(P) + (size_t)32 * GS_MAX_CLASSES * sizeof(float);  // F <= 32
+}
 
 template <int F>
 hipError_t launch_loss_t(const float* out, const float* rgb_t, const float* depth_t, const int32_t* labels,
                          const float* decoder, int K, const float* w, const gs_view* views, int n_views, int64_t P,
                          float* grad_out, double* loss, void* ws, hipStream_t s) {
     if (P == 0) return hipSuccess;
-    const int nblk = (int)((P + 255) / 256);
+    const int nblk = (int)((P + kLossThreads - 1) / kLossThreads);
     double* partials = static_cast<double*>(ws);
-    hipLaunchKernelGGL(k_loss<F>, dim3((unsigned)nblk), dim3(256), 0, s, out, P, rgb_t, depth_t, labels, decoder, K,
-                       w[0], w[1], w[2], views, n_views, grad_out, partials);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, partials, nblk, loss);
+    float* Wt = reinterpret_cast<float*>(static_cast<char*>(ws) + loss_partials_bytes(P));
+    const bool sem = F > 0 && K > 0 && w[2] != 0.0f;
+    if (sem)
+        hipLaunchKernelGGL(k_transpose_decoder, dim3((unsigned)ceil_div(F * K, 256)), dim3(256), 0, s, decoder, F, K,
+                           Wt);
+    if (sem && K > kLossKC)
+        hipLaunchKernelGGL((k_loss<F, false>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t, depth_t,
+                           labels, Wt, K, w[0], w[1], w[2], views, n_views, grad_out, partials);
+    else
+        hipLaunchKernelGGL((k_loss<F, true>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t, depth_t,
+                           labels, Wt, K, w[0], w[1], w[2], views, n_views, grad_out, partials);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, s, partials, nblk, loss);
     return hipGetLastError();
 }
 

@@ -159,6 +159,17 @@ def test_persistent_forward_is_bit_identical():
 
 @pytest.mark.parametrize("name", ["tiny3views-F16", "cfg2-160x120-20k-F16", "tiny-F32"])
 def test_loss_grad_parity(name):
+    _loss_case(name, K=20)
+
+
+@pytest.mark.parametrize("K", [1, 64, 65, 200])
+def test_loss_grad_class_counts(K):
+    """Class counts around the register-cached limit (64): cached logits and
+    the recomputing path give the oracle's loss and gradient alike."""
+    _loss_case("tiny-F8", K=K)
+
+
+def _loss_case(name, K):
     scene, views, r, g, cfg = _render(name, 16)
     F = scene.n_feat
     rng = np.random.default_rng(7)
@@ -166,7 +177,6 @@ def test_loss_grad_parity(name):
     out32 = r.out.cpu().numpy()
     rgb_t = rng.uniform(0, 1, size=(3, P)).astype(np.float32)
     dep_t = rng.uniform(1, 4, size=P).astype(np.float32)
-    K = 20
     lab = rng.integers(0, K, size=P).astype(np.int32)
     W = wl.decoder_matrix(rng, F, K)
     wts = (0.5, 1.0, 0.01)
