@@ -44,17 +44,20 @@ __device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, 
 // Value of `x` held by lane (lane ^ D) of the wavefront.  D = 1, 2: DPP
 // quad permutation; D = 8: DPP row rotation by 8 (within a row of 16 lanes
 // that is lane ^ 8); all three are VALU operand modifiers, no LDS traffic.
+// Their source lanes always exist, so bound_ctrl (read 0 for a missing
+// source) changes nothing but lets the compiler fold the move into the
+// consuming add.
 // D = 4, 16: ds_swizzle in xor mode (within 32-lane halves); D = 32:
 // ds_bpermute.
 template <int D>
 __device__ __forceinline__ float xor_lane(float x) {
     const int v = __float_as_int(x);
     if constexpr (D == 1) {
-        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));  // quad_perm [1,0,3,2]
     } else if constexpr (D == 2) {
-        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));  // quad_perm [2,3,0,1]
     } else if constexpr (D == 8) {
-        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));  // row_ror:8
+        return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true));  // row_ror:8
     } else if constexpr (D < 32) {
         return __int_as_float(__builtin_amdgcn_ds_swizzle(v, (D << 10) | 0x1F));  // xor_mask D, and_mask 31
     } else {
@@ -68,7 +71,7 @@ __device__ __forceinline__ float xor_lane(float x) {
 // and 1, so it serves as the bit-2 exchange of a butterfly only while the
 // values do not yet depend on bits 0 and 1.
 __device__ __forceinline__ float mirror8_lane(float x) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x141, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x141, 0xF, 0xF, true));
 }
 
 // One exchange of the transposing butterfly across lane bit log2(D) for

@@ -330,30 +330,36 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <
 }
 
 // Sum of the records of every (view, Gaussian) pair (contiguous emission
-// indices, fixed order), one thread per Gaussian looping over the views:
-// grad_geo[V][n][8] <- (dmx, dmy, dA, dB, dC, dd, 0, 0) for visible pairs
-// (others are not written); grad_app[n][4+F] <- the appearance part summed
-// over views.
+// indices, fixed order).  One lane per (Gaussian, view) pair: the VP lanes of
+// a Gaussian are adjacent in one wavefront (VP a power of two, VP <= 64; with
+// more views than VP a lane takes views vl, vl + VP, ...), so every pair's
+// chain of loads runs in parallel.  grad_geo[V][n][8] <- (dmx, dmy, dA, dB,
+// dC, dd, 0, 0) for visible pairs (others are not written); the appearance
+// part is summed over the Gaussian's lanes by a fixed xor tree and
+// grad_app[n][4+F] written by its first lane (deterministic).
 template <int F, bool PARAMS>
 __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict__ records,
                                                         const int32_t* __restrict__ pair_first,
                                                         const int32_t* __restrict__ touched, int n, int n_views,
-                                                        int64_t capacity, float* __restrict__ grad_geo,
+                                                        int vp_log2, int64_t capacity, float* __restrict__ grad_geo,
                                                         float* __restrict__ grad_app) {
     constexpr int NREAL = PARAMS ? 10 + F : 6;
     constexpr int RS = (NREAL + 3) / 4 * 4;
     constexpr int NA = PARAMS ? 4 + F : 1;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int vp = 1 << vp_log2;
+    const int64_t i64 = t >> vp_log2;
+    const int vl = (int)(t & (vp - 1));
+    const int i = (int)(i64 < n ? i64 : n);
     float appacc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) appacc[q] = 0.0f;
-    for (int v = 0; v < n_views; ++v) {
-        const size_t pair = (size_t)v * n + i;
-        const int cnt = touched[pair];
-        if (cnt <= 0) continue;
-        float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        {
+    if (i64 < n) {
+        for (int v = vl; v < n_views; v += vp) {
+            const size_t pair = (size_t)v * n + i;
+            const int cnt = touched[pair];
+            if (cnt <= 0) continue;
+            float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             const int64_t first = pair_first[pair];
             const int64_t stop = first + cnt < capacity ? first + cnt : capacity;  // truncated lists
             for (int64_t e = first; e < stop; ++e) {
@@ -374,15 +380,20 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
                     for (int q = 0; q < NA; ++q) appacc[q] += r[6 + q];
                 }
             }
+            float4* gg = reinterpret_cast<float4*>(grad_geo + pair * 8);
+            gg[0] = make_float4(geo[0], geo[1], geo[2], geo[3]);
+            gg[1] = make_float4(geo[4], geo[5], 0.f, 0.f);
         }
-        float4* gg = reinterpret_cast<float4*>(grad_geo + pair * 8);
-        gg[0] = make_float4(geo[0], geo[1], geo[2], geo[3]);
-        gg[1] = make_float4(geo[4], geo[5], 0.f, 0.f);
     }
     if (PARAMS) {
-        float* ga = grad_app + (size_t)i * (4 + F);
+        for (int d = 1; d < vp; d <<= 1)
 #pragma unroll
-        for (int q = 0; q < NA; ++q) ga[q] = appacc[q];
+            for (int q = 0; q < NA; ++q) appacc[q] += __shfl_xor(appacc[q], d, kWave);
+        if (i64 < n && vl == 0) {
+            float* ga = grad_app + (size_t)i * (4 + F);
+#pragma unroll
+            for (int q = 0; q < NA; ++q) ga[q] = appacc[q];
+        }
     }
 }
 
@@ -488,13 +499,16 @@ hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_fe
 template <int F>
 hipError_t launch_reduce_t(bool params, const float* records, const int32_t* pair_first, const int32_t* touched,
                            int n, int n_views, int64_t capacity, float* grad_geo, float* grad_app, hipStream_t s) {
-    const dim3 grid((unsigned)ceil_div(n, 256));
+    int vp_log2 = 0;
+    while ((1 << vp_log2) < n_views && vp_log2 < 6) ++vp_log2;
+    const int64_t lanes = (int64_t)n << vp_log2;
+    const dim3 grid((unsigned)((lanes + 255) / 256));
     if (params)
         hipLaunchKernelGGL((k_reduce_records<F, true>), grid, dim3(256), 0, s, records, pair_first, touched, n, n_views,
-                           capacity, grad_geo, grad_app);
+                           vp_log2, capacity, grad_geo, grad_app);
     else
         hipLaunchKernelGGL((k_reduce_records<F, false>), grid, dim3(256), 0, s, records, pair_first, touched, n,
-                           n_views, capacity, grad_geo, grad_app);
+                           n_views, vp_log2, capacity, grad_geo, grad_app);
     return hipGetLastError();
 }
 
