@@ -23,11 +23,27 @@ namespace {
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+constexpr int TOP_THREADS = 1024;
 
+// Radix passes run on a fixed grid of at most RS_MAXBLK blocks; the device
+// side count is split into contiguous chunks (multiples of RS_THREADS), one
+// per block, so the digit histograms stay small whatever the capacity and
+// only blocks with elements do work.
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int RS_MAXBLK = 1024;
 constexpr int RS_WAVES = RS_THREADS / kWave;
+
+int rs_blocks(int64_t n_max) {
+    const int64_t b = (n_max + RS_THREADS - 1) / RS_THREADS;
+    return (int)(b < RS_MAXBLK ? (b > 0 ? b : 1) : RS_MAXBLK);
+}
+
+__device__ __forceinline__ void rs_chunk(int64_t count, int nblk, int64_t& lo, int64_t& hi) {
+    const int64_t per = ((count + nblk - 1) / nblk + RS_THREADS - 1) / RS_THREADS * RS_THREADS;
+    lo = (int64_t)blockIdx.x * per;
+    lo = lo < count ? lo : count;
+    hi = lo + per < count ? lo + per : count;
+}
 
 __device__ __forceinline__ int64_t eff_count(const int64_t* count_dev, int64_t n_max) {
     if (count_dev == nullptr) return n_max;
@@ -52,7 +68,9 @@ struct LoadU32 {
     __device__ uint32_t operator()(int64_t i) const { return p[i]; }
 };
 
-// Exclusive scan of the block's SCAN_THREADS thread totals (in LDS).
+// Exclusive scan of the block's NT thread totals (wave scans, then the wave
+// totals in LDS); *total receives the block total.
+template <int NT>
 __device__ uint32_t block_exclusive(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     uint32_t x = v;
@@ -64,7 +82,7 @@ __device__ uint32_t block_exclusive(uint32_t v, uint32_t* s_tmp, uint32_t* total
     if (lane == kWave - 1) s_tmp[wave] = x;
     __syncthreads();
     uint32_t wbase = 0, tot = 0;
-    for (int w = 0; w < SCAN_THREADS / kWave; ++w) {
+    for (int w = 0; w < NT / kWave; ++w) {
         const uint32_t s = s_tmp[w];
         if (w < wave) wbase += s;
         tot += s;
@@ -85,23 +103,26 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_partial(Load ld, const in
     for (int k = 0; k < SCAN_ITEMS; ++k)
         if (base + k < count) acc += ld(base + k);
     uint32_t tot;
-    block_exclusive(acc, s_tmp, &tot);
+    block_exclusive<SCAN_THREADS>(acc, s_tmp, &tot);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// Single-block exclusive scan of the block sums, total to *total (int64).
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_top(uint32_t* block_sums, int nblocks, int64_t* total) {
-    __shared__ uint32_t s_tmp[SCAN_THREADS / kWave];
-    uint32_t carry = 0;
-    for (int base = 0; base < nblocks; base += SCAN_THREADS) {
-        const int i = base + threadIdx.x;
-        const uint32_t v = i < nblocks ? block_sums[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_exclusive(v, s_tmp, &tot);
-        if (i < nblocks) block_sums[i] = carry + ex;
-        carry += tot;
+// Single-block exclusive scan of the block sums, total to *total (int64):
+// each of the TOP_THREADS threads takes a contiguous run of sums.
+__global__ void __launch_bounds__(TOP_THREADS) k_scan_top(uint32_t* block_sums, int nblocks, int64_t* total) {
+    __shared__ uint32_t s_tmp[TOP_THREADS / kWave];
+    const int per = (nblocks + TOP_THREADS - 1) / TOP_THREADS;
+    const int b0 = min(nblocks, (int)threadIdx.x * per), b1 = min(nblocks, b0 + per);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += block_sums[b];
+    uint32_t tot;
+    uint32_t run = block_exclusive<TOP_THREADS>(sum, s_tmp, &tot);
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t v = block_sums[b];
+        block_sums[b] = run;
+        run += v;
     }
-    if (threadIdx.x == 0 && total != nullptr) *total = (int64_t)carry;
+    if (threadIdx.x == 0 && total != nullptr) *total = (int64_t)tot;
 }
 
 template <class Load>
@@ -119,7 +140,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_final(Load ld, const int6
         acc += v[k];
     }
     uint32_t tot;
-    uint32_t run = block_sums[blockIdx.x] + block_exclusive(acc, s_tmp, &tot);
+    uint32_t run = block_sums[blockIdx.x] + block_exclusive<SCAN_THREADS>(acc, s_tmp, &tot);
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         if (base + k < count) out[base + k] = run;
@@ -133,12 +154,12 @@ hipError_t exclusive_scan(Load ld, const int64_t* count_dev, int64_t n_max, uint
     const int nb = (int)((n_max + SCAN_TILE - 1) / SCAN_TILE);
     if (nb == 0) {
         if (total) {
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, block_sums, 0, total);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, block_sums, 0, total);
         }
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_partial<Load>, dim3(nb), dim3(SCAN_THREADS), 0, s, ld, count_dev, n_max, block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, block_sums, nb, total);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, block_sums, nb, total);
     hipLaunchKernelGGL(k_scan_final<Load>, dim3(nb), dim3(SCAN_THREADS), 0, s, ld, count_dev, n_max, block_sums,
                        out);
     return hipGetLastError();
@@ -166,17 +187,15 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint32_t* __res
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     h[tid] = 0;
     __syncthreads();
-    const int64_t count = eff_count(count_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    if (base < count) {
-        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        for (int it = 0; it < RS_ITEMS; ++it) {
-            const int64_t i = base + (int64_t)it * RS_THREADS + tid;
-            const bool valid = i < count;
-            const uint32_t d = valid ? ((keys[i] >> shift) & 0xffu) : 0u;
-            const uint64_t peers = match_digit(d, valid);
-            if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
-        }
+    int64_t lo, hi;
+    rs_chunk(eff_count(count_dev, n_max), nblk, lo, hi);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t i0 = lo; i0 < hi; i0 += RS_THREADS) {
+        const int64_t i = i0 + tid;
+        const bool valid = i < hi;
+        const uint32_t d = valid ? ((keys[i] >> shift) & 0xffu) : 0u;
+        const uint64_t peers = match_digit(d, valid);
+        if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
@@ -191,17 +210,17 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint32_t* __
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_wcnt[RS_WAVES][256];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int64_t count = eff_count(count_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    if (base >= count) return;  // uniform across the block
+    int64_t lo, hi;
+    rs_chunk(eff_count(count_dev, n_max), nblk, lo, hi);
+    if (lo >= hi) return;  // uniform across the block
     s_base[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
 #pragma unroll
     for (int w = 0; w < RS_WAVES; ++w) s_wcnt[w][tid] = 0;
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int it = 0; it < RS_ITEMS; ++it) {
-        const int64_t i = base + (int64_t)it * RS_THREADS + tid;
-        const bool valid = i < count;
+    for (int64_t i0 = lo; i0 < hi; i0 += RS_THREADS) {
+        const int64_t i = i0 + tid;
+        const bool valid = i < hi;
         const uint32_t key = valid ? keys_in[i] : 0u;
         const uint32_t val = valid ? vals_in[i] : 0u;
         const uint32_t d = (key >> shift) & 0xffu;
@@ -231,8 +250,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint32_t* __
 // ping-ponging with (keys2, vals2); an even pass count ends in (keys, vals).
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t* vals2, const int64_t* count_dev,
                       int64_t n_max, int passes, uint32_t* hist, uint32_t* block_sums, hipStream_t s) {
-    const int nblk = (int)((n_max + RS_TILE - 1) / RS_TILE);
-    if (nblk == 0) return hipSuccess;
+    if (n_max <= 0) return hipSuccess;
+    const int nblk = rs_blocks(n_max);
     uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
@@ -250,14 +269,65 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t*
 // ----------------------------------------------------------------------------
 // pipeline kernels
 // ----------------------------------------------------------------------------
-__global__ void k_compact_visible(const int32_t* __restrict__ touched, const float4* __restrict__ rec,
-                                  const uint32_t* __restrict__ pos, int64_t vn, uint32_t* __restrict__ keys,
-                                  uint32_t* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= vn || touched[i] <= 0) return;
-    const uint32_t p = pos[i];
-    keys[p] = __float_as_uint(rec[2 * i + 1].z);  // camera depth, positive: bits are monotone
-    vals[p] = (uint32_t)i;
+// Order-preserving compaction of the visible pairs in three steps: the
+// visible count of each run of CV_RUN consecutive pairs, an exclusive scan
+// of those counts (one block), then each run ranks its pairs with ballots
+// and writes (depth bits, pair index) at its offset.
+constexpr int CV_THREADS = 256;
+constexpr int CV_RUN = 1024;
+
+__global__ void __launch_bounds__(CV_THREADS) k_count_visible(const int32_t* __restrict__ touched, int64_t vn,
+                                                              uint32_t* __restrict__ run_counts) {
+    __shared__ uint32_t s_w[CV_THREADS / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t base = (int64_t)blockIdx.x * CV_RUN;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < CV_RUN / CV_THREADS; ++k) {
+        const int64_t i = base + k * CV_THREADS + tid;
+        c += (i < vn && touched[i] > 0) ? 1u : 0u;
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
+    if (lane == 0) s_w[wave] = c;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < CV_THREADS / kWave; ++w) t += s_w[w];
+        run_counts[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* __restrict__ touched,
+                                                                const float4* __restrict__ rec,
+                                                                const uint32_t* __restrict__ run_offs, int64_t vn,
+                                                                uint32_t* __restrict__ keys,
+                                                                uint32_t* __restrict__ vals) {
+    __shared__ uint32_t s_w[CV_THREADS / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t base = (int64_t)blockIdx.x * CV_RUN;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t run = run_offs[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < CV_RUN / CV_THREADS; ++k) {
+        const int64_t i = base + k * CV_THREADS + tid;
+        const bool vis = i < vn && touched[i] > 0;
+        const uint64_t m = __ballot(vis);
+        if (lane == 0) s_w[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t off = run, tot = 0;
+#pragma unroll
+        for (int w = 0; w < CV_THREADS / kWave; ++w) {
+            if (w < wave) off += s_w[w];
+            tot += s_w[w];
+        }
+        if (vis) {
+            const uint32_t p = off + (uint32_t)__popcll(m & lt);
+            keys[p] = __float_as_uint(rec[2 * i + 1].z);  // camera depth, positive: bits are monotone
+            vals[p] = (uint32_t)i;
+        }
+        run += tot;
+        __syncthreads();
+    }
 }
 
 __global__ void k_counts(const int64_t* n_inst, const int64_t* n_vis, int64_t capacity, int64_t* counts,
@@ -321,7 +391,7 @@ WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     const int64_t vn = (int64_t)n * n_views;
     const int64_t cap = capacity > 0 ? capacity : 1;
     const int64_t big = vn > cap ? vn : cap;
-    const int64_t nblk = (big + RS_TILE - 1) / RS_TILE;
+    const int64_t nblk = rs_blocks(big);
     const int64_t scan_n = (256 * nblk > big ? 256 * nblk : big);
     const int64_t nbs = (scan_n + SCAN_TILE - 1) / SCAN_TILE + 1;
     WsLayout L;
@@ -364,11 +434,14 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     hipError_t e;
 
     // 1. order-preserving compaction of the visible pairs, key = depth bits
-    e = exclusive_scan(LoadNonZero{touched}, nullptr, vn, bsum, pos, &cnt[0], s);
-    if (e != hipSuccess) return e;
     if (vn > 0) {
-        hipLaunchKernelGGL(k_compact_visible, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, touched,
+        const unsigned nrun = (unsigned)((vn + CV_RUN - 1) / CV_RUN);
+        hipLaunchKernelGGL(k_count_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched, vn, pos);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, pos, (int)nrun, &cnt[0]);
+        hipLaunchKernelGGL(k_compact_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched,
                            reinterpret_cast<const float4*>(rec), pos, vn, vis_k0, vis_v0);
+    } else {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, pos, 0, &cnt[0]);
     }
     // 2. stable sort of the visible pairs by depth (32 bits)
     e = radix_sort(vis_k0, vis_v0, vis_k1, vis_v1, &cnt[0], vn, 4, hist, bsum, s);
