@@ -27,8 +27,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, GB/s
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CUs x 2.4 GHz x 256 FLOP/clk, packed FMA)
 METRIC = "fwd+bwd Mpixel/s, 1M Gaussians RGB+D+16ch sem; batched vs per-view"
+
+# HBM bytes per launch of the compositing backward measured with rocprofv3
+# (FETCH_SIZE and WRITE_SIZE, scaled by the same counters' reading for a plain
+# copy), valid only for the kernel sources they were taken on: the record
+# holds the SHA-256 of those sources and is reported only while they match.
+TRAFFIC = None
+TRAFFIC_SOURCES = ("paper_2603_27781_amd/csrc/render_bwd.hip", "paper_2603_27781_amd/csrc/raster_common.h",
+                   "paper_2603_27781_amd/csrc/sgs_common.h")
 
 
 def log(*a):
@@ -36,20 +45,59 @@ def log(*a):
 
 
 def byte_model(F, AS, V, N, n_vis, I, P, T, K, params=True):
-    """Algorithmic bytes per launch of each entry point (FP32, see DESIGN.md)."""
+    """Algorithmic bytes per launch of each entry point (FP32)."""
     geo = 44                       # mu 12, log_scale 12, quat 16, logit 4
     inst_gather = 4 + 32 + 4 * AS  # gid, projected record, appearance record
     n_red = (10 + F) if params else 6
+    rec_floats = (n_red + 3) // 4 * 4
     m = {
         "project": V * N * (geo + 44) + N * (12 + 4 * F) + N * 4 * AS,
         "bin_sort": n_vis * 4 * 8 * 3 + I * 8 * 3 * 2 + T * 8,
         "render_fwd": I * inst_gather + P * (4 * (5 + F) + 8) + T * 8,
         "loss_grad": P * (4 * (5 + F) * 2 + 16 + 4) + 4 * F * K,
-        "render_bwd": I * (inst_gather + 4 + 4 * ((n_red + 3) // 4 * 4) * 2) + P * (4 * (5 + F) + 8) + T * 8
-                      + V * N * (4 + 4 + 32) + N * 4 * (4 + F),
+        "render_bwd_records": I * (inst_gather + 4 + 4 * rec_floats) + P * (4 * (5 + F) + 8) + T * 8,
+        "reduce_records": I * 4 * rec_floats + V * N * (4 + 4 + 32) + N * 4 * (4 + F),
         "project_bwd": N * (geo + 4 * (4 + F) + 2 * 4 * (14 + F)) + V * N * 32,
     }
     return m
+
+
+def stream_bytes(F, V, N, n_vis, I, P, params=True):
+    """Compulsory and streaming bytes of one fwd+bwd step (the step-level
+    HBM model): parameters read once per pass, images and per-pixel state,
+    instance keys; streaming adds the per-instance gathers and gradients."""
+    geo, app, Pg, Pi = 44, 12 + 4 * F, 56 + 4 * F, 4 * (5 + F)
+    comp = 2 * (N * geo + n_vis * app) + (N * Pg if params else 0) + 2 * P * Pi + 2 * P * 8 + 2 * I * 12 + 24 * V
+    stream = comp + 2 * I * (44 + 4 * F) + I * 4 * ((10 + F) if params else 6)
+    return comp, stream
+
+
+def composite_flops(F, params=True):
+    """FP32 operations per (pixel, list entry) pair visited by the
+    compositing kernels, counted from the equations (fma = 2):
+    alpha = min(a_max, o 2^(A'dx^2 + B'dx dy + C'dy^2)): 13 (exp as one);
+    forward, when the pair contributes: w = alpha T, T update, 4+F channel
+    accumulations -> 3 + 2 (4+F);
+    backward: T_i rebuild 2, w 1, g.x over 5+F channels 2 (5+F), dL/dalpha 3,
+    suffix sum 2, through the clamp 1; mean, conic, depth terms 8 + 6 + 1
+    and their 6 cross-pixel sums; with parameter gradients also opacity 1,
+    colour 3, features F and their 4+F sums."""
+    fwd = 13 + 3 + 2 * (4 + F)
+    bwd = 13 + (2 + 1 + 2 * (5 + F) + 3 + 2 + 1) + (8 + 6 + 1 + 6) + ((1 + 3 + F) + (4 + F) if params else 0)
+    return fwd, bwd
+
+
+def traffic_bytes():
+    """The recorded HBM bytes of the compositing backward, if its sources are
+    the ones the counters were taken on; otherwise None."""
+    if TRAFFIC is None:
+        return None
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC["bytes"] if h.hexdigest() == TRAFFIC["sha256"] else None
 
 
 def main():
@@ -141,7 +189,7 @@ def main():
 
     # ------------------------------------------- per-entry-point event times
     r = step.r
-    names = ["project", "bin_sort", "render_fwd", "loss_grad", "render_bwd", "project_bwd"]
+    names = ["project", "bin_sort", "render_fwd", "loss_grad", "render_bwd_records", "reduce_records", "project_bwd"]
     if pose:
         names.append("pose_grad")
     evs = {k: [] for k in names}
@@ -161,7 +209,8 @@ def main():
         timed("bin_sort", r.bin_sort)
         timed("render_fwd", r.render_fwd)
         timed("loss_grad", lambda: r.loss_grad(rgb_t, dep_t, lab, W, w.weights))
-        timed("render_bwd", lambda: r.render_bwd_2d(g, r.grad_out, step.flags))
+        timed("render_bwd_records", lambda: r.render_bwd_records(g, r.grad_out, step.flags))
+        timed("reduce_records", lambda: r.reduce_records(step.flags))
         if params:
             timed("project_bwd", lambda: r.project_bwd(g, step.grads))
         if pose:
@@ -189,16 +238,33 @@ def main():
         log(f"per-view plain launches: {ms_pv:.3f} ms/step ({per_view['value']} Mpix/s)")
 
     # ------------------------------------------------------------- roofline
+    # The compositing kernels are bound by VALU issue (rocprofv3 counters),
+    # so their roofline is the FP32 vector peak over the operations the
+    # method needs per visited (pixel, list entry) pair; the units are the
+    # pairs each pixel visits, i.e. the sum of `last` over the pixels.
     F = w.scene.n_feat
     K = w.n_classes
     bm = byte_model(F, r.AS, len(w.views), w.scene.n, n_vis, n_inst, P, step.views.total_tiles, K, params)
-    dom = max((k for k in kern_us if k in bm), key=lambda k: kern_us[k])
-    achieved = bm[dom] / (kern_us[dom] * 1e-6) / 1e9
-    step_bytes = sum(bm[k] for k in kern_us if k in bm)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes_per_launch": int(bm[dom]), "launch_us": round(kern_us[dom], 2),
-                "step_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    dom = max(kern_us, key=lambda k: kern_us[k])
+    visited = int(r.last[:P].to(torch.int64).sum().item())
+    fwd_flops, bwd_flops = composite_flops(F, params)
+    if dom in ("render_bwd_records", "render_fwd"):
+        per_pair = bwd_flops if dom == "render_bwd_records" else fwd_flops
+        achieved = visited * per_pair / (kern_us[dom] * 1e-6) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                    "traffic": traffic_bytes() if dom == "render_bwd_records" else None,
+                    "flops_per_pair": per_pair, "visited_pairs": visited, "launch_us": round(kern_us[dom], 2),
+                    "algorithmic_bytes_per_launch": int(bm[dom]),
+                    "hbm_frac": round(bm[dom] / (kern_us[dom] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    else:
+        achieved = bm[dom] / (kern_us[dom] * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "algorithmic_bytes_per_launch": int(bm[dom]), "launch_us": round(kern_us[dom], 2)}
+    comp, strm = stream_bytes(F, len(w.views), w.scene.n, n_vis, n_inst, P, params)
+    roofline["step"] = {"bytes_comp": int(comp), "bytes_stream": int(strm),
+                        "hbm_frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     # ------------------------------------------------------- CPU baseline
     cpu = None

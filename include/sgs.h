@@ -231,9 +231,12 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
  *   S_i = sum_{j>i} (g . x_j) alpha_j T_j,
  * with g the pixel's upstream gradient grad_out[5+F][P_total] and x_i the
  * Gaussian's channel values (colour, depth, 1, feature).  Per-Gaussian sums
- * are reduced across each wavefront and tile, written as one record per
- * instance into ws (no atomics), then summed per (view, Gaussian) pair in a
- * fixed order, so the result is deterministic.  WRITES grad2d:
+ * are reduced across each wavefront, added across the tile's wavefronts in
+ * LDS, written as one record per instance into ws (no global atomics), then
+ * summed per (view, Gaussian) pair in a fixed order.  The order in which the
+ * wavefronts of a tile add into LDS is not fixed, so results may differ
+ * between runs in the last bits (float rounding), nothing more.  WRITES
+ * grad2d:
  *   grad2d geo [V][n][8]  = dL/d(mx, my, A, B, C, d), 2 unused   (per view;
  *                           written only for visible pairs, tiles_touched > 0)
  *   grad2d app [n][4+F]   = dL/d(o, c0, c1, c2, f...)            (all views)
@@ -243,6 +246,18 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
  * inst, inst_gid, pair_first, tile_ranges, capacity: as given to / written by
  * gs_bin_sort; tiles_touched from gs_project.
  * gs_render_bwd_workspace gives grad2d_bytes and ws_bytes (capacity records).
+ *
+ * gs_render_bwd is gs_render_bwd_records followed by gs_reduce_records on the
+ * same stream; the two halves are exported so that each can be timed or
+ * scheduled on its own:
+ *   gs_render_bwd_records  writes the per-instance records into ws
+ *                          (ws_bytes as above; grad2d is not touched);
+ *   gs_reduce_records      sums them per (view, Gaussian) pair into grad2d
+ *                          (the record layout depends on flags and n_feat,
+ *                          which must match the records call).
+ * Errors: GS_EINVAL for NULL or misaligned (16 B) buffers, bad flags or
+ * sizes; GS_ECAPACITY when grad2d_bytes or ws_bytes is too small;
+ * GS_EUNSUPPORTED for an unsupported n_feat or launch configuration.
  * --------------------------------------------------------------------------- */
 int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags,
                             size_t* grad2d_bytes, size_t* ws_bytes);
@@ -252,6 +267,14 @@ int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, con
                   int32_t n_views, const gs_config* cfg, const float* T_final, const int32_t* last,
                   const float* grad_out, uint32_t flags, float* grad2d, size_t grad2d_bytes, void* ws,
                   size_t ws_bytes, int32_t* queue, gs_stream stream);
+int gs_render_bwd_records(const gs_gaussians* g, const float* rec, const float* app, const int32_t* inst,
+                          const int32_t* inst_gid, int64_t capacity, const int32_t* tile_ranges,
+                          const gs_view* views, const gs_view* views_dev, int32_t n_views, const gs_config* cfg,
+                          const float* T_final, const int32_t* last, const float* grad_out, uint32_t flags,
+                          void* ws, size_t ws_bytes, int32_t* queue, gs_stream stream);
+int gs_reduce_records(const void* ws, size_t ws_bytes, const int32_t* pair_first, const int32_t* tiles_touched,
+                      int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags, float* grad2d,
+                      size_t grad2d_bytes, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_project_bwd -- backward of gs_project (Eq. 2-3) for the mapping step:

@@ -22,8 +22,8 @@ GS_GRAD_PARAMS, GS_GRAD_POSE = 1, 2
 # symbols declared in include/sgs.h (checked by the ABI test)
 EXPORTS = [
     "gs_default_config", "gs_views_layout", "gs_app_stride", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
-    "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd",
-    "gs_pose_grad_workspace",
+    "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
+    "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_pose_grad_workspace",
     "gs_pose_grad", "gs_error_string", "gs_last_hip_error", "gs_version",
 ]
 
@@ -88,6 +88,11 @@ def load() -> ctypes.CDLL:
     L.gs_render_bwd.argtypes = [P(GsGaussians), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                 c_void_p, P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p,
                                 c_uint32, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p]
+    L.gs_render_bwd_records.argtypes = [P(GsGaussians), c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
+                                        P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p,
+                                        c_uint32, c_void_p, c_size_t, c_void_p, c_void_p]
+    L.gs_reduce_records.argtypes = [c_void_p, c_size_t, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int64,
+                                    c_uint32, c_void_p, c_size_t, c_void_p]
     L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
                                  c_size_t, P(GsGaussianGrads), c_void_p]
     L.gs_pose_grad_workspace.argtypes = [c_int32, c_int32, P(c_size_t)]

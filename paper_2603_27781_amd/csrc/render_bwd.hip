@@ -21,9 +21,11 @@
 // one tile, so after each batch the workgroup writes the instance's totals as
 // one contiguous record at its emission index.  The instances of a (view,
 // Gaussian) pair are contiguous in emission order, so k_reduce_records then
-// sums each pair's records in a fixed order: the gradients are
-// deterministic, and the scattered read-modify-write traffic of atomics
-// (which dominated this kernel) is replaced by streaming writes and reads.
+// sums each pair's records in a fixed order, and the scattered
+// read-modify-write traffic of global atomics (which dominated this kernel)
+// is replaced by streaming writes and reads.  The only order left to the
+// hardware is that of the (at most TS*TS/64) wavefront totals added into an
+// instance's LDS accumulator, which can change the last bits between runs.
 #include "raster_common.h"
 
 namespace sgs {
@@ -336,7 +338,7 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <
 // chain of loads runs in parallel.  grad_geo[V][n][8] <- (dmx, dmy, dA, dB,
 // dC, dd, 0, 0) for visible pairs (others are not written); the appearance
 // part is summed over the Gaussian's lanes by a fixed xor tree and
-// grad_app[n][4+F] written by its first lane (deterministic).
+// grad_app[n][4+F] written by its first lane (fixed order).
 template <int F, bool PARAMS>
 __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict__ records,
                                                         const int32_t* __restrict__ pair_first,

@@ -230,12 +230,11 @@ int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t 
     return GS_OK;
 }
 
-int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* inst,
-                  const int32_t* inst_gid, const int32_t* pair_first, const int32_t* tiles_touched, int64_t capacity,
-                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev, int32_t n_views,
-                  const gs_config* cfg, const float* T_final, const int32_t* last, const float* grad_out,
-                  uint32_t flags, float* grad2d, size_t grad2d_bytes_, void* ws, size_t ws_bytes, int32_t* queue,
-                  gs_stream stream) {
+int gs_render_bwd_records(const gs_gaussians* g, const float* rec, const float* app, const int32_t* inst,
+                          const int32_t* inst_gid, int64_t capacity, const int32_t* tile_ranges, const gs_view* views,
+                          const gs_view* views_dev, int32_t n_views, const gs_config* cfg, const float* T_final,
+                          const int32_t* last, const float* grad_out, uint32_t flags, void* ws, size_t ws_bytes,
+                          int32_t* queue, gs_stream stream) {
     const bool params = (flags & GS_GRAD_PARAMS) != 0;
     if (!g) return GS_EINVAL;
     if (g->n < 1) return GS_EINVAL;
@@ -246,26 +245,55 @@ int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, con
     int total_tiles = 0;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, &P, &total_tiles))) return st;
     if ((flags & ~(uint32_t)(GS_GRAD_PARAMS | GS_GRAD_POSE)) != 0 || flags == 0) return GS_EINVAL;
-    if (!rec || !app || !inst || !inst_gid || !pair_first || !tiles_touched || !tile_ranges || !T_final || !last ||
-        !grad_out || !grad2d || !ws)
-        return GS_EINVAL;
+    if (!rec || !app || !inst || !inst_gid || !tile_ranges || !T_final || !last || !grad_out || !ws) return GS_EINVAL;
     if (capacity < 0 || capacity >= (1ll << 31)) return GS_EINVAL;
     if (cfg->persistent && !queue) return GS_EINVAL;
-    if (grad2d_bytes_ < grad2d_bytes(g->n, g->n_feat, n_views)) return GS_ECAPACITY;
     const size_t rec_bytes = (size_t)(capacity > 0 ? capacity : 1) * bwd_record_floats(g->n_feat, params) * sizeof(float);
     if (ws_bytes < rec_bytes) return GS_ECAPACITY;
-    if (!aligned16(rec) || !aligned16(app) || !aligned16(grad2d) || !aligned16(ws)) return GS_EINVAL;
-    float* geo = grad2d;
-    float* appg = grad2d + (size_t)n_views * g->n * 8;
-    float* records = static_cast<float*>(ws);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!aligned16(rec) || !aligned16(app) || !aligned16(ws)) return GS_EINVAL;
     const int batch = cfg->lds_batch_bwd ? cfg->lds_batch_bwd : cfg->lds_batch;
-    hipError_t e = launch_render_bwd(rec, app, g->n, g->n_feat, inst, inst_gid, tile_ranges, views_dev, n_views,
-                                     total_tiles, P, make_const(cfg), batch, cfg->persistent, T_final, last,
-                                     grad_out, params, records, queue, s);
-    if (e != hipSuccess) return hip_status(e);
-    return hip_status(launch_reduce_records(records, pair_first, tiles_touched, g->n, g->n_feat, n_views, capacity,
-                                            params, geo, appg, s));
+    return hip_status(launch_render_bwd(rec, app, g->n, g->n_feat, inst, inst_gid, tile_ranges, views_dev, n_views,
+                                        total_tiles, P, make_const(cfg), batch, cfg->persistent, T_final, last,
+                                        grad_out, params, static_cast<float*>(ws), queue,
+                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_reduce_records(const void* ws, size_t ws_bytes, const int32_t* pair_first, const int32_t* tiles_touched,
+                      int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags, float* grad2d,
+                      size_t grad2d_bytes_, gs_stream stream) {
+    const bool params = (flags & GS_GRAD_PARAMS) != 0;
+    if (n < 1 || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+    if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
+    if ((flags & ~(uint32_t)(GS_GRAD_PARAMS | GS_GRAD_POSE)) != 0 || flags == 0) return GS_EINVAL;
+    if (!ws || !pair_first || !tiles_touched || !grad2d) return GS_EINVAL;
+    if (capacity < 0 || capacity >= (1ll << 31)) return GS_EINVAL;
+    if (grad2d_bytes_ < grad2d_bytes(n, n_feat, n_views)) return GS_ECAPACITY;
+    const size_t rec_bytes = (size_t)(capacity > 0 ? capacity : 1) * bwd_record_floats(n_feat, params) * sizeof(float);
+    if (ws_bytes < rec_bytes) return GS_ECAPACITY;
+    if (!aligned16(grad2d) || !aligned16(ws)) return GS_EINVAL;
+    float* geo = grad2d;
+    float* appg = grad2d + (size_t)n_views * n * 8;
+    return hip_status(launch_reduce_records(static_cast<const float*>(ws), pair_first, tiles_touched, n, n_feat,
+                                            n_views, capacity, params, geo, appg,
+                                            reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, const int32_t* inst,
+                  const int32_t* inst_gid, const int32_t* pair_first, const int32_t* tiles_touched, int64_t capacity,
+                  const int32_t* tile_ranges, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                  const gs_config* cfg, const float* T_final, const int32_t* last, const float* grad_out,
+                  uint32_t flags, float* grad2d, size_t grad2d_bytes_, void* ws, size_t ws_bytes, int32_t* queue,
+                  gs_stream stream) {
+    if (!g) return GS_EINVAL;
+    if (!pair_first || !tiles_touched || !grad2d) return GS_EINVAL;
+    if (g->n >= 1 && feat_supported(g->n_feat) && grad2d_bytes_ < grad2d_bytes(g->n, g->n_feat, n_views))
+        return GS_ECAPACITY;
+    if (!aligned16(grad2d)) return GS_EINVAL;
+    const int st = gs_render_bwd_records(g, rec, app, inst, inst_gid, capacity, tile_ranges, views, views_dev, n_views,
+                                         cfg, T_final, last, grad_out, flags, ws, ws_bytes, queue, stream);
+    if (st) return st;
+    return gs_reduce_records(ws, ws_bytes, pair_first, tiles_touched, g->n, g->n_feat, n_views, capacity, flags,
+                             grad2d, grad2d_bytes_, stream);
 }
 
 int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,

@@ -254,6 +254,23 @@ class Rasterizer:
                                    self.grad2d.data_ptr(), self.grad2d.numel() * 4, self.records.data_ptr(),
                                    self.records.numel() * 4, self.queue.data_ptr(), _stream()), "gs_render_bwd")
 
+    def render_bwd_records(self, g: Gaussians, grad_out: torch.Tensor, flags: int) -> None:
+        """First half of render_bwd_2d: per-instance records only."""
+        check(self.L.gs_render_bwd_records(ctypes.byref(g.c()), self.rec.data_ptr(), self.app.data_ptr(),
+                                           self.inst.data_ptr(), self.inst_gid.data_ptr(), self.capacity,
+                                           self.ranges.data_ptr(), self.views.host, self.views.dev_ptr(), self.views.n,
+                                           ctypes.byref(self.cc), self.T_final.data_ptr(), self.last.data_ptr(),
+                                           grad_out.data_ptr(), flags, self.records.data_ptr(),
+                                           self.records.numel() * 4, self.queue.data_ptr(), _stream()),
+              "gs_render_bwd_records")
+
+    def reduce_records(self, flags: int) -> None:
+        """Second half of render_bwd_2d: records -> grad2d."""
+        check(self.L.gs_reduce_records(self.records.data_ptr(), self.records.numel() * 4, self.pair_first.data_ptr(),
+                                       self.touched.data_ptr(), self.n, self.F, self.views.n, self.capacity, flags,
+                                       self.grad2d.data_ptr(), self.grad2d.numel() * 4, _stream()),
+              "gs_reduce_records")
+
     def project_bwd(self, g: Gaussians, grads: Gaussians) -> None:
         gc = _grads_c(grads)
         check(self.L.gs_project_bwd(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,

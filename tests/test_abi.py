@@ -101,5 +101,18 @@ def test_validation_rejects_before_any_launch():
                            None) == _lib.GS_ECAPACITY
     assert L.gs_project_bwd(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, dummy, 1 << 30, None,
                             None) == _lib.GS_EINVAL
+    # the two halves of gs_render_bwd validate on their own
+    assert L.gs_render_bwd_records(ctypes.byref(g), dummy, dummy, dummy, dummy, 100, dummy, V, dummy, 1,
+                                   ctypes.byref(cfg), dummy, dummy, dummy, 4, dummy, 1 << 30, dummy,
+                                   None) == _lib.GS_EINVAL
+    assert L.gs_render_bwd_records(ctypes.byref(g), dummy, dummy, dummy, dummy, 100, dummy, V, dummy, 1,
+                                   ctypes.byref(cfg), dummy, dummy, dummy, 1, dummy, 16, dummy,
+                                   None) == _lib.GS_ECAPACITY
+    assert L.gs_reduce_records(None, 1 << 30, dummy, dummy, 100, 16, 1, 100, 1, dummy, 1 << 30,
+                               None) == _lib.GS_EINVAL
+    assert L.gs_reduce_records(dummy, 1 << 30, dummy, dummy, 100, 16, 1, 100, 1, dummy, 16,
+                               None) == _lib.GS_ECAPACITY
+    assert L.gs_reduce_records(dummy, 1 << 30, dummy, dummy, 100, 12, 1, 100, 1, dummy, 1 << 30,
+                               None) == _lib.GS_EUNSUPPORTED
     assert L.gs_error_string(_lib.GS_ECAPACITY) == b"buffer too small"
     assert L.gs_version() >= 100

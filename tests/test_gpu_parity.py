@@ -242,6 +242,27 @@ def test_backward_launch_shapes(tile, lds_batch, persistent, lds_batch_bwd):
     _check_grads(*out, flags=3)
 
 
+@pytest.mark.parametrize("flags", [3, 2])
+def test_backward_split_entry_points(flags):
+    """gs_render_bwd_records followed by gs_reduce_records gives the grad2d of
+    gs_render_bwd (same kernels; only the order of the wavefront additions
+    into LDS may differ between runs, a last-bits effect)."""
+    scene, views, r, g, cfg = _render("tiny3views-F16", 16, 128, 1)
+    rng = np.random.default_rng(5)
+    go = torch.from_numpy(rng.normal(size=r.out.shape).astype(np.float32) * 1e-2).cuda()
+    r.render_bwd_2d(g, go, flags)
+    torch.cuda.synchronize()
+    geo1, app1 = r.grad_geo.clone(), r.grad_app.clone()
+    r.grad2d.fill_(float("nan"))
+    r.render_bwd_records(g, go, flags)
+    r.reduce_records(flags)
+    torch.cuda.synchronize()
+    assert not torch.isnan(r.grad_geo).any()
+    assert rel_err(r.grad_geo.cpu().numpy(), geo1.cpu().numpy()) <= 1e-5
+    if flags & 1:
+        assert rel_err(r.grad_app.cpu().numpy(), app1.cpu().numpy()) <= 1e-5
+
+
 def test_pose_only_backward():
     """Tracking mode (GS_GRAD_POSE only): the field is frozen, only the 2D
     geometric gradients and the twist are produced."""
