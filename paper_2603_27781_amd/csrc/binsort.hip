@@ -342,35 +342,70 @@ __global__ void k_counts(const int64_t* n_inst, const int64_t* n_vis, int64_t ca
 }
 
 // Emission: the visible pair at depth-sorted position i writes one instance
-// per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1:
-// key = global tile id, value = the emission index itself.  inst_gid[e] keeps
-// the Gaussian of emission index e, pair_first[pair] the first emission index
-// of the pair, so that the instances of one (view, Gaussian) pair stay
-// contiguous in emission space after the tile sort has reordered them.
-__global__ void k_emit(const uint32_t* __restrict__ vis_vals, const uint32_t* __restrict__ offs, const int64_t* n_vis,
-                       const uint2* __restrict__ rect, const gs_view* __restrict__ views, int n, int tile,
-                       int64_t capacity, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                       int32_t* __restrict__ inst_gid, int32_t* __restrict__ pair_first) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *n_vis) return;
-    const uint32_t pair = vis_vals[i];
-    const int v = (int)(pair / (uint32_t)n);
-    const uint32_t gid = pair - (uint32_t)v * (uint32_t)n;
-    const uint2 r = rect[pair];
-    const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16), x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
-    const int tx = ceil_div(views[v].width, tile);
-    const uint32_t tbase = (uint32_t)views[v].tile_offset;
-    int64_t o = offs[i];
-    pair_first[pair] = (int32_t)o;
-    for (int y = y0; y <= y1; ++y)
-        for (int x = x0; x <= x1; ++x) {
-            if (o < capacity) {
-                keys[o] = tbase + (uint32_t)(y * tx + x);
-                vals[o] = (uint32_t)o;
-                inst_gid[o] = (int32_t)gid;
-            }
-            ++o;
+// per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1
+// (row-major over the rectangle): key = global tile id, value = the emission
+// index itself.  inst_gid[e] keeps the Gaussian of emission index e,
+// pair_first[pair] the first emission index of the pair, so that the
+// instances of one (view, Gaussian) pair stay contiguous in emission space
+// after the tile sort has reordered them.
+// Each wavefront takes 64 consecutive pairs and its lanes stride over all of
+// their instances together (the pair of instance k found by binary search
+// over the pairs' starts in LDS), so a pair with many tiles does not stall
+// its wavefront and the writes are contiguous across lanes.
+__global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_vals,
+                                              const uint32_t* __restrict__ offs, const int64_t* n_vis,
+                                              const uint2* __restrict__ rect, const gs_view* __restrict__ views,
+                                              int n, int tile, int64_t capacity, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals, int32_t* __restrict__ inst_gid,
+                                              int32_t* __restrict__ pair_first) {
+    __shared__ uint32_t s_start[4][kWave];
+    __shared__ uint4 s_info[4][kWave];  // (x0 | y0 << 16, rect width, tile base, tiles per row)
+    __shared__ int32_t s_gid[4][kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t nv = *n_vis;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (int64_t)wave * kWave;
+    if (i0 >= nv) return;  // uniform across the wavefront
+    const int64_t i = i0 + lane;
+    const bool valid = i < nv;
+    int64_t o_i = 0, end_i = 0;
+    if (valid) {
+        const uint32_t pair = vis_vals[i];
+        const int v = (int)(pair / (uint32_t)n);
+        const uint32_t gid = pair - (uint32_t)v * (uint32_t)n;
+        const uint2 r = rect[pair];
+        const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
+        const uint32_t wr = x1 - x0 + 1, hr = y1 - y0 + 1;
+        o_i = offs[i];
+        end_i = o_i + (int64_t)wr * hr;
+        pair_first[pair] = (int32_t)o_i;
+        s_info[wave][lane] = make_uint4(x0 | (y0 << 16), wr, (uint32_t)views[v].tile_offset,
+                                        (uint32_t)ceil_div(views[v].width, tile));
+        s_gid[wave][lane] = (int32_t)gid;
+    }
+    const int64_t o_w = __shfl(o_i, 0, kWave);  // lane 0 is valid
+    s_start[wave][lane] = (uint32_t)(o_i - o_w);
+    const int nvalid = (int)__popcll(__ballot(valid));
+    const int64_t total = __shfl(end_i, nvalid - 1, kWave) - o_w;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int64_t k = lane; k < total; k += kWave) {
+        int lo = 0, hi = nvalid - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int64_t)s_start[wave][mid] <= k) lo = mid;
+            else hi = mid - 1;
         }
+        const uint4 info = s_info[wave][lo];
+        const uint32_t li = (uint32_t)(k - s_start[wave][lo]);
+        const uint32_t yy = (info.x >> 16) + li / info.y, xx = (info.x & 0xffffu) + li % info.y;
+        const int64_t o = o_w + k;
+        if (o < capacity) {
+            keys[o] = info.z + yy * info.w + xx;
+            vals[o] = (uint32_t)o;
+            inst_gid[o] = s_gid[wave][lo];
+        }
+    }
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_inst, int2* __restrict__ ranges) {

@@ -19,7 +19,7 @@
 namespace sgs {
 
 constexpr int kLossThreads = 256;
-constexpr int kLossKC = 64;  // classes whose logits are kept in registers
+constexpr int kLossKC = 64;  // most classes whose logits are kept in registers (32 or 64 variants)
 
 __global__ void k_transpose_decoder(const float* __restrict__ W, int F, int K, float* __restrict__ Wt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -28,17 +28,17 @@ __global__ void k_transpose_decoder(const float* __restrict__ W, int F, int K, f
     Wt[k * F + f] = W[i];
 }
 
-template <int F, bool CACHED>
+template <int F, int KC>
 __device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], const float* __restrict__ Wt, int K,
                                              int lab, float (&gf)[F > 0 ? F : 1]) {
     float m = -INFINITY, zl = 0.0f, se = 0.0f;
     float ga[F > 0 ? F : 1];
 #pragma unroll
     for (int f = 0; f < F; ++f) ga[f] = 0.0f;
-    if constexpr (CACHED) {
-        float z[kLossKC];
+    if constexpr (KC > 0) {
+        float z[KC];
 #pragma unroll
-        for (int k = 0; k < kLossKC; ++k) {
+        for (int k = 0; k < KC; ++k) {
             if (k < K) {
                 const float* wr = Wt + k * F;
                 float acc = 0.0f;
@@ -50,7 +50,7 @@ __device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], c
             }
         }
 #pragma unroll
-        for (int k = 0; k < kLossKC; ++k) {
+        for (int k = 0; k < KC; ++k) {
             if (k < K) {
                 const float* wr = Wt + k * F;
                 const float e = __expf(z[k] - m);
@@ -86,7 +86,7 @@ __device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], c
     return (m + __logf(se)) - zl;
 }
 
-template <int F, bool CACHED>
+template <int F, int KC>
 __global__ void __launch_bounds__(kLossThreads) k_loss(const float* __restrict__ out, int64_t P,
                                                        const float* __restrict__ rgb_t,
                                                        const float* __restrict__ depth_t,
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kLossThreads) k_loss(const float* __restrict__
             float gf[F > 0 ? F : 1];
 #pragma unroll
             for (int f = 0; f < F; ++f) gf[f] = 0.0f;
-            if (K > 0 && w2 != 0.0f) ls += (double)semantic_ce<F, CACHED>(fv, Wt, K, labels[p], gf);
+            if (K > 0 && w2 != 0.0f) ls += (double)semantic_ce<F, KC>(fv, Wt, K, labels[p], gf);
 #pragma unroll
             for (int f = 0; f < F; ++f) grad_out[(5 + f) * P + p] = gs * gf[f];
         }
@@ -203,10 +203,13 @@ hipError_t launch_loss_t(const float* out, const float* rgb_t, const float* dept
         hipLaunchKernelGGL(k_transpose_decoder, dim3((unsigned)ceil_div(F * K, 256)), dim3(256), 0, s, decoder, F, K,
                            Wt);
     if (sem && K > kLossKC)
-        hipLaunchKernelGGL((k_loss<F, false>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t, depth_t,
+        hipLaunchKernelGGL((k_loss<F, 0>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t, depth_t,
                            labels, Wt, K, w[0], w[1], w[2], views, n_views, grad_out, partials);
+    else if (sem && K > 32)
+        hipLaunchKernelGGL((k_loss<F, kLossKC>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t,
+                           depth_t, labels, Wt, K, w[0], w[1], w[2], views, n_views, grad_out, partials);
     else
-        hipLaunchKernelGGL((k_loss<F, true>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t, depth_t,
+        hipLaunchKernelGGL((k_loss<F, 32>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t, depth_t,
                            labels, Wt, K, w[0], w[1], w[2], views, n_views, grad_out, partials);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, s, partials, nblk, loss);
     return hipGetLastError();

@@ -162,9 +162,9 @@ def test_loss_grad_parity(name):
     _loss_case(name, K=20)
 
 
-@pytest.mark.parametrize("K", [1, 64, 65, 200])
+@pytest.mark.parametrize("K", [1, 32, 33, 64, 65, 200])
 def test_loss_grad_class_counts(K):
-    """Class counts around the register-cached limit (64): cached logits and
+    """Class counts around the register-cached limits (32, 64): cached logits and
     the recomputing path give the oracle's loss and gradient alike."""
     _loss_case("tiny-F8", K=K)
 
