@@ -33,15 +33,22 @@ namespace sgs {
 // Transposing butterfly over NV (a power of two) values per lane.  Each
 // halving step, across one lane bit, halves the CNT values a lane keeps: a
 // lane with the bit set keeps the upper half and receives its partner's
-// upper half, the partner the opposite, and both add.  Lane bits are taken
-// in the order 5, 4 (permlane swaps: one swap + one add per pair), 2 (DPP
-// half-row mirror, valid because bits 0 and 1 are still unused), 0, 1 (DPP
-// quad permutations), 3 (DPP row rotation): after log2(NV) halving steps
-// each lane holds one partial total, and the remaining bits finish the sum
-// across the wavefront.  No step goes through LDS.  Every index is a
-// compile-time constant (template recursion), so the values stay in
-// registers.
-__host__ __device__ constexpr int bfly_bit(int s) { return s == 0 ? 5 : (s == 1 ? 4 : (s == 2 ? 2 : (s == 3 ? 0 : (s == 4 ? 1 : 3)))); }
+// upper half, the partner the opposite, and both add.  After log2(NV)
+// halving steps each lane holds one partial total, and the remaining bits
+// of the order finish the sum.  Two bit orders:
+//   full wavefront (ORD 0): 5, 4 (permlane swaps: one swap + one add per
+//     pair), 2 (DPP half-row mirror, valid because bits 0 and 1 are still
+//     unused), 0, 1 (DPP quad permutations), 3 (DPP row rotation);
+//   within the 16 lanes that share bits 4 and 5 (ORD 1): 2, 0, 1, 3.
+// No step goes through LDS.  Every index is a compile-time constant
+// (template recursion), so the values stay in registers.
+template <int ORD>
+__host__ __device__ constexpr int bfly_bit(int s) {
+    return ORD == 0 ? (s == 0 ? 5 : (s == 1 ? 4 : (s == 2 ? 2 : (s == 3 ? 0 : (s == 4 ? 1 : 3)))))
+                    : (s == 0 ? 2 : (s == 1 ? 0 : (s == 2 ? 1 : 3)));
+}
+template <int ORD>
+__host__ __device__ constexpr int bfly_nbits() { return ORD == 0 ? 6 : 4; }
 
 template <int D>
 __device__ __forceinline__ float bfly_partner(float x) {
@@ -49,11 +56,11 @@ __device__ __forceinline__ float bfly_partner(float x) {
     else return xor_lane<D>(x);
 }
 
-template <int NV, int CNT, int S>
+template <int ORD, int NV, int CNT, int S>
 struct BflyStep {
     __device__ __forceinline__ static void run(float (&v)[NV], int lane) {
-        if constexpr (S < 6) {
-            constexpr int D = 1 << bfly_bit(S);
+        if constexpr (S < bfly_nbits<ORD>()) {
+            constexpr int D = 1 << bfly_bit<ORD>(S);
             if constexpr (CNT > 1) {
                 constexpr int HALF = CNT / 2;
                 if constexpr (D >= 16) {
@@ -68,29 +75,29 @@ struct BflyStep {
                         v[k] = keep + bfly_partner<D>(send);
                     }
                 }
-                BflyStep<NV, HALF, S + 1>::run(v, lane);
+                BflyStep<ORD, NV, HALF, S + 1>::run(v, lane);
             } else {
                 // full reduction across this bit; the mirror partner is only
                 // valid while bits 0 and 1 are unused, which holds here since
-                // bit 2 comes before them in the order
+                // bit 2 comes before them in both orders
                 v[0] += bfly_partner<D>(v[0]);
-                BflyStep<NV, 1, S + 1>::run(v, lane);
+                BflyStep<ORD, NV, 1, S + 1>::run(v, lane);
             }
         }
     }
 };
 
-template <int NV>
+template <int NV, int ORD = 0>
 struct Butterfly {
     static constexpr int steps() {
         int b = 0;
         while ((1 << b) < NV) ++b;
         return b;
     }
-    // After the call, the lane holds in v[0] the wavefront total of value
-    // index slot(lane).
+    // After the call, the lane holds in v[0] the total (over the lanes the
+    // order covers) of value index slot(lane).
     __device__ __forceinline__ static float reduce(float (&v)[NV], int lane) {
-        BflyStep<NV, NV, 0>::run(v, lane);
+        BflyStep<ORD, NV, NV, 0>::run(v, lane);
         return v[0];
     }
     __device__ __forceinline__ static int slot(int lane) {
@@ -98,7 +105,7 @@ struct Butterfly {
 #pragma unroll
         for (int st = 0; st < steps(); ++st) {
             cnt >>= 1;
-            if (lane & (1 << bfly_bit(st))) s += cnt;
+            if (lane & (1 << bfly_bit<ORD>(st))) s += cnt;
         }
         return s;
     }
@@ -106,10 +113,24 @@ struct Butterfly {
     // clear hold one copy of each slot total.
     static constexpr int reduced_mask() {
         int m = 0;
-        for (int st = steps(); st < 6; ++st) m |= 1 << bfly_bit(st);
+        for (int st = steps(); st < bfly_nbits<ORD>(); ++st) m |= 1 << bfly_bit<ORD>(st);
         return m;
     }
 };
+
+// The weights w of the four lanes that share this lane's bits 0-3, in the
+// order of their bits 4-5 (t = 0..3: lane (l & 15) | 16 t), from two
+// permlane swaps (the same order in every lane).
+__device__ __forceinline__ void quad_row_weights(float w, float (&W)[4]) {
+    const unsigned u = __float_as_uint(w);
+    const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);  // w(l & ~32), w(l | 32)
+    const auto a = __builtin_amdgcn_permlane16_swap(h[0], h[0], false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(h[1], h[1], false, false);
+    W[0] = __uint_as_float(a[0]);  // w(l & ~48)
+    W[1] = __uint_as_float(a[1]);  // w((l & ~48) | 16)
+    W[2] = __uint_as_float(b[0]);  // w((l & ~48) | 32)
+    W[3] = __uint_as_float(b[1]);  // w(l | 48)
+}
 
 template <int N>
 struct Pow2 {
@@ -130,8 +151,12 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                                          float4* s_g0, float4* s_g1, float4* s_app, int* s_max, float* s_acc) {
     constexpr int NT = TS * TS;
     constexpr int AV = AppRec<F>::vec;
-    constexpr int NREAL = PARAMS ? 10 + F : 6;
-    constexpr int NV = Pow2<NREAL>::value;
+    constexpr int NREAL = PARAMS ? 10 + F : 6;  // record slots
+    constexpr int NBF = 6;                      // full-wavefront butterfly: mean, conic, opacity | depth
+    constexpr int NV = Pow2<NBF>::value;
+    constexpr int LIN = PARAMS ? 4 + F : 0;     // linear channels: depth, colour, feature
+    constexpr int NL = LIN / 4;                 // linear channels per lane (a multiple of 4 channels)
+    constexpr int NVL = Pow2<(NL > 0 ? NL : 1)>::value;
     constexpr int RS = (NREAL + 3) / 4 * 4;  // record stride (floats), float4-aligned
     constexpr int AST = NREAL + 1;           // accumulator stride (odd: spreads LDS banks)
     constexpr int NQ = B / 64;               // 64-bit candidate masks per batch
@@ -179,13 +204,45 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
         for (int q = 0; q < RS / 4; ++q) r4[q] = z4;
     }
 
-    // per-slot scale: dmx, dmy <- -ln2; dA, dC <- -1/2; dB <- -1; others 1
-    const int my_slot = Butterfly<NV>::slot(lane);
-    const bool writer = (lane & Butterfly<NV>::reduced_mask()) == 0 && my_slot < NREAL;
+    // full-wavefront butterfly value k -> record slot: 0..4 (mean, conic) as
+    // they are; value 5 is the opacity (slot 6) with parameter gradients,
+    // else the depth (slot 5).  Scales: dmx, dmy <- -ln2; dA, dC <- -1/2;
+    // dB <- -1.
+    const int bslot = Butterfly<NV>::slot(lane);
+    const bool writer = (lane & Butterfly<NV>::reduced_mask()) == 0 && bslot < NBF;
+    const int my_slot = bslot < 5 ? bslot : (PARAMS ? 6 : 5);
     float scale = 1.0f;
-    if (my_slot < 2) scale = -kLn2;
-    else if (my_slot == 2 || my_slot == 4) scale = -0.5f;
-    else if (my_slot == 3) scale = -1.0f;
+    if (bslot < 2) scale = -kLn2;
+    else if (bslot == 2 || bslot == 4) scale = -0.5f;
+    else if (bslot == 3) scale = -1.0f;
+
+    // Linear channels c (0 depth, 1-3 colour, 4+ feature): their gradient is
+    // sum_p g_c(p) w(p) with g constant over the tile.  A lane owns the
+    // channels c = 4 m + q (q = lane bits 4-5) and keeps, for them, g of the
+    // four lanes sharing its bits 0-3; per Gaussian it takes those lanes'
+    // weights (two permlane swaps), forms the four-lane sums with FMAs and
+    // finishes over the 16 lanes of its row group with the ORD 1 butterfly.
+    const int q4 = (lane >> 4) & 3;
+    float gq[NL > 0 ? NL : 1][4];
+    if constexpr (PARAMS) {
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+            const int lp = (lane & 15) | (t4 << 4);
+            const int xx = tx * TS + sbx + (lp & 7), yy = ty * TS + sby + (lp >> 3);
+            const bool in = xx < vw.width && yy < vw.height;
+            const int64_t pp = vw.pixel_offset + (int64_t)yy * vw.width + xx;
+#pragma unroll
+            for (int m = 0; m < NL; ++m) {
+                const int ch = 4 * m + q4;
+                const int plane = ch == 0 ? 3 : (ch < 4 ? ch - 1 : ch + 1);
+                gq[m][t4] = in ? grad_out[plane * P + pp] : 0.0f;
+            }
+        }
+    }
+    const int lslot = Butterfly<NVL, 1>::slot(lane);
+    const bool lwriter = PARAMS && (lane & Butterfly<NVL, 1>::reduced_mask()) == 0 && lslot < NL;
+    const int lch = 4 * lslot + q4;
+    const int lin_slot = lch == 0 ? 5 : 6 + lch;
 
     for (int bend = end; bend > rg.x; bend -= B) {
         const int bstart = max(rg.x, bend - B);
@@ -258,19 +315,23 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     val[2] = h * dx * dx;
                     val[3] = h * dx * dy;
                     val[4] = h * dy * dy;
-                    val[5] = g[3] * w;
-                    if (PARAMS) {
-                        val[6] = hm * G;
-                        val[7] = g[0] * w;
-                        val[8] = g[1] * w;
-                        val[9] = g[2] * w;
+                    val[5] = PARAMS ? hm * G : g[3] * w;
 #pragma unroll
-                        for (int f = 0; f < F; ++f) val[10 + f] = g[5 + f] * w;
-                    }
-#pragma unroll
-                    for (int k = NREAL; k < NV; ++k) val[k] = 0.0f;
+                    for (int k = NBF; k < NV; ++k) val[k] = 0.0f;
                     const float tot = Butterfly<NV>::reduce(val, lane);
                     if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
+                    if constexpr (PARAMS) {
+                        float W[4];
+                        quad_row_weights(w, W);
+                        float lin[NVL];
+#pragma unroll
+                        for (int m = 0; m < NL; ++m)
+                            lin[m] = fmaf(gq[m][3], W[3], fmaf(gq[m][2], W[2], fmaf(gq[m][1], W[1], gq[m][0] * W[0])));
+#pragma unroll
+                        for (int m = NL; m < NVL; ++m) lin[m] = 0.0f;
+                        const float ltot = Butterfly<NVL, 1>::reduce(lin, lane);
+                        if (lwriter) atomicAdd(&s_acc[j * AST + lin_slot], ltot);
+                    }
                 }
                 if (jn < 0) break;
                 j = jn;
