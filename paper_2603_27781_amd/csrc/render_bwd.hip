@@ -180,9 +180,16 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     const int64_t p = inside ? vw.pixel_offset + (int64_t)y * vw.width + x : 0;
     float T = inside ? T_final[p] : 1.0f;
     const int lastp = inside ? last[p] : 0;
-    float g[5 + F];
+    // the pixel's upstream gradient: all 5+F channels in pose-only mode; with
+    // parameter gradients only the opacity channel (the others live in gq)
+    constexpr int NG = PARAMS ? 1 : 5 + F;
+    float g[NG];
+    if constexpr (PARAMS) {
+        g[0] = inside ? grad_out[4 * P + p] : 0.0f;
+    } else {
 #pragma unroll
-    for (int ch = 0; ch < 5 + F; ++ch) g[ch] = inside ? grad_out[ch * P + p] : 0.0f;
+        for (int ch = 0; ch < 5 + F; ++ch) g[ch] = inside ? grad_out[ch * P + p] : 0.0f;
+    }
     float Sg = 0.0f;
     const float amin = c.alpha_min, amax = c.alpha_max;
 
@@ -243,6 +250,14 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     const bool lwriter = PARAMS && (lane & Butterfly<NVL, 1>::reduced_mask()) == 0 && lslot < NL;
     const int lch = 4 * lslot + q4;
     const int lin_slot = lch == 0 ? 5 : 6 + lch;
+    // float index, within a staged appearance record, of this lane's channels
+    // c = 4 m + q (depth sits in the record's padding slot)
+    int xidx[NL > 0 ? NL : 1];
+#pragma unroll
+    for (int m = 0; m < NL; ++m) {
+        const int ch = 4 * m + q4;
+        xidx[m] = ch == 0 ? AV * 4 - 1 : ch - 1;
+    }
 
     for (int bend = end; bend > rg.x; bend -= B) {
         const int bstart = max(rg.x, bend - B);
@@ -256,6 +271,8 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             s_g1[k] = a1;
 #pragma unroll
             for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
+            // the record's last float is padding (3 + F is 3 mod 4): depth goes there
+            if constexpr (PARAMS) reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
         }
         for (int k = tid; k < nb * AST; k += NT) s_acc[k] = 0.0f;
         __syncthreads();
@@ -285,9 +302,23 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 // folded into a pointer select that leaves LDS addressing
                 const int jp = jn >= 0 ? jn : j;
                 const float4 g0n = s_g0[jp], g1n = s_g1[jp];
-                float4 av[AV];
+                // appearance of Gaussian j: with parameter gradients only this
+                // lane's channels, else the whole record
+                float xs[PARAMS ? (NL > 0 ? NL : 1) : AV * 4];
+                if constexpr (PARAMS) {
+                    const float* sa = reinterpret_cast<const float*>(s_app) + j * AV * 4;
 #pragma unroll
-                for (int qq = 0; qq < AV; ++qq) av[qq] = s_app[j * AV + qq];
+                    for (int m = 0; m < NL; ++m) xs[m] = sa[xidx[m]];
+                } else {
+#pragma unroll
+                    for (int qq = 0; qq < AV; ++qq) {
+                        const float4 a4 = s_app[j * AV + qq];
+                        xs[4 * qq] = a4.x;
+                        xs[4 * qq + 1] = a4.y;
+                        xs[4 * qq + 2] = a4.z;
+                        xs[4 * qq + 3] = a4.w;
+                    }
+                }
                 const int jl = bstart + j - rg.x;
                 float dx, dy, G;
                 bool unc;
@@ -298,13 +329,31 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     // contribution take alpha = 0 (T unchanged, exact since
                     // rcp(1) = 1, w = 0) and zero multipliers.
                     const float ac = contrib ? a : 0.0f;
-                    const float* ap = reinterpret_cast<const float*>(av);
                     const float ra = __builtin_amdgcn_rcpf(1.0f - ac);
                     T = T * ra;  // transmittance before this Gaussian
                     const float w = ac * T;
-                    float gx = fmaf(g[0], ap[0], fmaf(g[1], ap[1], fmaf(g[2], ap[2], fmaf(g[3], g1.z, g[4]))));
+                    // g . x over the 5+F channels of this lane's pixel
+                    float gx;
+                    if constexpr (PARAMS) {
+                        // partial dot products over this lane's channel quarter
+                        // for the four lanes of its group, then a transposing
+                        // reduce over lane bits 5 and 4 hands each lane its own
+                        float pt[4];
 #pragma unroll
-                    for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], ap[3 + f], gx);
+                        for (int t4 = 0; t4 < 4; ++t4) {
+                            float acc = gq[0][t4] * xs[0];
+#pragma unroll
+                            for (int m = 1; m < NL; ++m) acc = fmaf(gq[m][t4], xs[m], acc);
+                            pt[t4] = acc;
+                        }
+                        pt[0] = swap_halves_add<32>(pt[0], pt[2]);
+                        pt[1] = swap_halves_add<32>(pt[1], pt[3]);
+                        gx = swap_halves_add<16>(pt[0], pt[1]) + g[0];
+                    } else {
+                        gx = fmaf(g[0], xs[0], fmaf(g[1], xs[1], fmaf(g[2], xs[2], fmaf(g[3], g1.z, g[4]))));
+#pragma unroll
+                        for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], xs[3 + f], gx);
+                    }
                     const float dA = fmaf(T, gx, -Sg * ra);
                     Sg = fmaf(gx, w, Sg);
                     const float hm = (contrib && unc) ? dA : 0.0f;
@@ -315,7 +364,8 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     val[2] = h * dx * dx;
                     val[3] = h * dx * dy;
                     val[4] = h * dy * dy;
-                    val[5] = PARAMS ? hm * G : g[3] * w;
+                    if constexpr (PARAMS) val[5] = hm * G;
+                    else val[5] = g[3] * w;
 #pragma unroll
                     for (int k = NBF; k < NV; ++k) val[k] = 0.0f;
                     const float tot = Butterfly<NV>::reduce(val, lane);
