@@ -35,7 +35,7 @@ METRIC = "fwd+bwd Mpixel/s, 1M Gaussians RGB+D+16ch sem; batched vs per-view"
 # (FETCH_SIZE and WRITE_SIZE, scaled by the same counters' reading for a plain
 # copy), valid only for the kernel sources they were taken on: the record
 # holds the SHA-256 of those sources and is reported only while they match.
-TRAFFIC = None
+TRAFFIC = {"bytes": 2912780526, "sha256": "027f9af0aa95ee18414c9937b74755413b84365fd820465a71efdca4bc8f09c6"}
 TRAFFIC_SOURCES = ("paper_2603_27781_amd/csrc/render_bwd.hip", "paper_2603_27781_amd/csrc/raster_common.h",
                    "paper_2603_27781_amd/csrc/sgs_common.h")
 
