@@ -92,6 +92,35 @@ __device__ __forceinline__ float swap_halves_add(float lo, float hi) {
     }
 }
 
+// Minimum over t in [lo, hi] of a t^2 + b t + c0 (a > 0).
+__device__ __forceinline__ float quad_min_on(float a, float b, float c0, float lo, float hi) {
+    const float t = fminf(fmaxf(-b / (2.0f * a), lo), hi);
+    return fmaf(fmaf(a, t, b), t, c0);
+}
+
+// Exact (up to a margin) wavefront-level test: does the region where
+// alpha >= alpha_min reach a pixel centre of the 8x8 block whose first
+// centre is (x0, y0)?  With the staged conic, alpha = o 2^(-Q(dx, dy)),
+// Q = a dx^2 + b dx dy + c dy^2 positive definite (a = -A', b = -B2',
+// c = -C'), so alpha >= alpha_min needs Q <= log2(o / alpha_min).  Q is
+// convex, so its minimum over the rectangle of pixel centres is 0 if the
+// mean lies inside, else on one of the four edges (a clamped 1-D quadratic
+// each).  The margin (1e-3 absolute in Q) covers the rounding of both
+// evaluations, so the test only prunes pairs with alpha < alpha_min.
+__device__ __forceinline__ bool ellipse_misses(const float4& g0, const float4& g1, float x0, float y0,
+                                               float log2_amin) {
+    const float a = -g0.z, b = -g0.w, c = -g1.x;
+    const float K = __log2f(g1.y) - log2_amin;  // log2(o / alpha_min)
+    const float xl = x0 - g0.x, xh = xl + 7.0f, yl = y0 - g0.y, yh = yl + 7.0f;
+    if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return K < 0.0f;
+    // edges x = xl, xh: Q = c y^2 + (b x) y + a x^2; edges y = yl, yh likewise
+    float q = quad_min_on(c, b * xl, a * xl * xl, yl, yh);
+    q = fminf(q, quad_min_on(c, b * xh, a * xh * xh, yl, yh));
+    q = fminf(q, quad_min_on(a, b * yl, c * yl * yl, xl, xh));
+    q = fminf(q, quad_min_on(a, b * yh, c * yh * yh, xl, xh));
+    return q > K + 1e-3f;
+}
+
 // Conservative wavefront-level test: can the Gaussian reach any pixel centre
 // of the 8x8 block whose first centre is (x0, y0)?  Only prunes; a Gaussian
 // outside its box has alpha < alpha_min at every pixel centre.

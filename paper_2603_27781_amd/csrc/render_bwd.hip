@@ -191,6 +191,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
         for (int ch = 0; ch < 5 + F; ++ch) g[ch] = inside ? grad_out[ch * P + p] : 0.0f;
     }
     float Sg = 0.0f;
+    const float log2_amin = __log2f(c.alpha_min);
     const float amin = c.alpha_min, amax = c.alpha_max;
 
     if (tid == 0) *s_max = 0;
@@ -286,7 +287,10 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
         for (int q = 0; q < NQ; ++q) {
             const int k = 64 * q + lane;
             bool ok = false;
-            if (k < nb && bstart + k - rg.x < wlast) ok = !box_misses(s_g0[k], s_g1[k], wx0, wy0);
+            if (k < nb && bstart + k - rg.x < wlast) {
+                const float4 a0 = s_g0[k], a1 = s_g1[k];
+                ok = !box_misses(a0, a1, wx0, wy0) && !ellipse_misses(a0, a1, wx0, wy0, log2_amin);
+            }
             cand[q] = __ballot(ok);
         }
 #pragma unroll

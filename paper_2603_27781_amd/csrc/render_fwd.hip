@@ -56,6 +56,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
     float T = 1.0f;
     int lastj = 0;
     bool done = !inside;
+    const float log2_amin = __log2f(c.alpha_min);
     const float amin = c.alpha_min, amax = c.alpha_max, tmin = c.T_min;
 
     for (int b0 = rg.x; b0 < rg.y; b0 += B) {
@@ -76,7 +77,12 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int k = 64 * q + lane;
-                cand[q] = __ballot(k < nb && !box_misses(s_g0[k], s_g1[k], wx0, wy0));
+                bool ok = false;
+                if (k < nb) {
+                    const float4 a0 = s_g0[k], a1 = s_g1[k];
+                    ok = !box_misses(a0, a1, wx0, wy0) && !ellipse_misses(a0, a1, wx0, wy0, log2_amin);
+                }
+                cand[q] = __ballot(ok);
             }
             bool wdone = false;
 #pragma unroll
