@@ -153,13 +153,23 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const gs_view*
         const float* Rt = vw.Rt;
         for (int k = 0; k < 3; ++k) dmu[k] += Rt[k] * dp[0] + Rt[4 + k] * dp[1] + Rt[8 + k] * dp[2];
     }
-    const float* ga = grad_app + (size_t)i * GA;
-    // appearance: opacity through the sigmoid, colour and feature as they are
+    // appearance: opacity through the sigmoid, colour and feature as they
+    // are; the row of 4+F floats is 16-byte aligned (4+F is a multiple of 4)
+    const float4* ga4 = reinterpret_cast<const float4*>(grad_app + (size_t)i * GA);
+    const float4 a0 = ga4[0];
     const float lg = g.logit[i];
     const float o = 1.0f / (1.0f + __expf(-lg));
-    out.logit[i] += ga[0] * o * (1.0f - o);
-    for (int k = 0; k < 3; ++k) out.color[(size_t)k * n + i] += ga[1 + k];
-    for (int f = 0; f < F; ++f) out.feat[(size_t)f * n + i] += ga[4 + f];
+    out.logit[i] += a0.x * o * (1.0f - o);
+    out.color[i] += a0.y;
+    out.color[(size_t)n + i] += a0.z;
+    out.color[2 * (size_t)n + i] += a0.w;
+    for (int f4 = 0; f4 < F / 4; ++f4) {
+        const float4 a = ga4[1 + f4];
+        out.feat[(size_t)(4 * f4) * n + i] += a.x;
+        out.feat[(size_t)(4 * f4 + 1) * n + i] += a.y;
+        out.feat[(size_t)(4 * f4 + 2) * n + i] += a.z;
+        out.feat[(size_t)(4 * f4 + 3) * n + i] += a.w;
+    }
     if (!any) return;
     for (int k = 0; k < 3; ++k) out.mu[(size_t)k * n + i] += dmu[k];
     // M = R diag(s)

@@ -507,9 +507,11 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
 #pragma unroll
             for (int q = 0; q < NA; ++q) appacc[q] += __shfl_xor(appacc[q], d, kWave);
         if (i64 < n && vl == 0) {
-            float* ga = grad_app + (size_t)i * (4 + F);
+            // the row of 4+F floats is 16-byte aligned (4+F is a multiple of 4)
+            float4* ga = reinterpret_cast<float4*>(grad_app + (size_t)i * (4 + F));
 #pragma unroll
-            for (int q = 0; q < NA; ++q) ga[q] = appacc[q];
+            for (int q = 0; q < NA / 4; ++q)
+                ga[q] = make_float4(appacc[4 * q], appacc[4 * q + 1], appacc[4 * q + 2], appacc[4 * q + 3]);
         }
     }
 }
