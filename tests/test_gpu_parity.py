@@ -20,12 +20,29 @@ def _multi_view_tiny(seed=61, n=300, F=16):
     return w.scene, w.views + [v2, v3]
 
 
+def _stacked():
+    """600 large Gaussians in a small region: every tile list spans several
+    LDS batches and most pixels stop at T_min."""
+    w = wl.tiny_scene(65, 600, F=16, W=48, H=40, f=40.0, log_scale_mu=-1.6, spread=0.15)
+    return w.scene, w.views
+
+
+def _with_empty_view():
+    """A batch whose second view faces away from every Gaussian."""
+    w = wl.tiny_scene(66, 250, F=8, W=36, H=28, f=30.0)
+    away = wl.make_view(32, 24, 30.0, wl.se3_exp(np.array([0.0, 0.0, 0.0, 0.0, np.pi, 0.0])))
+    return w.scene, w.views + [away]
+
+
 CASES = {
     "tiny3views-F16": lambda: _multi_view_tiny(),
     "cfg1-64x64-2k": lambda: (wl.config1().scene, wl.config1().views),
     "cfg2-160x120-20k-F16": lambda: (lambda w: (w.scene, w.views))(wl.config2(n=20_000, width=160, height=120)),
     "tiny-F8": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(62, 200, F=8, W=40, H=40, f=35.0)),
     "tiny-F32": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(63, 200, F=32, W=40, H=24, f=35.0)),
+    "tiny-F0": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(64, 200, F=0, W=40, H=40, f=35.0)),
+    "stacked600-F16": _stacked,
+    "empty-view-F8": _with_empty_view,
 }
 
 
