@@ -449,11 +449,15 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <
 // Sum of the records of every (view, Gaussian) pair (contiguous emission
 // indices, fixed order).  One lane per (Gaussian, view) pair: the VP lanes of
 // a Gaussian are adjacent in one wavefront (VP a power of two, VP <= 64; with
-// more views than VP a lane takes views vl, vl + VP, ...), so every pair's
-// chain of loads runs in parallel.  grad_geo[V][n][8] <- (dmx, dmy, dA, dB,
-// dC, dd, 0, 0) for visible pairs (others are not written); the appearance
-// part is summed over the Gaussian's lanes by a fixed xor tree and
-// grad_app[n][4+F] written by its first lane (fixed order).
+// more views than VP the lanes take views vl, vl + VP, ... in rounds).  Few
+// pairs are visible and their record counts vary widely, so a wavefront
+// flattens the records of its pairs (an exclusive scan of the counts) and
+// loads them 64 at a time, one record per lane (consecutive records of a
+// pair are adjacent in memory), into LDS; each owner lane then adds its own
+// records from LDS in emission order.  grad_geo[V][n][8] <- (dmx, dmy, dA,
+// dB, dC, dd, 0, 0) for visible pairs (others are not written); the
+// appearance part is summed over the Gaussian's lanes by a fixed xor tree
+// and grad_app[n][4+F] written by its first lane (fixed order).
 template <int F, bool PARAMS>
 __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict__ records,
                                                         const int32_t* __restrict__ pair_first,
@@ -463,6 +467,10 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
     constexpr int NREAL = PARAMS ? 10 + F : 6;
     constexpr int RS = (NREAL + 3) / 4 * 4;
     constexpr int NA = PARAMS ? 4 + F : 1;
+    __shared__ float4 s_rec[256 / kWave][kWave][RS / 4];
+    __shared__ int s_start[256 / kWave][kWave];
+    __shared__ int s_first[256 / kWave][kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int vp = 1 << vp_log2;
     const int64_t i64 = t >> vp_log2;
@@ -471,36 +479,79 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
     float appacc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) appacc[q] = 0.0f;
-    if (i64 < n) {
-        for (int v = vl; v < n_views; v += vp) {
-            const size_t pair = (size_t)v * n + i;
-            const int cnt = touched[pair];
-            if (cnt <= 0) continue;
-            float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            const int64_t first = pair_first[pair];
-            const int64_t stop = first + cnt < capacity ? first + cnt : capacity;  // truncated lists
-            for (int64_t e = first; e < stop; ++e) {
+    for (int v0 = 0; v0 < n_views; v0 += vp) {
+        const int v = v0 + vl;
+        const size_t pair = (size_t)v * n + i;
+        const bool vis = i64 < n && v < n_views && touched[pair] > 0;
+        int cnt = 0, first = 0;
+        if (vis) {
+            first = pair_first[pair];
+            const int64_t stop = (int64_t)first + touched[pair];
+            cnt = (int)((stop < capacity ? stop : capacity) - first);  // truncated lists
+            cnt = cnt > 0 ? cnt : 0;
+        }
+        // exclusive scan of the counts over the wavefront
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int y = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += y;
+        }
+        const int start = incl - cnt;
+        const int total = __shfl(incl, kWave - 1, kWave);
+        s_start[wave][lane] = start;
+        s_first[wave][lane] = first;
+        float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int base = 0; base < total; base += kWave) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int idx = base + lane;
+            if (idx < total) {
+                // owner: the last lane whose start is <= idx (it has records)
+                int lo = 0, hi = kWave - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_start[wave][mid] <= idx) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int64_t e = (int64_t)s_first[wave][lo] + (idx - s_start[wave][lo]);
                 const float4* r4 = reinterpret_cast<const float4*>(records + (size_t)e * RS);
-                float r[RS];
+#pragma unroll
+                for (int q = 0; q < RS / 4; ++q) s_rec[wave][lane][q] = r4[q];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int r0 = start > base ? start : base;
+            const int r1 = start + cnt < base + kWave ? start + cnt : base + kWave;
+            for (int r = r0; r < r1; ++r) {
+                float rr[RS];
 #pragma unroll
                 for (int q = 0; q < RS / 4; ++q) {
-                    const float4 a = r4[q];
-                    r[4 * q] = a.x;
-                    r[4 * q + 1] = a.y;
-                    r[4 * q + 2] = a.z;
-                    r[4 * q + 3] = a.w;
+                    const float4 a = s_rec[wave][r - base][q];
+                    rr[4 * q] = a.x;
+                    rr[4 * q + 1] = a.y;
+                    rr[4 * q + 2] = a.z;
+                    rr[4 * q + 3] = a.w;
                 }
 #pragma unroll
-                for (int q = 0; q < 6; ++q) geo[q] += r[q];
+                for (int q = 0; q < 6; ++q) geo[q] += rr[q];
                 if (PARAMS) {
 #pragma unroll
-                    for (int q = 0; q < NA; ++q) appacc[q] += r[6 + q];
+                    for (int q = 0; q < NA; ++q) appacc[q] += rr[6 + q];
                 }
             }
+        }
+        if (vis) {
             float4* gg = reinterpret_cast<float4*>(grad_geo + pair * 8);
             gg[0] = make_float4(geo[0], geo[1], geo[2], geo[3]);
             gg[1] = make_float4(geo[4], geo[5], 0.f, 0.f);
         }
+        // the next round reuses this wavefront's LDS
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (PARAMS) {
         for (int d = 1; d < vp; d <<= 1)
