@@ -151,6 +151,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                                          float4* s_g0, float4* s_g1, float4* s_app, int* s_max, float* s_acc) {
     constexpr int NT = TS * TS;
     constexpr int AV = AppRec<F>::vec;
+    static_assert((3 + F) % 4 == 3, "the staged appearance record needs its padding slot for the depth");
     constexpr int NREAL = PARAMS ? 10 + F : 6;  // record slots
     constexpr int NBF = 6;                      // full-wavefront butterfly: mean, conic, opacity | depth
     constexpr int NV = Pow2<NBF>::value;
@@ -273,7 +274,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 #pragma unroll
             for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
             // the record's last float is padding (3 + F is 3 mod 4): depth goes there
-            if constexpr (PARAMS) reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
+            reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
         }
         for (int k = tid; k < nb * AST; k += NT) s_acc[k] = 0.0f;
         __syncthreads();
@@ -302,10 +303,6 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             for (;;) {
                 m &= ~(1ull << (j - 64 * q));
                 const int jn = m ? 64 * q + 63 - __builtin_clzll(m) : -1;
-                // unconditional load (index clamped): a conditional one is
-                // folded into a pointer select that leaves LDS addressing
-                const int jp = jn >= 0 ? jn : j;
-                const float4 g0n = s_g0[jp], g1n = s_g1[jp];
                 // appearance of Gaussian j: with parameter gradients only this
                 // lane's channels, else the whole record
                 float xs[PARAMS ? (NL > 0 ? NL : 1) : AV * 4];
@@ -327,6 +324,20 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 float dx, dy, G;
                 bool unc;
                 const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
+                // derivatives of q' along dx and dy (up to the factors the
+                // record scales apply), formed now so that g0 and g1 are dead:
+                // the next candidate's geometry is loaded into them (no
+                // register copies at the end of the step), unconditionally
+                // with a clamped index (a conditional load becomes a pointer
+                // select that leaves LDS addressing)
+                float qx = fmaf(2.0f * g0.z, dx, g0.w * dy);
+                float qy = fmaf(g0.w, dx, 2.0f * g1.x * dy);
+                // keeps both here (an empty statement, no instruction): sunk
+                // into the branch below they would keep g0 and g1 alive
+                __asm__ volatile("" : "+v"(qx), "+v"(qy));
+                const int jp = jn >= 0 ? jn : j;
+                g0 = s_g0[jp];
+                g1 = s_g1[jp];
                 const bool contrib = jl < lastp && a >= amin;
                 if (__any(contrib)) {
                     // Branch-free over the wavefront: lanes without a
@@ -354,7 +365,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                         pt[1] = swap_halves_add<32>(pt[1], pt[3]);
                         gx = swap_halves_add<16>(pt[0], pt[1]) + g[0];
                     } else {
-                        gx = fmaf(g[0], xs[0], fmaf(g[1], xs[1], fmaf(g[2], xs[2], fmaf(g[3], g1.z, g[4]))));
+                        gx = fmaf(g[0], xs[0], fmaf(g[1], xs[1], fmaf(g[2], xs[2], fmaf(g[3], xs[AV * 4 - 1], g[4]))));
 #pragma unroll
                         for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], xs[3 + f], gx);
                     }
@@ -363,8 +374,8 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     const float hm = (contrib && unc) ? dA : 0.0f;
                     const float h = hm * a;
                     float val[NV];
-                    val[0] = h * fmaf(2.0f * g0.z, dx, g0.w * dy);
-                    val[1] = h * fmaf(g0.w, dx, 2.0f * g1.x * dy);
+                    val[0] = h * qx;
+                    val[1] = h * qy;
                     val[2] = h * dx * dx;
                     val[3] = h * dx * dy;
                     val[4] = h * dy * dy;
@@ -389,8 +400,6 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 }
                 if (jn < 0) break;
                 j = jn;
-                g0 = g0n;
-                g1 = g1n;
             }
         }
         __syncthreads();

@@ -32,6 +32,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                                          int32_t* __restrict__ last, float4* s_g0, float4* s_g1, float4* s_app) {
     constexpr int NT = TS * TS;
     constexpr int AV = AppRec<F>::vec;
+    static_assert((3 + F) % 4 == 3, "the staged appearance record needs its padding slot for the depth");
     constexpr int NQ = B / 64;  // 64-bit candidate masks per batch
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     constexpr int WPR = TS / 8;
@@ -70,6 +71,8 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
             s_g1[k] = a1;
 #pragma unroll
             for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
+            // the record's last float is padding (3 + F is 3 mod 4): depth goes there
+            reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
         }
         __syncthreads();
         if (!__all(done)) {
@@ -94,16 +97,20 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                 for (;;) {
                     m &= m - 1;
                     const int jn = m ? 64 * q + __builtin_ctzll(m) : -1;
-                    // unconditional load (index clamped): a conditional one is
-                    // folded into a pointer select that leaves LDS addressing
-                    const int jp = jn >= 0 ? jn : j;
-                    const float4 g0n = s_g0[jp], g1n = s_g1[jp];
                     float4 av[AV];
 #pragma unroll
                     for (int qq = 0; qq < AV; ++qq) av[qq] = s_app[j * AV + qq];
                     float dx, dy, G;
                     bool unc;
                     const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
+                    // g0 and g1 are dead from here: the next candidate's
+                    // geometry is loaded into them (no register copies at the
+                    // end of the step), unconditionally with a clamped index
+                    // (a conditional load becomes a pointer select that
+                    // leaves LDS addressing)
+                    const int jp = jn >= 0 ? jn : j;
+                    g0 = s_g0[jp];
+                    g1 = s_g1[jp];
                     const bool ok = !done && a >= amin;
                     const float Tn = T * (1.0f - a);
                     const bool use = ok && !(Tn < tmin);
@@ -114,7 +121,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                         acc[0] = fmaf(w, ap[0], acc[0]);
                         acc[1] = fmaf(w, ap[1], acc[1]);
                         acc[2] = fmaf(w, ap[2], acc[2]);
-                        acc[3] = fmaf(w, g1.z, acc[3]);
+                        acc[3] = fmaf(w, ap[AV * 4 - 1], acc[3]);
 #pragma unroll
                         for (int f = 0; f < F; ++f) acc[4 + f] = fmaf(w, ap[3 + f], acc[4 + f]);
                         T = use ? Tn : T;
@@ -127,8 +134,6 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     }
                     if (jn < 0) break;
                     j = jn;
-                    g0 = g0n;
-                    g1 = g1n;
                 }
             }
         }
