@@ -16,10 +16,15 @@
 //   dL/drho = sum dp,  dL/dphi = sum p x dp + 2 (Sigma_c G - G Sigma_c)_(12, 20, 01).
 #include "sgs_common.h"
 
+// This file is value path only (no decision feeds an integer): the compiler
+// may fuse multiplies and adds here, unlike the rest of the library.
+#pragma clang fp contract(fast)
+
 namespace sgs {
 
 struct Fwd {
     float p[3];
+    float iz;  // 1 / p_z
     float xn, yn;
     float j00, j02, j11, j12;
     float T[6];   // J R_CW, 2x3
@@ -51,14 +56,16 @@ __device__ __forceinline__ void load_gauss(const GaussPtrs& g, int i, Gauss& G) 
         for (int k = 0; k < 3; ++k) G.M[3 * r + k] = G.R[3 * r + k] * G.s[k];
 }
 
-__device__ __forceinline__ void forward(const Gauss& G, const float* mu, const gs_view& vw, float blur, Fwd& f) {
-    const float* Rt = vw.Rt;
+// Rt: row-major [R|t] of the view; fx, fy its focal lengths.  Divisions go
+// through one hardware reciprocal (about 1 ulp): nothing here is compared.
+__device__ __forceinline__ void forward(const Gauss& G, const float* mu, const float* Rt, float fx, float fy,
+                                        float blur, Fwd& f) {
     for (int k = 0; k < 3; ++k) f.p[k] = Rt[4 * k] * mu[0] + Rt[4 * k + 1] * mu[1] + Rt[4 * k + 2] * mu[2] + Rt[4 * k + 3];
-    const float z = f.p[2];
-    f.xn = f.p[0] / z;
-    f.yn = f.p[1] / z;
-    f.j00 = vw.fx / z;
-    f.j11 = vw.fy / z;
+    f.iz = __builtin_amdgcn_rcpf(f.p[2]);
+    f.xn = f.p[0] * f.iz;
+    f.yn = f.p[1] * f.iz;
+    f.j00 = fx * f.iz;
+    f.j11 = fy * f.iz;
     f.j02 = -f.j00 * f.xn;
     f.j12 = -f.j11 * f.yn;
     for (int k = 0; k < 3; ++k) {
@@ -74,11 +81,11 @@ __device__ __forceinline__ void forward(const Gauss& G, const float* mu, const g
 }
 
 // Backward of one view: accumulates dM (3x3), returns dp (3) and D (Sigma2D gradient).
-__device__ __forceinline__ void backward_view(const Gauss& G, const Fwd& f, const gs_view& vw, const float4 g0,
-                                              const float4 g1, float* dM, float* dp, float* D) {
+__device__ __forceinline__ void backward_view(const Gauss& G, const Fwd& f, const float* Rt, float fx, float fy,
+                                              const float4 g0, const float4 g1, float* dM, float* dp, float* D) {
     // conic Q from Sigma2D
-    const float det = f.a * f.c - f.b * f.b;
-    const float A = f.c / det, Bq = -f.b / det, C = f.a / det;
+    const float idet = __builtin_amdgcn_rcpf(f.a * f.c - f.b * f.b);
+    const float A = f.c * idet, Bq = -f.b * idet, C = f.a * idet;
     const float dA = g0.z, dBh = 0.5f * g0.w, dC = g1.x;  // symmetric dQ: off-diagonals carry dB/2
     // D = -Q dQ Q
     D[0] = -(A * A * dA + 2.f * A * Bq * dBh + Bq * Bq * dC);
@@ -98,13 +105,11 @@ __device__ __forceinline__ void backward_view(const Gauss& G, const Fwd& f, cons
     for (int l = 0; l < 3; ++l)
         for (int k = 0; k < 3; ++k) dM[3 * l + k] += f.T[l] * dU[k] + f.T[3 + l] * dU[3 + k];
     // dJ = dT R_CW^T for the four non-zero entries of J
-    const float* Rt = vw.Rt;
     const float dJ00 = dT[0] * Rt[0] + dT[1] * Rt[1] + dT[2] * Rt[2];
     const float dJ02 = dT[0] * Rt[8] + dT[1] * Rt[9] + dT[2] * Rt[10];
     const float dJ11 = dT[3] * Rt[4] + dT[4] * Rt[5] + dT[5] * Rt[6];
     const float dJ12 = dT[3] * Rt[8] + dT[4] * Rt[9] + dT[5] * Rt[10];
-    const float z = f.p[2], iz = 1.0f / z, iz2 = iz * iz;
-    const float fx = vw.fx, fy = vw.fy;
+    const float iz = f.iz, iz2 = iz * iz;
     // mean2d = (fx x/z + cx, fy y/z + cy); depth = z
     float gx = g0.x * fx * iz;
     float gy = g0.y * fy * iz;
@@ -123,52 +128,84 @@ __device__ __forceinline__ bool nonzero(const float4 a, const float4 b) {
     return a.x != 0.f || a.y != 0.f || a.z != 0.f || a.w != 0.f || b.x != 0.f || b.y != 0.f;
 }
 
-// Parameter gradients, one thread per Gaussian, looping over the views (no
-// atomics: every view's contribution is summed in registers).
-__global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const gs_view* __restrict__ views, int n_views,
-                                                     float blur, const int32_t* __restrict__ touched,
-                                                     const float4* __restrict__ grad_geo,
-                                                     const float* __restrict__ grad_app, GradPtrs out) {
+// Parameter gradients, one thread per Gaussian (no atomics: the views'
+// contributions are summed in registers, in view order).  A Gaussian touches
+// few of the views, so each lane walks only its own touched views (a bit
+// mask, lowest view first): a wavefront runs as many rounds as its busiest
+// lane has views, not one round per view, and each lane reads the camera of
+// its current view from LDS.  Every plane the thread reads is loaded up
+// front in one batch; the feature count is a template parameter so those
+// loads are unrolled.
+constexpr int kPbThreads = 256;
+constexpr int kPbViewFloats = 16;  // Rt (12), fx, fy, 2 unused
+
+template <int F>
+__global__ void __launch_bounds__(kPbThreads) k_project_bwd(GaussPtrs g, const gs_view* __restrict__ views,
+                                                            int n_views, float blur,
+                                                            const int32_t* __restrict__ touched,
+                                                            const float4* __restrict__ grad_geo,
+                                                            const float4* __restrict__ grad_app, GradPtrs out) {
+    constexpr int GA4 = (4 + F) / 4;  // float4 per appearance-gradient row
+    __shared__ float4 s_vw4[GS_MAX_VIEWS * kPbViewFloats / 4];
+    float* s_vw = reinterpret_cast<float*>(s_vw4);
+    for (int v = threadIdx.x; v < n_views; v += kPbThreads) {
+        const gs_view& vw = views[v];
+        float* d = s_vw + v * kPbViewFloats;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) d[k] = vw.Rt[k];
+        d[12] = vw.fx;
+        d[13] = vw.fy;
+    }
+    __syncthreads();
     const int n = g.n;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kPbThreads + threadIdx.x;
     if (i >= n) return;
-    const int F = g.n_feat, GA = 4 + F;
+
+    // views whose pair this Gaussian touches
+    uint64_t mask = 0;
+#pragma unroll 8
+    for (int v = 0; v < n_views; ++v) mask |= (uint64_t)(touched[(size_t)v * n + i] > 0) << v;
+
+    // appearance: opacity through the sigmoid, colour and feature as they are
+    float4 ga[GA4];
+#pragma unroll
+    for (int q = 0; q < GA4; ++q) ga[q] = grad_app[(size_t)i * GA4 + q];
+    const float lg = g.logit[i];
+    float oc[3], of[F > 0 ? F : 1];
+    const float ol = out.logit[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) oc[k] = out.color[(size_t)k * n + i];
+#pragma unroll
+    for (int f = 0; f < F; ++f) of[f] = out.feat[(size_t)f * n + i];
+    const float* gaf = reinterpret_cast<const float*>(ga);
+    const float o = 1.0f / (1.0f + __expf(-lg));
+    out.logit[i] = ol + gaf[0] * o * (1.0f - o);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out.color[(size_t)k * n + i] = oc[k] + gaf[1 + k];
+#pragma unroll
+    for (int f = 0; f < F; ++f) out.feat[(size_t)f * n + i] = of[f] + gaf[4 + f];
+    if (mask == 0) return;
+
     Gauss G;
     load_gauss(g, i, G);
     const float mu[3] = {g.mu[i], g.mu[(size_t)n + i], g.mu[2 * (size_t)n + i]};
     float dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float dmu[3] = {0, 0, 0};
     bool any = false;
-    for (int v = 0; v < n_views; ++v) {
-        const size_t o = (size_t)v * n + i;
-        if (touched[o] <= 0) continue;
-        const float4 g0 = grad_geo[2 * o], g1 = grad_geo[2 * o + 1];
+    while (mask != 0) {
+        const int v = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const size_t o2 = (size_t)v * n + i;
+        const float4 g0 = grad_geo[2 * o2], g1 = grad_geo[2 * o2 + 1];
         if (!nonzero(g0, g1)) continue;
         any = true;
-        const gs_view& vw = views[v];
+        const float* Rt = s_vw + v * kPbViewFloats;
+        const float fx = Rt[12], fy = Rt[13];
         Fwd f;
-        forward(G, mu, vw, blur, f);
+        forward(G, mu, Rt, fx, fy, blur, f);
         float dp[3], D[3];
-        backward_view(G, f, vw, g0, g1, dM, dp, D);
-        const float* Rt = vw.Rt;
+        backward_view(G, f, Rt, fx, fy, g0, g1, dM, dp, D);
         for (int k = 0; k < 3; ++k) dmu[k] += Rt[k] * dp[0] + Rt[4 + k] * dp[1] + Rt[8 + k] * dp[2];
-    }
-    // appearance: opacity through the sigmoid, colour and feature as they
-    // are; the row of 4+F floats is 16-byte aligned (4+F is a multiple of 4)
-    const float4* ga4 = reinterpret_cast<const float4*>(grad_app + (size_t)i * GA);
-    const float4 a0 = ga4[0];
-    const float lg = g.logit[i];
-    const float o = 1.0f / (1.0f + __expf(-lg));
-    out.logit[i] += a0.x * o * (1.0f - o);
-    out.color[i] += a0.y;
-    out.color[(size_t)n + i] += a0.z;
-    out.color[2 * (size_t)n + i] += a0.w;
-    for (int f4 = 0; f4 < F / 4; ++f4) {
-        const float4 a = ga4[1 + f4];
-        out.feat[(size_t)(4 * f4) * n + i] += a.x;
-        out.feat[(size_t)(4 * f4 + 1) * n + i] += a.y;
-        out.feat[(size_t)(4 * f4 + 2) * n + i] += a.z;
-        out.feat[(size_t)(4 * f4 + 3) * n + i] += a.w;
     }
     if (!any) return;
     for (int k = 0; k < 3; ++k) out.mu[(size_t)k * n + i] += dmu[k];
@@ -214,10 +251,10 @@ __global__ void __launch_bounds__(256) k_pose_partial(GaussPtrs g, const gs_view
             const float mu[3] = {g.mu[i], g.mu[(size_t)n + i], g.mu[2 * (size_t)n + i]};
             const gs_view& vw = views[v];
             Fwd f;
-            forward(G, mu, vw, blur, f);
+            forward(G, mu, vw.Rt, vw.fx, vw.fy, blur, f);
             float dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             float dp[3], D[3];
-            backward_view(G, f, vw, g0, g1, dM, dp, D);
+            backward_view(G, f, vw.Rt, vw.fx, vw.fy, g0, g1, dM, dp, D);
             // G_c = J^T D J with J = [[j00, 0, j02], [0, j11, j12]]
             const float J0[3] = {f.j00, 0.f, f.j02}, J1[3] = {0.f, f.j11, f.j12};
             float Gc[9];
@@ -282,8 +319,17 @@ hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int 
                               const int32_t* touched, const float* grad_geo, const float* grad_app,
                               const GradPtrs& out, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)ceil_div(g.n, 256)), dim3(256), 0, s, g, views_dev, n_views,
-                       c.blur, touched, reinterpret_cast<const float4*>(grad_geo), grad_app, out);
+    auto kern = k_project_bwd<16>;
+    switch (g.n_feat) {
+        case 0: kern = k_project_bwd<0>; break;
+        case 8: kern = k_project_bwd<8>; break;
+        case 32: kern = k_project_bwd<32>; break;
+        case 16: break;
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(g.n, kPbThreads)), dim3(kPbThreads), 0, s, g, views_dev, n_views,
+                       c.blur, touched, reinterpret_cast<const float4*>(grad_geo),
+                       reinterpret_cast<const float4*>(grad_app), out);
     return hipGetLastError();
 }
 
