@@ -4,7 +4,7 @@
 // Two stable sorts replace one wide-key sort:
 //   1. the visible (view, Gaussian) pairs, compacted in (view, index) order,
 //      are radix-sorted by the binary32 bits of their camera depth (4 passes
-//      of 8 bits);
+//      of 8 bits; the last pass also writes each sorted pair's tile count);
 //   2. each pair, in that depth order, emits one instance per tile of its
 //      rectangle, keyed by global tile id, and the instances are radix-sorted
 //      by tile id (ceil(log2 tiles) bits).
@@ -14,16 +14,23 @@
 // Every count that the host does not know (visible pairs, instances) stays on
 // the device; grids are sized for the capacity and blocks beyond the count
 // exit early, so the whole pipeline is graph-capturable.
+//
+// Prefix sums take one launch where the input is short and two or three
+// where it is long.  The radix digit offsets (256 per block) are a single-pass scan with
+// decoupled look-back: a block takes a ticket, scans its tile, publishes its
+// total and reads the totals of the tiles before it until it meets a
+// published prefix; it only ever waits for blocks that took an earlier
+// ticket, which are already running, so every wait ends (the spin is bounded
+// all the same).  The long scan of the instance offsets (thousands of
+// tiles, where such a chain of waits costs more than it saves) writes tile
+// totals first, and each tile then sums the totals before it itself; the
+// compaction counts runs, scans the run counts in one block and ranks
+// inside a run with ballots.
 #include "sgs_common.h"
 
 namespace sgs {
 
 namespace {
-
-constexpr int SCAN_THREADS = 256;
-constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
-constexpr int TOP_THREADS = 1024;
 
 // Radix passes run on a fixed grid of at most RS_MAXBLK blocks; the device
 // side count is split into contiguous chunks (multiples of RS_THREADS), one
@@ -32,6 +39,8 @@ constexpr int TOP_THREADS = 1024;
 constexpr int RS_THREADS = 256;
 constexpr int RS_MAXBLK = 1024;
 constexpr int RS_WAVES = RS_THREADS / kWave;
+constexpr int RS_ITEMS = 4;                        // keys per thread per scatter tile
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;     // chunks are whole tiles
 
 int rs_blocks(int64_t n_max) {
     const int64_t b = (n_max + RS_THREADS - 1) / RS_THREADS;
@@ -39,7 +48,7 @@ int rs_blocks(int64_t n_max) {
 }
 
 __device__ __forceinline__ void rs_chunk(int64_t count, int nblk, int64_t& lo, int64_t& hi) {
-    const int64_t per = ((count + nblk - 1) / nblk + RS_THREADS - 1) / RS_THREADS * RS_THREADS;
+    const int64_t per = ((count + nblk - 1) / nblk + RS_TILE - 1) / RS_TILE * RS_TILE;
     lo = (int64_t)blockIdx.x * per;
     lo = lo < count ? lo : count;
     hi = lo + per < count ? lo + per : count;
@@ -54,15 +63,6 @@ __device__ __forceinline__ int64_t eff_count(const int64_t* count_dev, int64_t n
 // ----------------------------------------------------------------------------
 // loaders for the generic exclusive scan
 // ----------------------------------------------------------------------------
-struct LoadNonZero {  // 1 if touched[i] > 0
-    const int32_t* p;
-    __device__ uint32_t operator()(int64_t i) const { return p[i] > 0 ? 1u : 0u; }
-};
-struct LoadGatherTouched {  // touched[idx[i]]
-    const int32_t* touched;
-    const uint32_t* idx;
-    __device__ uint32_t operator()(int64_t i) const { return (uint32_t)touched[idx[i]]; }
-};
 struct LoadU32 {
     const uint32_t* p;
     __device__ uint32_t operator()(int64_t i) const { return p[i]; }
@@ -92,20 +92,28 @@ __device__ uint32_t block_exclusive(uint32_t v, uint32_t* s_tmp, uint32_t* total
     return wbase + x - v;
 }
 
-template <class Load>
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_partial(Load ld, const int64_t* count_dev, int64_t n_max,
-                                                               uint32_t* block_sums) {
-    __shared__ uint32_t s_tmp[SCAN_THREADS / kWave];
-    const int64_t count = eff_count(count_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    uint32_t acc = 0;
+// Sum of a[0 .. m) by the whole block (all threads get it): used by a block
+// to find its offset from the totals of the tiles before it, so that the
+// large scans need no top-level scan launch and no waiting between blocks.
+// The totals are few (one per tile) and were just written, so they are
+// read from L2.
+template <int NT>
+__device__ __forceinline__ uint32_t block_sum_before(const uint32_t* __restrict__ a, int m, uint32_t* s_tmp) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint32_t x = 0;
+    for (int i = tid; i < m; i += NT) x += a[i];
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k)
-        if (base + k < count) acc += ld(base + k);
-    uint32_t tot;
-    block_exclusive<SCAN_THREADS>(acc, s_tmp, &tot);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    if (lane == 0) s_tmp[wave] = x;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) t += s_tmp[w];
+    __syncthreads();
+    return t;
 }
+
+constexpr int TOP_THREADS = 1024;
 
 // Single-block exclusive scan of the block sums, total to *total (int64):
 // each of the TOP_THREADS threads takes a contiguous run of sums.
@@ -125,44 +133,205 @@ __global__ void __launch_bounds__(TOP_THREADS) k_scan_top(uint32_t* block_sums, 
     if (threadIdx.x == 0 && total != nullptr) *total = (int64_t)tot;
 }
 
+// Single-pass exclusive scan with decoupled look-back.  Status word of a
+// tile: bits 62-63 the state (0 not ready, 1 tile total, 2 inclusive prefix),
+// bits 0-31 the value.
+constexpr int LB_THREADS = 256;
+constexpr int LB_ITEMS = 8;
+constexpr int LB_TILE = LB_THREADS * LB_ITEMS;
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 2ull << 62;
+constexpr int LB_SPIN_MAX = 1 << 20;
+
+int64_t lb_tiles(int64_t n) { return (n + LB_TILE - 1) / LB_TILE; }
+
+__device__ __forceinline__ void lb_publish(uint64_t* st, uint64_t state, uint32_t value) {
+    __hip_atomic_store(st, state | value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lb_read(const uint64_t* st) {
+    return __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of tile `tile` (> 0) from the status words of the tiles
+// before it; called by one whole wavefront, which reads 64 of them at a
+// time, newest first.  Positions before tile 0 count as an inclusive 0.
+__device__ uint32_t lb_lookback(const uint64_t* status, int tile) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t prefix = 0;
+    for (int j = tile - 1;; j -= kWave) {
+        const int k = j - lane;
+        uint64_t s = k >= 0 ? lb_read(status + k) : LB_INC;
+        for (int spin = 0; __any((s >> 62) == 0) && spin < LB_SPIN_MAX; ++spin)
+            if ((s >> 62) == 0) s = lb_read(status + k);
+        const uint64_t inc = __ballot((s >> 62) == 2);
+        uint32_t v = (uint32_t)s;
+        if (inc != 0 && lane > __builtin_ctzll(inc)) v = 0;  // stop at the nearest inclusive prefix
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+        prefix += v;
+        if (inc != 0) return prefix;
+    }
+}
+
+// Ticket, tile scan and look-back shared by the single-pass kernels: returns
+// the exclusive prefix of this thread's items (excl added to the tile's
+// prefix) and the tile's total; all threads of the block call it.
+__device__ __forceinline__ uint32_t lb_block(uint32_t acc, int tile, uint64_t* status, uint32_t* s_tmp,
+                                             uint32_t* s_prefix, uint32_t* tile_total) {
+    uint32_t tot;
+    const uint32_t excl = block_exclusive<LB_THREADS>(acc, s_tmp, &tot);
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        uint32_t prefix = 0;
+        if (tile == 0) {
+            if (lane == 0) lb_publish(status, LB_INC, tot);
+        } else {
+            if (lane == 0) lb_publish(status + tile, LB_AGG, tot);
+            prefix = lb_lookback(status, tile);
+            if (lane == 0) lb_publish(status + tile, LB_INC, prefix + tot);
+        }
+        if (lane == 0) *s_prefix = prefix;
+    }
+    __syncthreads();
+    *tile_total = tot;
+    return *s_prefix + excl;
+}
+
+__device__ __forceinline__ int lb_ticket(uint32_t* ticket, int* s_tile) {
+    if (threadIdx.x == 0) *s_tile = (int)atomicAdd(ticket, 1u);
+    __syncthreads();
+    return *s_tile;
+}
+
+// Instance bookkeeping written by the last tile of the instance-offset scan.
+struct CountsOut {
+    int64_t* counts;         // (instances, visible pairs, overflow flag, 0)
+    int64_t* n_clamped;      // min(instances, capacity)
+    const int64_t* n_vis;
+    int64_t capacity;
+};
+
+// Two-step exclusive scan for long inputs: tile totals, then every tile
+// sums the totals before it and scans its own items (no top-level launch,
+// no waiting between blocks).  Tiles of LB_TILE items, LB_ITEMS consecutive
+// items per thread.
 template <class Load>
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_final(Load ld, const int64_t* count_dev, int64_t n_max,
-                                                             const uint32_t* block_sums, uint32_t* out) {
-    __shared__ uint32_t s_tmp[SCAN_THREADS / kWave];
+__global__ void __launch_bounds__(LB_THREADS) k_tile_sums(Load ld, const int64_t* count_dev, int64_t n_max,
+                                                          uint32_t* __restrict__ sums) {
+    __shared__ uint32_t s_tmp[LB_THREADS / kWave];
     const int64_t count = eff_count(count_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    if ((int64_t)blockIdx.x * SCAN_TILE >= count) return;  // whole block beyond the count
-    uint32_t v[SCAN_ITEMS];
+    const int64_t tbase = (int64_t)blockIdx.x * LB_TILE;
+    if (tbase >= count) return;  // uniform; no later tile reads this sum
+    const int64_t base = tbase + (int64_t)threadIdx.x * LB_ITEMS;
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
+    for (int k = 0; k < LB_ITEMS; ++k)
+        if (base + k < count) acc += ld(base + k);
+    uint32_t tot;
+    block_exclusive<LB_THREADS>(acc, s_tmp, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+template <class Load>
+__global__ void __launch_bounds__(LB_THREADS) k_tile_scan(Load ld, const int64_t* count_dev, int64_t n_max,
+                                                          const uint32_t* __restrict__ sums, uint32_t* out,
+                                                          int64_t* total, CountsOut co) {
+    __shared__ uint32_t s_tmp[LB_THREADS / kWave];
+    const int64_t count = eff_count(count_dev, n_max);
+    const int64_t tbase = (int64_t)blockIdx.x * LB_TILE;
+    if (tbase >= count && blockIdx.x != 0) return;  // uniform
+    const uint32_t prefix = block_sum_before<LB_THREADS>(sums, (int)blockIdx.x, s_tmp);
+    const int64_t base = tbase + (int64_t)threadIdx.x * LB_ITEMS;
+    uint32_t v[LB_ITEMS];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
         v[k] = (base + k < count) ? ld(base + k) : 0u;
         acc += v[k];
     }
     uint32_t tot;
-    uint32_t run = block_sums[blockIdx.x] + block_exclusive<SCAN_THREADS>(acc, s_tmp, &tot);
+    uint32_t run = prefix + block_exclusive<LB_THREADS>(acc, s_tmp, &tot);
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
+    for (int k = 0; k < LB_ITEMS; ++k) {
         if (base + k < count) out[base + k] = run;
         run += v[k];
     }
+    if (threadIdx.x == 0 && tbase + LB_TILE >= count) {  // the last tile with items (tile 0 if none)
+        const int64_t I = (int64_t)prefix + tot;
+        if (total != nullptr) *total = I;
+        if (co.counts != nullptr) {
+            co.counts[0] = I;
+            co.counts[1] = *co.n_vis;
+            co.counts[2] = I > co.capacity ? 1 : 0;
+            co.counts[3] = 0;
+            *co.n_clamped = I < co.capacity ? I : co.capacity;
+        }
+    }
 }
 
+// Exclusive scan of ld(0 .. count) into out (in place allowed: a tile is
+// read before it is written and by no other block); *total <- the sum.
+// Grid: lb_tiles(n_max) blocks.
 template <class Load>
-hipError_t exclusive_scan(Load ld, const int64_t* count_dev, int64_t n_max, uint32_t* block_sums, uint32_t* out,
-                          int64_t* total, hipStream_t s) {
-    const int nb = (int)((n_max + SCAN_TILE - 1) / SCAN_TILE);
-    if (nb == 0) {
-        if (total) {
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, block_sums, 0, total);
-        }
-        return hipGetLastError();
+__global__ void __launch_bounds__(LB_THREADS) k_scan_lb(Load ld, const int64_t* count_dev, int64_t n_max,
+                                                        uint64_t* status, uint32_t* ticket, uint32_t* out,
+                                                        int64_t* total) {
+    __shared__ uint32_t s_tmp[LB_THREADS / kWave];
+    __shared__ uint32_t s_prefix;
+    __shared__ int s_tile;
+    const int tile = lb_ticket(ticket, &s_tile);
+    const int64_t count = eff_count(count_dev, n_max);
+    const int64_t tbase = (int64_t)tile * LB_TILE;
+    if (tbase >= count && tile != 0) return;  // uniform: no later tile reads this one
+    const int64_t base = tbase + (int64_t)threadIdx.x * LB_ITEMS;
+    uint32_t v[LB_ITEMS];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+        v[k] = (base + k < count) ? ld(base + k) : 0u;
+        acc += v[k];
     }
-    hipLaunchKernelGGL(k_scan_partial<Load>, dim3(nb), dim3(SCAN_THREADS), 0, s, ld, count_dev, n_max, block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, block_sums, nb, total);
-    hipLaunchKernelGGL(k_scan_final<Load>, dim3(nb), dim3(SCAN_THREADS), 0, s, ld, count_dev, n_max, block_sums,
-                       out);
+    uint32_t tot;
+    uint32_t run = lb_block(acc, tile, status, s_tmp, &s_prefix, &tot);
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+        if (base + k < count) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0 && total != nullptr && tbase + LB_TILE >= count) *total = (int64_t)s_prefix + tot;
+}
+
+// Single-pass scan for short inputs (few tiles: the look-back stays short).
+template <class Load>
+hipError_t exclusive_scan(Load ld, const int64_t* count_dev, int64_t n_max, uint64_t* status, uint32_t* ticket,
+                          uint32_t* out, int64_t* total, hipStream_t s) {
+    const int64_t nt = lb_tiles(n_max);
+    hipLaunchKernelGGL(k_scan_lb<Load>, dim3((unsigned)(nt > 0 ? nt : 1)), dim3(LB_THREADS), 0, s, ld, count_dev,
+                       n_max, status, ticket, out, total);
     return hipGetLastError();
+}
+
+// Two-step scan for long inputs; sums holds lb_tiles(n_max) words.
+template <class Load>
+hipError_t exclusive_scan_long(Load ld, const int64_t* count_dev, int64_t n_max, uint32_t* sums, uint32_t* out,
+                               int64_t* total, hipStream_t s, CountsOut co) {
+    const int64_t nt = lb_tiles(n_max) > 0 ? lb_tiles(n_max) : 1;
+    hipLaunchKernelGGL(k_tile_sums<Load>, dim3((unsigned)nt), dim3(LB_THREADS), 0, s, ld, count_dev, n_max, sums);
+    hipLaunchKernelGGL(k_tile_scan<Load>, dim3((unsigned)nt), dim3(LB_THREADS), 0, s, ld, count_dev, n_max, sums,
+                       out, total, co);
+    return hipGetLastError();
+}
+
+// Zeroes the look-back status words and tickets of one binning call and the
+// per-tile ranges (a fill kernel rather than a memset, so that graph replays
+// stay correct).
+__global__ void k_bin_reset(uint64_t* status, int64_t n_status, uint32_t* tickets, int n_tickets, uint32_t* ranges,
+                            int64_t n_ranges) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_status; i += stride) status[i] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_ranges; i += stride) ranges[i] = 0;
+    if (blockIdx.x == 0 && (int)threadIdx.x < n_tickets) tickets[threadIdx.x] = 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -180,9 +349,21 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     return m;
 }
 
-__global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, const int64_t* count_dev,
-                                                           int64_t n_max, int shift, uint32_t* __restrict__ hist,
-                                                           int nblk) {
+// Key source of a radix pass: the (key, value) arrays of the previous pass.
+// (A source may also skip elements, key() returning false: the histogram
+// and the scatter then leave them out.)
+struct SrcKV {
+    const uint32_t* keys;
+    const uint32_t* vals;
+    __device__ bool key(int64_t i, uint32_t& k) const {
+        k = keys[i];
+        return true;
+    }
+    __device__ uint32_t val(int64_t i) const { return vals[i]; }
+};
+template <class Src>
+__global__ void __launch_bounds__(RS_THREADS) k_radix_hist(Src src, const int64_t* count_dev, int64_t n_max,
+                                                           int shift, uint32_t* __restrict__ hist, int nblk) {
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     h[tid] = 0;
@@ -192,8 +373,9 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint32_t* __res
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int64_t i0 = lo; i0 < hi; i0 += RS_THREADS) {
         const int64_t i = i0 + tid;
-        const bool valid = i < hi;
-        const uint32_t d = valid ? ((keys[i] >> shift) & 0xffu) : 0u;
+        uint32_t key = 0;
+        const bool valid = i < hi && src.key(i, key);
+        const uint32_t d = valid ? ((key >> shift) & 0xffu) : 0u;
         const uint64_t peers = match_digit(d, valid);
         if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
@@ -201,65 +383,120 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint32_t* __res
     hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
 }
 
-__global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint32_t* __restrict__ keys_in,
-                                                              const uint32_t* __restrict__ vals_in,
-                                                              const int64_t* count_dev, int64_t n_max, int shift,
-                                                              const uint32_t* __restrict__ offs, int nblk,
-                                                              uint32_t* __restrict__ keys_out,
-                                                              uint32_t* __restrict__ vals_out) {
-    __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_wcnt[RS_WAVES][256];
+// Stable scatter of one pass, a tile of RS_TILE keys at a time: every key is
+// ranked inside the tile (wavefront ballots per row of RS_THREADS keys, then
+// per digit a prefix over the rows and wavefronts, then over the digits),
+// the tile is reordered by digit in LDS, and each digit's run of keys is
+// written to its global position as consecutive addresses, instead of every
+// key going to a different place.  touched_out (may be null): also writes
+// touched[value] at each output position (the last depth pass, so that the
+// instance offsets scan a plain array in sorted order).
+template <class Src>
+__global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int64_t* count_dev, int64_t n_max,
+                                                              int shift, const uint32_t* __restrict__ offs,
+                                                              int nblk, uint32_t* __restrict__ keys_out,
+                                                              uint32_t* __restrict__ vals_out,
+                                                              const int32_t* __restrict__ touched,
+                                                              uint32_t* __restrict__ touched_out) {
+    constexpr int SLOTS = RS_ITEMS * RS_WAVES;  // (row, wavefront) slots of a tile
+    __shared__ uint32_t s_base[256];             // next global position per digit
+    __shared__ uint32_t s_lstart[256];           // first tile position per digit
+    __shared__ uint32_t s_cnt[SLOTS][256];       // per slot: count, then offset within the digit
+    __shared__ uint32_t s_key[RS_TILE];
+    __shared__ uint32_t s_val[RS_TILE];
+    __shared__ uint32_t s_tmp[RS_WAVES];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     int64_t lo, hi;
     rs_chunk(eff_count(count_dev, n_max), nblk, lo, hi);
     if (lo >= hi) return;  // uniform across the block
     s_base[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
-#pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) s_wcnt[w][tid] = 0;
-    __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t i0 = lo; i0 < hi; i0 += RS_THREADS) {
-        const int64_t i = i0 + tid;
-        const bool valid = i < hi;
-        const uint32_t key = valid ? keys_in[i] : 0u;
-        const uint32_t val = valid ? vals_in[i] : 0u;
-        const uint32_t d = (key >> shift) & 0xffu;
-        const uint64_t peers = match_digit(d, valid);
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t off = s_base[d] + rank;
-            for (int w = 0; w < wave; ++w) off += s_wcnt[w][d];
-            keys_out[off] = key;
-            vals_out[off] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
+    for (int64_t t0 = lo; t0 < hi; t0 += RS_TILE) {
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) {
-            add += s_wcnt[w][tid];
-            s_wcnt[w][tid] = 0;
-        }
-        s_base[tid] += add;
+        for (int sl = 0; sl < SLOTS; ++sl) s_cnt[sl][tid] = 0;
         __syncthreads();
+        uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
+        bool valid[RS_ITEMS];
+#pragma unroll
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            const int64_t i = t0 + k * RS_THREADS + tid;
+            key[k] = 0;
+            valid[k] = i < hi && src.key(i, key[k]);
+            val[k] = valid[k] ? src.val(i) : 0u;
+            const uint32_t d = (key[k] >> shift) & 0xffu;
+            const uint64_t peers = match_digit(d, valid[k]);
+            rank[k] = (uint32_t)__popcll(peers & lt);
+            if (valid[k] && rank[k] == 0) s_cnt[k * RS_WAVES + wave][d] = (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        // thread d: offsets of digit d's slots, in tile order
+        uint32_t run = 0;
+#pragma unroll
+        for (int sl = 0; sl < SLOTS; ++sl) {
+            const uint32_t c = s_cnt[sl][tid];
+            s_cnt[sl][tid] = run;
+            run += c;
+        }
+        uint32_t nvalid;
+        s_lstart[tid] = block_exclusive<RS_THREADS>(run, s_tmp, &nvalid);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            if (valid[k]) {
+                const uint32_t d = (key[k] >> shift) & 0xffu;
+                const uint32_t p = s_lstart[d] + s_cnt[k * RS_WAVES + wave][d] + rank[k];
+                s_key[p] = key[k];
+                s_val[p] = val[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            const uint32_t p = (uint32_t)(k * RS_THREADS + tid);
+            if (p < nvalid) {
+                const uint32_t kk = s_key[p], vv = s_val[p];
+                const uint32_t d = (kk >> shift) & 0xffu;
+                const uint32_t g = s_base[d] + (p - s_lstart[d]);
+                keys_out[g] = kk;
+                vals_out[g] = vv;
+                if (touched_out != nullptr) touched_out[g] = (uint32_t)touched[vv];
+            }
+        }
+        __syncthreads();
+        s_base[tid] += run;
     }
+}
+
+// One radix pass from src into (ko, vo): digit histograms, their look-back
+// scan (status words and ticket zeroed beforehand; *total <- the number of
+// keys that took part), then the stable scatter.
+template <class Src>
+hipError_t radix_pass(Src src, const int64_t* count_dev, int64_t n_max, int shift, uint32_t* hist,
+                      uint64_t* status, uint32_t* ticket, int64_t* total, uint32_t* ko, uint32_t* vo,
+                      const int32_t* touched, uint32_t* touched_out, hipStream_t s) {
+    const int nblk = rs_blocks(n_max);
+    hipLaunchKernelGGL(k_radix_hist<Src>, dim3(nblk), dim3(RS_THREADS), 0, s, src, count_dev, n_max, shift, hist,
+                       nblk);
+    hipError_t e = exclusive_scan(LoadU32{hist}, nullptr, (int64_t)256 * nblk, status, ticket, hist, total, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter<Src>, dim3(nblk), dim3(RS_THREADS), 0, s, src, count_dev, n_max, shift, hist,
+                       nblk, ko, vo, touched, touched_out);
+    return hipGetLastError();
 }
 
 // Sorts (keys, vals) in place over `passes` 8-bit digits starting at bit 0,
 // ping-ponging with (keys2, vals2); an even pass count ends in (keys, vals).
+// Pass p scans its digit offsets with status words status + p * spine_tiles
+// and ticket tickets[p] (all zeroed beforehand).
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t* vals2, const int64_t* count_dev,
-                      int64_t n_max, int passes, uint32_t* hist, uint32_t* block_sums, hipStream_t s) {
+                      int64_t n_max, int passes, uint32_t* hist, uint64_t* status, int64_t spine_tiles,
+                      uint32_t* tickets, hipStream_t s) {
     if (n_max <= 0) return hipSuccess;
-    const int nblk = rs_blocks(n_max);
     uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(RS_THREADS), 0, s, ki, count_dev, n_max, shift, hist, nblk);
-        hipError_t e = exclusive_scan(LoadU32{hist}, nullptr, (int64_t)256 * nblk, block_sums, hist, nullptr, s);
+        hipError_t e = radix_pass(SrcKV{ki, vi}, count_dev, n_max, 8 * p, hist, status + p * spine_tiles,
+                                  tickets + p, nullptr, ko, vo, nullptr, nullptr, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(RS_THREADS), 0, s, ki, vi, count_dev, n_max, shift, hist,
-                           nblk, ko, vo);
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
@@ -330,17 +567,6 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
     }
 }
 
-__global__ void k_counts(const int64_t* n_inst, const int64_t* n_vis, int64_t capacity, int64_t* counts,
-                         int64_t* n_clamped) {
-    if (threadIdx.x != 0) return;
-    const int64_t I = *n_inst;
-    counts[0] = I;
-    counts[1] = *n_vis;
-    counts[2] = I > capacity ? 1 : 0;
-    counts[3] = 0;
-    *n_clamped = I < capacity ? I : capacity;
-}
-
 // Emission: the visible pair at depth-sorted position i writes one instance
 // per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1
 // (row-major over the rectangle): key = global tile id, value = the emission
@@ -398,7 +624,19 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
         }
         const uint4 info = s_info[wave][lo];
         const uint32_t li = (uint32_t)(k - s_start[wave][lo]);
-        const uint32_t yy = (info.x >> 16) + li / info.y, xx = (info.x & 0xffffu) + li % info.y;
+        // row and column of instance li in the rectangle (width info.y):
+        // the quotient is below 2^16, so a float estimate is within one of
+        // it and one correction step makes it exact
+        int64_t q = (int64_t)((float)li * __builtin_amdgcn_rcpf((float)info.y));
+        int64_t r = (int64_t)li - q * (int64_t)info.y;
+        if (r < 0) {
+            --q;
+            r += info.y;
+        } else if (r >= (int64_t)info.y) {
+            ++q;
+            r -= info.y;
+        }
+        const uint32_t yy = (info.x >> 16) + (uint32_t)q, xx = (info.x & 0xffffu) + (uint32_t)r;
         const int64_t o = o_w + k;
         if (o < capacity) {
             keys[o] = info.z + yy * info.w + xx;
@@ -418,8 +656,12 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ins
 }
 
 struct WsLayout {
-    size_t vis_k0, vis_v0, vis_k1, vis_v1, pos, inst_k2, inst_v2, hist, bsum, cnt, total;
+    size_t vis_k0, vis_v0, vis_k1, vis_v1, pos, inst_k2, inst_v2, hist, sums, status, tickets, cnt, total;
+    int64_t spine_tiles, n_status;
 };
+
+constexpr int kMaxPasses = 4;            // radix passes per sort (32-bit keys)
+constexpr int kTickets = 2 * kMaxPasses; // one per radix pass: depth sort, then tile sort
 
 WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -427,9 +669,14 @@ WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     const int64_t cap = capacity > 0 ? capacity : 1;
     const int64_t big = vn > cap ? vn : cap;
     const int64_t nblk = rs_blocks(big);
-    const int64_t scan_n = (256 * nblk > big ? 256 * nblk : big);
-    const int64_t nbs = (scan_n + SCAN_TILE - 1) / SCAN_TILE + 1;
     WsLayout L;
+    L.spine_tiles = lb_tiles(256 * nblk);
+    // run counts of the compaction, then tile totals of the instance-offset
+    // scan (runs are the shorter, so there are more of them)
+    const int64_t vt = (vn + CV_RUN - 1) / CV_RUN > 0 ? (vn + CV_RUN - 1) / CV_RUN : 1;
+    static_assert(CV_RUN <= LB_TILE, "the run counts need at least as many words as the tile totals");
+    // look-back status words: 2 x kMaxPasses radix spines
+    L.n_status = 2 * kMaxPasses * L.spine_tiles;
     size_t o = 0;
     L.vis_k0 = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
     L.vis_v0 = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
@@ -439,7 +686,9 @@ WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     L.inst_k2 = o; o += al(4 * (size_t)cap);
     L.inst_v2 = o; o += al(4 * (size_t)cap);
     L.hist = o; o += al(4 * (size_t)(256 * nblk + 1));
-    L.bsum = o; o += al(4 * (size_t)nbs);
+    L.sums = o; o += al(4 * (size_t)vt);
+    L.status = o; o += al(8 * (size_t)L.n_status);
+    L.tickets = o; o += al(4 * (size_t)kTickets);
     L.cnt = o; o += al(8 * 4);
     L.total = o;
     return L;
@@ -463,32 +712,51 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     uint32_t* ik2 = reinterpret_cast<uint32_t*>(w + L.inst_k2);
     uint32_t* iv2 = reinterpret_cast<uint32_t*>(w + L.inst_v2);
     uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
-    uint32_t* bsum = reinterpret_cast<uint32_t*>(w + L.bsum);
+    uint32_t* sums = reinterpret_cast<uint32_t*>(w + L.sums);
+    uint64_t* status = reinterpret_cast<uint64_t*>(w + L.status);
+    uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
     int64_t* cnt = reinterpret_cast<int64_t*>(w + L.cnt);  // [0] n_vis [1] n_inst [2] clamped
     const int64_t vn = (int64_t)n * n_views;
+    uint64_t* st_depth = status;
+    uint64_t* st_tile = st_depth + kMaxPasses * L.spine_tiles;
     hipError_t e;
 
+    // 0. zero the scan state and the counts, and clear the per-tile ranges
+    hipLaunchKernelGGL(k_bin_reset, dim3(64), dim3(256), 0, s, status, L.n_status, tickets, kTickets,
+                       reinterpret_cast<uint32_t*>(ranges), 2 * (int64_t)total_tiles);
     // 1. order-preserving compaction of the visible pairs, key = depth bits
     if (vn > 0) {
         const unsigned nrun = (unsigned)((vn + CV_RUN - 1) / CV_RUN);
-        hipLaunchKernelGGL(k_count_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched, vn, pos);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, pos, (int)nrun, &cnt[0]);
+        hipLaunchKernelGGL(k_count_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched, vn, sums);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, sums, (int)nrun, &cnt[0]);
         hipLaunchKernelGGL(k_compact_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched,
-                           reinterpret_cast<const float4*>(rec), pos, vn, vis_k0, vis_v0);
+                           reinterpret_cast<const float4*>(rec), sums, vn, vis_k0, vis_v0);
     } else {
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, pos, 0, &cnt[0]);
+        e = fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 8, s);
+        if (e != hipSuccess) return e;
     }
-    // 2. stable sort of the visible pairs by depth (32 bits)
-    e = radix_sort(vis_k0, vis_v0, vis_k1, vis_v1, &cnt[0], vn, 4, hist, bsum, s);
+    // 2. stable sort of the visible pairs by depth (32 bits, 4 passes); the
+    //    last pass also writes each sorted pair's tile count
+    if (vn > 0) {
+        uint32_t *ki = vis_k0, *vi = vis_v0, *ko = vis_k1, *vo = vis_v1;
+        for (int p = 0; p < 4; ++p) {
+            e = radix_pass(SrcKV{ki, vi}, &cnt[0], vn, 8 * p, hist, st_depth + p * L.spine_tiles, &tickets[p],
+                           nullptr, ko, vo, touched, p == 3 ? pos : nullptr, s);
+            if (e != hipSuccess) return e;
+            uint32_t* t = ki; ki = ko; ko = t;
+            t = vi; vi = vo; vo = t;
+        }  // four passes: the sorted pairs end in (vis_k0, vis_v0)
+    }
+    // 3. instance offsets in depth order (in place over the tile counts),
+    //    total instance count and the counts
+    e = exclusive_scan_long(LoadU32{pos}, &cnt[0], vn, sums, pos, &cnt[1], s,
+                            CountsOut{counts, &cnt[2], &cnt[0], capacity});
     if (e != hipSuccess) return e;
-    // 3. instance offsets in depth order, total instance count
-    e = exclusive_scan(LoadGatherTouched{touched, vis_v0}, &cnt[0], vn, bsum, pos, &cnt[1], s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, s, &cnt[1], &cnt[0], capacity, counts, &cnt[2]);
     // 4. emission, then stable sort by global tile id
     int bits = 1;
     while ((1ll << bits) < (int64_t)total_tiles) ++bits;
     const int passes = (bits + 7) / 8;
+    if (passes > kMaxPasses) return hipErrorInvalidValue;
     uint32_t* ek = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(tile_keys) : ik2;
     uint32_t* ev = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(inst) : iv2;
     uint32_t* ok = (passes % 2 == 0) ? ik2 : reinterpret_cast<uint32_t*>(tile_keys);
@@ -498,11 +766,9 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
                            reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, ev, inst_gid,
                            pair_first);
     }
-    e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, bsum, s);
+    e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, st_tile, L.spine_tiles, &tickets[kMaxPasses], s);
     if (e != hipSuccess) return e;
-    // 5. per-tile [start, end)
-    e = fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)total_tiles, s);
-    if (e != hipSuccess) return e;
+    // 5. per-tile [start, end) (the ranges were cleared in step 0)
     if (capacity > 0) {
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s,
                            reinterpret_cast<const uint32_t*>(tile_keys), &cnt[2], reinterpret_cast<int2*>(ranges));

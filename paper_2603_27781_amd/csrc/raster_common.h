@@ -25,10 +25,17 @@ __device__ __forceinline__ void stage_geometry(const float4* __restrict__ rec, s
     g1 = make_float4(kQ * r1.x, r1.y, r1.z, r1.w);
 }
 
+// Wavefront votes on a lane condition.  The condition goes to the ballot as
+// it is, so it stays a lane mask in scalar registers (the int-typed library
+// votes turn it into a 0/1 vector value and compare it back first).
+__device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
+__device__ __forceinline__ bool wave_all(bool c) { return __builtin_amdgcn_ballot_w64(!c) == 0; }
+
 // alpha of one (pixel, Gaussian) pair.  The forward and the backward kernels
 // both call this with the same staged values, so every alpha_min / T_min
 // decision of the backward reproduces the forward exactly.
-//   G = 2^min(q', 0) (the Gaussian factor), returns min(alpha_max, o G).
+//   G = 2^min(q', 0) (the Gaussian factor), returns min(alpha_max, o G)
+// (fminf: for a NaN product it too returns alpha_max, like a < amax ? a : amax).
 __device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, float px, float py, float amax,
                                             float& dx, float& dy, float& G, bool& unclamped) {
     dx = px - g0.x;
@@ -38,7 +45,7 @@ __device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, 
     G = __builtin_amdgcn_exp2f(q);
     const float a = g1.y * G;
     unclamped = a < amax;
-    return unclamped ? a : amax;
+    return fminf(a, amax);
 }
 
 // Value of `x` held by lane (lane ^ D) of the wavefront.  D = 1, 2: DPP

@@ -56,7 +56,12 @@ __device__ __forceinline__ float bfly_partner(float x) {
     else return xor_lane<D>(x);
 }
 
-template <int ORD, int NV, int CNT, int S>
+// NR: the values v[NR ..] are padding.  In the first step a pair whose
+// upper value is padding needs no selects: the lanes with the bit clear get
+// the pair total of the lower value from one add, and the lanes with the bit
+// set, which would carry the padding slot, get a value nobody reads (the
+// slots never mix, so it cannot reach a real total).
+template <int ORD, int NV, int CNT, int S, int NR>
 struct BflyStep {
     __device__ __forceinline__ static void run(float (&v)[NV], int lane) {
         if constexpr (S < bfly_nbits<ORD>()) {
@@ -67,27 +72,35 @@ struct BflyStep {
 #pragma unroll
                     for (int k = 0; k < HALF; ++k) v[k] = swap_halves_add<D>(v[k], v[k + HALF]);
                 } else {
+                    // both pair totals (one DPP add each), then the lane's
+                    // half; selecting between computed values rather than
+                    // between array elements keeps the compiler from turning
+                    // the selects into a lane-dependent index into v
                     const bool up = (lane & D) != 0;
 #pragma unroll
                     for (int k = 0; k < HALF; ++k) {
-                        const float send = up ? v[k] : v[k + HALF];
-                        const float keep = up ? v[k + HALF] : v[k];
-                        v[k] = keep + bfly_partner<D>(send);
+                        const float lo = v[k] + bfly_partner<D>(v[k]);
+                        if (S == 0 && k + HALF >= NR) {
+                            v[k] = lo;
+                        } else {
+                            const float hi = v[k + HALF] + bfly_partner<D>(v[k + HALF]);
+                            v[k] = up ? hi : lo;
+                        }
                     }
                 }
-                BflyStep<ORD, NV, HALF, S + 1>::run(v, lane);
+                BflyStep<ORD, NV, HALF, S + 1, NR>::run(v, lane);
             } else {
                 // full reduction across this bit; the mirror partner is only
                 // valid while bits 0 and 1 are unused, which holds here since
                 // bit 2 comes before them in both orders
                 v[0] += bfly_partner<D>(v[0]);
-                BflyStep<ORD, NV, 1, S + 1>::run(v, lane);
+                BflyStep<ORD, NV, 1, S + 1, NR>::run(v, lane);
             }
         }
     }
 };
 
-template <int NV, int ORD = 0>
+template <int NV, int ORD = 0, int NR = NV>
 struct Butterfly {
     static constexpr int steps() {
         int b = 0;
@@ -97,7 +110,7 @@ struct Butterfly {
     // After the call, the lane holds in v[0] the total (over the lanes the
     // order covers) of value index slot(lane).
     __device__ __forceinline__ static float reduce(float (&v)[NV], int lane) {
-        BflyStep<ORD, NV, NV, 0>::run(v, lane);
+        BflyStep<ORD, NV, NV, 0, NR>::run(v, lane);
         return v[0];
     }
     __device__ __forceinline__ static int slot(int lane) {
@@ -118,18 +131,51 @@ struct Butterfly {
     }
 };
 
-// The weights w of the four lanes that share this lane's bits 0-3, in the
-// order of their bits 4-5 (t = 0..3: lane (l & 15) | 16 t), from two
-// permlane swaps (the same order in every lane).
+// Sum over the 64 lanes of six values per lane, transposed: afterwards the
+// lanes with bits 0, 1 and 3 clear hold one total each, of value
+// geo6_slot(lane) (6: none).  Bit 5 pairs (0, 4), (1, 5) and (2, 3), so the
+// lower half keeps values 0, 1, 2 and the upper half 4, 5, 3 and no swap is
+// spent on padding; bit 4 pairs (a, c) and (b, dead register); bit 2 is the
+// DPP half-row mirror (valid while bits 0 and 1 are unused), then bits 0, 1
+// and 3 finish with DPP adds.
+__device__ __forceinline__ int geo6_slot(int lane) {
+    const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b2 = (lane >> 2) & 1;
+    if (b4 == 0) return b2 == 0 ? 4 * b5 : 1 + 4 * b5;
+    return b2 == 0 ? 2 + b5 : 6;
+}
+
+__device__ __forceinline__ float geo6_reduce(const float (&v)[6], int lane) {
+    const float a = swap_halves_add<32>(v[0], v[4]);
+    const float b = swap_halves_add<32>(v[1], v[5]);
+    const unsigned cu = __float_as_uint(v[2]), du = __float_as_uint(v[3]);
+    const auto r = __builtin_amdgcn_permlane32_swap(cu, du, false, false);
+    const float c = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    // bit 4: the second operand of b's swap is r[1], dead after the add above
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(c), false, false);
+    const float a2 = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(b), r[1], false, false);
+    const float b2 = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    // bit 2
+    const bool up = (lane & 4) != 0;
+    const float lo = a2 + mirror8_lane(a2), hi = b2 + mirror8_lane(b2);
+    float t = up ? hi : lo;
+    t += xor_lane<1>(t);
+    t += xor_lane<2>(t);
+    t += xor_lane<8>(t);
+    return t;
+}
+
+// The weights w of the four lanes that share this lane's bits 0-3.  W[x] is
+// w of the lane whose bits 4-5 are t = x ^ b4 (b4 = this lane's bit 4): one
+// permlane32 swap gives the lanes l & ~32 and l | 32, and a ds_swizzle (xor
+// 16, no VALU work) each of their bit-4 partners.
 __device__ __forceinline__ void quad_row_weights(float w, float (&W)[4]) {
     const unsigned u = __float_as_uint(w);
     const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);  // w(l & ~32), w(l | 32)
-    const auto a = __builtin_amdgcn_permlane16_swap(h[0], h[0], false, false);
-    const auto b = __builtin_amdgcn_permlane16_swap(h[1], h[1], false, false);
-    W[0] = __uint_as_float(a[0]);  // w(l & ~48)
-    W[1] = __uint_as_float(a[1]);  // w((l & ~48) | 16)
-    W[2] = __uint_as_float(b[0]);  // w((l & ~48) | 32)
-    W[3] = __uint_as_float(b[1]);  // w(l | 48)
+    W[0] = __uint_as_float(h[0]);
+    W[1] = xor_lane<16>(__uint_as_float(h[0]));
+    W[2] = __uint_as_float(h[1]);
+    W[3] = xor_lane<16>(__uint_as_float(h[1]));
 }
 
 template <int N>
@@ -154,7 +200,6 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     static_assert((3 + F) % 4 == 3, "the staged appearance record needs its padding slot for the depth");
     constexpr int NREAL = PARAMS ? 10 + F : 6;  // record slots
     constexpr int NBF = 6;                      // full-wavefront butterfly: mean, conic, opacity | depth
-    constexpr int NV = Pow2<NBF>::value;
     constexpr int LIN = PARAMS ? 4 + F : 0;     // linear channels: depth, colour, feature
     constexpr int NL = LIN / 4;                 // linear channels per lane (a multiple of 4 channels)
     constexpr int NVL = Pow2<(NL > 0 ? NL : 1)>::value;
@@ -217,8 +262,8 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     // they are; value 5 is the opacity (slot 6) with parameter gradients,
     // else the depth (slot 5).  Scales: dmx, dmy <- -ln2; dA, dC <- -1/2;
     // dB <- -1.
-    const int bslot = Butterfly<NV>::slot(lane);
-    const bool writer = (lane & Butterfly<NV>::reduced_mask()) == 0 && bslot < NBF;
+    const int bslot = geo6_slot(lane);
+    const bool writer = (lane & 0xB) == 0 && bslot < NBF;
     const int my_slot = bslot < 5 ? bslot : (PARAMS ? 6 : 5);
     float scale = 1.0f;
     if (bslot < 2) scale = -kLn2;
@@ -228,15 +273,16 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     // Linear channels c (0 depth, 1-3 colour, 4+ feature): their gradient is
     // sum_p g_c(p) w(p) with g constant over the tile.  A lane owns the
     // channels c = 4 m + q (q = lane bits 4-5) and keeps, for them, g of the
-    // four lanes sharing its bits 0-3; per Gaussian it takes those lanes'
-    // weights (two permlane swaps), forms the four-lane sums with FMAs and
-    // finishes over the 16 lanes of its row group with the ORD 1 butterfly.
-    const int q4 = (lane >> 4) & 3;
+    // four lanes sharing its bits 0-3 (in the order of quad_row_weights);
+    // per Gaussian it takes those lanes' weights (one permlane swap, two
+    // swizzles), forms the four-lane sums with FMAs and finishes over the 16
+    // lanes of its row group with the ORD 1 butterfly.
+    const int q4 = (lane >> 4) & 3, b4 = q4 & 1;
     float gq[NL > 0 ? NL : 1][4];
     if constexpr (PARAMS) {
 #pragma unroll
         for (int t4 = 0; t4 < 4; ++t4) {
-            const int lp = (lane & 15) | (t4 << 4);
+            const int lp = (lane & 15) | ((t4 ^ b4) << 4);  // the order of quad_row_weights
             const int xx = tx * TS + sbx + (lp & 7), yy = ty * TS + sby + (lp >> 3);
             const bool in = xx < vw.width && yy < vw.height;
             const int64_t pp = vw.pixel_offset + (int64_t)yy * vw.width + xx;
@@ -292,7 +338,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 const float4 a0 = s_g0[k], a1 = s_g1[k];
                 ok = !box_misses(a0, a1, wx0, wy0) && !ellipse_misses(a0, a1, wx0, wy0, log2_amin);
             }
-            cand[q] = __ballot(ok);
+            cand[q] = __builtin_amdgcn_ballot_w64(ok);
         }
 #pragma unroll
         for (int q = NQ - 1; q >= 0; --q) {
@@ -339,10 +385,12 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 g0 = s_g0[jp];
                 g1 = s_g1[jp];
                 const bool contrib = jl < lastp && a >= amin;
-                if (__any(contrib)) {
-                    // Branch-free over the wavefront: lanes without a
-                    // contribution take alpha = 0 (T unchanged, exact since
-                    // rcp(1) = 1, w = 0) and zero multipliers.
+                // No branch on whether any lane contributes (nearly every
+                // candidate step has a contributor).  Branch-free over the
+                // wavefront: lanes without a contribution take alpha = 0 (T
+                // unchanged, exact since rcp(1) = 1, w = 0) and zero
+                // multipliers, so a step without contributors adds zeros.
+                {
                     const float ac = contrib ? a : 0.0f;
                     const float ra = __builtin_amdgcn_rcpf(1.0f - ac);
                     T = T * ra;  // transmittance before this Gaussian
@@ -361,9 +409,12 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                             for (int m = 1; m < NL; ++m) acc = fmaf(gq[m][t4], xs[m], acc);
                             pt[t4] = acc;
                         }
+                        // pt[x] is for the pixel t = x ^ b4: after bit 5, pt[0]
+                        // is this lane's own pixel and pt[1] its bit-4
+                        // partner's, so bit 4 is one swizzle and one add
                         pt[0] = swap_halves_add<32>(pt[0], pt[2]);
                         pt[1] = swap_halves_add<32>(pt[1], pt[3]);
-                        gx = swap_halves_add<16>(pt[0], pt[1]) + g[0];
+                        gx = (pt[0] + xor_lane<16>(pt[1])) + g[0];
                     } else {
                         gx = fmaf(g[0], xs[0], fmaf(g[1], xs[1], fmaf(g[2], xs[2], fmaf(g[3], xs[AV * 4 - 1], g[4]))));
 #pragma unroll
@@ -373,7 +424,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     Sg = fmaf(gx, w, Sg);
                     const float hm = (contrib && unc) ? dA : 0.0f;
                     const float h = hm * a;
-                    float val[NV];
+                    float val[NBF];
                     val[0] = h * qx;
                     val[1] = h * qy;
                     val[2] = h * dx * dx;
@@ -381,9 +432,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     val[4] = h * dy * dy;
                     if constexpr (PARAMS) val[5] = hm * G;
                     else val[5] = g[3] * w;
-#pragma unroll
-                    for (int k = NBF; k < NV; ++k) val[k] = 0.0f;
-                    const float tot = Butterfly<NV>::reduce(val, lane);
+                    const float tot = geo6_reduce(val, lane);
                     if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
                     if constexpr (PARAMS) {
                         float W[4];
@@ -394,7 +443,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                             lin[m] = fmaf(gq[m][3], W[3], fmaf(gq[m][2], W[2], fmaf(gq[m][1], W[1], gq[m][0] * W[0])));
 #pragma unroll
                         for (int m = NL; m < NVL; ++m) lin[m] = 0.0f;
-                        const float ltot = Butterfly<NVL, 1>::reduce(lin, lane);
+                        const float ltot = Butterfly<NVL, 1, NL>::reduce(lin, lane);
                         if (lwriter) atomicAdd(&s_acc[j * AST + lin_slot], ltot);
                     }
                 }
@@ -491,11 +540,16 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
     for (int v0 = 0; v0 < n_views; v0 += vp) {
         const int v = v0 + vl;
         const size_t pair = (size_t)v * n + i;
-        const bool vis = i64 < n && v < n_views && touched[pair] > 0;
+        const bool in = i64 < n && v < n_views;
+        // both loads in one round trip (pair_first is only meaningful, and
+        // only used, for visible pairs)
+        const int tc = in ? touched[pair] : 0;
+        const int pf = in ? pair_first[pair] : 0;
+        const bool vis = tc > 0;
         int cnt = 0, first = 0;
         if (vis) {
-            first = pair_first[pair];
-            const int64_t stop = (int64_t)first + touched[pair];
+            first = pf;
+            const int64_t stop = (int64_t)first + tc;
             cnt = (int)((stop < capacity ? stop : capacity) - first);  // truncated lists
             cnt = cnt > 0 ? cnt : 0;
         }

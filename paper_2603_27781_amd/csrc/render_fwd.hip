@@ -75,7 +75,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
             reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
         }
         __syncthreads();
-        if (!__all(done)) {
+        if (!wave_all(done)) {
             uint64_t cand[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -85,7 +85,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     const float4 a0 = s_g0[k], a1 = s_g1[k];
                     ok = !box_misses(a0, a1, wx0, wy0) && !ellipse_misses(a0, a1, wx0, wy0, log2_amin);
                 }
-                cand[q] = __ballot(ok);
+                cand[q] = __builtin_amdgcn_ballot_w64(ok);
             }
             bool wdone = false;
 #pragma unroll
@@ -114,8 +114,10 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     const bool ok = !done && a >= amin;
                     const float Tn = T * (1.0f - a);
                     const bool use = ok && !(Tn < tmin);
-                    if (__any(use)) {
-                        // lanes not contributing add exactly 0 * x
+                    // No branch on whether any lane contributes: the
+                    // candidates reach the block, so nearly every step has a
+                    // contributor, and lanes not contributing add exactly 0 * x.
+                    {
                         const float w = use ? a * T : 0.0f;
                         const float* ap = reinterpret_cast<const float*>(av);
                         acc[0] = fmaf(w, ap[0], acc[0]);
@@ -128,7 +130,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                         lastj = use ? b0 - rg.x + j + 1 : lastj;
                     }
                     done = done || (ok && Tn < tmin);
-                    if (__all(done)) {
+                    if (wave_all(done)) {
                         wdone = true;
                         break;
                     }
