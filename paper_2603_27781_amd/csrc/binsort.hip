@@ -511,7 +511,7 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t*
 // of those counts (one block), then each run ranks its pairs with ballots
 // and writes (depth bits, pair index) at its offset.
 constexpr int CV_THREADS = 256;
-constexpr int CV_RUN = 1024;
+constexpr int CV_RUN = 2048;
 
 __global__ void __launch_bounds__(CV_THREADS) k_count_visible(const int32_t* __restrict__ touched, int64_t vn,
                                                               uint32_t* __restrict__ run_counts) {
@@ -567,6 +567,19 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
     }
 }
 
+// Inclusive max-scan over the wavefront (lanes without a predecessor take
+// -1): DPP row shifts by 1, 2, 4, 8 within rows of 16, then the row
+// broadcasts of lanes 15 and 31 carry it across rows.
+__device__ __forceinline__ int wave_max_scan(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));  // row_bcast:15 into rows 1, 3
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));  // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 // Emission: the visible pair at depth-sorted position i writes one instance
 // per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1
 // (row-major over the rectangle): key = global tile id, value = the emission
@@ -575,9 +588,11 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
 // instances of one (view, Gaussian) pair stay contiguous in emission space
 // after the tile sort has reordered them.
 // Each wavefront takes 64 consecutive pairs and its lanes stride over all of
-// their instances together (the pair of instance k found by binary search
-// over the pairs' starts in LDS), so a pair with many tiles does not stall
-// its wavefront and the writes are contiguous across lanes.
+// their instances together, 64 at a time, so a pair with many tiles does
+// not stall its wavefront and the writes are contiguous across lanes.  The
+// pair of each instance: every pair whose first instance falls in the
+// current 64 marks that slot with its lane in LDS, and a max-scan over the
+// wavefront (DPP) carries the latest mark to every later slot.
 __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_vals,
                                               const uint32_t* __restrict__ offs, const int64_t* n_vis,
                                               const uint2* __restrict__ rect, const gs_view* __restrict__ views,
@@ -587,6 +602,7 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
     __shared__ uint32_t s_start[4][kWave];
     __shared__ uint4 s_info[4][kWave];  // (x0 | y0 << 16, rect width, tile base, tiles per row)
     __shared__ int32_t s_gid[4][kWave];
+    __shared__ int32_t s_mark[4][kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int64_t nv = *n_vis;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (int64_t)wave * kWave;
@@ -615,13 +631,23 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int64_t k = lane; k < total; k += kWave) {
-        int lo = 0, hi = nvalid - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((int64_t)s_start[wave][mid] <= k) lo = mid;
-            else hi = mid - 1;
-        }
+    const int64_t my_start = valid ? o_i - o_w : -1;
+    int carry = 0;  // the pair of the last instance before the current 64
+    for (int64_t base = 0; base < total; base += kWave) {
+        const int64_t k = base + lane;
+        s_mark[wave][lane] = -1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // starts strictly increase (a visible pair has an instance), so a
+        // slot is marked at most once
+        if (my_start >= base && my_start < base + kWave) s_mark[wave][my_start - base] = lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int lo = max(wave_max_scan(s_mark[wave][lane]), carry);
+        carry = __builtin_amdgcn_readlane(lo, kWave - 1);
+        if (k >= total) continue;
         const uint4 info = s_info[wave][lo];
         const uint32_t li = (uint32_t)(k - s_start[wave][lo]);
         // row and column of instance li in the rectangle (width info.y):
