@@ -34,18 +34,27 @@ __device__ __forceinline__ bool wave_all(bool c) { return __builtin_amdgcn_ballo
 // alpha of one (pixel, Gaussian) pair.  The forward and the backward kernels
 // both call this with the same staged values, so every alpha_min / T_min
 // decision of the backward reproduces the forward exactly.
-//   G = 2^min(q', 0) (the Gaussian factor), returns min(alpha_max, o G)
-// (fminf: for a NaN product it too returns alpha_max, like a < amax ? a : amax).
+//   G = 2^min(q', 0) (the Gaussian factor), returns min(alpha_max, o G) as a
+// median of three (o G >= 0; one instruction with alpha_max in a scalar
+// register; a NaN product stays NaN and so fails every alpha test).
+// qx, qy: the derivatives of q' along dx and dy, 2A'dx + B2'dy and
+// B2'dx + 2C'dy, formed from the intermediates of q' (the forward does not
+// read them, so they cost it nothing).
 __device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, float px, float py, float amax,
-                                            float& dx, float& dy, float& G, bool& unclamped) {
+                                            float& dx, float& dy, float& G, bool& unclamped, float& qx,
+                                            float& qy) {
     dx = px - g0.x;
     dy = py - g0.y;
-    float q = fmaf(g0.z * dx, dx, dy * fmaf(g0.w, dx, g1.x * dy));
+    const float adx = g0.z * dx, cdy = g1.x * dy;
+    const float v = fmaf(g0.w, dx, cdy);  // B2'dx + C'dy
+    float q = fmaf(adx, dx, dy * v);
+    qx = fmaf(2.0f, adx, g0.w * dy);
+    qy = v + cdy;
     q = fminf(q, 0.0f);
     G = __builtin_amdgcn_exp2f(q);
     const float a = g1.y * G;
     unclamped = a < amax;
-    return fminf(a, amax);
+    return __builtin_amdgcn_fmed3f(a, 0.0f, amax);
 }
 
 // Value of `x` held by lane (lane ^ D) of the wavefront.  D = 1, 2: DPP

@@ -367,19 +367,17 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     }
                 }
                 const int jl = bstart + j - rg.x;
-                float dx, dy, G;
+                float dx, dy, G, qx, qy;
                 bool unc;
-                const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
-                // derivatives of q' along dx and dy (up to the factors the
-                // record scales apply), formed now so that g0 and g1 are dead:
+                const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc, qx, qy);
+                // qx, qy (the derivatives of q' along dx and dy, up to the
+                // factors the record scales apply) are kept here by an empty
+                // statement (no instruction): sunk further down they would
+                // keep g0 and g1 alive, and g0 and g1 are dead from here --
                 // the next candidate's geometry is loaded into them (no
                 // register copies at the end of the step), unconditionally
                 // with a clamped index (a conditional load becomes a pointer
                 // select that leaves LDS addressing)
-                float qx = fmaf(2.0f * g0.z, dx, g0.w * dy);
-                float qy = fmaf(g0.w, dx, 2.0f * g1.x * dy);
-                // keeps both here (an empty statement, no instruction): sunk
-                // into the branch below they would keep g0 and g1 alive
                 __asm__ volatile("" : "+v"(qx), "+v"(qy));
                 const int jp = jn >= 0 ? jn : j;
                 g0 = s_g0[jp];

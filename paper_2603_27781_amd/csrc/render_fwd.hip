@@ -100,9 +100,9 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     float4 av[AV];
 #pragma unroll
                     for (int qq = 0; qq < AV; ++qq) av[qq] = s_app[j * AV + qq];
-                    float dx, dy, G;
+                    float dx, dy, G, qx, qy;
                     bool unc;
-                    const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc);
+                    const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc, qx, qy);
                     // g0 and g1 are dead from here: the next candidate's
                     // geometry is loaded into them (no register copies at the
                     // end of the step), unconditionally with a clamped index
