@@ -108,9 +108,12 @@ __device__ __forceinline__ float swap_halves_add(float lo, float hi) {
     }
 }
 
-// Minimum over t in [lo, hi] of a t^2 + b t + c0 (a > 0).
-__device__ __forceinline__ float quad_min_on(float a, float b, float c0, float lo, float hi) {
-    const float t = fminf(fmaxf(-b / (2.0f * a), lo), hi);
+// Minimum over t in [lo, hi] of a t^2 + b t + c0 (a > 0), given inv2a =
+// 1 / (2a).  The vertex comes from a hardware reciprocal: any t in [lo, hi]
+// gives a value at least the true minimum, and a relative error e in t
+// raises it by only a (e t)^2, far inside the test's margin.
+__device__ __forceinline__ float quad_min_on(float a, float b, float c0, float lo, float hi, float inv2a) {
+    const float t = fminf(fmaxf(-b * inv2a, lo), hi);
     return fmaf(fmaf(a, t, b), t, c0);
 }
 
@@ -130,10 +133,11 @@ __device__ __forceinline__ bool ellipse_misses(const float4& g0, const float4& g
     const float xl = x0 - g0.x, xh = xl + 7.0f, yl = y0 - g0.y, yh = yl + 7.0f;
     if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return K < 0.0f;
     // edges x = xl, xh: Q = c y^2 + (b x) y + a x^2; edges y = yl, yh likewise
-    float q = quad_min_on(c, b * xl, a * xl * xl, yl, yh);
-    q = fminf(q, quad_min_on(c, b * xh, a * xh * xh, yl, yh));
-    q = fminf(q, quad_min_on(a, b * yl, c * yl * yl, xl, xh));
-    q = fminf(q, quad_min_on(a, b * yh, c * yh * yh, xl, xh));
+    const float i2c = __builtin_amdgcn_rcpf(2.0f * c), i2a = __builtin_amdgcn_rcpf(2.0f * a);
+    float q = quad_min_on(c, b * xl, a * xl * xl, yl, yh, i2c);
+    q = fminf(q, quad_min_on(c, b * xh, a * xh * xh, yl, yh, i2c));
+    q = fminf(q, quad_min_on(a, b * yl, c * yl * yl, xl, xh, i2a));
+    q = fminf(q, quad_min_on(a, b * yh, c * yh * yh, xl, xh, i2a));
     return q > K + 1e-3f;
 }
 
