@@ -144,7 +144,10 @@ __device__ __forceinline__ int geo6_slot(int lane) {
     return b2 == 0 ? 2 + b5 : 6;
 }
 
-__device__ __forceinline__ float geo6_reduce(const float (&v)[6], int lane) {
+// Bits 5 and 4 of the six-value sum: afterwards a2 holds value
+// A(b5, b4) = b4 ? 2 + b5 : 4 b5 and b2 value B(b5, b4) = 1 + 4 b5 (garbage
+// where b4 is set), each still to be summed over bits 0-3.
+__device__ __forceinline__ void geo6_bits54(const float (&v)[6], float& a2, float& b2) {
     const float a = swap_halves_add<32>(v[0], v[4]);
     const float b = swap_halves_add<32>(v[1], v[5]);
     const unsigned cu = __float_as_uint(v[2]), du = __float_as_uint(v[3]);
@@ -152,9 +155,14 @@ __device__ __forceinline__ float geo6_reduce(const float (&v)[6], int lane) {
     const float c = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     // bit 4: the second operand of b's swap is r[1], dead after the add above
     const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(c), false, false);
-    const float a2 = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    a2 = __uint_as_float(p[0]) + __uint_as_float(p[1]);
     const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(b), r[1], false, false);
-    const float b2 = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    b2 = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
+__device__ __forceinline__ float geo6_reduce(const float (&v)[6], int lane) {
+    float a2, b2;
+    geo6_bits54(v, a2, b2);
     // bit 2
     const bool up = (lane & 4) != 0;
     const float lo = a2 + mirror8_lane(a2), hi = b2 + mirror8_lane(b2);
@@ -202,7 +210,6 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     constexpr int NBF = 6;                      // full-wavefront butterfly: mean, conic, opacity | depth
     constexpr int LIN = PARAMS ? 4 + F : 0;     // linear channels: depth, colour, feature
     constexpr int NL = LIN / 4;                 // linear channels per lane (a multiple of 4 channels)
-    constexpr int NVL = Pow2<(NL > 0 ? NL : 1)>::value;
     constexpr int RS = (NREAL + 3) / 4 * 4;  // record stride (floats), float4-aligned
     constexpr int AST = NREAL + 1;           // accumulator stride (odd: spreads LDS banks)
     constexpr int NQ = B / 64;               // 64-bit candidate masks per batch
@@ -294,10 +301,29 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             }
         }
     }
-    const int lslot = Butterfly<NVL, 1>::slot(lane);
-    const bool lwriter = PARAMS && (lane & Butterfly<NVL, 1>::reduced_mask()) == 0 && lslot < NL;
-    const int lch = 4 * lslot + q4;
-    const int lin_slot = lch == 0 ? 5 : 6 + lch;
+    // With parameter gradients the last four steps of the six-value sum
+    // (bits 2, 0, 1, 3) and the sum of the linear channels over the 16 lanes
+    // of a row group run as one ORD 1 butterfly over NC values per lane:
+    // the two geometry values still open after bits 5 and 4, then the NL
+    // linear channels.  Value index -> record slot and scale of this lane:
+    constexpr int NC = Pow2<2 + NL>::value;
+    const int cs = Butterfly<NC, 1>::slot(lane);
+    int cslot = -1;
+    float cscale = 1.0f;
+    {
+        const int b5 = (lane >> 5) & 1;
+        int gi = -1;  // geometry value index
+        if (cs == 0) gi = b4 ? 2 + b5 : 4 * b5;
+        else if (cs == 1 && !b4) gi = 1 + 4 * b5;
+        if (gi >= 0) {
+            cslot = gi < 5 ? gi : 6;
+            cscale = gi < 2 ? -kLn2 : (gi == 2 || gi == 4 ? -0.5f : (gi == 3 ? -1.0f : 1.0f));
+        } else if (cs >= 2 && cs < 2 + NL) {
+            const int ch = 4 * (cs - 2) + q4;
+            cslot = ch == 0 ? 5 : 6 + ch;
+        }
+    }
+    const bool cwriter = PARAMS && (lane & Butterfly<NC, 1>::reduced_mask()) == 0 && cslot >= 0;
     // float index, within a staged appearance record, of this lane's channels
     // c = 4 m + q (depth sits in the record's padding slot)
     int xidx[NL > 0 ? NL : 1];
@@ -430,19 +456,22 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     val[4] = h * dy * dy;
                     if constexpr (PARAMS) val[5] = hm * G;
                     else val[5] = g[3] * w;
-                    const float tot = geo6_reduce(val, lane);
-                    if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
                     if constexpr (PARAMS) {
+                        float cv[NC];
+                        geo6_bits54(val, cv[0], cv[1]);
                         float W[4];
                         quad_row_weights(w, W);
-                        float lin[NVL];
 #pragma unroll
                         for (int m = 0; m < NL; ++m)
-                            lin[m] = fmaf(gq[m][3], W[3], fmaf(gq[m][2], W[2], fmaf(gq[m][1], W[1], gq[m][0] * W[0])));
+                            cv[2 + m] =
+                                fmaf(gq[m][3], W[3], fmaf(gq[m][2], W[2], fmaf(gq[m][1], W[1], gq[m][0] * W[0])));
 #pragma unroll
-                        for (int m = NL; m < NVL; ++m) lin[m] = 0.0f;
-                        const float ltot = Butterfly<NVL, 1, NL>::reduce(lin, lane);
-                        if (lwriter) atomicAdd(&s_acc[j * AST + lin_slot], ltot);
+                        for (int m = 2 + NL; m < NC; ++m) cv[m] = 0.0f;
+                        const float tot = Butterfly<NC, 1, 2 + NL>::reduce(cv, lane);
+                        if (cwriter) atomicAdd(&s_acc[j * AST + cslot], tot * cscale);
+                    } else {
+                        const float tot = geo6_reduce(val, lane);
+                        if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
                     }
                 }
                 if (jn < 0) break;
