@@ -31,6 +31,21 @@ __device__ __forceinline__ void stage_geometry(const float4* __restrict__ rec, s
 __device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
 __device__ __forceinline__ bool wave_all(bool c) { return __builtin_amdgcn_ballot_w64(!c) == 0; }
 
+// Lane selects driven by a wavefront lane mask held in scalar registers
+// (bit l of m decides lane l): one v_cndmask, where a bool derived from the
+// mask would first cost a vector shift and compare.  Plain register
+// operands only, no memory access.
+__device__ __forceinline__ float mask_select(uint64_t m, float if_set, float if_clear) {
+    float r;
+    __asm__("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(m));
+    return r;
+}
+__device__ __forceinline__ int mask_select(uint64_t m, int if_set, int if_clear) {
+    int r;
+    __asm__("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(m));
+    return r;
+}
+
 // alpha of one (pixel, Gaussian) pair.  The forward and the backward kernels
 // both call this with the same staged values, so every alpha_min / T_min
 // decision of the backward reproduces the forward exactly.

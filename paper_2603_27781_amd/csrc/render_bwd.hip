@@ -408,6 +408,9 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 const int jp = jn >= 0 ? jn : j;
                 g0 = s_g0[jp];
                 g1 = s_g1[jp];
+                // issue those loads here, most of a step ahead of their use
+                // (left alone, the scheduler sinks them towards the end)
+                __builtin_amdgcn_sched_barrier(0);
                 const bool contrib = jl < lastp && a >= amin;
                 // No branch on whether any lane contributes (nearly every
                 // candidate step has a contributor).  Branch-free over the

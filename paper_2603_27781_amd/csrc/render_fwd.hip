@@ -56,12 +56,15 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
     for (int k = 0; k < 4 + F; ++k) acc[k] = 0.0f;
     float T = 1.0f;
     int lastj = 0;
-    bool done = !inside;
+    // lanes whose pixel is finished (outside the view, or T would fall
+    // below T_min), as a wavefront mask: the per-step bookkeeping is then
+    // scalar work on ballots of the two comparisons the step makes anyway
+    uint64_t done_m = __builtin_amdgcn_ballot_w64(!inside);
     const float log2_amin = __log2f(c.alpha_min);
     const float amin = c.alpha_min, amax = c.alpha_max, tmin = c.T_min;
 
     for (int b0 = rg.x; b0 < rg.y; b0 += B) {
-        if (__syncthreads_and(done)) break;
+        if (__syncthreads_and(done_m == ~0ull)) break;
         const int nb = min(B, rg.y - b0);
         for (int k = tid; k < nb; k += NT) {
             const int gid = inst_gid[inst[b0 + k]];
@@ -75,7 +78,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
             reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
         }
         __syncthreads();
-        if (!wave_all(done)) {
+        if (done_m != ~0ull) {
             uint64_t cand[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -111,14 +114,19 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     const int jp = jn >= 0 ? jn : j;
                     g0 = s_g0[jp];
                     g1 = s_g1[jp];
-                    const bool ok = !done && a >= amin;
+                    // issue those loads here, half a step ahead of their use
+                    // (left alone, the scheduler sinks them to the end of the
+                    // step, next to their use)
+                    __builtin_amdgcn_sched_barrier(0);
                     const float Tn = T * (1.0f - a);
-                    const bool use = ok && !(Tn < tmin);
+                    const uint64_t ok = __builtin_amdgcn_ballot_w64(a >= amin) & ~done_m;
+                    const uint64_t low = __builtin_amdgcn_ballot_w64(Tn < tmin);
+                    const uint64_t use = ok & ~low;
                     // No branch on whether any lane contributes: the
                     // candidates reach the block, so nearly every step has a
                     // contributor, and lanes not contributing add exactly 0 * x.
                     {
-                        const float w = use ? a * T : 0.0f;
+                        const float w = mask_select(use, a * T, 0.0f);
                         const float* ap = reinterpret_cast<const float*>(av);
                         acc[0] = fmaf(w, ap[0], acc[0]);
                         acc[1] = fmaf(w, ap[1], acc[1]);
@@ -126,11 +134,11 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                         acc[3] = fmaf(w, ap[AV * 4 - 1], acc[3]);
 #pragma unroll
                         for (int f = 0; f < F; ++f) acc[4 + f] = fmaf(w, ap[3 + f], acc[4 + f]);
-                        T = use ? Tn : T;
-                        lastj = use ? b0 - rg.x + j + 1 : lastj;
+                        T = mask_select(use, Tn, T);
+                        lastj = mask_select(use, b0 - rg.x + j + 1, lastj);
                     }
-                    done = done || (ok && Tn < tmin);
-                    if (wave_all(done)) {
+                    done_m |= ok & low;
+                    if (done_m == ~0ull) {
                         wdone = true;
                         break;
                     }
