@@ -567,19 +567,6 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
     }
 }
 
-// Inclusive max-scan over the wavefront (lanes without a predecessor take
-// -1): DPP row shifts by 1, 2, 4, 8 within rows of 16, then the row
-// broadcasts of lanes 15 and 31 carry it across rows.
-__device__ __forceinline__ int wave_max_scan(int x) {
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));  // row_shr:1
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));  // row_shr:2
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));  // row_shr:4
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));  // row_shr:8
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));  // row_bcast:15 into rows 1, 3
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));  // row_bcast:31 into rows 2, 3
-    return x;
-}
-
 // Emission: the visible pair at depth-sorted position i writes one instance
 // per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1
 // (row-major over the rectangle): key = global tile id, value = the emission

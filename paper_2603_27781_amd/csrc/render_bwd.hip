@@ -558,6 +558,7 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
     __shared__ float4 s_rec[256 / kWave][kWave][RS / 4];
     __shared__ int s_start[256 / kWave][kWave];
     __shared__ int s_first[256 / kWave][kWave];
+    __shared__ int s_mark[256 / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int vp = 1 << vp_log2;
@@ -584,30 +585,30 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
             cnt = cnt > 0 ? cnt : 0;
         }
         // exclusive scan of the counts over the wavefront
-        int incl = cnt;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int y = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += y;
-        }
+        const int incl = wave_add_scan(cnt);
         const int start = incl - cnt;
-        const int total = __shfl(incl, kWave - 1, kWave);
+        const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
         s_start[wave][lane] = start;
         s_first[wave][lane] = first;
         float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int carry = -1;  // owner of the last record before the current 64
         for (int base = 0; base < total; base += kWave) {
+            // owner of record base + lane: the last lane with records whose
+            // start is at or before it -- each such lane marks its start's
+            // slot (starts of lanes with records are distinct) and a
+            // max-scan carries the marks forward
+            s_mark[wave][lane] = -1;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (cnt > 0 && start >= base && start < base + kWave) s_mark[wave][start - base] = lane;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int lo = max(wave_max_scan(s_mark[wave][lane]), carry);
+            carry = __builtin_amdgcn_readlane(lo, kWave - 1);
             const int idx = base + lane;
             if (idx < total) {
-                // owner: the last lane whose start is <= idx (it has records)
-                int lo = 0, hi = kWave - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_start[wave][mid] <= idx) lo = mid;
-                    else hi = mid - 1;
-                }
                 const int64_t e = (int64_t)s_first[wave][lo] + (idx - s_start[wave][lo]);
                 const float4* r4 = reinterpret_cast<const float4*>(records + (size_t)e * RS);
 #pragma unroll
@@ -647,9 +648,27 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (PARAMS) {
-        for (int d = 1; d < vp; d <<= 1)
+        // sum over the Gaussian's VP lanes (bits 0 .. vp_log2-1), DPP and
+        // swizzles; the half-row mirror serves bit 2 once bits 0 and 1 are
+        // summed (every lane of a quad then holds the quad's total)
+        if (vp_log2 > 0)
 #pragma unroll
-            for (int q = 0; q < NA; ++q) appacc[q] += __shfl_xor(appacc[q], d, kWave);
+            for (int q = 0; q < NA; ++q) appacc[q] += xor_lane<1>(appacc[q]);
+        if (vp_log2 > 1)
+#pragma unroll
+            for (int q = 0; q < NA; ++q) appacc[q] += xor_lane<2>(appacc[q]);
+        if (vp_log2 > 2)
+#pragma unroll
+            for (int q = 0; q < NA; ++q) appacc[q] += mirror8_lane(appacc[q]);
+        if (vp_log2 > 3)
+#pragma unroll
+            for (int q = 0; q < NA; ++q) appacc[q] += xor_lane<8>(appacc[q]);
+        if (vp_log2 > 4)
+#pragma unroll
+            for (int q = 0; q < NA; ++q) appacc[q] += xor_lane<16>(appacc[q]);
+        if (vp_log2 > 5)
+#pragma unroll
+            for (int q = 0; q < NA; ++q) appacc[q] += xor_lane<32>(appacc[q]);
         if (i64 < n && vl == 0) {
             // the row of 4+F floats is 16-byte aligned (4+F is a multiple of 4)
             float4* ga = reinterpret_cast<float4*>(grad_app + (size_t)i * (4 + F));

@@ -63,6 +63,29 @@ __device__ inline float2 unpack_radii(float packed) {
                        __half2float(__ushort_as_half((unsigned short)(bits >> 16))));
 }
 
+// Inclusive scans over the wavefront with DPP (no LDS): row shifts by 1, 2,
+// 4, 8 within rows of 16 lanes, then the row broadcasts of lanes 15 and 31
+// carry the row totals across rows.  Lanes without a predecessor at a step
+// take the identity (-1 for the max over non-negative values, 0 for the sum).
+__device__ __forceinline__ int wave_max_scan(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));  // row_bcast:15 into rows 1, 3
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));  // row_bcast:31 into rows 2, 3
+    return x;
+}
+__device__ __forceinline__ int wave_add_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
+    return x;
+}
+
 // Fill kernel (used instead of hipMemsetAsync so that calls stay correct
 // when captured in a HIP graph and replayed).
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count);
