@@ -73,12 +73,8 @@ struct LoadU32 {
 template <int NT>
 __device__ uint32_t block_exclusive(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
+    // wave inclusive scan (DPP; two's-complement adds are the unsigned ones)
+    const uint32_t x = (uint32_t)wave_add_scan((int)v);
     if (lane == kWave - 1) s_tmp[wave] = x;
     __syncthreads();
     uint32_t wbase = 0, tot = 0;
