@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4]
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -219,6 +220,32 @@ def main():
     kern_us = {k: float(np.mean([a.elapsed_time(b) for a, b in v]) * 1e3) for k, v in evs.items() if v}
     log("entry-point times (us): " + ", ".join(f"{k} {v:.1f}" for k, v in kern_us.items()))
 
+    # ------------------------------------------- the other launch mode
+    # The same graph-captured step with the other compositing launch mode
+    # (persistent workgroups pulling tiles from a queue, or one workgroup
+    # per tile), timed the same way, so that both are on the record.
+    other = None
+    if not args.no_perview:
+        ocfg = raster.Config(**{**dataclasses.asdict(cfg), "persistent": 1 - int(cfg.persistent)})
+        ost = batched.MappingStep(g, w.views, ocfg, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose)
+        ost.ensure_capacity()
+        ost.capture(warmup=max(args.warmup, 1))
+        for _ in range(args.warmup):
+            ost.replay()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            ost.replay()
+        end.record()
+        torch.cuda.synchronize()
+        ms_o = start.elapsed_time(end) / args.steps
+        other = {"persistent": int(ocfg.persistent), "ms_per_step": round(ms_o, 4),
+                 "value": round(P / (ms_o * 1e-3) / 1e6, 2)}
+        log(f"{'persistent' if ocfg.persistent else 'one workgroup per tile'}: {ms_o:.3f} ms/step "
+            f"({other['value']} Mpix/s)")
+        del ost
+        torch.cuda.empty_cache()
+
     # ------------------------------------------------------------ per-view
     per_view = None
     if not args.no_perview and len(w.views) > 1:
@@ -281,7 +308,8 @@ def main():
                    "grad": ("params" if params else "") + ("+pose" if pose else ""), "mode": "batched hipGraph",
                    "tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
                    "lds_batch_bwd": cfg.lds_batch_bwd},
-        "per_view": per_view, "entry_us": {k: round(v, 2) for k, v in kern_us.items()},
+        "per_view": per_view, "other_launch_mode": other,
+        "entry_us": {k: round(v, 2) for k, v in kern_us.items()},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

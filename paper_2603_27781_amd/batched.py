@@ -26,7 +26,7 @@ from .raster import Config, Gaussians, Rasterizer, Views
 
 # Launch configuration the benchmark times (chosen with autotune.tune on the
 # 8 x 1200x680, 1M-Gaussian, F=16 mapping step).
-BENCH_CONFIG = {"tile": 16, "lds_batch": 256, "persistent": 1, "lds_batch_bwd": 128}
+BENCH_CONFIG = {"tile": 16, "lds_batch": 256, "persistent": 0, "lds_batch_bwd": 128}
 
 
 class MappingStep:
