@@ -118,7 +118,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     // (left alone, the scheduler sinks them to the end of the
                     // step, next to their use)
                     __builtin_amdgcn_sched_barrier(0);
-                    const float Tn = T * (1.0f - a);
+                    const float Tn = fmaf(-a, T, T);  // T (1 - alpha), one rounding
                     const uint64_t ok = __builtin_amdgcn_ballot_w64(a >= amin) & ~done_m;
                     const uint64_t low = __builtin_amdgcn_ballot_w64(Tn < tmin);
                     const uint64_t use = ok & ~low;
