@@ -205,9 +205,9 @@ hipError_t launch_fwd_t(const float* rec, const float* app, int n, const int32_t
     unsigned grid = (unsigned)total_tiles;
     if (persistent) {
         int dev = 0, cus = 0, per_cu = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TS * TS, 0);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TS * TS, 0);
         if (per_cu < 1) per_cu = 1;
         unsigned cap = (unsigned)(cus * per_cu);
         grid = cap < grid ? cap : grid;
