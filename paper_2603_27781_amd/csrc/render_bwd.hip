@@ -696,6 +696,7 @@ hipError_t launch_bwd_t(const float* rec, const float* app, int n, const int32_t
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TS * TS, 0);
         if (per_cu < 1) per_cu = 1;
+        if (cus < 1) cus = 1;  // a failed query still drains the queue, with fewer workgroups
         const unsigned cap = (unsigned)(cus * per_cu);
         grid = cap < grid ? cap : grid;
         hipLaunchKernelGGL(k_reset_queue_bwd, dim3(1), dim3(64), 0, s, queue);
