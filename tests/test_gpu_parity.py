@@ -34,6 +34,21 @@ def _with_empty_view():
     return w.scene, w.views + [away]
 
 
+def _many_views(seed=67, n=300, F=8, V=40):
+    """40 small views of mixed sizes and poses (some seeing little): more
+    views than lanes of a wavefront's projection queue drains at once, view
+    masks past bit 31 in the projection backward, and the record
+    reduction's cross-lane sum over 64 lanes per Gaussian."""
+    w = wl.tiny_scene(seed, n, F=F, W=24, H=20, f=25.0)
+    rng = np.random.default_rng(seed)
+    views = list(w.views)
+    for _ in range(V - 1):
+        xi = rng.normal(size=6) * np.array([0.05, 0.05, 0.05, 0.2, 0.2, 0.1])
+        views.append(wl.make_view(int(rng.integers(12, 33)), int(rng.integers(10, 25)),
+                                  float(rng.uniform(18.0, 35.0)), wl.se3_exp(xi)))
+    return w.scene, views
+
+
 CASES = {
     "tiny3views-F16": lambda: _multi_view_tiny(),
     "cfg1-64x64-2k": lambda: (wl.config1().scene, wl.config1().views),
@@ -43,6 +58,7 @@ CASES = {
     "tiny-F0": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(64, 200, F=0, W=40, H=40, f=35.0)),
     "stacked600-F16": _stacked,
     "empty-view-F8": _with_empty_view,
+    "40views-F8": _many_views,
 }
 
 
