@@ -357,6 +357,16 @@ struct SrcKV {
     }
     __device__ uint32_t val(int64_t i) const { return vals[i]; }
 };
+// Key source whose value is the key's own position (the first pass of a
+// sort that carries the input order along, so nobody has to write it out).
+struct SrcKI {
+    const uint32_t* keys;
+    __device__ bool key(int64_t i, uint32_t& k) const {
+        k = keys[i];
+        return true;
+    }
+    __device__ uint32_t val(int64_t i) const { return (uint32_t)i; }
+};
 template <class Src>
 __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(Src src, const int64_t* count_dev, int64_t n_max,
                                                            int shift, uint32_t* __restrict__ hist, int nblk) {
@@ -480,8 +490,9 @@ hipError_t radix_pass(Src src, const int64_t* count_dev, int64_t n_max, int shif
     return hipGetLastError();
 }
 
-// Sorts (keys, vals) in place over `passes` 8-bit digits starting at bit 0,
-// ping-ponging with (keys2, vals2); an even pass count ends in (keys, vals).
+// Sorts keys over `passes` 8-bit digits starting at bit 0, each key carrying
+// its input position as its value (vals is not read), ping-ponging with
+// (keys2, vals2); an even pass count ends in (keys, vals).
 // Pass p scans its digit offsets with status words status + p * spine_tiles
 // and ticket tickets[p] (all zeroed beforehand).
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t* vals2, const int64_t* count_dev,
@@ -490,8 +501,11 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t*
     if (n_max <= 0) return hipSuccess;
     uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
     for (int p = 0; p < passes; ++p) {
-        hipError_t e = radix_pass(SrcKV{ki, vi}, count_dev, n_max, 8 * p, hist, status + p * spine_tiles,
-                                  tickets + p, nullptr, ko, vo, nullptr, nullptr, s);
+        hipError_t e = (p == 0) ? radix_pass(SrcKI{ki}, count_dev, n_max, 0, hist, status, tickets, nullptr, ko,
+                                             vo, nullptr, nullptr, s)
+                                : radix_pass(SrcKV{ki, vi}, count_dev, n_max, 8 * p, hist,
+                                             status + p * spine_tiles, tickets + p, nullptr, ko, vo, nullptr,
+                                             nullptr, s);
         if (e != hipSuccess) return e;
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -565,8 +579,8 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
 
 // Emission: the visible pair at depth-sorted position i writes one instance
 // per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1
-// (row-major over the rectangle): key = global tile id, value = the emission
-// index itself.  inst_gid[e] keeps the Gaussian of emission index e,
+// (row-major over the rectangle): key = global tile id (the first tile-sort
+// pass attaches the emission index as the value).  inst_gid[e] keeps the Gaussian of emission index e,
 // pair_first[pair] the first emission index of the pair, so that the
 // instances of one (view, Gaussian) pair stay contiguous in emission space
 // after the tile sort has reordered them.
@@ -580,7 +594,7 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
                                               const uint32_t* __restrict__ offs, const int64_t* n_vis,
                                               const uint2* __restrict__ rect, const gs_view* __restrict__ views,
                                               int n, int tile, int64_t capacity, uint32_t* __restrict__ keys,
-                                              uint32_t* __restrict__ vals, int32_t* __restrict__ inst_gid,
+                                              int32_t* __restrict__ inst_gid,
                                               int32_t* __restrict__ pair_first) {
     __shared__ uint32_t s_start[4][kWave];
     __shared__ uint4 s_info[4][kWave];  // (x0 | y0 << 16, rect width, tile base, tiles per row)
@@ -649,7 +663,6 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
         const int64_t o = o_w + k;
         if (o < capacity) {
             keys[o] = info.z + yy * info.w + xx;
-            vals[o] = (uint32_t)o;
             inst_gid[o] = s_gid[wave][lo];
         }
     }
@@ -772,7 +785,7 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     uint32_t* ov = (passes % 2 == 0) ? iv2 : reinterpret_cast<uint32_t*>(inst);
     if (vn > 0) {
         hipLaunchKernelGGL(k_emit, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, vis_v0, pos, &cnt[0],
-                           reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, ev, inst_gid,
+                           reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, inst_gid,
                            pair_first);
     }
     e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, st_tile, L.spine_tiles, &tickets[kMaxPasses], s);
