@@ -44,6 +44,7 @@ def lib() -> ctypes.CDLL:
         _lib = ctypes.CDLL(_LIB)
         _lib.orc_bin.restype = ctypes.c_int64
         _lib.orc_total_tiles.restype = ctypes.c_int64
+        _lib.orc_depth_median.restype = ctypes.c_float
     return _lib
 
 
@@ -219,6 +220,81 @@ def loss(out: np.ndarray, views, rgb_t, depth_t, labels=None, decoder=None, weig
                _p(np.ascontiguousarray(out, np.float64)), _p(np.ascontiguousarray(rgb_t, np.float64)),
                _p(np.ascontiguousarray(depth_t, np.float64)), _p(lab), _p(Wd), _p(w), _p(g), _p(terms))
     return g, terms
+
+
+@dataclasses.dataclass
+class SlamLossOpts:
+    """Weights and thresholds of the SLAM losses (Eq. 11, 15, 18, 21).
+
+    tau_obs / tau_unobs are not stated in the paper; the defaults follow the
+    silhouette thresholds of the SplaTAM work that the masks are modelled on.
+    The residual factors 10 and 50 are Eq. (21)'s and Eq. (11)'s."""
+    w_color: float = 0.5
+    w_depth: float = 1.0
+    w_sem: float = 0.01
+    ssim_lambda: float = 0.2
+    tau_obs: float = 0.99
+    tau_unobs: float = 0.5
+    obs_factor: float = 10.0
+    unobs_factor: float = 50.0
+    use_obs: bool = False
+
+    def array(self) -> np.ndarray:
+        # every value as the binary32 the device receives, upcast exactly
+        v = [self.w_color, self.w_depth, self.w_sem, self.ssim_lambda, self.tau_obs, self.tau_unobs,
+             self.obs_factor, self.unobs_factor]
+        return np.array([float(np.float32(x)) for x in v] + [1.0 if self.use_obs else 0.0], np.float64)
+
+
+def depth_median(depth, depth_t) -> np.float32:
+    """Lower median of the binary32 residual |D - D*| over pixels with D* > 0."""
+    d = np.ascontiguousarray(depth, np.float64)
+    t = np.ascontiguousarray(depth_t, np.float64)
+    return np.float32(lib().orc_depth_median(ctypes.c_int64(d.size), _p(d), _p(t)))
+
+
+def ssim_map(x, y) -> np.ndarray:
+    """Per-pixel SSIM of one H x W channel (11x11 Gaussian window, zero padding)."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    H, W = x.shape
+    s = np.zeros_like(x)
+    lib().orc_ssim_map(ctypes.c_int(W), ctypes.c_int(H), _p(x), _p(y), _p(s))
+    return s
+
+
+def slam_loss(out, wh, rgb_t, depth_t, labels=None, decoder=None, opts: SlamLossOpts = SlamLossOpts(),
+              medians=None, norm_counts=None):
+    """SLAM loss (Eq. 15 / 18 / 21) of views of sizes wh = [(W, H), ...].
+
+    Returns (grad_out [5+F][P] FP64, terms[5] = colour L1, SSIM, depth,
+    semantic, total; masks uint8 [P] = M_obs | M_unobs << 1; medians float32
+    [V]).  `medians` (float32 [V]) replaces the computed median depth errors
+    and `norm_counts` the P_v of each view's means (crops of larger views)."""
+    L = lib()
+    out = np.ascontiguousarray(out, np.float64)
+    F = out.shape[0] - 5
+    K = 0 if decoder is None else int(decoder.shape[1])
+    P = out.shape[1]
+    V = len(wh)
+    whs = np.ascontiguousarray(np.asarray(wh, np.int32).reshape(V, 2))
+    assert int((whs[:, 0].astype(np.int64) * whs[:, 1]).sum()) == P
+    nc = (whs[:, 0].astype(np.int64) * whs[:, 1]) if norm_counts is None else np.asarray(norm_counts, np.int64)
+    nc = np.ascontiguousarray(nc, np.int64)
+    g = np.zeros_like(out)
+    terms = np.zeros(5, np.float64)
+    masks = np.zeros(P, np.uint8)
+    med_out = np.zeros(V, np.float32)
+    med_in = None if medians is None else np.ascontiguousarray(medians, np.float32)
+    lab = np.zeros(P, np.int32) if labels is None else np.ascontiguousarray(labels, np.int32)
+    Wd = np.zeros((max(F, 1), 1)) if decoder is None else np.ascontiguousarray(decoder, np.float64)
+    o = opts.array()
+    if K == 0:
+        o[2] = 0.0
+    L.orc_slam_loss(ctypes.c_int(F), ctypes.c_int(K), ctypes.c_int(V), _p(whs), _p(nc), _p(out),
+                    _p(np.ascontiguousarray(rgb_t, np.float64)), _p(np.ascontiguousarray(depth_t, np.float64)),
+                    _p(lab), _p(Wd), _p(o), _p(med_in), _p(med_out), _p(masks), _p(g), _p(terms))
+    return g, terms, masks, med_out
 
 
 GRAD_PARAMS = 1

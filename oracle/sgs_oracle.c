@@ -914,3 +914,279 @@ void orc_geom(const double* mu, const double* ls, const double* q, double logit,
 void orc_dec_exp(int n, const float* x, float* y) {
     for (int i = 0; i < n; ++i) y[i] = dec_expf(x[i]);
 }
+
+/* ========================================================================= */
+/* SLAM-loss extensions of the image-space losses (Sec. 3.3.1, Eq. (11);     */
+/* Sec. 3.3.4, Eq. (15); Sec. 3.4, Eq. (21)).                                 */
+/*   - the median depth error of a view (the reference value of both masks), */
+/*   - the masks M_obs (Eq. 21) and M_unobs (Eq. 11),                         */
+/*   - the colour term (1 - lambda) L1 + lambda (1 - SSIM) of Eq. (15),       */
+/*   - every term optionally weighted per pixel by M_obs (Eq. 21).            */
+/* Every decision (the depth residual that is ranked, the mask tests) is     */
+/* taken in binary32 on the binary32 roundings of the inputs; the values     */
+/* (losses, gradients, SSIM) are FP64.                                        */
+/* ========================================================================= */
+
+static int cmp_u32(const void* a, const void* b) {
+    const uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* binary32 depth residual |fl(D - D*)| of one pixel */
+static float depth_residual32(double d, double dt) {
+    const float a = (float)d, b = (float)dt;
+    const float r = a - b;
+    return fabsf(r);
+}
+
+/* Median depth error of one view: over its pixels with a valid observed
+ * depth (D* > 0), the lower median (rank floor((m - 1) / 2) of m, counted
+ * from 0) of the binary32 residuals, ranked by their bit patterns (the
+ * float order for non-negative values; a NaN ranks above +inf).  0 if no
+ * pixel has a valid depth. */
+float orc_depth_median(int64_t n, const double* depth, const double* depth_t) {
+    uint32_t* u = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!((float)depth_t[i] > 0.0f)) continue;
+        const float r = depth_residual32(depth[i], depth_t[i]);
+        uint32_t b;
+        memcpy(&b, &r, 4);
+        u[m++] = b;
+    }
+    float med = 0.0f;
+    if (m > 0) {
+        qsort(u, (size_t)m, sizeof(uint32_t), cmp_u32);
+        memcpy(&med, &u[(m - 1) / 2], 4);
+    }
+    free(u);
+    return med;
+}
+
+/* Masks of one pixel, binary32 tests:
+ *   bit 0  M_obs   = (O > tau_obs) and (r < obs_factor * med)            Eq. (21)
+ *   bit 1  M_unobs = (O < tau_unobs) or (D > D* and r > unobs_factor * med)  Eq. (11) */
+static int pixel_masks(double d, double dt, double op, float med, float tau_obs, float tau_unobs,
+                       float obs_factor, float unobs_factor) {
+    const float r = depth_residual32(d, dt);
+    const float o = (float)op, df = (float)d, dtf = (float)dt;
+    const float lim_obs = obs_factor * med, lim_unobs = unobs_factor * med;
+    const int obs = (o > tau_obs) && (r < lim_obs);
+    const int unobs = (o < tau_unobs) || ((df > dtf) && (r > lim_unobs));
+    return obs | (unobs << 1);
+}
+
+/* The SSIM window of Wang et al. (2004) as used by Eq. (15): 11 x 11
+ * samples of a Gaussian of standard deviation 1.5 pixels centred on the
+ * pixel, scaled to sum to 1. */
+static void ssim_window(double w[11][11]) {
+    double tot = 0.0;
+    for (int a = 0; a < 11; ++a)
+        for (int b = 0; b < 11; ++b) {
+            const double da = a - 5, db = b - 5;
+            w[a][b] = exp(-(da * da + db * db) / (2.0 * 1.5 * 1.5));
+            tot += w[a][b];
+        }
+    for (int a = 0; a < 11; ++a)
+        for (int b = 0; b < 11; ++b) w[a][b] /= tot;
+}
+
+#define SSIM_C1 (0.01 * 0.01)
+#define SSIM_C2 (0.03 * 0.03)
+
+/* SSIM of one channel of one W x H image at pixel (i, j) (row i), with
+ * zero padding outside the image: local means, variances and covariance
+ * under the window, then
+ *   s = (2 mx my + C1)(2 cxy + C2) / ((mx^2 + my^2 + C1)(vx + vy + C2)).
+ * Also the partial derivatives of s with respect to the three windowed sums
+ * that depend on x: mx = sum w x, sxx = sum w x^2, sxy = sum w x y (each
+ * taken with the other two fixed; vx = sxx - mx^2, cxy = sxy - mx my). */
+static double ssim_at(int W, int H, const double* x, const double* y, int i, int j, const double w[11][11],
+                      double* d_mx, double* d_sxx, double* d_sxy) {
+    double mx = 0, my = 0, sxx = 0, syy = 0, sxy = 0;
+    for (int a = -5; a <= 5; ++a) {
+        const int ii = i + a;
+        if (ii < 0 || ii >= H) continue;
+        for (int b = -5; b <= 5; ++b) {
+            const int jj = j + b;
+            if (jj < 0 || jj >= W) continue;
+            const double wt = w[a + 5][b + 5];
+            const double xv = x[(size_t)ii * W + jj], yv = y[(size_t)ii * W + jj];
+            mx += wt * xv;
+            my += wt * yv;
+            sxx += wt * xv * xv;
+            syy += wt * yv * yv;
+            sxy += wt * xv * yv;
+        }
+    }
+    const double vx = sxx - mx * mx, vy = syy - my * my, cxy = sxy - mx * my;
+    const double N1 = 2.0 * mx * my + SSIM_C1, N2 = 2.0 * cxy + SSIM_C2;
+    const double D1 = mx * mx + my * my + SSIM_C1, D2 = vx + vy + SSIM_C2;
+    const double s = (N1 * N2) / (D1 * D2);
+    if (d_mx) {
+        /* dN1/dmx = 2 my, dN2/dmx = -2 my, dD1/dmx = 2 mx, dD2/dmx = -2 mx */
+        *d_mx = (2.0 * my * N2 - 2.0 * my * N1) / (D1 * D2) - s * (2.0 * mx) / D1 + s * (2.0 * mx) / D2;
+        *d_sxx = -s / D2;            /* dD2/dsxx = 1 */
+        *d_sxy = 2.0 * N1 / (D1 * D2); /* dN2/dsxy = 2 */
+    }
+    return s;
+}
+
+/* SSIM map of one channel (exposed for the closed-form pins). */
+void orc_ssim_map(int W, int H, const double* x, const double* y, double* s) {
+    double w[11][11];
+    ssim_window(w);
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) s[(size_t)i * W + j] = ssim_at(W, H, x, y, i, j, w, NULL, NULL, NULL);
+}
+
+/* sum_p m(p) (1 - s(p)) over one channel, and coef * d/dx(q) of
+ * sum_p m(p) s(p) added into g: with mx(p) = sum_o w(o) x(p + o),
+ *   d mx(p) / d x(q) = w(q - p),  d sxx(p) / d x(q) = 2 w(q - p) x(q),
+ *   d sxy(p) / d x(q) = w(q - p) y(q). */
+static double ssim_channel(int W, int H, const double* x, const double* y, const uint8_t* m, double coef,
+                           double* g) {
+    double w[11][11];
+    ssim_window(w);
+    const size_t n = (size_t)W * H;
+    double* dm = (double*)calloc(n, sizeof(double));
+    double* dxx = (double*)calloc(n, sizeof(double));
+    double* dxy = (double*)calloc(n, sizeof(double));
+    double sum = 0.0;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const size_t p = (size_t)i * W + j;
+            if (m && !m[p]) continue;
+            double a, b, c;
+            const double s = ssim_at(W, H, x, y, i, j, w, &a, &b, &c);
+            sum += 1.0 - s;
+            dm[p] = a;
+            dxx[p] = b;
+            dxy[p] = c;
+        }
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const size_t q = (size_t)i * W + j;
+            double acc = 0.0;
+            for (int a = -5; a <= 5; ++a) {
+                const int pi = i - a; /* q - p = (a, b) */
+                if (pi < 0 || pi >= H) continue;
+                for (int b = -5; b <= 5; ++b) {
+                    const int pj = j - b;
+                    if (pj < 0 || pj >= W) continue;
+                    const size_t p = (size_t)pi * W + pj;
+                    const double wt = w[a + 5][b + 5];
+                    acc += wt * (dm[p] + 2.0 * x[q] * dxx[p] + y[q] * dxy[p]);
+                }
+            }
+            g[q] += coef * acc;
+        }
+    free(dm);
+    free(dxx);
+    free(dxy);
+    return sum;
+}
+
+/* SLAM loss of V views and its gradient d L / d out.
+ *   wh[2v], wh[2v+1]: width and height of view v (its pixels are the next
+ *     W*H of the planar images, row-major);
+ *   norm_count[v]: the P_v the view's means divide by (normally W*H);
+ *   opts: w0, w1, w2 (lambda_c, lambda_d, lambda_s), lambda (Eq. 15),
+ *     tau_obs, tau_unobs, obs_factor, unobs_factor, use_obs (0/1);
+ *   med_in: per-view median depth errors to use, or NULL to compute them
+ *     (orc_depth_median); med_out[V] receives the ones used.
+ * Per view, with M(p) = M_obs(p) if use_obs else 1:
+ *   colour L1  (1 - lambda) w0 / (3 P_v) sum_p M(p) sum_c |C_c - C*_c|
+ *   SSIM       lambda w0 / (3 P_v) sum_c sum_p M(p) (1 - s_c(p))
+ *   depth      w1 / P_v sum_p M(p) |D - D*|
+ *   semantic   w2 / P_v sum_p M(p) CE(softmax(W^T F), label)
+ * terms[5] = (colour L1, SSIM, depth, semantic, total) summed over views;
+ * masks[p] = M_obs | M_unobs << 1; grad_out [5+F][P] (opacity channel 0). */
+void orc_slam_loss(int F, int K, int V, const int32_t* wh, const int64_t* norm_count, const double* out,
+                   const double* rgb_t, const double* depth_t, const int32_t* labels, const double* Wd,
+                   const double* opts, const float* med_in, float* med_out, uint8_t* masks, double* grad_out,
+                   double* terms) {
+    int64_t P = 0;
+    for (int v = 0; v < V; ++v) P += (int64_t)wh[2 * v] * wh[2 * v + 1];
+    const int NC = 5 + F;
+    memset(grad_out, 0, sizeof(double) * (size_t)NC * P);
+    const double w0 = opts[0], w1 = opts[1], w2 = opts[2], lam = opts[3];
+    const float tau_obs = (float)opts[4], tau_unobs = (float)opts[5];
+    const float fobs = (float)opts[6], funobs = (float)opts[7];
+    const int use_obs = opts[8] != 0.0;
+    double T[5] = {0, 0, 0, 0, 0};
+    int64_t base = 0;
+    for (int v = 0; v < V; ++v) {
+        const int W = wh[2 * v], H = wh[2 * v + 1];
+        const int64_t Pv = (int64_t)W * H;
+        const double nv = (double)norm_count[v];
+        const float med =
+            med_in ? med_in[v] : orc_depth_median(Pv, out + 3 * (size_t)P + base, depth_t + base);
+        med_out[v] = med;
+        uint8_t* mv = masks + base;
+        for (int64_t j = 0; j < Pv; ++j) {
+            const int64_t p = base + j;
+            mv[j] = (uint8_t)pixel_masks(out[3 * (size_t)P + p], depth_t[p], out[4 * (size_t)P + p], med, tau_obs,
+                                         tau_unobs, fobs, funobs);
+        }
+        const double gc = (1.0 - lam) * w0 / (3.0 * nv), gd = w1 / nv, gs = w2 / nv;
+        double lc = 0, ld = 0, lsum = 0;
+        for (int64_t j = 0; j < Pv; ++j) {
+            const int64_t p = base + j;
+            const double M = use_obs ? (double)(mv[j] & 1) : 1.0;
+            if (M == 0.0) continue;
+            for (int ch = 0; ch < 3; ++ch) {
+                const double r = out[(size_t)ch * P + p] - rgb_t[(size_t)ch * P + p];
+                lc += fabs(r);
+                grad_out[(size_t)ch * P + p] = r > 0 ? gc : (r < 0 ? -gc : 0.0);
+            }
+            const double rd = out[3 * (size_t)P + p] - depth_t[p];
+            ld += fabs(rd);
+            grad_out[3 * (size_t)P + p] = rd > 0 ? gd : (rd < 0 ? -gd : 0.0);
+            if (K > 0 && F > 0 && w2 != 0.0) {
+                double z[1024], mx = -INFINITY;
+                for (int k = 0; k < K; ++k) {
+                    double acc = 0;
+                    for (int f = 0; f < F; ++f) acc += Wd[(size_t)f * K + k] * out[(size_t)(5 + f) * P + p];
+                    z[k] = acc;
+                    if (acc > mx) mx = acc;
+                }
+                double se = 0;
+                for (int k = 0; k < K; ++k) se += exp(z[k] - mx);
+                const int lab = labels[p];
+                lsum += (mx + log(se)) - z[lab];
+                for (int f = 0; f < F; ++f) {
+                    double g = 0;
+                    for (int k = 0; k < K; ++k) {
+                        const double sm = exp(z[k] - mx) / se - (k == lab ? 1.0 : 0.0);
+                        g += Wd[(size_t)f * K + k] * sm;
+                    }
+                    grad_out[(size_t)(5 + f) * P + p] = gs * g;
+                }
+            }
+        }
+        double ls = 0.0;
+        if (lam != 0.0) {
+            uint8_t* m = NULL;
+            if (use_obs) {
+                m = (uint8_t*)malloc((size_t)Pv);
+                for (int64_t j = 0; j < Pv; ++j) m[j] = mv[j] & 1;
+            }
+            const double coef = -lam * w0 / (3.0 * nv);
+            for (int ch = 0; ch < 3; ++ch)
+                ls += ssim_channel(W, H, out + (size_t)ch * P + base, rgb_t + (size_t)ch * P + base, m, coef,
+                                   grad_out + (size_t)ch * P + base);
+            free(m);
+        }
+        T[0] += gc * lc;
+        T[1] += lam * w0 * ls / (3.0 * nv);
+        T[2] += gd * ld;
+        T[3] += gs * lsum;
+        base += Pv;
+    }
+    terms[0] = T[0];
+    terms[1] = T[1];
+    terms[2] = T[2];
+    terms[3] = T[3];
+    terms[4] = T[0] + T[1] + T[2] + T[3];
+}
