@@ -225,6 +225,62 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
                  void* ws, size_t ws_bytes, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * gs_slam_loss -- the SLAM losses with their masks: the mapping colour term
+ * of Sec. 3.3.4, Eq. (15) (L1 plus an SSIM term), the observed-region mask
+ * of the tracking loss, Sec. 3.4, Eq. (21), and the unobserved-region mask
+ * of Sec. 3.3.1, Eq. (11), with the median depth error both masks refer to.
+ *   median (per view): the lower median (rank floor((m-1)/2), from 0, of m)
+ *     of the binary32 residuals r = |D - D*| over the view's pixels with
+ *     D* > 0, ranked by bit pattern (the float order; a NaN ranks above
+ *     +inf); 0 when no pixel has D* > 0.  Exact (a radix select).
+ *   masks[p], binary32 tests:
+ *     bit 0  M_obs   = (O > tau_obs) and (r < obs_factor * median)
+ *     bit 1  M_unobs = (O < tau_unobs) or (D > D* and r > unobs_factor * median)
+ *   loss, per view v (P_v pixels), with M(p) = M_obs(p) if flags has
+ *   GS_LOSS_OBS_MASK, else 1:
+ *     colour L1  (1 - lambda) w_color / (3 P_v) sum_p M(p) |C(p) - C*(p)|_1
+ *     SSIM       lambda w_color / (3 P_v) sum_c sum_p M(p) (1 - SSIM_c(p))
+ *     depth      w_depth / P_v sum_p M(p) |D(p) - D*(p)|
+ *     semantic   w_sem / P_v sum_p M(p) CE(softmax(W^T F(p)), label(p))
+ *   SSIM_c(p) (Wang et al. 2004) of colour channel c: local means,
+ *   variances and covariance of the rendered and the target image under an
+ *   11x11 Gaussian window of standard deviation 1.5 px (weights summing to
+ *   1), pixels outside the view taken as 0, C1 = 0.01^2, C2 = 0.03^2.
+ *   The masks are constants of the loss (no gradient flows through them).
+ * Arguments: out [5+F][P_total] (the render), rgb_target [3][P_total],
+ * depth_target [P_total], labels [P_total] int32 in [0, n_classes), decoder
+ * W [n_feat][n_classes] row-major (n_classes == 0 drops the semantic term);
+ * opts is a HOST struct.  WRITES grad_out [5+F][P_total] = dL/d out (opacity
+ * channel 0); loss[5] (double) = (colour L1, SSIM, depth, semantic, total),
+ * each summed over the views in a fixed order (deterministic); median[V]
+ * (float, may be NULL); masks [P_total] (uint8, may be NULL).  ws: at least
+ * gs_slam_loss_workspace bytes (with_ssim != 0 when ssim_lambda != 0),
+ * 256-byte aligned, contents need not be initialised.  Views as for the
+ * other entry points.  Errors: GS_EINVAL (null or misaligned pointer, bad
+ * view list, n_classes out of range), GS_ECAPACITY (ws too small),
+ * GS_EUNSUPPORTED (n_feat not compiled).
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    float w_color, w_depth, w_sem; /* lambda_c, lambda_d, lambda_s (Eq. 18, 21)        */
+    float ssim_lambda;             /* lambda of Eq. (15); 0 = L1 colour only (Eq. 21)  */
+    float tau_obs, tau_unobs;      /* opacity thresholds of Eq. (21) and Eq. (11)      */
+    float obs_factor;              /* 10: M_obs residual bound, in medians (Eq. 21)    */
+    float unobs_factor;            /* 50: M_unobs residual bound, in medians (Eq. 11)  */
+    uint32_t flags;                /* GS_LOSS_OBS_MASK: weight every term by M_obs     */
+} gs_slam_loss_opts;
+
+enum { GS_LOSS_OBS_MASK = 1 };
+
+/* Fills *opts with w = (0.5, 1.0, 0.01), lambda 0.2, tau_obs 0.99,
+ * tau_unobs 0.5, factors 10 and 50, no mask (the mapping loss). */
+int gs_default_slam_loss_opts(gs_slam_loss_opts* opts);
+int gs_slam_loss_workspace(const gs_view* views, int32_t n_views, int32_t with_ssim, size_t* bytes);
+int gs_slam_loss(const float* out, int32_t n_feat, const float* rgb_target, const float* depth_target,
+                 const int32_t* labels, const float* decoder, int32_t n_classes, const gs_slam_loss_opts* opts,
+                 const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
+                 float* median, uint8_t* masks, void* ws, size_t ws_bytes, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
  * gs_render_bwd -- backward of gs_render_fwd.  Re-traverses each pixel's list
  * from `last` down, rebuilding T_i = T_{i+1} / (1 - alpha_i), and forms
  *   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),

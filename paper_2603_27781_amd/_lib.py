@@ -24,8 +24,10 @@ EXPORTS = [
     "gs_default_config", "gs_views_layout", "gs_app_stride", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
     "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
     "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_pose_grad_workspace",
-    "gs_pose_grad", "gs_error_string", "gs_last_hip_error", "gs_version",
+    "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_error_string",
+    "gs_last_hip_error", "gs_version",
 ]
+GS_LOSS_OBS_MASK = 1
 
 
 class GsGaussians(ctypes.Structure):
@@ -50,7 +52,13 @@ class GsConfig(ctypes.Structure):
                 ("persistent", c_int32), ("lds_batch_bwd", c_int32)]
 
 
-assert ctypes.sizeof(GsView) == 88 and ctypes.sizeof(GsConfig) == 40
+class GsSlamLossOpts(ctypes.Structure):
+    _fields_ = [("w_color", c_float), ("w_depth", c_float), ("w_sem", c_float), ("ssim_lambda", c_float),
+                ("tau_obs", c_float), ("tau_unobs", c_float), ("obs_factor", c_float), ("unobs_factor", c_float),
+                ("flags", c_uint32)]
+
+
+assert ctypes.sizeof(GsView) == 88 and ctypes.sizeof(GsConfig) == 40 and ctypes.sizeof(GsSlamLossOpts) == 36
 
 _lib = None
 
@@ -98,6 +106,11 @@ def load() -> ctypes.CDLL:
     L.gs_pose_grad_workspace.argtypes = [c_int32, c_int32, P(c_size_t)]
     L.gs_pose_grad.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
                                c_void_p, c_size_t, c_void_p, c_void_p]
+    L.gs_default_slam_loss_opts.argtypes = [P(GsSlamLossOpts)]
+    L.gs_slam_loss_workspace.argtypes = [P(GsView), c_int32, c_int32, P(c_size_t)]
+    L.gs_slam_loss.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                               P(GsSlamLossOpts), P(GsView), c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_size_t, c_void_p]
     L.gs_error_string.argtypes = [ctypes.c_int]
     L.gs_error_string.restype = ctypes.c_char_p
     L.gs_last_hip_error.restype = ctypes.c_char_p

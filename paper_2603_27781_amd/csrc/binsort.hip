@@ -68,26 +68,6 @@ struct LoadU32 {
     __device__ uint32_t operator()(int64_t i) const { return p[i]; }
 };
 
-// Exclusive scan of the block's NT thread totals (wave scans, then the wave
-// totals in LDS); *total receives the block total.
-template <int NT>
-__device__ uint32_t block_exclusive(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    // wave inclusive scan (DPP; two's-complement adds are the unsigned ones)
-    const uint32_t x = (uint32_t)wave_add_scan((int)v);
-    if (lane == kWave - 1) s_tmp[wave] = x;
-    __syncthreads();
-    uint32_t wbase = 0, tot = 0;
-    for (int w = 0; w < NT / kWave; ++w) {
-        const uint32_t s = s_tmp[w];
-        if (w < wave) wbase += s;
-        tot += s;
-    }
-    __syncthreads();
-    *total = tot;
-    return wbase + x - v;
-}
-
 // Sum of a[0 .. m) by the whole block (all threads get it): used by a block
 // to find its offset from the totals of the tiles before it, so that the
 // large scans need no top-level scan launch and no waiting between blocks.
@@ -333,18 +313,6 @@ __global__ void k_bin_reset(uint64_t* status, int64_t n_status, uint32_t* ticket
 // ----------------------------------------------------------------------------
 // stable LSD radix sort of (u32 key, u32 value), 8-bit digits
 // ----------------------------------------------------------------------------
-// Lanes of the wave holding the same digit (8 ballots, one per digit bit).
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        m &= bit ? bb : ~bb;
-    }
-    return m;
-}
-
 // Key source of a radix pass: the (key, value) arrays of the previous pass.
 // (A source may also skip elements, key() returning false: the histogram
 // and the scatter then leave them out.)

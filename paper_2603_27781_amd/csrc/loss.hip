@@ -14,7 +14,7 @@
 // More classes recompute z in the second pass.  The loss value is reduced
 // per block into a partial-sum array and then summed in a fixed order by
 // one block (no same-address atomics, deterministic).
-#include "sgs_common.h"
+#include "loss_common.h"
 
 namespace sgs {
 
@@ -26,64 +26,6 @@ __global__ void k_transpose_decoder(const float* __restrict__ W, int F, int K, f
     if (i >= F * K) return;
     const int f = i / K, k = i - f * K;
     Wt[k * F + f] = W[i];
-}
-
-template <int F, int KC>
-__device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], const float* __restrict__ Wt, int K,
-                                             int lab, float (&gf)[F > 0 ? F : 1]) {
-    float m = -INFINITY, zl = 0.0f, se = 0.0f;
-    float ga[F > 0 ? F : 1];
-#pragma unroll
-    for (int f = 0; f < F; ++f) ga[f] = 0.0f;
-    if constexpr (KC > 0) {
-        float z[KC];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            if (k < K) {
-                const float* wr = Wt + k * F;
-                float acc = 0.0f;
-#pragma unroll
-                for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
-                z[k] = acc;
-                m = fmaxf(m, acc);
-                zl = k == lab ? acc : zl;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            if (k < K) {
-                const float* wr = Wt + k * F;
-                const float e = __expf(z[k] - m);
-                se += e;
-#pragma unroll
-                for (int f = 0; f < F; ++f) ga[f] = fmaf(wr[f], e, ga[f]);
-            }
-        }
-    } else {
-        for (int k = 0; k < K; ++k) {
-            const float* wr = Wt + k * F;
-            float acc = 0.0f;
-#pragma unroll
-            for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
-            m = fmaxf(m, acc);
-            zl = k == lab ? acc : zl;
-        }
-        for (int k = 0; k < K; ++k) {
-            const float* wr = Wt + k * F;
-            float acc = 0.0f;
-#pragma unroll
-            for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
-            const float e = __expf(acc - m);
-            se += e;
-#pragma unroll
-            for (int f = 0; f < F; ++f) ga[f] = fmaf(wr[f], e, ga[f]);
-        }
-    }
-    const float inv = 1.0f / se;
-    const bool lab_ok = lab >= 0 && lab < K;
-#pragma unroll
-    for (int f = 0; f < F; ++f) gf[f] = ga[f] * inv - (lab_ok ? Wt[lab * F + f] : 0.0f);
-    return (m + __logf(se)) - zl;
 }
 
 template <int F, int KC>

@@ -86,6 +86,39 @@ __device__ __forceinline__ int wave_add_scan(int x) {
     return x;
 }
 
+// Lanes of the wavefront holding the same 8-bit digit as this lane, among
+// the valid lanes (8 ballots, one per digit bit).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+// Exclusive scan of the block's NT thread totals (wave scans, then the wave
+// totals in LDS); *total receives the block total.
+template <int NT>
+__device__ uint32_t block_exclusive(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    // wave inclusive scan (DPP; two's-complement adds are the unsigned ones)
+    const uint32_t x = (uint32_t)wave_add_scan((int)v);
+    if (lane == kWave - 1) s_tmp[wave] = x;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+    for (int w = 0; w < NT / kWave; ++w) {
+        const uint32_t s = s_tmp[w];
+        if (w < wave) wbase += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + x - v;
+}
+
 // Fill kernel (used instead of hipMemsetAsync so that calls stay correct
 // when captured in a HIP graph and replayed).
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count);
@@ -111,6 +144,11 @@ hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_fe
                              int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
                              float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s);
 
+size_t slam_loss_workspace_bytes(int64_t P, const gs_view* views_host, int n_views, bool ssim);
+hipError_t launch_slam_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t,
+                            const int32_t* labels, const float* decoder, int n_classes, const gs_slam_loss_opts& o,
+                            const gs_view* views_host, const gs_view* views_dev, int n_views, int64_t P,
+                            float* grad_out, double* loss, float* median, uint8_t* masks, void* ws, hipStream_t s);
 size_t loss_workspace_bytes(int64_t P);
 hipError_t launch_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t,
                        const int32_t* labels, const float* decoder, int n_classes, const float* weights,

@@ -1,0 +1,602 @@
+// SLAM losses of GS^3LAM with their masks (Sec. 3.3.1, Eq. 11; Sec. 3.3.4,
+// Eq. 15-18; Sec. 3.4, Eq. 21), all on the device and graph-capturable:
+//
+//   1. median depth error per view: the lower median of the binary32
+//      residuals r = |D - D*| over the pixels with D* > 0, found exactly by
+//      a radix select over the residual bits (non-negative floats order as
+//      their bit patterns): four passes of 8 bits, each a histogram of the
+//      digit among the residuals that match the prefix selected so far
+//      (k_median_hist), then one block per view that locates the bucket
+//      holding the wanted rank (k_median_select).  Integer counts only, so
+//      the result is the same every run.
+//   2. one thread per pixel (k_slam_loss): the masks M_obs (Eq. 21) and
+//      M_unobs (Eq. 11) from binary32 tests, then the L1 colour and depth
+//      terms and the semantic cross-entropy, each weighted by M_obs when the
+//      tracking mask is on, with their gradients.
+//   3. with lambda > 0, the SSIM part of Eq. (15)'s colour term: per colour
+//      channel and 32x16 output tile, k_ssim_fwd filters x, y, x^2, y^2 and
+//      xy with the separable 11-tap Gaussian (sigma 1.5) over the tile plus
+//      a 5-pixel apron staged in LDS (zero outside the view), forms SSIM and
+//      its partial derivatives with respect to the three windowed sums that
+//      depend on x, and writes them, scaled, as three maps; k_ssim_bwd
+//      filters the maps again (the window is symmetric, so the adjoint is the
+//      same filter) and adds G*m_mu + 2 x G*m_xx + y G*m_xy to the colour
+//      gradient.
+//   4. a fixed-order sum of the per-block partial losses (deterministic).
+#include "loss_common.h"
+
+namespace sgs {
+
+namespace {
+
+constexpr int kSlamThreads = 256;
+constexpr int kMedItems = 8;  // pixels per thread in a histogram block
+constexpr int kMedChunk = kSlamThreads * kMedItems;
+constexpr int kSsimTX = 32, kSsimTY = 16, kSsimR = 5;  // output tile, window radius
+constexpr int kSsimIX = kSsimTX + 2 * kSsimR, kSsimIY = kSsimTY + 2 * kSsimR;
+constexpr int kSsimRows = kSsimTY / (kSlamThreads / kSsimTX);  // output rows per thread (2)
+
+struct SlamParams {
+    float w0, w1, w2, lam;
+    float tau_obs, tau_unobs, obs_factor, unobs_factor;
+    int use_obs;
+};
+
+struct SsimConst {
+    float g[2 * kSsimR + 1];  // 1-D window; the 2-D window is g[a] g[b]
+    float c1, c2, lam_w0;     // lambda * w_color
+};
+
+// First SSIM tile of each view (tiles of kSsimTX x kSsimTY, row-major per view).
+struct SsimTiles {
+    int first[GS_MAX_VIEWS + 1];
+    int n_views;
+};
+
+__device__ __forceinline__ int view_of_pixel(const gs_view* views, int n_views, int64_t p) {
+    int v = 0;
+    while (v + 1 < n_views && views[v + 1].pixel_offset <= p) ++v;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// 1. median depth error
+// ---------------------------------------------------------------------------
+// sel[4 v + 0..2]: selected prefix, rank still wanted within it, number of
+// valid pixels of the view.
+template <int PASS>
+__global__ void __launch_bounds__(kSlamThreads) k_median_hist(const float* __restrict__ depth,
+                                                              const float* __restrict__ depth_t,
+                                                              const gs_view* __restrict__ views,
+                                                              uint32_t* __restrict__ hist,
+                                                              const uint32_t* __restrict__ sel) {
+    constexpr int shift = 24 - 8 * PASS;
+    __shared__ uint32_t h[256];
+    const int v = blockIdx.y, tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int64_t off = views[v].pixel_offset;
+    const int64_t Pv = (int64_t)views[v].width * views[v].height;
+    const int64_t b0 = (int64_t)blockIdx.x * kMedChunk;
+    if (b0 >= Pv) return;  // uniform over the block
+    uint32_t prefix = 0;
+    if constexpr (PASS > 0) {
+        if (sel[4 * v + 2] == 0) return;  // no valid pixel in the view
+        prefix = sel[4 * v];
+    }
+    h[tid] = 0;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+#pragma unroll
+    for (int k = 0; k < kMedItems; ++k) {
+        const int64_t j = b0 + k * kSlamThreads + tid;
+        bool ok = false;
+        uint32_t d = 0;
+        if (j < Pv) {
+            const float dt = depth_t[off + j];
+            if (dt > 0.0f) {
+                const uint32_t u = __float_as_uint(fabsf(depth[off + j] - dt));
+                if constexpr (PASS == 0) ok = true;
+                else ok = (u >> (shift + 8)) == prefix;
+                d = (u >> shift) & 0xffu;
+            }
+        }
+        // one LDS add per distinct digit of the wavefront (the residuals of
+        // a view mostly share a few top digits)
+        const uint64_t peers = match_digit(d, ok);
+        if (ok && (peers & below) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    if (h[tid] != 0) atomicAdd(&hist[256 * v + tid], h[tid]);
+}
+
+template <int PASS>
+__global__ void __launch_bounds__(256) k_median_select(uint32_t* __restrict__ hist, uint32_t* __restrict__ sel,
+                                                      float* __restrict__ med_ws, float* __restrict__ med_out) {
+    __shared__ uint32_t s_tmp[256 / kWave];
+    const int v = blockIdx.x, tid = threadIdx.x;
+    const uint32_t c = hist[256 * v + tid];
+    hist[256 * v + tid] = 0;  // cleared for the next pass (or the next call)
+    uint32_t total;
+    const uint32_t excl = block_exclusive<256>(c, s_tmp, &total);
+    uint32_t prefix = 0, rank, count;
+    if constexpr (PASS == 0) {
+        count = total;
+        rank = count > 0 ? (count - 1) / 2 : 0;
+    } else {
+        prefix = sel[4 * v];
+        rank = sel[4 * v + 1];
+        count = sel[4 * v + 2];
+    }
+    __syncthreads();  // every thread has read sel before one of them rewrites it
+    const bool mine = count > 0 && excl <= rank && rank < excl + c;  // exactly one thread when count > 0
+    if (mine) {
+        sel[4 * v] = (prefix << 8) | (uint32_t)tid;
+        sel[4 * v + 1] = rank - excl;
+    }
+    if (PASS == 0 && tid == 0) sel[4 * v + 2] = count;
+    if constexpr (PASS == 3) {
+        // the selected residual (whatever its bits), or 0 for a view without
+        // a valid depth
+        if (mine || (count == 0 && tid == 0)) {
+            const float m = mine ? __uint_as_float((prefix << 8) | (uint32_t)tid) : 0.0f;
+            med_ws[v] = m;
+            if (med_out != nullptr) med_out[v] = m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. per-pixel masks, L1 terms and cross-entropy
+// ---------------------------------------------------------------------------
+template <int F, int KC>
+__global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restrict__ out, int64_t P,
+                                                            const float* __restrict__ rgb_t,
+                                                            const float* __restrict__ depth_t,
+                                                            const int32_t* __restrict__ labels,
+                                                            const float* __restrict__ Wt, int K, SlamParams sp,
+                                                            const float* __restrict__ med,
+                                                            const gs_view* __restrict__ views, int n_views,
+                                                            float* __restrict__ grad_out,
+                                                            uint8_t* __restrict__ masks,
+                                                            double* __restrict__ partials) {
+    __shared__ double s_red[3][kSlamThreads / kWave];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + tid;
+    double lc = 0.0, ld = 0.0, ls = 0.0;
+    if (p < P) {
+        const int v = view_of_pixel(views, n_views, p);
+        const float Pv = (float)((int64_t)views[v].width * views[v].height);
+        const float d = out[3 * P + p], dt = depth_t[p], o = out[4 * P + p];
+        // Eq. (21) / Eq. (11), binary32 tests
+        const float r = fabsf(d - dt), m = med[v];
+        const float lim_obs = sp.obs_factor * m, lim_unobs = sp.unobs_factor * m;
+        const bool obs = (o > sp.tau_obs) && (r < lim_obs);
+        const bool unobs = (o < sp.tau_unobs) || ((d > dt) && (r > lim_unobs));
+        masks[p] = (uint8_t)((obs ? 1 : 0) | (unobs ? 2 : 0));
+        const bool on = !sp.use_obs || obs;
+        const float gc = (1.0f - sp.lam) * sp.w0 / (3.0f * Pv), gd = sp.w1 / Pv, gs = sp.w2 / Pv;
+        if (on) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float rc = out[ch * P + p] - rgb_t[ch * P + p];
+                lc += (double)fabsf(rc);
+                grad_out[ch * P + p] = rc > 0.0f ? gc : (rc < 0.0f ? -gc : 0.0f);
+            }
+            const float rd = d - dt;
+            ld += (double)fabsf(rd);
+            grad_out[3 * P + p] = rd > 0.0f ? gd : (rd < 0.0f ? -gd : 0.0f);
+        } else {
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) grad_out[ch * P + p] = 0.0f;
+        }
+        grad_out[4 * P + p] = 0.0f;
+        if (F > 0) {
+            float gf[F > 0 ? F : 1];
+#pragma unroll
+            for (int f = 0; f < F; ++f) gf[f] = 0.0f;
+            if (on && K > 0 && sp.w2 != 0.0f) {
+                float fv[F > 0 ? F : 1];
+#pragma unroll
+                for (int f = 0; f < F; ++f) fv[f] = out[(5 + f) * P + p];
+                ls += (double)semantic_ce<F, KC>(fv, Wt, K, labels[p], gf);
+            }
+#pragma unroll
+            for (int f = 0; f < F; ++f) grad_out[(5 + f) * P + p] = gs * gf[f];
+        }
+        lc *= (double)gc;
+        ld *= (double)sp.w1 / (double)Pv;
+        ls *= (double)sp.w2 / (double)Pv;
+    }
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    for (int dd = kWave / 2; dd > 0; dd >>= 1) {
+        lc += __shfl_xor(lc, dd, kWave);
+        ld += __shfl_xor(ld, dd, kWave);
+        ls += __shfl_xor(ls, dd, kWave);
+    }
+    if (lane == 0) {
+        s_red[0][wave] = lc;
+        s_red[1][wave] = ld;
+        s_red[2][wave] = ls;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double a = 0;
+        for (int w = 0; w < kSlamThreads / kWave; ++w) a += s_red[tid][w];
+        partials[3 * (size_t)blockIdx.x + tid] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. SSIM term
+// ---------------------------------------------------------------------------
+struct TileIdx {
+    int v, x0, y0, W, H;
+};
+__device__ __forceinline__ TileIdx ssim_tile(const SsimTiles& st, const gs_view* views, int t) {
+    int v = 0;
+    while (v + 1 < st.n_views && st.first[v + 1] <= t) ++v;
+    TileIdx ti;
+    ti.v = v;
+    ti.W = views[v].width;
+    ti.H = views[v].height;
+    const int tx = ceil_div(ti.W, kSsimTX);
+    const int lt = t - st.first[v];
+    ti.x0 = (lt % tx) * kSsimTX;
+    ti.y0 = (lt / tx) * kSsimTY;
+    return ti;
+}
+
+// maps: [3 channels][3 maps][P]: m_mu, m_xx, m_xy, each coef * M(p) * the
+// partial derivative of SSIM(p) (coef = -lambda w0 / (3 P_v)).
+__global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restrict__ out,
+                                                           const float* __restrict__ rgb_t, int64_t P,
+                                                           const gs_view* __restrict__ views, SsimTiles st,
+                                                           SsimConst sc, const uint8_t* __restrict__ masks,
+                                                           int use_obs, float* __restrict__ maps,
+                                                           double* __restrict__ partials) {
+    __shared__ float sx[kSsimIY][kSsimIX], sy[kSsimIY][kSsimIX];
+    __shared__ float hs[5][kSsimIY][kSsimTX];
+    __shared__ double s_red[kSlamThreads / kWave];
+    const int tid = threadIdx.x, c = blockIdx.y;
+    const TileIdx ti = ssim_tile(st, views, blockIdx.x);
+    const int64_t base = views[ti.v].pixel_offset;
+    const float* X = out + c * P + base;
+    const float* Y = rgb_t + c * P + base;
+    for (int i = tid; i < kSsimIY * kSsimIX; i += kSlamThreads) {
+        const int r = i / kSsimIX, q = i - r * kSsimIX;
+        const int gy = ti.y0 - kSsimR + r, gx = ti.x0 - kSsimR + q;
+        const bool in = gx >= 0 && gx < ti.W && gy >= 0 && gy < ti.H;
+        const int64_t o = in ? (int64_t)gy * ti.W + gx : 0;
+        sx[r][q] = in ? X[o] : 0.0f;
+        sy[r][q] = in ? Y[o] : 0.0f;
+    }
+    __syncthreads();
+    // horizontal 11-tap sums of x, y, x^2, y^2, xy over every staged row
+    for (int i = tid; i < kSsimIY * kSsimTX; i += kSlamThreads) {
+        const int r = i / kSsimTX, q = i - r * kSsimTX;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+        for (int t = 0; t <= 2 * kSsimR; ++t) {
+            const float xv = sx[r][q + t], yv = sy[r][q + t], w = sc.g[t];
+            const float wx = w * xv, wy = w * yv;
+            a0 += wx;
+            a1 += wy;
+            a2 = fmaf(wx, xv, a2);
+            a3 = fmaf(wy, yv, a3);
+            a4 = fmaf(wx, yv, a4);
+        }
+        hs[0][r][q] = a0;
+        hs[1][r][q] = a1;
+        hs[2][r][q] = a2;
+        hs[3][r][q] = a3;
+        hs[4][r][q] = a4;
+    }
+    __syncthreads();
+    const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimRows;
+    const float coef = -sc.lam_w0 / (3.0f * (float)((int64_t)ti.W * ti.H));
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSsimRows; ++k) {
+        const int r = r0 + k, gx = ti.x0 + q, gy = ti.y0 + r;
+        float mx = 0.f, my = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
+#pragma unroll
+        for (int t = 0; t <= 2 * kSsimR; ++t) {
+            const float w = sc.g[t];
+            mx = fmaf(w, hs[0][r + t][q], mx);
+            my = fmaf(w, hs[1][r + t][q], my);
+            sxx = fmaf(w, hs[2][r + t][q], sxx);
+            syy = fmaf(w, hs[3][r + t][q], syy);
+            sxy = fmaf(w, hs[4][r + t][q], sxy);
+        }
+        if (gx < ti.W && gy < ti.H) {
+            const int64_t p = (int64_t)gy * ti.W + gx;
+            const float vx = sxx - mx * mx, vy = syy - my * my, cxy = sxy - mx * my;
+            const float N1 = 2.0f * mx * my + sc.c1, N2 = 2.0f * cxy + sc.c2;
+            const float D1 = mx * mx + my * my + sc.c1, D2 = vx + vy + sc.c2;
+            const float iD1 = 1.0f / D1, iD2 = 1.0f / D2;
+            const float s = N1 * N2 * iD1 * iD2;
+            const float m = (use_obs && !(masks[base + p] & 1)) ? 0.0f : 1.0f;
+            const float k1 = coef * m;
+            // partials of s with the other two windowed sums fixed
+            const float d_mu = 2.0f * my * (N2 - N1) * iD1 * iD2 + 2.0f * mx * s * (iD2 - iD1);
+            const float d_xx = -s * iD2;
+            const float d_xy = 2.0f * N1 * iD1 * iD2;
+            float* mp = maps + (size_t)(3 * c) * P + base + p;
+            mp[0] = k1 * d_mu;
+            mp[P] = k1 * d_xx;
+            mp[2 * P] = k1 * d_xy;
+            acc += (double)(m * (1.0f - s));
+        }
+    }
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    for (int dd = kWave / 2; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, kWave);
+    if (lane == 0) s_red[wave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0;
+        for (int w = 0; w < kSlamThreads / kWave; ++w) a += s_red[w];
+        partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] =
+            a * (double)sc.lam_w0 / (3.0 * (double)((int64_t)ti.W * ti.H));
+    }
+}
+
+__global__ void __launch_bounds__(kSlamThreads) k_ssim_bwd(const float* __restrict__ out,
+                                                           const float* __restrict__ rgb_t, int64_t P,
+                                                           const gs_view* __restrict__ views, SsimTiles st,
+                                                           SsimConst sc, const float* __restrict__ maps,
+                                                           float* __restrict__ grad_out) {
+    __shared__ float sm[3][kSsimIY][kSsimIX];
+    __shared__ float hs[3][kSsimIY][kSsimTX];
+    const int tid = threadIdx.x, c = blockIdx.y;
+    const TileIdx ti = ssim_tile(st, views, blockIdx.x);
+    const int64_t base = views[ti.v].pixel_offset;
+    const float* M = maps + (size_t)(3 * c) * P + base;
+    for (int i = tid; i < kSsimIY * kSsimIX; i += kSlamThreads) {
+        const int r = i / kSsimIX, q = i - r * kSsimIX;
+        const int gy = ti.y0 - kSsimR + r, gx = ti.x0 - kSsimR + q;
+        const bool in = gx >= 0 && gx < ti.W && gy >= 0 && gy < ti.H;
+        const int64_t o = in ? (int64_t)gy * ti.W + gx : 0;
+        sm[0][r][q] = in ? M[o] : 0.0f;
+        sm[1][r][q] = in ? M[P + o] : 0.0f;
+        sm[2][r][q] = in ? M[2 * P + o] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = tid; i < kSsimIY * kSsimTX; i += kSlamThreads) {
+        const int r = i / kSsimTX, q = i - r * kSsimTX;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+        for (int t = 0; t <= 2 * kSsimR; ++t) {
+            const float w = sc.g[t];
+            a0 = fmaf(w, sm[0][r][q + t], a0);
+            a1 = fmaf(w, sm[1][r][q + t], a1);
+            a2 = fmaf(w, sm[2][r][q + t], a2);
+        }
+        hs[0][r][q] = a0;
+        hs[1][r][q] = a1;
+        hs[2][r][q] = a2;
+    }
+    __syncthreads();
+    const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimRows;
+#pragma unroll
+    for (int k = 0; k < kSsimRows; ++k) {
+        const int r = r0 + k, gx = ti.x0 + q, gy = ti.y0 + r;
+        float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+#pragma unroll
+        for (int t = 0; t <= 2 * kSsimR; ++t) {
+            const float w = sc.g[t];
+            b0 = fmaf(w, hs[0][r + t][q], b0);
+            b1 = fmaf(w, hs[1][r + t][q], b1);
+            b2 = fmaf(w, hs[2][r + t][q], b2);
+        }
+        if (gx < ti.W && gy < ti.H) {
+            const int64_t p = base + (int64_t)gy * ti.W + gx;
+            const float xv = out[c * P + p], yv = rgb_t[c * P + p];
+            grad_out[c * P + p] += b0 + 2.0f * xv * b1 + yv * b2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. fixed-order sum: loss = (colour L1, SSIM, depth, semantic, total)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_slam_loss_final(const double* __restrict__ partials, int nblk,
+                                                          const double* __restrict__ ssim_partials, int nssim,
+                                                          double* __restrict__ loss) {
+    __shared__ double s[4][1024];
+    const int t = threadIdx.x;
+    double a[4] = {0, 0, 0, 0};
+    for (int b = t; b < nblk; b += 1024) {
+        a[0] += partials[3 * (size_t)b];
+        a[2] += partials[3 * (size_t)b + 1];
+        a[3] += partials[3 * (size_t)b + 2];
+    }
+    for (int b = t; b < nssim; b += 1024) a[1] += ssim_partials[b];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k][t] = a[k];
+    __syncthreads();
+    for (int d = 512; d > 0; d >>= 1) {
+        if (t < d)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s[k][t] += s[k][t + d];
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int k = 0; k < 4; ++k) loss[k] = s[k][0];
+        loss[4] = ((s[0][0] + s[1][0]) + s[2][0]) + s[3][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct SlamWs {
+    size_t hist, sel, med, part, spart, wt, mask, maps, total;
+};
+
+int ssim_tiles(const gs_view* views, int n_views, SsimTiles* st) {
+    int t = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (st) st->first[v] = t;
+        t += ceil_div(views[v].width, kSsimTX) * ceil_div(views[v].height, kSsimTY);
+    }
+    if (st) {
+        st->first[n_views] = t;
+        st->n_views = n_views;
+    }
+    return t;
+}
+
+SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim) {
+    SlamWs L;
+    size_t o = 0;
+    L.hist = o;
+    o += align256((size_t)n_views * 256 * 4);
+    L.sel = o;
+    o += align256((size_t)n_views * 4 * 4);
+    L.med = o;
+    o += align256((size_t)n_views * 4);
+    const int64_t nblk = (P + kSlamThreads - 1) / kSlamThreads;
+    L.part = o;
+    o += align256((size_t)nblk * 3 * 8);
+    const int nt = ssim ? ssim_tiles(views, n_views, nullptr) : 0;
+    L.spart = o;
+    o += align256((size_t)nt * 3 * 8);
+    L.wt = o;
+    o += align256((size_t)32 * GS_MAX_CLASSES * 4);
+    L.mask = o;
+    o += align256((size_t)P);
+    L.maps = o;
+    if (ssim) o += align256((size_t)9 * P * 4);
+    L.total = o;
+    return L;
+}
+
+template <int F, int KC>
+void launch_slam_pixels(unsigned nblk, hipStream_t s, const float* out, int64_t P, const float* rgb_t,
+                        const float* depth_t, const int32_t* labels, const float* Wt, int K, const SlamParams& sp,
+                        const float* med, const gs_view* views, int n_views, float* grad_out, uint8_t* masks,
+                        double* partials) {
+    hipLaunchKernelGGL((k_slam_loss<F, KC>), dim3(nblk), dim3(kSlamThreads), 0, s, out, P, rgb_t, depth_t, labels,
+                       Wt, K, sp, med, views, n_views, grad_out, masks, partials);
+}
+
+template <int F>
+hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* depth_t, const int32_t* labels,
+                         const float* decoder, int K, const gs_slam_loss_opts& o, const gs_view* views_host,
+                         const gs_view* views_dev, int n_views, int64_t P, float* grad_out, double* loss,
+                         float* median, uint8_t* masks, char* ws, hipStream_t s) {
+    const bool ssim = o.ssim_lambda != 0.0f;
+    const SlamWs L = slam_layout(P, views_host, n_views, ssim);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+    uint32_t* sel = reinterpret_cast<uint32_t*>(ws + L.sel);
+    float* med = reinterpret_cast<float*>(ws + L.med);
+    double* part = reinterpret_cast<double*>(ws + L.part);
+    double* spart = reinterpret_cast<double*>(ws + L.spart);
+    float* Wt = reinterpret_cast<float*>(ws + L.wt);
+    uint8_t* mk = masks != nullptr ? masks : reinterpret_cast<uint8_t*>(ws + L.mask);
+    float* maps = reinterpret_cast<float*>(ws + L.maps);
+
+    // 1. median depth error per view
+    hipError_t e = fill_u32(hist, 0u, (int64_t)n_views * (256 + 4), s);  // hist and sel are adjacent
+    if (e != hipSuccess) return e;
+    int64_t pmax = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const int64_t pv = (int64_t)views_host[v].width * views_host[v].height;
+        pmax = pv > pmax ? pv : pmax;
+    }
+    const dim3 hg((unsigned)((pmax + kMedChunk - 1) / kMedChunk), (unsigned)n_views);
+    const float* dep = out + 3 * P;
+    hipLaunchKernelGGL(k_median_hist<0>, hg, dim3(kSlamThreads), 0, s, dep, depth_t, views_dev, hist, sel);
+    hipLaunchKernelGGL(k_median_select<0>, dim3(n_views), dim3(256), 0, s, hist, sel, med, median);
+    hipLaunchKernelGGL(k_median_hist<1>, hg, dim3(kSlamThreads), 0, s, dep, depth_t, views_dev, hist, sel);
+    hipLaunchKernelGGL(k_median_select<1>, dim3(n_views), dim3(256), 0, s, hist, sel, med, median);
+    hipLaunchKernelGGL(k_median_hist<2>, hg, dim3(kSlamThreads), 0, s, dep, depth_t, views_dev, hist, sel);
+    hipLaunchKernelGGL(k_median_select<2>, dim3(n_views), dim3(256), 0, s, hist, sel, med, median);
+    hipLaunchKernelGGL(k_median_hist<3>, hg, dim3(kSlamThreads), 0, s, dep, depth_t, views_dev, hist, sel);
+    hipLaunchKernelGGL(k_median_select<3>, dim3(n_views), dim3(256), 0, s, hist, sel, med, median);
+
+    // 2. masks, L1 and cross-entropy
+    SlamParams sp;
+    sp.w0 = o.w_color;
+    sp.w1 = o.w_depth;
+    sp.w2 = o.w_sem;
+    sp.lam = o.ssim_lambda;
+    sp.tau_obs = o.tau_obs;
+    sp.tau_unobs = o.tau_unobs;
+    sp.obs_factor = o.obs_factor;
+    sp.unobs_factor = o.unobs_factor;
+    sp.use_obs = (o.flags & GS_LOSS_OBS_MASK) != 0;
+    const bool sem = F > 0 && K > 0 && sp.w2 != 0.0f;
+    if (sem)
+        hipLaunchKernelGGL(k_transpose_decoder, dim3((unsigned)ceil_div(F * K, 256)), dim3(256), 0, s, decoder, F,
+                           K, Wt);
+    const unsigned nblk = (unsigned)((P + kSlamThreads - 1) / kSlamThreads);
+    const int Ke = sem ? K : 0;
+    if (Ke > 64)
+        launch_slam_pixels<F, 0>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, Ke, sp, med, views_dev, n_views,
+                                 grad_out, mk, part);
+    else if (Ke > 32)
+        launch_slam_pixels<F, 64>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, Ke, sp, med, views_dev, n_views,
+                                  grad_out, mk, part);
+    else
+        launch_slam_pixels<F, 32>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, Ke, sp, med, views_dev, n_views,
+                                  grad_out, mk, part);
+
+    // 3. SSIM
+    int nssim = 0;
+    if (ssim) {
+        SsimTiles st;
+        const int nt = ssim_tiles(views_host, n_views, &st);
+        SsimConst sc;
+        double g[2 * kSsimR + 1], tot = 0.0;
+        for (int t = 0; t <= 2 * kSsimR; ++t) {
+            const double d = t - kSsimR;
+            g[t] = exp(-d * d / (2.0 * 1.5 * 1.5));
+            tot += g[t];
+        }
+        for (int t = 0; t <= 2 * kSsimR; ++t) sc.g[t] = (float)(g[t] / tot);
+        sc.c1 = (float)(0.01 * 0.01);
+        sc.c2 = (float)(0.03 * 0.03);
+        sc.lam_w0 = o.ssim_lambda * o.w_color;
+        if (nt > 0) {
+            hipLaunchKernelGGL(k_ssim_fwd, dim3((unsigned)nt, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev,
+                               st, sc, mk, sp.use_obs, maps, spart);
+            hipLaunchKernelGGL(k_ssim_bwd, dim3((unsigned)nt, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev,
+                               st, sc, maps, grad_out);
+        }
+        nssim = 3 * nt;
+    }
+    // 4. loss terms
+    hipLaunchKernelGGL(k_slam_loss_final, dim3(1), dim3(1024), 0, s, part, (int)nblk, spart, nssim, loss);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t slam_loss_workspace_bytes(int64_t P, const gs_view* views_host, int n_views, bool ssim) {
+    return slam_layout(P, views_host, n_views, ssim).total;
+}
+
+hipError_t launch_slam_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t,
+                            const int32_t* labels, const float* decoder, int n_classes, const gs_slam_loss_opts& o,
+                            const gs_view* views_host, const gs_view* views_dev, int n_views, int64_t P,
+                            float* grad_out, double* loss, float* median, uint8_t* masks, void* ws, hipStream_t s) {
+    char* w = static_cast<char*>(ws);
+    switch (n_feat) {
+        case 0:
+            return launch_slam_t<0>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
+                                    n_views, P, grad_out, loss, median, masks, w, s);
+        case 8:
+            return launch_slam_t<8>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
+                                    n_views, P, grad_out, loss, median, masks, w, s);
+        case 32:
+            return launch_slam_t<32>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
+                                     n_views, P, grad_out, loss, median, masks, w, s);
+        default:
+            return launch_slam_t<16>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
+                                     n_views, P, grad_out, loss, median, masks, w, s);
+    }
+}
+
+}  // namespace sgs

@@ -238,6 +238,41 @@ class Rasterizer:
                                   _stream()), "gs_loss_grad")
         return self.grad_out
 
+    def slam_loss(self, rgb_t, depth_t, labels=None, decoder=None, opts=None,
+                  out: Optional[torch.Tensor] = None, masks: bool = True) -> torch.Tensor:
+        """SLAM losses with masks (gs_slam_loss): writes self.grad_out, the
+        terms (colour L1, SSIM, depth, semantic, total) to self.slam_terms,
+        the per-view median depth error to self.median and, with masks=True,
+        M_obs | M_unobs << 1 per pixel to self.masks.  `opts` is a
+        GsSlamLossOpts (default: gs_default_slam_loss_opts)."""
+        out = self.out if out is None else out
+        L = self.L
+        if opts is None:
+            opts = _lib.GsSlamLossOpts()
+            check(L.gs_default_slam_loss_opts(ctypes.byref(opts)), "gs_default_slam_loss_opts")
+        ssim = 1 if opts.ssim_lambda != 0.0 else 0
+        b = ctypes.c_size_t(0)
+        check(L.gs_slam_loss_workspace(self.views.host, self.views.n, ssim, ctypes.byref(b)),
+              "gs_slam_loss_workspace")
+        if getattr(self, "slam_ws", None) is None or self.slam_ws_bytes < b.value:
+            self.slam_ws = torch.empty(b.value + 256, dtype=torch.uint8, device=self.device)
+            self.slam_ws_bytes = b.value
+        off = (-self.slam_ws.data_ptr()) % 256
+        if getattr(self, "slam_terms", None) is None:
+            dev = dict(device=self.device)
+            self.slam_terms = torch.zeros(5, dtype=torch.float64, **dev)
+            self.median = torch.zeros(self.views.n, dtype=torch.float32, **dev)
+            self.masks = torch.zeros(self.views.total_pixels, dtype=torch.uint8, **dev)
+        K = 0 if decoder is None else int(decoder.shape[1])
+        check(L.gs_slam_loss(out.data_ptr(), self.F, rgb_t.data_ptr(), depth_t.data_ptr(),
+                             labels.data_ptr() if labels is not None else None,
+                             decoder.data_ptr() if decoder is not None else None, K, ctypes.byref(opts),
+                             self.views.host, self.views.dev_ptr(), self.views.n, self.grad_out.data_ptr(),
+                             self.slam_terms.data_ptr(), self.median.data_ptr(),
+                             self.masks.data_ptr() if masks else None, self.slam_ws.data_ptr() + off,
+                             self.slam_ws_bytes, _stream()), "gs_slam_loss")
+        return self.grad_out
+
     def render_bwd(self, g: Gaussians, grad_out: torch.Tensor, flags: int, grads: Optional[Gaussians]) -> None:
         """Backward of the compositing into the 2D gradient buffer and, with
         GS_GRAD_PARAMS, of the projection into `grads` (+=)."""

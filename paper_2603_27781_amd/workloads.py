@@ -303,6 +303,62 @@ def decoder_matrix(rng, F, K) -> np.ndarray:
     return (rng.normal(size=(F, K)) / math.sqrt(F)).astype(np.float32)
 
 
+@dataclasses.dataclass
+class LossImages:
+    """A render and its targets for the image-space losses alone (no scene):
+    out[5+F][P] (colour, depth, opacity, feature planes), rgb_t[3][P],
+    depth_t[P] (0 = no valid depth), labels[P]; views back to back."""
+    out: np.ndarray
+    rgb_t: np.ndarray
+    depth_t: np.ndarray
+    labels: np.ndarray
+    sizes: List[tuple]
+
+
+def loss_images(rng, sizes, F: int, K: int, missing: float = 0.02, front: float = 0.05,
+                behind: float = 0.03) -> LossImages:
+    """Smooth synthetic renders with noisy targets, shaped like a SLAM frame:
+    colour fields of a few random waves in [0, 1] and targets a noisy copy;
+    depth a tilted wavy surface at 1-3.5 m, observed with 1 cm noise, a
+    fraction `front` of pixels observed further away (rendered geometry in
+    front) and `behind` observed nearer (rendered geometry behind), and
+    `missing` with no depth (0); opacity near 1 except a low-opacity blob (a
+    region the map does not cover); features N(0, 1); labels uniform."""
+    outs, rgbs, deps, labs = [], [], [], []
+    for (W, H) in sizes:
+        yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+        col = np.empty((3, H, W))
+        for c in range(3):
+            a = rng.uniform(0.05, 0.4, 2)
+            col[c] = 0.5 + 0.25 * np.sin(a[0] * xx + rng.uniform(0, 6.3)) * np.cos(a[1] * yy + rng.uniform(0, 6.3))
+            col[c] += 0.1 * np.sin(rng.uniform(0.5, 1.5) * (xx + yy))
+        col = np.clip(col, 0.0, 1.0)
+        rgb = np.clip(col + rng.normal(0, 0.05, col.shape), 0.0, 1.0)
+        dep = 1.5 + 0.5 * np.sin(0.07 * xx + rng.uniform(0, 6.3)) + 1.0 * yy / max(H, 1)
+        dt = dep + rng.normal(0, 0.01, dep.shape)
+        u = rng.random(dep.shape)
+        dt = np.where(u < front, dt + rng.uniform(0.3, 1.5, dep.shape), dt)
+        dt = np.where((u >= front) & (u < front + behind), np.maximum(dt - rng.uniform(0.5, 1.0, dep.shape), 0.05),
+                      dt)
+        dt = np.where(rng.random(dep.shape) < missing, 0.0, dt)
+        cx, cy, sg = rng.uniform(0, W), rng.uniform(0, H), 0.1 * max(W, H)
+        op = np.clip(1.02 - 0.8 * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * sg * sg)), 0.0, 1.0)
+        op = op - rng.uniform(0, 0.004, op.shape) * (op > 0.99)
+        o = np.empty((5 + F, H * W))
+        o[:3] = col.reshape(3, -1)
+        o[3] = dep.reshape(-1)
+        o[4] = op.reshape(-1)
+        o[5:] = rng.normal(0, 1, (F, H * W))
+        outs.append(o)
+        rgbs.append(rgb.reshape(3, -1))
+        deps.append(dt.reshape(-1))
+        labs.append(rng.integers(0, max(K, 1), H * W))
+    return LossImages(np.ascontiguousarray(np.concatenate(outs, 1), np.float32),
+                      np.ascontiguousarray(np.concatenate(rgbs, 1), np.float32),
+                      np.ascontiguousarray(np.concatenate(deps), np.float32),
+                      np.ascontiguousarray(np.concatenate(labs), np.int32), list(sizes))
+
+
 # ----------------------------------------------------------------------------
 # the five workloads
 # ----------------------------------------------------------------------------

@@ -116,3 +116,40 @@ def test_validation_rejects_before_any_launch():
                                None) == _lib.GS_EUNSUPPORTED
     assert L.gs_error_string(_lib.GS_ECAPACITY) == b"buffer too small"
     assert L.gs_version() >= 100
+
+
+def test_slam_loss_host_side():
+    """Defaults, workspace sizes and argument checks of gs_slam_loss (host
+    only; every rejected call returns before any launch)."""
+    L = _lib.load()
+    o = _lib.GsSlamLossOpts()
+    assert L.gs_default_slam_loss_opts(ctypes.byref(o)) == 0
+    assert (o.w_color, o.w_depth, o.ssim_lambda, o.obs_factor, o.unobs_factor, o.flags) == \
+        (0.5, 1.0, pytest.approx(0.2), 10.0, 50.0, 0)
+    assert o.w_sem == pytest.approx(0.01) and o.tau_obs == pytest.approx(0.99) and o.tau_unobs == 0.5
+    V = (_lib.GsView * 2)()
+    for i, (w, h) in enumerate([(100, 60), (33, 17)]):
+        V[i].width, V[i].height, V[i].fx, V[i].fy = w, h, 50.0, 50.0
+    L.gs_views_layout(V, 2, 16, None, None)
+    b0, b1 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.gs_slam_loss_workspace(V, 2, 0, ctypes.byref(b0)) == 0
+    assert L.gs_slam_loss_workspace(V, 2, 1, ctypes.byref(b1)) == 0
+    P = 100 * 60 + 33 * 17
+    assert b0.value >= P and b1.value >= b0.value + 9 * 4 * P  # the SSIM maps
+    assert L.gs_slam_loss_workspace(V, 0, 1, ctypes.byref(b1)) == _lib.GS_EINVAL
+    dummy = 1 << 20
+    ws = 1 << 24  # 256-byte aligned
+
+    def call(opts=o, n_feat=16, ws_ptr=ws, ws_bytes=1 << 30, out=dummy, K=20, labels=dummy):
+        return L.gs_slam_loss(out, n_feat, dummy, dummy, labels, dummy, K, ctypes.byref(opts), V, dummy, 2, dummy,
+                              dummy, None, None, ws_ptr, ws_bytes, None)
+
+    assert call(n_feat=12) == _lib.GS_EUNSUPPORTED
+    assert call(out=None) == _lib.GS_EINVAL
+    assert call(labels=None) == _lib.GS_EINVAL
+    assert call(K=10_000) == _lib.GS_EINVAL
+    assert call(ws_ptr=ws + 16) == _lib.GS_EINVAL
+    assert call(ws_bytes=b0.value) == _lib.GS_ECAPACITY  # SSIM on: needs the larger size
+    bad = _lib.GsSlamLossOpts.from_buffer_copy(o)
+    bad.flags = 4
+    assert call(opts=bad) == _lib.GS_EINVAL

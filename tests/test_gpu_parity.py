@@ -203,18 +203,21 @@ def test_loss_grad_class_counts(K):
 
 
 def _loss_case(name, K):
+    """The loss of a synthetic render (seeded; not the GPU's render, so that
+    no oracle input comes from the device) on the case's views."""
     scene, views, r, g, cfg = _render(name, 16)
     F = scene.n_feat
     rng = np.random.default_rng(7)
     P = r.views.total_pixels
-    out32 = r.out.cpu().numpy()
+    li = wl.loss_images(rng, [(v.width, v.height) for v in views], F, K)
+    out32 = li.out
     rgb_t = rng.uniform(0, 1, size=(3, P)).astype(np.float32)
     dep_t = rng.uniform(1, 4, size=P).astype(np.float32)
     lab = rng.integers(0, K, size=P).astype(np.int32)
     W = wl.decoder_matrix(rng, F, K)
     wts = (0.5, 1.0, 0.01)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    r.loss_grad(dev(rgb_t), dev(dep_t), dev(lab), dev(W), wts)
+    r.loss_grad(dev(rgb_t), dev(dep_t), dev(lab), dev(W), wts, out=dev(out32))
     go = r.grad_out.cpu().numpy()
     gref, terms = oracle.loss(out32.astype(np.float64), views, rgb_t, dep_t, lab, W.astype(np.float64), wts)
     assert np.array_equal(np.sign(go[0:4]), np.sign(gref[0:4]))

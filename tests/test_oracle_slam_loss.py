@@ -233,3 +233,27 @@ def test_ssim_term_value():
     s = sum(oracle.ssim_map(out[c].reshape(10, 12), rgb[c].reshape(10, 12)).sum() for c in range(3))
     want = 0.2 * np.float32(0.5) * (3 * 120 - s) / (3 * 120)
     assert t[1] == pytest.approx(want, rel=1e-12)
+
+
+def test_crop_reproduces_full_view_gradient():
+    """The full-size GPU check takes the oracle's gradient at a pixel q from
+    the crop q +- 10 of its view (with the view's median and pixel count):
+    every windowed sum that reaches q lies inside that crop, so the result
+    equals the full view's."""
+    from paper_2603_27781_amd import workloads as wl
+    sz = [(47, 33)]
+    li = wl.loss_images(np.random.default_rng(9), sz, 8, 6)
+    W = wl.decoder_matrix(np.random.default_rng(10), 8, 6).astype(np.float64)
+    o = oracle.SlamLossOpts(use_obs=True)
+    gf, _, mf, med = oracle.slam_loss(li.out, sz, li.rgb_t, li.depth_t, li.labels, W, o)
+    Wv, Hv = sz[0]
+    for q in [(0, 0), (32, 46), (16, 23), (3, 40), (29, 10)]:
+        r0, r1 = max(q[0] - 10, 0), min(q[0] + 11, Hv)
+        c0, c1 = max(q[1] - 10, 0), min(q[1] + 11, Wv)
+        idx = (np.arange(r0, r1)[:, None] * Wv + np.arange(c0, c1)[None, :]).reshape(-1)
+        g, _, m, _ = oracle.slam_loss(li.out[:, idx].astype(np.float64), [(c1 - c0, r1 - r0)], li.rgb_t[:, idx],
+                                      li.depth_t[idx], li.labels[idx], W, o, medians=med, norm_counts=[Wv * Hv])
+        k = (q[0] - r0) * (c1 - c0) + (q[1] - c0)
+        p = q[0] * Wv + q[1]
+        assert m[k] == mf[p]
+        assert np.allclose(g[:, k], gf[:, p], rtol=1e-12, atol=1e-18), q
