@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4]
 from __future__ import annotations
 
 import argparse
+import ctypes
 import dataclasses
 import json
 import os
@@ -114,6 +115,7 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-perview", action="store_true")
+    ap.add_argument("--no-slam", action="store_true", help="skip the SLAM-loss (masks, SSIM) timing")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -293,6 +295,11 @@ def main():
     roofline["step"] = {"bytes_comp": int(comp), "bytes_stream": int(strm),
                         "hbm_frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    # ------------------------------------------------ SLAM losses
+    slam = None
+    if not args.no_slam:
+        slam = slam_loss_bench(r, rgb_t, dep_t, lab, W, args.steps, args.warmup, F, P)
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
@@ -310,9 +317,52 @@ def main():
                    "lds_batch_bwd": cfg.lds_batch_bwd},
         "per_view": per_view, "other_launch_mode": other,
         "entry_us": {k: round(v, 2) for k, v in kern_us.items()},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "slam_loss": slam,
     }
     print(json.dumps(rec), flush=True)
+
+
+def slam_loss_bench(r, rgb_t, dep_t, lab, W, steps, warmup, F, P):
+    """gs_slam_loss on the batch the step just rendered, in its two uses:
+    the mapping loss (L1 + SSIM colour with lambda 0.2, depth, semantic; no
+    mask) and the tracking loss (every term under M_obs, L1 colour).  Time
+    per call from HIP events around `steps` back-to-back calls; algorithmic
+    bytes per call = the render and the targets read once, the gradient and
+    the masks written once."""
+    import torch
+    from paper_2603_27781_amd import _lib
+    L = _lib.load()
+    res = {}
+    for mode in ("mapping", "tracking"):
+        o = _lib.GsSlamLossOpts()
+        L.gs_default_slam_loss_opts(ctypes.byref(o))
+        if mode == "tracking":
+            o.ssim_lambda, o.w_sem, o.flags = 0.0, 0.001, _lib.GS_LOSS_OBS_MASK
+        for _ in range(max(warmup, 1)):
+            r.slam_loss(rgb_t, dep_t, lab, W, o)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            r.slam_loss(rgb_t, dep_t, lab, W, o)
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) / steps * 1e3
+        res[mode] = {"us": round(us, 2), "Mpixel_per_s": round(P / (us * 1e-6) / 1e6, 1),
+                     "terms": [round(x, 6) for x in r.slam_terms.cpu().tolist()]}
+    m = r.masks[:P].cpu().numpy()
+    res["mask_fraction"] = {"obs": round(float(np.mean(m & 1)), 4), "unobs": round(float(np.mean(m >> 1)), 4)}
+    res["median_depth_error"] = [round(x, 6) for x in r.median.cpu().tolist()]
+    alg = P * ((5 + F) * 4 + 3 * 4 + 4 + 4 + (5 + F) * 4 + 1)
+    res["algorithmic_bytes_per_call"] = int(alg)
+    res["roofline"] = {}
+    for mode in ("mapping", "tracking"):
+        gbs = alg / (res[mode]["us"] * 1e-6) / 1e9
+        res["roofline"][mode] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"slam loss: mapping {res['mapping']['us']:.1f} us, tracking {res['tracking']['us']:.1f} us, "
+        f"masks obs {res['mask_fraction']['obs']}, unobs {res['mask_fraction']['unobs']}")
+    return res
 
 
 def cpu_baseline(w, rgb_t, dep_t, lab, W, cfg, budget_s=10.0):

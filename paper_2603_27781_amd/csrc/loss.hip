@@ -28,6 +28,33 @@ __global__ void k_transpose_decoder(const float* __restrict__ W, int F, int K, f
     Wt[k * F + f] = W[i];
 }
 
+__global__ void __launch_bounds__(kSumThreads) k_sum_stage(const double* __restrict__ src, int n, int terms,
+                                                           double* __restrict__ dst) {
+    __shared__ double s[kSumThreads / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    for (int k = 0; k < terms; ++k) {
+        double x[kSumPer];
+#pragma unroll
+        for (int u = 0; u < kSumPer; ++u) {
+            const int i = blockIdx.x * kSumChunk + u * kSumThreads + tid;
+            x[u] = src[(size_t)k * n + (i < n ? i : n - 1)];
+            x[u] = i < n ? x[u] : 0.0;
+        }
+        double a = 0.0;
+#pragma unroll
+        for (int u = 0; u < kSumPer; ++u) a += x[u];
+        for (int d = kWave / 2; d > 0; d >>= 1) a += __shfl_xor(a, d, kWave);
+        if (lane == 0) s[wave] = a;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kSumThreads / kWave; ++w) t += s[w];
+            dst[(size_t)k * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
 template <int F, int KC>
 __global__ void __launch_bounds__(kLossThreads) k_loss(const float* __restrict__ out, int64_t P,
                                                        const float* __restrict__ rgb_t,
@@ -86,47 +113,44 @@ __global__ void __launch_bounds__(kLossThreads) k_loss(const float* __restrict__
     if (tid < 3) {
         double a = 0;
         for (int w = 0; w < (int)(blockDim.x / kWave); ++w) a += s_red[tid][w];
-        partials[3 * (size_t)blockIdx.x + tid] = a;
+        partials[(size_t)tid * gridDim.x + blockIdx.x] = a;  // term-major
     }
 }
 
-// Fixed-order sum of the per-block partials: loss = (colour, depth, semantic,
-// total).  Thread t sums partials t, t + 1024, ... (four independent chains
-// per term), then a fixed tree over the threads.
-__global__ void __launch_bounds__(1024) k_loss_final(const double* __restrict__ partials, int nblk,
-                                                     double* __restrict__ loss) {
-    __shared__ double s[3][1024];
-    const int t = threadIdx.x;
-    double acc[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    int b = t;
-    for (; b + 3 * 1024 < nblk; b += 4 * 1024)
+// Last stage of the fixed-order sum: stage holds the first-stage sums,
+// term-major [3][nst]; loss = (colour, depth, semantic, total).  One block,
+// wavefront shuffles, every sum in a fixed order.
+__global__ void __launch_bounds__(kSumThreads) k_loss_final(const double* __restrict__ stage, int nst,
+                                                            double* __restrict__ loss) {
+    __shared__ double s[3][kSumThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = t; i < nst; i += kSumThreads)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int k = 0; k < 3; ++k) a[k] += stage[(size_t)k * nst + i];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) acc[k][u] += partials[3 * (size_t)(b + u * 1024) + k];
-    for (int u = 0; b < nblk; b += 1024, ++u)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) acc[k][u & 3] += partials[3 * (size_t)b + k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) s[k][t] = (acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3]);
+    for (int k = 0; k < 3; ++k) {
+        for (int d = kWave / 2; d > 0; d >>= 1) a[k] += __shfl_xor(a[k], d, kWave);
+        if (lane == 0) s[k][wave] = a[k];
+    }
     __syncthreads();
-    for (int d = 512; d > 0; d >>= 1) {
-        if (t < d)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) s[k][t] += s[k][t + d];
-        __syncthreads();
-    }
     if (t == 0) {
-        loss[0] = s[0][0];
-        loss[1] = s[1][0];
-        loss[2] = s[2][0];
-        loss[3] = s[0][0] + s[1][0] + s[2][0];
+        double r[3];
+        for (int k = 0; k < 3; ++k) {
+            r[k] = 0.0;
+            for (int w = 0; w < kSumThreads / kWave; ++w) r[k] += s[k][w];
+            loss[k] = r[k];
+        }
+        loss[3] = (r[0] + r[1]) + r[2];
     }
 }
 
-// workspace: per-block partials (3 doubles each), then the transposed decoder
+// workspace: per-block partials (3 doubles each), their first-stage sums,
+// then the transposed decoder
 static size_t loss_partials_bytes(int64_t P) {
-    return ((size_t)((P + kLossThreads - 1) / kLossThreads) * 3 * sizeof(double) + 255) / 256 * 256;
+    const int64_t nblk = (P + kLossThreads - 1) / kLossThreads;
+    return ((size_t)nblk * 3 * sizeof(double) + 255) / 256 * 256 +
+           ((size_t)sum_stage_blocks(nblk) * 3 * sizeof(double) + 255) / 256 * 256;
 }
 size_t loss_workspace_bytes(int64_t P) {
     return loss_partials_bytes(P) + (size_t)32 * GS_MAX_CLASSES * sizeof(float);  // F <= 32
@@ -153,7 +177,10 @@ hipError_t launch_loss_t(const float* out, const float* rgb_t, const float* dept
     else
         hipLaunchKernelGGL((k_loss<F, 32>), dim3((unsigned)nblk), dim3(kLossThreads), 0, s, out, P, rgb_t, depth_t,
                            labels, Wt, K, w[0], w[1], w[2], views, n_views, grad_out, partials);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, s, partials, nblk, loss);
+    double* stage = partials + ((size_t)nblk * 3 * sizeof(double) + 255) / 256 * 256 / sizeof(double);
+    const int nst = sum_stage_blocks(nblk);
+    hipLaunchKernelGGL(k_sum_stage, dim3((unsigned)nst), dim3(kSumThreads), 0, s, partials, nblk, 3, stage);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kSumThreads), 0, s, stage, nst, loss);
     return hipGetLastError();
 }
 

@@ -10,6 +10,15 @@ namespace sgs {
 // a class row is contiguous for the per-pixel kernels.
 __global__ void k_transpose_decoder(const float* __restrict__ W, int F, int K, float* __restrict__ Wt);
 
+// Fixed-order sums of per-block partials, first stage over many workgroups:
+// block b sums elements [b * kSumChunk, (b + 1) * kSumChunk) of each of the
+// `terms` term-major arrays src[term][n] into dst[term][gridDim.x] (the
+// partials are written from every XCD, so one workgroup reading them all
+// would pay many long round trips).
+constexpr int kSumThreads = 256, kSumPer = 16, kSumChunk = kSumThreads * kSumPer;
+__global__ void k_sum_stage(const double* __restrict__ src, int n, int terms, double* __restrict__ dst);
+inline int sum_stage_blocks(int64_t n) { return (int)((n + kSumChunk - 1) / kSumChunk); }
+
 // Cross-entropy of softmax(W^T f) against `lab` for one pixel (the fixed
 // linear decoder standing in for F_cnn, Sec. 3.2.2, Eq. 8) and its gradient
 // gf = dCE/df = sum_k W[.][k] softmax_k - W[.][lab].  With at most KC

@@ -10,18 +10,19 @@
 //      holding the wanted rank (k_median_select).  Integer counts only, so
 //      the result is the same every run.
 //   2. one thread per pixel (k_slam_loss): the masks M_obs (Eq. 21) and
-//      M_unobs (Eq. 11) from binary32 tests, then the L1 colour and depth
-//      terms and the semantic cross-entropy, each weighted by M_obs when the
-//      tracking mask is on, with their gradients.
+//      M_unobs (Eq. 11) from binary32 tests, then the L1
+//      colour and depth terms and the semantic cross-entropy, each weighted
+//      by M_obs when the tracking mask is on, with their gradients.
 //   3. with lambda > 0, the SSIM part of Eq. (15)'s colour term: per colour
-//      channel and 32x16 output tile, k_ssim_fwd filters x, y, x^2, y^2 and
+//      channel and 64x16 output tile, k_ssim_fwd filters x, y, x^2, y^2 and
 //      xy with the separable 11-tap Gaussian (sigma 1.5) over the tile plus
 //      a 5-pixel apron staged in LDS (zero outside the view), forms SSIM and
 //      its partial derivatives with respect to the three windowed sums that
 //      depend on x, and writes them, scaled, as three maps; k_ssim_bwd
 //      filters the maps again (the window is symmetric, so the adjoint is the
 //      same filter) and adds G*m_mu + 2 x G*m_xx + y G*m_xy to the colour
-//      gradient.
+//      gradient.  Both walk the tiles persistently, loading the next tile
+//      while the current one is filtered.
 //   4. a fixed-order sum of the per-block partial losses (deterministic).
 #include "loss_common.h"
 
@@ -30,11 +31,10 @@ namespace sgs {
 namespace {
 
 constexpr int kSlamThreads = 256;
-constexpr int kMedItems = 8;  // pixels per thread in a histogram block
+constexpr int kMedItems = 16;  // pixels per thread in a histogram block
 constexpr int kMedChunk = kSlamThreads * kMedItems;
-constexpr int kSsimTX = 32, kSsimTY = 16, kSsimR = 5;  // output tile, window radius
+constexpr int kSsimTX = 64, kSsimTY = 16, kSsimR = 5;  // output tile, window radius
 constexpr int kSsimIX = kSsimTX + 2 * kSsimR, kSsimIY = kSsimTY + 2 * kSsimR;
-constexpr int kSsimRows = kSsimTY / (kSlamThreads / kSsimTX);  // output rows per thread (2)
 
 struct SlamParams {
     float w0, w1, w2, lam;
@@ -85,20 +85,23 @@ __global__ void __launch_bounds__(kSlamThreads) k_median_hist(const float* __res
     h[tid] = 0;
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    // every load first (index clamped into the view), then the decisions
+    float dtv[kMedItems], dv[kMedItems];
 #pragma unroll
     for (int k = 0; k < kMedItems; ++k) {
         const int64_t j = b0 + k * kSlamThreads + tid;
-        bool ok = false;
-        uint32_t d = 0;
-        if (j < Pv) {
-            const float dt = depth_t[off + j];
-            if (dt > 0.0f) {
-                const uint32_t u = __float_as_uint(fabsf(depth[off + j] - dt));
-                if constexpr (PASS == 0) ok = true;
-                else ok = (u >> (shift + 8)) == prefix;
-                d = (u >> shift) & 0xffu;
-            }
-        }
+        const int64_t jc = j < Pv ? j : Pv - 1;
+        dtv[k] = depth_t[off + jc];
+        dv[k] = depth[off + jc];
+    }
+#pragma unroll
+    for (int k = 0; k < kMedItems; ++k) {
+        const int64_t j = b0 + k * kSlamThreads + tid;
+        const uint32_t u = __float_as_uint(fabsf(dv[k] - dtv[k]));
+        bool ok = j < Pv && dtv[k] > 0.0f;
+        if constexpr (PASS > 0) ok = ok && (u >> (shift + 8)) == prefix;
+        const uint32_t d = (u >> shift) & 0xffu;
+        if (__builtin_amdgcn_ballot_w64(ok) == 0) continue;  // uniform
         // one LDS add per distinct digit of the wavefront (the residuals of
         // a view mostly share a few top digits)
         const uint64_t peers = match_digit(d, ok);
@@ -160,9 +163,10 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
                                                             double* __restrict__ partials) {
     __shared__ double s_red[3][kSlamThreads / kWave];
     const int tid = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + tid;
     double lc = 0.0, ld = 0.0, ls = 0.0;
+    const int64_t p = (int64_t)blockIdx.x * kSlamThreads + tid;
     if (p < P) {
+        double pc = 0.0, pd = 0.0, ps = 0.0;
         const int v = view_of_pixel(views, n_views, p);
         const float Pv = (float)((int64_t)views[v].width * views[v].height);
         const float d = out[3 * P + p], dt = depth_t[p], o = out[4 * P + p];
@@ -178,11 +182,11 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 const float rc = out[ch * P + p] - rgb_t[ch * P + p];
-                lc += (double)fabsf(rc);
+                pc += (double)fabsf(rc);
                 grad_out[ch * P + p] = rc > 0.0f ? gc : (rc < 0.0f ? -gc : 0.0f);
             }
             const float rd = d - dt;
-            ld += (double)fabsf(rd);
+            pd += (double)fabsf(rd);
             grad_out[3 * P + p] = rd > 0.0f ? gd : (rd < 0.0f ? -gd : 0.0f);
         } else {
 #pragma unroll
@@ -197,14 +201,14 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
                 float fv[F > 0 ? F : 1];
 #pragma unroll
                 for (int f = 0; f < F; ++f) fv[f] = out[(5 + f) * P + p];
-                ls += (double)semantic_ce<F, KC>(fv, Wt, K, labels[p], gf);
+                ps += (double)semantic_ce<F, KC>(fv, Wt, K, labels[p], gf);
             }
 #pragma unroll
             for (int f = 0; f < F; ++f) grad_out[(5 + f) * P + p] = gs * gf[f];
         }
-        lc *= (double)gc;
-        ld *= (double)sp.w1 / (double)Pv;
-        ls *= (double)sp.w2 / (double)Pv;
+        lc = pc * (double)gc;
+        ld = pd * ((double)sp.w1 / (double)Pv);
+        ls = ps * ((double)sp.w2 / (double)Pv);
     }
     const int lane = tid & (kWave - 1), wave = tid / kWave;
     for (int dd = kWave / 2; dd > 0; dd >>= 1) {
@@ -221,7 +225,7 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
     if (tid < 3) {
         double a = 0;
         for (int w = 0; w < kSlamThreads / kWave; ++w) a += s_red[tid][w];
-        partials[3 * (size_t)blockIdx.x + tid] = a;
+        partials[(size_t)tid * gridDim.x + blockIdx.x] = a;  // term-major
     }
 }
 
@@ -245,87 +249,200 @@ __device__ __forceinline__ TileIdx ssim_tile(const SsimTiles& st, const gs_view*
     return ti;
 }
 
+// Staged input of one tile: rows of the output tile plus a kSsimR apron
+// above and below, kSsimIX columns (the tile plus the apron left and right)
+// padded to kSsimLD so that every row starts 16-byte aligned.
+constexpr int kSsimLD = (kSsimIX + 3) / 4 * 4;
+// horizontal pass: a thread slides the window over kSsimHX consecutive
+// outputs of one staged row; vertical pass: over kSsimVY rows of one column
+constexpr int kSsimHX = 8;
+constexpr int kSsimVY = kSsimTY / (kSlamThreads / kSsimTX);
+static_assert(kSsimTX % kSsimHX == 0 && kSsimIY * (kSsimTX / kSsimHX) <= kSlamThreads, "one horizontal item per thread");
+static_assert(kSsimHX + 2 * kSsimR <= kSsimLD - kSsimHX * (kSsimTX / kSsimHX - 1), "horizontal window inside the row");
+
+// n consecutive floats of an LDS row from a 16-byte aligned start
+template <int N>
+__device__ __forceinline__ void lds_row(const float* __restrict__ src, float (&v)[N]) {
+    static_assert(N % 4 == 0, "whole float4");
+#pragma unroll
+    for (int k = 0; k < N / 4; ++k) {
+        const float4 a = reinterpret_cast<const float4*>(src)[k];
+        v[4 * k] = a.x;
+        v[4 * k + 1] = a.y;
+        v[4 * k + 2] = a.z;
+        v[4 * k + 3] = a.w;
+    }
+}
+constexpr int kSsimHN = (kSsimHX + 2 * kSsimR + 3) / 4 * 4;  // floats read per horizontal item (18 -> 20)
+
+// Stages rows [y0 - R, y0 + TY + R) x columns [x0 - R, x0 + TX + R) of NP
+// planes into LDS, zero outside the view (and in the row padding).
+// Staging of one tile in two halves: ssim_load issues every global load of
+// the thread into registers (one memory round trip, and in flight while the
+// previous tile is filtered), ssim_store writes them to LDS.
+constexpr int kSsimN = kSsimIY * kSsimLD, kSsimIT = (kSsimN + kSlamThreads - 1) / kSlamThreads;
+template <int NP>
+__device__ __forceinline__ void ssim_load(const float* const (&src)[NP], const TileIdx& ti, float (&v)[kSsimIT][NP]) {
+#pragma unroll
+    for (int it = 0; it < kSsimIT; ++it) {
+        const int i = it * kSlamThreads + threadIdx.x;
+        const int r = i / kSsimLD, q = i - r * kSsimLD;
+        const int gy = ti.y0 - kSsimR + r, gx = ti.x0 - kSsimR + q;
+        const bool in = i < kSsimN && q < kSsimIX && gx >= 0 && gx < ti.W && gy >= 0 && gy < ti.H;
+        const int64_t o = in ? (int64_t)gy * ti.W + gx : 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) v[it][k] = in ? src[k][o] : 0.0f;
+    }
+}
+template <int NP>
+__device__ __forceinline__ void ssim_store(const float (&v)[kSsimIT][NP], float (*dst)[kSsimIY][kSsimLD]) {
+#pragma unroll
+    for (int it = 0; it < kSsimIT; ++it) {
+        const int i = it * kSlamThreads + threadIdx.x;
+        if (i < kSsimN) {
+            const int r = i / kSsimLD, q = i - r * kSsimLD;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) dst[k][r][q] = v[it][k];
+        }
+    }
+}
+
 // maps: [3 channels][3 maps][P]: m_mu, m_xx, m_xy, each coef * M(p) * the
-// partial derivative of SSIM(p) (coef = -lambda w0 / (3 P_v)).
+// partial derivative of SSIM(p) (coef = -lambda w0 / (3 P_v)).  Persistent:
+// block (b, channel) takes tiles b, b + gridDim.x, ... of that channel.
 __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restrict__ out,
                                                            const float* __restrict__ rgb_t, int64_t P,
                                                            const gs_view* __restrict__ views, SsimTiles st,
                                                            SsimConst sc, const uint8_t* __restrict__ masks,
                                                            int use_obs, float* __restrict__ maps,
                                                            double* __restrict__ partials) {
-    __shared__ float sx[kSsimIY][kSsimIX], sy[kSsimIY][kSsimIX];
-    __shared__ float hs[5][kSsimIY][kSsimTX];
+    __shared__ __align__(16) float sxy[2][kSsimIY][kSsimLD];  // x, y
+    __shared__ __align__(16) float hs[5][kSsimIY][kSsimTX];   // horizontal sums of x, y, xx, yy, xy
     __shared__ double s_red[kSlamThreads / kWave];
     const int tid = threadIdx.x, c = blockIdx.y;
-    const TileIdx ti = ssim_tile(st, views, blockIdx.x);
-    const int64_t base = views[ti.v].pixel_offset;
-    const float* X = out + c * P + base;
-    const float* Y = rgb_t + c * P + base;
-    for (int i = tid; i < kSsimIY * kSsimIX; i += kSlamThreads) {
-        const int r = i / kSsimIX, q = i - r * kSsimIX;
-        const int gy = ti.y0 - kSsimR + r, gx = ti.x0 - kSsimR + q;
-        const bool in = gx >= 0 && gx < ti.W && gy >= 0 && gy < ti.H;
-        const int64_t o = in ? (int64_t)gy * ti.W + gx : 0;
-        sx[r][q] = in ? X[o] : 0.0f;
-        sy[r][q] = in ? Y[o] : 0.0f;
-    }
-    __syncthreads();
-    // horizontal 11-tap sums of x, y, x^2, y^2, xy over every staged row
-    for (int i = tid; i < kSsimIY * kSsimTX; i += kSlamThreads) {
-        const int r = i / kSsimTX, q = i - r * kSsimTX;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+    const int ntiles = st.first[st.n_views];
+    double acc = 0.0;  // sum of lambda w0 / (3 P_v) M(p) (1 - s(p)) over this thread's outputs
+    const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimVY;  // vertical-pass outputs of the thread
+    // one tile's global data: staged x, y and M(p) at the thread's outputs
+    // (every load of a tile goes out together: the wait for any of them is
+    // a wait for all, counts being in order)
+    float pre[kSsimIT][2], mkn[kSsimVY];
+    auto load_tile = [&](const TileIdx& tl) {
+        const int64_t b = views[tl.v].pixel_offset;
+        const float* const src[2] = {out + c * P + b, rgb_t + c * P + b};
+        ssim_load<2>(src, tl, pre);
+        const int gx = tl.x0 + q;
 #pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float xv = sx[r][q + t], yv = sy[r][q + t], w = sc.g[t];
-            const float wx = w * xv, wy = w * yv;
-            a0 += wx;
-            a1 += wy;
-            a2 = fmaf(wx, xv, a2);
-            a3 = fmaf(wy, yv, a3);
-            a4 = fmaf(wx, yv, a4);
+        for (int j = 0; j < kSsimVY; ++j) {
+            const int gy = tl.y0 + r0 + j;
+            // the mask plane is always written, so the load is unconditional
+            const bool in = gx < tl.W && gy < tl.H;
+            const uint8_t mb = masks[b + (in ? (int64_t)gy * tl.W + gx : 0)];
+            mkn[j] = (!use_obs || (mb & 1)) ? 1.0f : 0.0f;
         }
-        hs[0][r][q] = a0;
-        hs[1][r][q] = a1;
-        hs[2][r][q] = a2;
-        hs[3][r][q] = a3;
-        hs[4][r][q] = a4;
-    }
-    __syncthreads();
-    const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimRows;
-    const float coef = -sc.lam_w0 / (3.0f * (float)((int64_t)ti.W * ti.H));
-    double acc = 0.0;
+    };
+    int t = blockIdx.x;
+    TileIdx ti = ssim_tile(st, views, t < ntiles ? t : 0);
+    load_tile(ti);
+    for (; t < ntiles; t += gridDim.x) {
+        const int64_t base = views[ti.v].pixel_offset;
+        __syncthreads();  // the previous tile's readers of sxy and hs are done
+        ssim_store<2>(pre, sxy);
+        float mk[kSsimVY];
 #pragma unroll
-    for (int k = 0; k < kSsimRows; ++k) {
-        const int r = r0 + k, gx = ti.x0 + q, gy = ti.y0 + r;
-        float mx = 0.f, my = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
+        for (int j = 0; j < kSsimVY; ++j) mk[j] = mkn[j];
+        __syncthreads();
+        // the next tile's loads fly while this one is filtered
+        const int tn = t + gridDim.x;
+        const TileIdx tin = ssim_tile(st, views, tn < ntiles ? tn : t);
+        if (tn < ntiles) load_tile(tin);
+        // horizontal: item (row r, outputs h0 .. h0 + HX - 1)
+        if (tid < kSsimIY * (kSsimTX / kSsimHX)) {
+            const int r = tid / (kSsimTX / kSsimHX), h0 = (tid - r * (kSsimTX / kSsimHX)) * kSsimHX;
+            float xv[kSsimHN], yv[kSsimHN];
+            lds_row<kSsimHN>(&sxy[0][r][h0], xv);
+            lds_row<kSsimHN>(&sxy[1][r][h0], yv);
+            float a[5][kSsimHX];
 #pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float w = sc.g[t];
-            mx = fmaf(w, hs[0][r + t][q], mx);
-            my = fmaf(w, hs[1][r + t][q], my);
-            sxx = fmaf(w, hs[2][r + t][q], sxx);
-            syy = fmaf(w, hs[3][r + t][q], syy);
-            sxy = fmaf(w, hs[4][r + t][q], sxy);
+            for (int j = 0; j < kSsimHX; ++j)
+#pragma unroll
+                for (int k = 0; k < 5; ++k) a[k][j] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kSsimHX + 2 * kSsimR; ++i) {
+                const float x = xv[i], y = yv[i], xx = x * x, yy = y * y, xy = x * y;
+#pragma unroll
+                for (int j = 0; j < kSsimHX; ++j) {
+                    const int tp = i - j;  // tap of input i for output j
+                    if (tp >= 0 && tp <= 2 * kSsimR) {
+                        const float w = sc.g[tp];
+                        a[0][j] = fmaf(w, x, a[0][j]);
+                        a[1][j] = fmaf(w, y, a[1][j]);
+                        a[2][j] = fmaf(w, xx, a[2][j]);
+                        a[3][j] = fmaf(w, yy, a[3][j]);
+                        a[4][j] = fmaf(w, xy, a[4][j]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int j = 0; j < kSsimHX; j += 4)
+                    *reinterpret_cast<float4*>(&hs[k][r][h0 + j]) =
+                        make_float4(a[k][j], a[k][j + 1], a[k][j + 2], a[k][j + 3]);
         }
-        if (gx < ti.W && gy < ti.H) {
-            const int64_t p = (int64_t)gy * ti.W + gx;
-            const float vx = sxx - mx * mx, vy = syy - my * my, cxy = sxy - mx * my;
-            const float N1 = 2.0f * mx * my + sc.c1, N2 = 2.0f * cxy + sc.c2;
-            const float D1 = mx * mx + my * my + sc.c1, D2 = vx + vy + sc.c2;
-            const float iD1 = 1.0f / D1, iD2 = 1.0f / D2;
-            const float s = N1 * N2 * iD1 * iD2;
-            const float m = (use_obs && !(masks[base + p] & 1)) ? 0.0f : 1.0f;
-            const float k1 = coef * m;
-            // partials of s with the other two windowed sums fixed
-            const float d_mu = 2.0f * my * (N2 - N1) * iD1 * iD2 + 2.0f * mx * s * (iD2 - iD1);
-            const float d_xx = -s * iD2;
-            const float d_xy = 2.0f * N1 * iD1 * iD2;
-            float* mp = maps + (size_t)(3 * c) * P + base + p;
-            mp[0] = k1 * d_mu;
-            mp[P] = k1 * d_xx;
-            mp[2 * P] = k1 * d_xy;
-            acc += (double)(m * (1.0f - s));
+        __syncthreads();
+        // vertical: column q, output rows r0 .. r0 + VY - 1
+        const int gx = ti.x0 + q;
+        float m[5][kSsimVY];
+#pragma unroll
+        for (int j = 0; j < kSsimVY; ++j)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) m[k][j] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kSsimVY + 2 * kSsimR; ++i) {
+            float h[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) h[k] = hs[k][r0 + i][q];
+#pragma unroll
+            for (int j = 0; j < kSsimVY; ++j) {
+                const int tp = i - j;
+                if (tp >= 0 && tp <= 2 * kSsimR) {
+                    const float w = sc.g[tp];
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) m[k][j] = fmaf(w, h[k], m[k][j]);
+                }
+            }
         }
+        const float Pv = (float)((int64_t)ti.W * ti.H);
+        const float coef = -sc.lam_w0 / (3.0f * Pv);
+        float part = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kSsimVY; ++j) {
+            const int gy = ti.y0 + r0 + j;
+            if (gx < ti.W && gy < ti.H) {
+                const int64_t p = (int64_t)gy * ti.W + gx;
+                const float mx = m[0][j], my = m[1][j];
+                const float vx = m[2][j] - mx * mx, vy = m[3][j] - my * my, cxy = m[4][j] - mx * my;
+                const float N1 = 2.0f * mx * my + sc.c1, N2 = 2.0f * cxy + sc.c2;
+                const float D1 = mx * mx + my * my + sc.c1, D2 = vx + vy + sc.c2;
+                // hardware reciprocals: ~1 ulp, far inside the loss tolerance
+                const float iD1 = __builtin_amdgcn_rcpf(D1), iD2 = __builtin_amdgcn_rcpf(D2);
+                const float iD12 = iD1 * iD2;
+                const float s = N1 * N2 * iD12;
+                const float k1 = coef * mk[j];
+                // partials of s with the other two windowed sums fixed
+                const float d_mu = 2.0f * my * (N2 - N1) * iD12 + 2.0f * mx * s * (iD2 - iD1);
+                const float d_xx = -s * iD2;
+                const float d_xy = 2.0f * N1 * iD12;
+                float* mp = maps + (size_t)(3 * c) * P + base + p;
+                mp[0] = k1 * d_mu;
+                mp[P] = k1 * d_xx;
+                mp[2 * P] = k1 * d_xy;
+                part += mk[j] * (1.0f - s);
+            }
+        }
+        acc += (double)part * ((double)sc.lam_w0 / (3.0 * (double)Pv));
+        ti = tin;
     }
     const int lane = tid & (kWave - 1), wave = tid / kWave;
     for (int dd = kWave / 2; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, kWave);
@@ -334,8 +451,7 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restri
     if (tid == 0) {
         double a = 0;
         for (int w = 0; w < kSlamThreads / kWave; ++w) a += s_red[w];
-        partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] =
-            a * (double)sc.lam_w0 / (3.0 * (double)((int64_t)ti.W * ti.H));
+        partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = a;
     }
 }
 
@@ -344,84 +460,135 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_bwd(const float* __restri
                                                            const gs_view* __restrict__ views, SsimTiles st,
                                                            SsimConst sc, const float* __restrict__ maps,
                                                            float* __restrict__ grad_out) {
-    __shared__ float sm[3][kSsimIY][kSsimIX];
-    __shared__ float hs[3][kSsimIY][kSsimTX];
+    __shared__ __align__(16) float sm[3][kSsimIY][kSsimLD];
+    __shared__ __align__(16) float hs[3][kSsimIY][kSsimTX];
     const int tid = threadIdx.x, c = blockIdx.y;
-    const TileIdx ti = ssim_tile(st, views, blockIdx.x);
-    const int64_t base = views[ti.v].pixel_offset;
-    const float* M = maps + (size_t)(3 * c) * P + base;
-    for (int i = tid; i < kSsimIY * kSsimIX; i += kSlamThreads) {
-        const int r = i / kSsimIX, q = i - r * kSsimIX;
-        const int gy = ti.y0 - kSsimR + r, gx = ti.x0 - kSsimR + q;
-        const bool in = gx >= 0 && gx < ti.W && gy >= 0 && gy < ti.H;
-        const int64_t o = in ? (int64_t)gy * ti.W + gx : 0;
-        sm[0][r][q] = in ? M[o] : 0.0f;
-        sm[1][r][q] = in ? M[P + o] : 0.0f;
-        sm[2][r][q] = in ? M[2 * P + o] : 0.0f;
-    }
-    __syncthreads();
-    for (int i = tid; i < kSsimIY * kSsimTX; i += kSlamThreads) {
-        const int r = i / kSsimTX, q = i - r * kSsimTX;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    const int ntiles = st.first[st.n_views];
+    const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimVY;  // vertical-pass outputs of the thread
+    // one tile's global data: the staged maps, and x, y and the gradient so
+    // far at the thread's outputs (loaded together, see k_ssim_fwd)
+    float pre[kSsimIT][3], xn[kSsimVY], yn[kSsimVY], gn[kSsimVY];
+    auto load_tile = [&](const TileIdx& tl) {
+        const int64_t b = views[tl.v].pixel_offset;
+        const float* M = maps + (size_t)(3 * c) * P + b;
+        const float* const src[3] = {M, M + P, M + 2 * P};
+        ssim_load<3>(src, tl, pre);
+        const int gx = tl.x0 + q;
 #pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float w = sc.g[t];
-            a0 = fmaf(w, sm[0][r][q + t], a0);
-            a1 = fmaf(w, sm[1][r][q + t], a1);
-            a2 = fmaf(w, sm[2][r][q + t], a2);
+        for (int j = 0; j < kSsimVY; ++j) {
+            const int gy = tl.y0 + r0 + j;
+            const bool in = gx < tl.W && gy < tl.H;
+            const int64_t p = b + (in ? (int64_t)gy * tl.W + gx : 0);
+            xn[j] = in ? out[c * P + p] : 0.0f;
+            yn[j] = in ? rgb_t[c * P + p] : 0.0f;
+            gn[j] = in ? grad_out[c * P + p] : 0.0f;
         }
-        hs[0][r][q] = a0;
-        hs[1][r][q] = a1;
-        hs[2][r][q] = a2;
-    }
-    __syncthreads();
-    const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimRows;
+    };
+    int t = blockIdx.x;
+    TileIdx ti = ssim_tile(st, views, t < ntiles ? t : 0);
+    load_tile(ti);
+    for (; t < ntiles; t += gridDim.x) {
+        const int64_t base = views[ti.v].pixel_offset;
+        __syncthreads();
+        ssim_store<3>(pre, sm);
+        float xv[kSsimVY], yv[kSsimVY], gv[kSsimVY];
 #pragma unroll
-    for (int k = 0; k < kSsimRows; ++k) {
-        const int r = r0 + k, gx = ti.x0 + q, gy = ti.y0 + r;
-        float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+        for (int j = 0; j < kSsimVY; ++j) {
+            xv[j] = xn[j];
+            yv[j] = yn[j];
+            gv[j] = gn[j];
+        }
+        __syncthreads();
+        const int tn = t + gridDim.x;
+        const TileIdx tin = ssim_tile(st, views, tn < ntiles ? tn : t);
+        if (tn < ntiles) load_tile(tin);
+        if (tid < kSsimIY * (kSsimTX / kSsimHX)) {
+            const int r = tid / (kSsimTX / kSsimHX), h0 = (tid - r * (kSsimTX / kSsimHX)) * kSsimHX;
+            float a[3][kSsimHX];
 #pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float w = sc.g[t];
-            b0 = fmaf(w, hs[0][r + t][q], b0);
-            b1 = fmaf(w, hs[1][r + t][q], b1);
-            b2 = fmaf(w, hs[2][r + t][q], b2);
+            for (int k = 0; k < 3; ++k) {
+                float v[kSsimHN];
+                lds_row<kSsimHN>(&sm[k][r][h0], v);
+#pragma unroll
+                for (int j = 0; j < kSsimHX; ++j) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int tp = 0; tp <= 2 * kSsimR; ++tp) acc = fmaf(sc.g[tp], v[j + tp], acc);
+                    a[k][j] = acc;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < kSsimHX; j += 4)
+                    *reinterpret_cast<float4*>(&hs[k][r][h0 + j]) =
+                        make_float4(a[k][j], a[k][j + 1], a[k][j + 2], a[k][j + 3]);
         }
-        if (gx < ti.W && gy < ti.H) {
-            const int64_t p = base + (int64_t)gy * ti.W + gx;
-            const float xv = out[c * P + p], yv = rgb_t[c * P + p];
-            grad_out[c * P + p] += b0 + 2.0f * xv * b1 + yv * b2;
+        __syncthreads();
+        const int gx = ti.x0 + q;
+        float b[3][kSsimVY];
+#pragma unroll
+        for (int j = 0; j < kSsimVY; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[k][j] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kSsimVY + 2 * kSsimR; ++i) {
+            float h[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) h[k] = hs[k][r0 + i][q];
+#pragma unroll
+            for (int j = 0; j < kSsimVY; ++j) {
+                const int tp = i - j;
+                if (tp >= 0 && tp <= 2 * kSsimR) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) b[k][j] = fmaf(sc.g[tp], h[k], b[k][j]);
+                }
+            }
         }
+#pragma unroll
+        for (int j = 0; j < kSsimVY; ++j) {
+            const int gy = ti.y0 + r0 + j;
+            if (gx < ti.W && gy < ti.H) {
+                const int64_t p = base + (int64_t)gy * ti.W + gx;
+                grad_out[c * P + p] = gv[j] + (b[0][j] + 2.0f * xv[j] * b[1][j] + yv[j] * b[2][j]);
+            }
+        }
+        ti = tin;
     }
 }
 
 // ---------------------------------------------------------------------------
 // 4. fixed-order sum: loss = (colour L1, SSIM, depth, semantic, total)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_slam_loss_final(const double* __restrict__ partials, int nblk,
-                                                          const double* __restrict__ ssim_partials, int nssim,
-                                                          double* __restrict__ loss) {
-    __shared__ double s[4][1024];
-    const int t = threadIdx.x;
-    double a[4] = {0, 0, 0, 0};
-    for (int b = t; b < nblk; b += 1024) {
-        a[0] += partials[3 * (size_t)b];
-        a[2] += partials[3 * (size_t)b + 1];
-        a[3] += partials[3 * (size_t)b + 2];
+// stage: the first-stage sums of the pixel kernel's (colour, depth,
+// semantic) partials, term-major [3][nst]; ssim: the SSIM kernel's per-block
+// partials.  One block; every sum in a fixed order.
+__global__ void __launch_bounds__(kSumThreads) k_slam_loss_final(const double* __restrict__ stage, int nst,
+                                                                 const double* __restrict__ ssim, int nssim,
+                                                                 double* __restrict__ loss) {
+    __shared__ double s[4][kSumThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = t; i < nst; i += kSumThreads) {
+        a[0] += stage[i];
+        a[2] += stage[nst + i];
+        a[3] += stage[2 * (size_t)nst + i];
     }
-    for (int b = t; b < nssim; b += 1024) a[1] += ssim_partials[b];
+    for (int i = t; i < nssim; i += kSumThreads) a[1] += ssim[i];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s[k][t] = a[k];
+    for (int k = 0; k < 4; ++k) {
+        for (int d = kWave / 2; d > 0; d >>= 1) a[k] += __shfl_xor(a[k], d, kWave);
+        if (lane == 0) s[k][wave] = a[k];
+    }
     __syncthreads();
-    for (int d = 512; d > 0; d >>= 1) {
-        if (t < d)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s[k][t] += s[k][t + d];
-        __syncthreads();
-    }
     if (t == 0) {
-        for (int k = 0; k < 4; ++k) loss[k] = s[k][0];
-        loss[4] = ((s[0][0] + s[1][0]) + s[2][0]) + s[3][0];
+        double r[4];
+        for (int k = 0; k < 4; ++k) {
+            r[k] = 0.0;
+            for (int w = 0; w < kSumThreads / kWave; ++w) r[k] += s[k][w];
+            loss[k] = r[k];
+        }
+        loss[4] = ((r[0] + r[1]) + r[2]) + r[3];
     }
 }
 
@@ -430,8 +597,11 @@ __global__ void __launch_bounds__(1024) k_slam_loss_final(const double* __restri
 // ---------------------------------------------------------------------------
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// Pixel-kernel grid: one thread per pixel.
+unsigned slam_blocks(int64_t P) { return (unsigned)((P + kSlamThreads - 1) / kSlamThreads); }
+
 struct SlamWs {
-    size_t hist, sel, med, part, spart, wt, mask, maps, total;
+    size_t hist, sel, med, part, spart, stage, wt, mask, maps, total;
 };
 
 int ssim_tiles(const gs_view* views, int n_views, SsimTiles* st) {
@@ -456,12 +626,14 @@ SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim) {
     o += align256((size_t)n_views * 4 * 4);
     L.med = o;
     o += align256((size_t)n_views * 4);
-    const int64_t nblk = (P + kSlamThreads - 1) / kSlamThreads;
+    const int64_t nblk = slam_blocks(P);
     L.part = o;
     o += align256((size_t)nblk * 3 * 8);
     const int nt = ssim ? ssim_tiles(views, n_views, nullptr) : 0;
     L.spart = o;
     o += align256((size_t)nt * 3 * 8);
+    L.stage = o;
+    o += align256((size_t)sum_stage_blocks(nblk) * 3 * 8);
     L.wt = o;
     o += align256((size_t)32 * GS_MAX_CLASSES * 4);
     L.mask = o;
@@ -470,6 +642,20 @@ SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim) {
     if (ssim) o += align256((size_t)9 * P * 4);
     L.total = o;
     return L;
+}
+
+// Blocks per channel of a persistent SSIM launch: the resident blocks of the
+// device split over the three channels, at most one per tile.
+unsigned ssim_grid(const void* kern, int ntiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kSlamThreads, 0);
+    if (cus < 1) cus = 1;
+    if (per_cu < 1) per_cu = 1;
+    int g = (cus * per_cu + 2) / 3;
+    if (g > ntiles) g = ntiles;
+    return (unsigned)(g > 0 ? g : 1);
 }
 
 template <int F, int KC>
@@ -531,7 +717,7 @@ hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* dept
     if (sem)
         hipLaunchKernelGGL(k_transpose_decoder, dim3((unsigned)ceil_div(F * K, 256)), dim3(256), 0, s, decoder, F,
                            K, Wt);
-    const unsigned nblk = (unsigned)((P + kSlamThreads - 1) / kSlamThreads);
+    const unsigned nblk = slam_blocks(P);
     const int Ke = sem ? K : 0;
     if (Ke > 64)
         launch_slam_pixels<F, 0>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, Ke, sp, med, views_dev, n_views,
@@ -559,16 +745,23 @@ hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* dept
         sc.c1 = (float)(0.01 * 0.01);
         sc.c2 = (float)(0.03 * 0.03);
         sc.lam_w0 = o.ssim_lambda * o.w_color;
+        // persistent grids: as many blocks per channel as fit on the device
+        // at once (a third of the resident blocks each), each walking tiles
+        const unsigned gf = ssim_grid(reinterpret_cast<const void*>(&k_ssim_fwd), nt);
+        const unsigned gb = ssim_grid(reinterpret_cast<const void*>(&k_ssim_bwd), nt);
         if (nt > 0) {
-            hipLaunchKernelGGL(k_ssim_fwd, dim3((unsigned)nt, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev,
-                               st, sc, mk, sp.use_obs, maps, spart);
-            hipLaunchKernelGGL(k_ssim_bwd, dim3((unsigned)nt, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev,
-                               st, sc, maps, grad_out);
+            hipLaunchKernelGGL(k_ssim_fwd, dim3(gf, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev, st, sc, mk,
+                               sp.use_obs, maps, spart);
+            hipLaunchKernelGGL(k_ssim_bwd, dim3(gb, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev, st, sc,
+                               maps, grad_out);
         }
-        nssim = 3 * nt;
+        nssim = nt > 0 ? 3 * (int)gf : 0;
     }
-    // 4. loss terms
-    hipLaunchKernelGGL(k_slam_loss_final, dim3(1), dim3(1024), 0, s, part, (int)nblk, spart, nssim, loss);
+    // 4. loss terms: the per-block partials summed in two fixed-order stages
+    double* stage = reinterpret_cast<double*>(ws + L.stage);
+    const int nst = sum_stage_blocks(nblk);
+    hipLaunchKernelGGL(k_sum_stage, dim3((unsigned)nst), dim3(kSumThreads), 0, s, part, (int)nblk, 3, stage);
+    hipLaunchKernelGGL(k_slam_loss_final, dim3(1), dim3(kSumThreads), 0, s, stage, nst, spart, nssim, loss);
     return hipGetLastError();
 }
 
