@@ -277,6 +277,30 @@ constexpr int kSsimHN = (kSsimHX + 2 * kSsimR + 3) / 4 * 4;  // floats read per 
 
 // Stages rows [y0 - R, y0 + TY + R) x columns [x0 - R, x0 + TX + R) of NP
 // planes into LDS, zero outside the view (and in the row padding).
+// Work items of the persistent SSIM kernels: (channel, tile) pairs, item =
+// c * ntiles + t.  With a grid of 8k workgroups, XCD x (the workgroups whose
+// linear id is x mod 8: the dispatcher places them round-robin) takes the
+// x-th of eight contiguous chunks of items and its k workgroups stride
+// through it, so the tiles in flight on one XCD are neighbours and share
+// their aprons (and row-end cache lines) in its L2.  Other grid sizes stride
+// over all items.
+struct ItemWalk {
+    int first, stride, end;
+    __device__ explicit ItemWalk(int nitems) {
+        const int G = gridDim.x, b = blockIdx.x;
+        if (G >= 8 && (G & 7) == 0) {
+            const int chunk = (nitems + 7) / 8, x = b & 7;
+            first = x * chunk + (b >> 3);
+            stride = G >> 3;
+            end = min((x + 1) * chunk, nitems);
+        } else {
+            first = b;
+            stride = G;
+            end = nitems;
+        }
+    }
+};
+
 // Staging of one tile in two halves: ssim_load issues every global load of
 // the thread into registers (one memory round trip, and in flight while the
 // previous tile is filtered), ssim_store writes them to LDS.
@@ -309,7 +333,7 @@ __device__ __forceinline__ void ssim_store(const float (&v)[kSsimIT][NP], float 
 
 // maps: [3 channels][3 maps][P]: m_mu, m_xx, m_xy, each coef * M(p) * the
 // partial derivative of SSIM(p) (coef = -lambda w0 / (3 P_v)).  Persistent:
-// block (b, channel) takes tiles b, b + gridDim.x, ... of that channel.
+// each workgroup walks (channel, tile) items (ItemWalk).
 __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restrict__ out,
                                                            const float* __restrict__ rgb_t, int64_t P,
                                                            const gs_view* __restrict__ views, SsimTiles st,
@@ -319,17 +343,18 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restri
     __shared__ __align__(16) float sxy[2][kSsimIY][kSsimLD];  // x, y
     __shared__ __align__(16) float hs[5][kSsimIY][kSsimTX];   // horizontal sums of x, y, xx, yy, xy
     __shared__ double s_red[kSlamThreads / kWave];
-    const int tid = threadIdx.x, c = blockIdx.y;
+    const int tid = threadIdx.x;
     const int ntiles = st.first[st.n_views];
+    const ItemWalk iw(3 * ntiles);
     double acc = 0.0;  // sum of lambda w0 / (3 P_v) M(p) (1 - s(p)) over this thread's outputs
     const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimVY;  // vertical-pass outputs of the thread
     // one tile's global data: staged x, y and M(p) at the thread's outputs
     // (every load of a tile goes out together: the wait for any of them is
     // a wait for all, counts being in order)
     float pre[kSsimIT][2], mkn[kSsimVY];
-    auto load_tile = [&](const TileIdx& tl) {
+    auto load_tile = [&](const TileIdx& tl, int ch) {
         const int64_t b = views[tl.v].pixel_offset;
-        const float* const src[2] = {out + c * P + b, rgb_t + c * P + b};
+        const float* const src[2] = {out + ch * P + b, rgb_t + ch * P + b};
         ssim_load<2>(src, tl, pre);
         const int gx = tl.x0 + q;
 #pragma unroll
@@ -341,10 +366,11 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restri
             mkn[j] = (!use_obs || (mb & 1)) ? 1.0f : 0.0f;
         }
     };
-    int t = blockIdx.x;
-    TileIdx ti = ssim_tile(st, views, t < ntiles ? t : 0);
-    load_tile(ti);
-    for (; t < ntiles; t += gridDim.x) {
+    int it = iw.first;
+    int c = it < iw.end ? it / ntiles : 0;
+    TileIdx ti = ssim_tile(st, views, it < iw.end ? it - c * ntiles : 0);
+    if (it < iw.end) load_tile(ti, c);
+    for (; it < iw.end; it += iw.stride) {
         const int64_t base = views[ti.v].pixel_offset;
         __syncthreads();  // the previous tile's readers of sxy and hs are done
         ssim_store<2>(pre, sxy);
@@ -352,10 +378,11 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restri
 #pragma unroll
         for (int j = 0; j < kSsimVY; ++j) mk[j] = mkn[j];
         __syncthreads();
-        // the next tile's loads fly while this one is filtered
-        const int tn = t + gridDim.x;
-        const TileIdx tin = ssim_tile(st, views, tn < ntiles ? tn : t);
-        if (tn < ntiles) load_tile(tin);
+        // the next item's loads fly while this one is filtered
+        const int itn = it + iw.stride;
+        const int cn = itn < iw.end ? itn / ntiles : c;
+        const TileIdx tin = ssim_tile(st, views, itn < iw.end ? itn - cn * ntiles : 0);
+        if (itn < iw.end) load_tile(tin, cn);
         // horizontal: item (row r, outputs h0 .. h0 + HX - 1)
         if (tid < kSsimIY * (kSsimTX / kSsimHX)) {
             const int r = tid / (kSsimTX / kSsimHX), h0 = (tid - r * (kSsimTX / kSsimHX)) * kSsimHX;
@@ -443,6 +470,7 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restri
         }
         acc += (double)part * ((double)sc.lam_w0 / (3.0 * (double)Pv));
         ti = tin;
+        c = cn;
     }
     const int lane = tid & (kWave - 1), wave = tid / kWave;
     for (int dd = kWave / 2; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, kWave);
@@ -451,7 +479,7 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_fwd(const float* __restri
     if (tid == 0) {
         double a = 0;
         for (int w = 0; w < kSlamThreads / kWave; ++w) a += s_red[w];
-        partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = a;
+        partials[blockIdx.x] = a;
     }
 }
 
@@ -462,15 +490,16 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_bwd(const float* __restri
                                                            float* __restrict__ grad_out) {
     __shared__ __align__(16) float sm[3][kSsimIY][kSsimLD];
     __shared__ __align__(16) float hs[3][kSsimIY][kSsimTX];
-    const int tid = threadIdx.x, c = blockIdx.y;
+    const int tid = threadIdx.x;
     const int ntiles = st.first[st.n_views];
+    const ItemWalk iw(3 * ntiles);
     const int q = tid % kSsimTX, r0 = (tid / kSsimTX) * kSsimVY;  // vertical-pass outputs of the thread
     // one tile's global data: the staged maps, and x, y and the gradient so
     // far at the thread's outputs (loaded together, see k_ssim_fwd)
     float pre[kSsimIT][3], xn[kSsimVY], yn[kSsimVY], gn[kSsimVY];
-    auto load_tile = [&](const TileIdx& tl) {
+    auto load_tile = [&](const TileIdx& tl, int ch) {
         const int64_t b = views[tl.v].pixel_offset;
-        const float* M = maps + (size_t)(3 * c) * P + b;
+        const float* M = maps + (size_t)(3 * ch) * P + b;
         const float* const src[3] = {M, M + P, M + 2 * P};
         ssim_load<3>(src, tl, pre);
         const int gx = tl.x0 + q;
@@ -479,15 +508,16 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_bwd(const float* __restri
             const int gy = tl.y0 + r0 + j;
             const bool in = gx < tl.W && gy < tl.H;
             const int64_t p = b + (in ? (int64_t)gy * tl.W + gx : 0);
-            xn[j] = in ? out[c * P + p] : 0.0f;
-            yn[j] = in ? rgb_t[c * P + p] : 0.0f;
-            gn[j] = in ? grad_out[c * P + p] : 0.0f;
+            xn[j] = in ? out[ch * P + p] : 0.0f;
+            yn[j] = in ? rgb_t[ch * P + p] : 0.0f;
+            gn[j] = in ? grad_out[ch * P + p] : 0.0f;
         }
     };
-    int t = blockIdx.x;
-    TileIdx ti = ssim_tile(st, views, t < ntiles ? t : 0);
-    load_tile(ti);
-    for (; t < ntiles; t += gridDim.x) {
+    int it = iw.first;
+    int c = it < iw.end ? it / ntiles : 0;
+    TileIdx ti = ssim_tile(st, views, it < iw.end ? it - c * ntiles : 0);
+    if (it < iw.end) load_tile(ti, c);
+    for (; it < iw.end; it += iw.stride) {
         const int64_t base = views[ti.v].pixel_offset;
         __syncthreads();
         ssim_store<3>(pre, sm);
@@ -499,9 +529,10 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_bwd(const float* __restri
             gv[j] = gn[j];
         }
         __syncthreads();
-        const int tn = t + gridDim.x;
-        const TileIdx tin = ssim_tile(st, views, tn < ntiles ? tn : t);
-        if (tn < ntiles) load_tile(tin);
+        const int itn = it + iw.stride;
+        const int cn = itn < iw.end ? itn / ntiles : c;
+        const TileIdx tin = ssim_tile(st, views, itn < iw.end ? itn - cn * ntiles : 0);
+        if (itn < iw.end) load_tile(tin, cn);
         if (tid < kSsimIY * (kSsimTX / kSsimHX)) {
             const int r = tid / (kSsimTX / kSsimHX), h0 = (tid - r * (kSsimTX / kSsimHX)) * kSsimHX;
             float a[3][kSsimHX];
@@ -554,6 +585,7 @@ __global__ void __launch_bounds__(kSlamThreads) k_ssim_bwd(const float* __restri
             }
         }
         ti = tin;
+        c = cn;
     }
 }
 
@@ -631,7 +663,7 @@ SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim) {
     o += align256((size_t)nblk * 3 * 8);
     const int nt = ssim ? ssim_tiles(views, n_views, nullptr) : 0;
     L.spart = o;
-    o += align256((size_t)nt * 3 * 8);
+    o += align256((size_t)(3 * nt + 8) * 8);  // one partial per SSIM workgroup (at most 3 nt rounded up to 8)
     L.stage = o;
     o += align256((size_t)sum_stage_blocks(nblk) * 3 * 8);
     L.wt = o;
@@ -644,18 +676,20 @@ SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim) {
     return L;
 }
 
-// Blocks per channel of a persistent SSIM launch: the resident blocks of the
-// device split over the three channels, at most one per tile.
-unsigned ssim_grid(const void* kern, int ntiles) {
+// Workgroups of a persistent SSIM launch: as many as are resident on the
+// device at once, rounded down to a multiple of the 8 XCDs (ItemWalk), at
+// least 8, at most the items rounded up to 8.
+unsigned ssim_grid(const void* kern, int nitems) {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kSlamThreads, 0);
     if (cus < 1) cus = 1;
     if (per_cu < 1) per_cu = 1;
-    int g = (cus * per_cu + 2) / 3;
-    if (g > ntiles) g = ntiles;
-    return (unsigned)(g > 0 ? g : 1);
+    int g = cus * per_cu / 8 * 8;
+    const int cap = (nitems + 7) / 8 * 8;
+    if (g > cap) g = cap;
+    return (unsigned)(g >= 8 ? g : 8);
 }
 
 template <int F, int KC>
@@ -745,17 +779,16 @@ hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* dept
         sc.c1 = (float)(0.01 * 0.01);
         sc.c2 = (float)(0.03 * 0.03);
         sc.lam_w0 = o.ssim_lambda * o.w_color;
-        // persistent grids: as many blocks per channel as fit on the device
-        // at once (a third of the resident blocks each), each walking tiles
-        const unsigned gf = ssim_grid(reinterpret_cast<const void*>(&k_ssim_fwd), nt);
-        const unsigned gb = ssim_grid(reinterpret_cast<const void*>(&k_ssim_bwd), nt);
+        // persistent grids walking the (channel, tile) items
+        const unsigned gf = ssim_grid(reinterpret_cast<const void*>(&k_ssim_fwd), 3 * nt);
+        const unsigned gb = ssim_grid(reinterpret_cast<const void*>(&k_ssim_bwd), 3 * nt);
         if (nt > 0) {
-            hipLaunchKernelGGL(k_ssim_fwd, dim3(gf, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev, st, sc, mk,
+            hipLaunchKernelGGL(k_ssim_fwd, dim3(gf), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev, st, sc, mk,
                                sp.use_obs, maps, spart);
-            hipLaunchKernelGGL(k_ssim_bwd, dim3(gb, 3), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev, st, sc,
-                               maps, grad_out);
+            hipLaunchKernelGGL(k_ssim_bwd, dim3(gb), dim3(kSlamThreads), 0, s, out, rgb_t, P, views_dev, st, sc, maps,
+                               grad_out);
         }
-        nssim = nt > 0 ? 3 * (int)gf : 0;
+        nssim = nt > 0 ? (int)gf : 0;
     }
     // 4. loss terms: the per-block partials summed in two fixed-order stages
     double* stage = reinterpret_cast<double*>(ws + L.stage);
