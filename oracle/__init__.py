@@ -238,12 +238,14 @@ class SlamLossOpts:
     obs_factor: float = 10.0
     unobs_factor: float = 50.0
     use_obs: bool = False
+    bce: bool = False  # semantic term: BCE on softmax (Eq. 16) instead of CE
 
     def array(self) -> np.ndarray:
         # every value as the binary32 the device receives, upcast exactly
         v = [self.w_color, self.w_depth, self.w_sem, self.ssim_lambda, self.tau_obs, self.tau_unobs,
              self.obs_factor, self.unobs_factor]
-        return np.array([float(np.float32(x)) for x in v] + [1.0 if self.use_obs else 0.0], np.float64)
+        return np.array([float(np.float32(x)) for x in v] + [1.0 if self.use_obs else 0.0,
+                                                              1.0 if self.bce else 0.0], np.float64)
 
 
 def depth_median(depth, depth_t) -> np.float32:
@@ -264,13 +266,15 @@ def ssim_map(x, y) -> np.ndarray:
 
 
 def slam_loss(out, wh, rgb_t, depth_t, labels=None, decoder=None, opts: SlamLossOpts = SlamLossOpts(),
-              medians=None, norm_counts=None):
+              medians=None, norm_counts=None, bias=None, decoder_grads=False):
     """SLAM loss (Eq. 15 / 18 / 21) of views of sizes wh = [(W, H), ...].
 
     Returns (grad_out [5+F][P] FP64, terms[5] = colour L1, SSIM, depth,
     semantic, total; masks uint8 [P] = M_obs | M_unobs << 1; medians float32
-    [V]).  `medians` (float32 [V]) replaces the computed median depth errors
-    and `norm_counts` the P_v of each view's means (crops of larger views)."""
+    [V]), and with decoder_grads=True also (dL/dW [F][K], dL/db [K]).
+    `medians` (float32 [V]) replaces the computed median depth errors and
+    `norm_counts` the P_v of each view's means (crops of larger views);
+    `bias` [K] is the decoder's bias (z = W^T f + b)."""
     L = lib()
     out = np.ascontiguousarray(out, np.float64)
     F = out.shape[0] - 5
@@ -291,9 +295,15 @@ def slam_loss(out, wh, rgb_t, depth_t, labels=None, decoder=None, opts: SlamLoss
     o = opts.array()
     if K == 0:
         o[2] = 0.0
-    L.orc_slam_loss(ctypes.c_int(F), ctypes.c_int(K), ctypes.c_int(V), _p(whs), _p(nc), _p(out),
-                    _p(np.ascontiguousarray(rgb_t, np.float64)), _p(np.ascontiguousarray(depth_t, np.float64)),
-                    _p(lab), _p(Wd), _p(o), _p(med_in), _p(med_out), _p(masks), _p(g), _p(terms))
+    bz = None if bias is None else np.ascontiguousarray(bias, np.float64)
+    gW = np.zeros((max(F, 1), max(K, 1)))
+    gb = np.zeros(max(K, 1))
+    L.orc_slam_loss2(ctypes.c_int(F), ctypes.c_int(K), ctypes.c_int(V), _p(whs), _p(nc), _p(out),
+                     _p(np.ascontiguousarray(rgb_t, np.float64)), _p(np.ascontiguousarray(depth_t, np.float64)),
+                     _p(lab), _p(Wd), _p(bz), _p(o), _p(med_in), _p(med_out), _p(masks), _p(g), _p(terms), _p(gW),
+                     _p(gb))
+    if decoder_grads:
+        return g, terms, masks, med_out, gW[:F, :K], gb[:K]
     return g, terms, masks, med_out
 
 

@@ -1102,10 +1102,64 @@ static double ssim_channel(int W, int H, const double* x, const double* y, const
  *   semantic   w2 / P_v sum_p M(p) CE(softmax(W^T F), label)
  * terms[5] = (colour L1, SSIM, depth, semantic, total) summed over views;
  * masks[p] = M_obs | M_unobs << 1; grad_out [5+F][P] (opacity channel 0). */
+void orc_slam_loss2(int F, int K, int V, const int32_t* wh, const int64_t* norm_count, const double* out,
+                    const double* rgb_t, const double* depth_t, const int32_t* labels, const double* Wd,
+                    const double* bias, const double* opts, const float* med_in, float* med_out, uint8_t* masks,
+                    double* grad_out, double* terms, double* gW, double* gb);
+
+/* Semantic term of one pixel through the decoder z = W^T f + b (a 1x1
+ * convolution standing in for F_cnn, Eq. 8) and its gradient with respect
+ * to the logits, dz[K]:
+ *   CE  (bce = 0): -log softmax(z)[lab]
+ *   BCE (bce = 1, Eq. 16): -sum_k [y_k log p_k + (1 - y_k) log(1 - p_k)],
+ *       p = softmax(z), y the one-hot label, each log clamped at -100 (a
+ *       clamped log contributes no gradient). */
+static double sem_term(int F, int K, const double* f, const double* Wd, const double* bias, int lab, int bce,
+                       double* dz) {
+    double z[1024], pk[1024], mx = -INFINITY;
+    for (int k = 0; k < K; ++k) {
+        double acc = bias ? bias[k] : 0.0;
+        for (int i = 0; i < F; ++i) acc += Wd[(size_t)i * K + k] * f[i];
+        z[k] = acc;
+        if (acc > mx) mx = acc;
+    }
+    double se = 0;
+    for (int k = 0; k < K; ++k) se += exp(z[k] - mx);
+    for (int k = 0; k < K; ++k) pk[k] = exp(z[k] - mx) / se;
+    if (!bce) {
+        for (int k = 0; k < K; ++k) dz[k] = pk[k] - (k == lab ? 1.0 : 0.0);
+        return (mx + log(se)) - z[lab];
+    }
+    /* dL/dp_k, then dL/dz_j = p_j (dL/dp_j - sum_k p_k dL/dp_k) */
+    double L = 0.0, dp[1024], s = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double y = (k == lab) ? 1.0 : 0.0;
+        const double lp = log(pk[k]), lq = log(1.0 - pk[k]);
+        const double cp = lp > -100.0 ? lp : -100.0, cq = lq > -100.0 ? lq : -100.0;
+        L -= y * cp + (1.0 - y) * cq;
+        dp[k] = (y != 0.0 && lp > -100.0 ? -y / pk[k] : 0.0) + (y != 1.0 && lq > -100.0 ? (1.0 - y) / (1.0 - pk[k]) : 0.0);
+        s += pk[k] * dp[k];
+    }
+    for (int k = 0; k < K; ++k) dz[k] = pk[k] * (dp[k] - s);
+    return L;
+}
+
 void orc_slam_loss(int F, int K, int V, const int32_t* wh, const int64_t* norm_count, const double* out,
                    const double* rgb_t, const double* depth_t, const int32_t* labels, const double* Wd,
                    const double* opts, const float* med_in, float* med_out, uint8_t* masks, double* grad_out,
                    double* terms) {
+    orc_slam_loss2(F, K, V, wh, norm_count, out, rgb_t, depth_t, labels, Wd, NULL, opts, med_in, med_out, masks,
+                   grad_out, terms, NULL, NULL);
+}
+
+/* As orc_slam_loss, with a decoder bias (NULL = 0), opts[9] = 1 for BCE
+ * instead of CE, and the decoder gradients: gW [F][K] = sum over pixels of
+ * w_sem / P_v * M(p) f(p) dz(p)^T and gb [K] the same without f (either may
+ * be NULL). */
+void orc_slam_loss2(int F, int K, int V, const int32_t* wh, const int64_t* norm_count, const double* out,
+                    const double* rgb_t, const double* depth_t, const int32_t* labels, const double* Wd,
+                    const double* bias, const double* opts, const float* med_in, float* med_out, uint8_t* masks,
+                    double* grad_out, double* terms, double* gW, double* gb) {
     int64_t P = 0;
     for (int v = 0; v < V; ++v) P += (int64_t)wh[2 * v] * wh[2 * v + 1];
     const int NC = 5 + F;
@@ -1114,6 +1168,9 @@ void orc_slam_loss(int F, int K, int V, const int32_t* wh, const int64_t* norm_c
     const float tau_obs = (float)opts[4], tau_unobs = (float)opts[5];
     const float fobs = (float)opts[6], funobs = (float)opts[7];
     const int use_obs = opts[8] != 0.0;
+    const int bce = opts[9] != 0.0;
+    if (gW) memset(gW, 0, sizeof(double) * (size_t)F * K);
+    if (gb) memset(gb, 0, sizeof(double) * (size_t)K);
     double T[5] = {0, 0, 0, 0, 0};
     int64_t base = 0;
     for (int v = 0; v < V; ++v) {
@@ -1144,25 +1201,19 @@ void orc_slam_loss(int F, int K, int V, const int32_t* wh, const int64_t* norm_c
             ld += fabs(rd);
             grad_out[3 * (size_t)P + p] = rd > 0 ? gd : (rd < 0 ? -gd : 0.0);
             if (K > 0 && F > 0 && w2 != 0.0) {
-                double z[1024], mx = -INFINITY;
-                for (int k = 0; k < K; ++k) {
-                    double acc = 0;
-                    for (int f = 0; f < F; ++f) acc += Wd[(size_t)f * K + k] * out[(size_t)(5 + f) * P + p];
-                    z[k] = acc;
-                    if (acc > mx) mx = acc;
-                }
-                double se = 0;
-                for (int k = 0; k < K; ++k) se += exp(z[k] - mx);
-                const int lab = labels[p];
-                lsum += (mx + log(se)) - z[lab];
+                double fv[1024], dz[1024];
+                for (int f = 0; f < F; ++f) fv[f] = out[(size_t)(5 + f) * P + p];
+                lsum += sem_term(F, K, fv, Wd, bias, labels[p], bce, dz);
                 for (int f = 0; f < F; ++f) {
                     double g = 0;
-                    for (int k = 0; k < K; ++k) {
-                        const double sm = exp(z[k] - mx) / se - (k == lab ? 1.0 : 0.0);
-                        g += Wd[(size_t)f * K + k] * sm;
-                    }
+                    for (int k = 0; k < K; ++k) g += Wd[(size_t)f * K + k] * dz[k];
                     grad_out[(size_t)(5 + f) * P + p] = gs * g;
                 }
+                if (gW)
+                    for (int f = 0; f < F; ++f)
+                        for (int k = 0; k < K; ++k) gW[(size_t)f * K + k] += gs * fv[f] * dz[k];
+                if (gb)
+                    for (int k = 0; k < K; ++k) gb[k] += gs * dz[k];
             }
         }
         double ls = 0.0;

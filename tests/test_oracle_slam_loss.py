@@ -257,3 +257,90 @@ def test_crop_reproduces_full_view_gradient():
         p = q[0] * Wv + q[1]
         assert m[k] == mf[p]
         assert np.allclose(g[:, k], gf[:, p], rtol=1e-12, atol=1e-18), q
+
+
+# --------------------------------------------------------------------------
+# learned decoder (z = W^T f + b), CE and BCE (Eq. 16), decoder gradients
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("bce", [False, True])
+def test_semantic_term_and_decoder_grads_match_torch(bce):
+    """The semantic term, its feature gradient and the decoder gradients
+    against torch autograd through torch's own cross_entropy /
+    binary_cross_entropy (FP64; binary_cross_entropy clamps its logs at -100
+    as the reading does)."""
+    torch = pytest.importorskip("torch")
+    import torch.nn.functional as tf
+    from paper_2603_27781_amd import workloads as wl
+    sz = [(9, 7), (6, 5)]
+    F, K = 8, 6
+    li = wl.loss_images(np.random.default_rng(31), sz, F, K)
+    rng = np.random.default_rng(32)
+    W = rng.normal(0, 0.7, (F, K))
+    b = rng.normal(0, 0.5, K)
+    o = oracle.SlamLossOpts(ssim_lambda=0.0, w_color=0.0, w_depth=0.0, w_sem=0.3, bce=bce)
+    g, t, _, _, gW, gb = oracle.slam_loss(li.out, sz, li.rgb_t, li.depth_t, li.labels, W, o, bias=b,
+                                          decoder_grads=True)
+    f = torch.tensor(li.out[5:].astype(np.float64).T, requires_grad=True)  # [P][F]
+    Wt = torch.tensor(W, requires_grad=True)
+    bt = torch.tensor(b, requires_grad=True)
+    lab = torch.tensor(li.labels.astype(np.int64))
+    z = f @ Wt + bt
+    per = (tf.cross_entropy(z, lab, reduction="none") if not bce else
+           tf.binary_cross_entropy(torch.softmax(z, 1), tf.one_hot(lab, K).double(), reduction="none").sum(1))
+    w = torch.cat([torch.full((w_ * h_,), float(np.float32(0.3)) / (w_ * h_), dtype=torch.float64) for w_, h_ in sz])
+    loss = (w * per).sum()
+    loss.backward()
+    assert t[3] == pytest.approx(loss.item(), rel=1e-12)
+    assert np.allclose(g[5:].T, f.grad.numpy(), rtol=1e-10, atol=1e-15)
+    assert np.allclose(gW, Wt.grad.numpy(), rtol=1e-10, atol=1e-15)
+    assert np.allclose(gb, bt.grad.numpy(), rtol=1e-10, atol=1e-15)
+
+
+def test_bce_log_clamp():
+    """A pixel whose softmax saturates: the clamped logs (at -100) give the
+    torch value and no gradient through the clamped terms."""
+    torch = pytest.importorskip("torch")
+    import torch.nn.functional as tf
+    F, K = 2, 3
+    out = np.zeros((5 + F, 1))
+    out[5:, 0] = [400.0, -400.0]
+    W = np.array([[1.0, 0.0, -1.0], [0.0, 1.0, 0.0]])
+    lab = np.array([2], np.int32)
+    o = oracle.SlamLossOpts(ssim_lambda=0.0, w_color=0.0, w_depth=0.0, w_sem=1.0, bce=True)
+    g, t, _, _, gW, gb = oracle.slam_loss(out, [(1, 1)], np.zeros((3, 1)), np.ones(1), lab, W, o, decoder_grads=True)
+    z = torch.tensor(out[5:, 0]) @ torch.tensor(W)
+    want = tf.binary_cross_entropy(torch.softmax(z, 0), tf.one_hot(torch.tensor(2), K).double(), reduction="sum")
+    assert t[3] == pytest.approx(want.item(), rel=1e-12)
+    assert np.all(np.isfinite(g)) and np.all(np.isfinite(gW)) and np.all(np.isfinite(gb))
+
+
+@pytest.mark.parametrize("bce", [False, True])
+def test_decoder_gradient_finite_differences(bce):
+    """dL/dW and dL/db of the whole loss (SSIM colour, masks, semantic term)
+    against central differences of the oracle's own FP64 loss."""
+    from paper_2603_27781_amd import workloads as wl
+    sz = [(11, 9), (7, 6)]
+    F, K = 8, 5
+    li = wl.loss_images(np.random.default_rng(41 + bce), sz, F, K)
+    rng = np.random.default_rng(42)
+    W = rng.normal(0, 0.6, (F, K))
+    b = rng.normal(0, 0.4, K)
+    o = oracle.SlamLossOpts(use_obs=True, tau_obs=0.95, w_sem=0.05, bce=bce)
+    _, _, _, med = oracle.slam_loss(li.out, sz, li.rgb_t, li.depth_t, li.labels, W, o, bias=b)
+    _, _, _, _, gW, gb = oracle.slam_loss(li.out, sz, li.rgb_t, li.depth_t, li.labels, W, o, medians=med, bias=b,
+                                          decoder_grads=True)
+    h = 1e-6
+
+    def L(Wx, bx):
+        return oracle.slam_loss(li.out, sz, li.rgb_t, li.depth_t, li.labels, Wx, o, medians=med, bias=bx)[1][4]
+
+    for (i, k) in [(0, 0), (3, 2), (7, 4), (5, 1)]:
+        Wp, Wm = W.copy(), W.copy()
+        Wp[i, k] += h
+        Wm[i, k] -= h
+        assert (L(Wp, b) - L(Wm, b)) / (2 * h) == pytest.approx(gW[i, k], rel=1e-5, abs=1e-10), (i, k)
+    for k in range(K):
+        bp, bm = b.copy(), b.copy()
+        bp[k] += h
+        bm[k] -= h
+        assert (L(W, bp) - L(W, bm)) / (2 * h) == pytest.approx(gb[k], rel=1e-5, abs=1e-10), k
