@@ -228,7 +228,10 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
  * gs_slam_loss -- the SLAM losses with their masks: the mapping colour term
  * of Sec. 3.3.4, Eq. (15) (L1 plus an SSIM term), the observed-region mask
  * of the tracking loss, Sec. 3.4, Eq. (21), and the unobserved-region mask
- * of Sec. 3.3.1, Eq. (11), with the median depth error both masks refer to.
+ * of Sec. 3.3.1, Eq. (11), with the median depth error both masks refer to;
+ * the semantic term through a learnable decoder (Sec. 3.2.2, Eq. 8), as a
+ * cross-entropy or as the binary cross-entropy of Eq. (16), with the
+ * decoder's own gradients.
  *   median (per view): the lower median (rank floor((m-1)/2), from 0, of m)
  *     of the binary32 residuals r = |D - D*| over the view's pixels with
  *     D* > 0, ranked by bit pattern (the float order; a NaN ranks above
@@ -241,24 +244,30 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
  *     colour L1  (1 - lambda) w_color / (3 P_v) sum_p M(p) |C(p) - C*(p)|_1
  *     SSIM       lambda w_color / (3 P_v) sum_c sum_p M(p) (1 - SSIM_c(p))
  *     depth      w_depth / P_v sum_p M(p) |D(p) - D*(p)|
- *     semantic   w_sem / P_v sum_p M(p) CE(softmax(W^T F(p)), label(p))
+ *     semantic   w_sem / P_v sum_p M(p) S(p)
  *   SSIM_c(p) (Wang et al. 2004) of colour channel c: local means,
  *   variances and covariance of the rendered and the target image under an
  *   11x11 Gaussian window of standard deviation 1.5 px (weights summing to
  *   1), pixels outside the view taken as 0, C1 = 0.01^2, C2 = 0.03^2.
+ *   S(p): the decoder is a 1x1 convolution, z = W^T F(p) + b, p = softmax(z),
+ *   y = one-hot(label(p)); CE: S = -log p_label; BCE (GS_LOSS_BCE, Eq. 16):
+ *   S = -sum_k [y_k log p_k + (1 - y_k) log(1 - p_k)], every log clamped at
+ *   -100 (a clamped log contributes no gradient).
  *   The masks are constants of the loss (no gradient flows through them).
  * Arguments: out [5+F][P_total] (the render), rgb_target [3][P_total],
- * depth_target [P_total], labels [P_total] int32 in [0, n_classes), decoder
- * W [n_feat][n_classes] row-major (n_classes == 0 drops the semantic term);
- * opts is a HOST struct.  WRITES grad_out [5+F][P_total] = dL/d out (opacity
- * channel 0); loss[5] (double) = (colour L1, SSIM, depth, semantic, total),
- * each summed over the views in a fixed order (deterministic); median[V]
- * (float, may be NULL); masks [P_total] (uint8, may be NULL).  ws: at least
- * gs_slam_loss_workspace bytes (with_ssim != 0 when ssim_lambda != 0),
- * 256-byte aligned, contents need not be initialised.  Views as for the
- * other entry points.  Errors: GS_EINVAL (null or misaligned pointer, bad
- * view list, n_classes out of range), GS_ECAPACITY (ws too small),
- * GS_EUNSUPPORTED (n_feat not compiled).
+ * depth_target [P_total], labels [P_total] int32 in [0, n_classes); dec
+ * (HOST struct, may be NULL: no semantic term); opts is a HOST struct.
+ * WRITES grad_out [5+F][P_total] = dL/d out (opacity channel 0); loss[5]
+ * (double) = (colour L1, SSIM, depth, semantic, total), each summed over
+ * the views in a fixed order (deterministic); median[V] (float, may be
+ * NULL); masks [P_total] (uint8, may be NULL); dec->grad_weight [F][K] and
+ * dec->grad_bias [K] when not NULL (written, not accumulated; summed in a
+ * fixed order).  ws: at least gs_slam_loss_workspace bytes for the same
+ * views, n_feat, dec and opts, 256-byte aligned, contents need not be
+ * initialised.  Views as for the other entry points.  Errors: GS_EINVAL
+ * (null or misaligned pointer, bad view list, flags), GS_ECAPACITY (ws too
+ * small), GS_EUNSUPPORTED (n_feat not compiled, or more than
+ * GS_SLAM_MAX_CLASSES classes).
  * --------------------------------------------------------------------------- */
 typedef struct {
     float w_color, w_depth, w_sem; /* lambda_c, lambda_d, lambda_s (Eq. 18, 21)        */
@@ -266,19 +275,34 @@ typedef struct {
     float tau_obs, tau_unobs;      /* opacity thresholds of Eq. (21) and Eq. (11)      */
     float obs_factor;              /* 10: M_obs residual bound, in medians (Eq. 21)    */
     float unobs_factor;            /* 50: M_unobs residual bound, in medians (Eq. 11)  */
-    uint32_t flags;                /* GS_LOSS_OBS_MASK: weight every term by M_obs     */
+    uint32_t flags;                /* GS_LOSS_OBS_MASK | GS_LOSS_BCE                   */
 } gs_slam_loss_opts;
 
-enum { GS_LOSS_OBS_MASK = 1 };
+enum {
+    GS_LOSS_OBS_MASK = 1,          /* weight every term by M_obs (tracking, Eq. 21)    */
+    GS_LOSS_BCE = 2,               /* semantic term: BCE of Eq. (16), not CE            */
+    GS_SLAM_MAX_CLASSES = 64
+};
+
+/* The semantic decoder (a 1x1 convolution F -> K) and its gradients. */
+typedef struct {
+    const float* weight;           /* W [n_feat][n_classes], row-major (device)        */
+    const float* bias;             /* b [n_classes] (device), or NULL for none          */
+    float* grad_weight;            /* WRITTEN dL/dW [n_feat][n_classes], or NULL        */
+    float* grad_bias;              /* WRITTEN dL/db [n_classes], or NULL                */
+    int32_t n_classes;             /* K in [0, GS_SLAM_MAX_CLASSES]; 0 = no term        */
+    int32_t reserved;
+} gs_decoder;
 
 /* Fills *opts with w = (0.5, 1.0, 0.01), lambda 0.2, tau_obs 0.99,
- * tau_unobs 0.5, factors 10 and 50, no mask (the mapping loss). */
+ * tau_unobs 0.5, factors 10 and 50, CE, no mask (the mapping loss). */
 int gs_default_slam_loss_opts(gs_slam_loss_opts* opts);
-int gs_slam_loss_workspace(const gs_view* views, int32_t n_views, int32_t with_ssim, size_t* bytes);
+int gs_slam_loss_workspace(const gs_view* views, int32_t n_views, int32_t n_feat, const gs_decoder* dec,
+                           const gs_slam_loss_opts* opts, size_t* bytes);
 int gs_slam_loss(const float* out, int32_t n_feat, const float* rgb_target, const float* depth_target,
-                 const int32_t* labels, const float* decoder, int32_t n_classes, const gs_slam_loss_opts* opts,
-                 const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
-                 float* median, uint8_t* masks, void* ws, size_t ws_bytes, gs_stream stream);
+                 const int32_t* labels, const gs_decoder* dec, const gs_slam_loss_opts* opts, const gs_view* views,
+                 const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss, float* median,
+                 uint8_t* masks, void* ws, size_t ws_bytes, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_render_bwd -- backward of gs_render_fwd.  Re-traverses each pixel's list

@@ -27,7 +27,7 @@ EXPORTS = [
     "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_error_string",
     "gs_last_hip_error", "gs_version",
 ]
-GS_LOSS_OBS_MASK = 1
+GS_LOSS_OBS_MASK, GS_LOSS_BCE = 1, 2
 
 
 class GsGaussians(ctypes.Structure):
@@ -58,7 +58,13 @@ class GsSlamLossOpts(ctypes.Structure):
                 ("flags", c_uint32)]
 
 
+class GsDecoder(ctypes.Structure):
+    _fields_ = [("weight", c_void_p), ("bias", c_void_p), ("grad_weight", c_void_p), ("grad_bias", c_void_p),
+                ("n_classes", c_int32), ("reserved", c_int32)]
+
+
 assert ctypes.sizeof(GsView) == 88 and ctypes.sizeof(GsConfig) == 40 and ctypes.sizeof(GsSlamLossOpts) == 36
+assert ctypes.sizeof(GsDecoder) == 40
 
 _lib = None
 
@@ -107,10 +113,10 @@ def load() -> ctypes.CDLL:
     L.gs_pose_grad.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
                                c_void_p, c_size_t, c_void_p, c_void_p]
     L.gs_default_slam_loss_opts.argtypes = [P(GsSlamLossOpts)]
-    L.gs_slam_loss_workspace.argtypes = [P(GsView), c_int32, c_int32, P(c_size_t)]
-    L.gs_slam_loss.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
-                               P(GsSlamLossOpts), P(GsView), c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
-                               c_void_p, c_void_p, c_size_t, c_void_p]
+    L.gs_slam_loss_workspace.argtypes = [P(GsView), c_int32, c_int32, P(GsDecoder), P(GsSlamLossOpts), P(c_size_t)]
+    L.gs_slam_loss.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, P(GsDecoder), P(GsSlamLossOpts),
+                               P(GsView), c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_size_t, c_void_p]
     L.gs_error_string.argtypes = [ctypes.c_int]
     L.gs_error_string.restype = ctypes.c_char_p
     L.gs_last_hip_error.restype = ctypes.c_char_p

@@ -19,7 +19,7 @@ constexpr int kSumThreads = 256, kSumPer = 16, kSumChunk = kSumThreads * kSumPer
 __global__ void k_sum_stage(const double* __restrict__ src, int n, int terms, double* __restrict__ dst);
 inline int sum_stage_blocks(int64_t n) { return (int)((n + kSumChunk - 1) / kSumChunk); }
 
-// Cross-entropy of softmax(W^T f) against `lab` for one pixel (the fixed
+// Cross-entropy of softmax(W^T f + b) (b optional) against `lab` for one pixel (the fixed
 // linear decoder standing in for F_cnn, Sec. 3.2.2, Eq. 8) and its gradient
 // gf = dCE/df = sum_k W[.][k] softmax_k - W[.][lab].  With at most KC
 // classes the logits stay in registers; KC = 0 recomputes them in the second
@@ -27,7 +27,8 @@ inline int sum_stage_blocks(int64_t n) { return (int)((n + kSumChunk - 1) / kSum
 // loads feeding the FMAs directly.
 template <int F, int KC>
 __device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], const float* __restrict__ Wt, int K,
-                                             int lab, float (&gf)[F > 0 ? F : 1]) {
+                                             int lab, float (&gf)[F > 0 ? F : 1],
+                                             const float* __restrict__ bias = nullptr) {
     float m = -INFINITY, zl = 0.0f, se = 0.0f;
     float ga[F > 0 ? F : 1];
 #pragma unroll
@@ -38,7 +39,7 @@ __device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], c
         for (int k = 0; k < KC; ++k) {
             if (k < K) {
                 const float* wr = Wt + k * F;
-                float acc = 0.0f;
+                float acc = bias != nullptr ? bias[k] : 0.0f;
 #pragma unroll
                 for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
                 z[k] = acc;
@@ -59,7 +60,7 @@ __device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], c
     } else {
         for (int k = 0; k < K; ++k) {
             const float* wr = Wt + k * F;
-            float acc = 0.0f;
+            float acc = bias != nullptr ? bias[k] : 0.0f;
 #pragma unroll
             for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
             m = fmaxf(m, acc);
@@ -67,7 +68,7 @@ __device__ __forceinline__ float semantic_ce(const float (&fv)[F > 0 ? F : 1], c
         }
         for (int k = 0; k < K; ++k) {
             const float* wr = Wt + k * F;
-            float acc = 0.0f;
+            float acc = bias != nullptr ? bias[k] : 0.0f;
 #pragma unroll
             for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
             const float e = __expf(acc - m);

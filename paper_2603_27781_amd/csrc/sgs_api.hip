@@ -233,32 +233,45 @@ int gs_default_slam_loss_opts(gs_slam_loss_opts* o) {
     return GS_OK;
 }
 
-int gs_slam_loss_workspace(const gs_view* views, int32_t n_views, int32_t with_ssim, size_t* bytes) {
-    if (!bytes) return GS_EINVAL;
+static int check_decoder(int32_t n_feat, const gs_decoder* dec, const int32_t* labels) {
+    if (dec == nullptr) return GS_OK;
+    if (dec->n_classes < 0) return GS_EINVAL;
+    if (dec->n_classes > GS_SLAM_MAX_CLASSES) return GS_EUNSUPPORTED;
+    if (dec->n_classes > 0 && n_feat > 0 && (!dec->weight || !labels)) return GS_EINVAL;
+    return GS_OK;
+}
+
+int gs_slam_loss_workspace(const gs_view* views, int32_t n_views, int32_t n_feat, const gs_decoder* dec,
+                           const gs_slam_loss_opts* opts, size_t* bytes) {
+    if (!bytes || !opts) return GS_EINVAL;
+    if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
     int64_t P = 0;
-    const int st = check_views(views, views, n_views, 0, &P, nullptr);
+    int st = check_views(views, views, n_views, 0, &P, nullptr);
     if (st) return st;
-    *bytes = slam_loss_workspace_bytes(P, views, n_views, with_ssim != 0);
+    if (dec && (dec->n_classes < 0 || dec->n_classes > GS_SLAM_MAX_CLASSES))
+        return dec->n_classes < 0 ? GS_EINVAL : GS_EUNSUPPORTED;
+    *bytes = slam_loss_workspace_bytes(P, views, n_views, n_feat, dec, *opts);
     return GS_OK;
 }
 
 int gs_slam_loss(const float* out, int32_t n_feat, const float* rgb_target, const float* depth_target,
-                 const int32_t* labels, const float* decoder, int32_t n_classes, const gs_slam_loss_opts* opts,
-                 const gs_view* views, const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss,
-                 float* median, uint8_t* masks, void* ws, size_t ws_bytes, gs_stream stream) {
+                 const int32_t* labels, const gs_decoder* dec, const gs_slam_loss_opts* opts, const gs_view* views,
+                 const gs_view* views_dev, int32_t n_views, float* grad_out, double* loss, float* median,
+                 uint8_t* masks, void* ws, size_t ws_bytes, gs_stream stream) {
     if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
     int64_t P = 0;
     int st = check_views(views, views_dev, n_views, 0, &P, nullptr);
     if (st) return st;
     if (!out || !rgb_target || !depth_target || !opts || !grad_out || !loss || !ws) return GS_EINVAL;
-    if (n_classes < 0 || n_classes > GS_MAX_CLASSES) return GS_EINVAL;
-    if (n_classes > 0 && n_feat > 0 && (!labels || !decoder)) return GS_EINVAL;
-    if ((opts->flags & ~(uint32_t)GS_LOSS_OBS_MASK) != 0) return GS_EINVAL;
+    if ((st = check_decoder(n_feat, dec, labels))) return st;
+    if ((opts->flags & ~(uint32_t)(GS_LOSS_OBS_MASK | GS_LOSS_BCE)) != 0) return GS_EINVAL;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return GS_EINVAL;
-    if (ws_bytes < slam_loss_workspace_bytes(P, views, n_views, opts->ssim_lambda != 0.0f)) return GS_ECAPACITY;
-    return hip_status(launch_slam_loss(out, n_feat, rgb_target, depth_target, labels, decoder,
-                                       n_feat > 0 ? n_classes : 0, *opts, views, views_dev, n_views, P, grad_out,
-                                       loss, median, masks, ws, reinterpret_cast<hipStream_t>(stream)));
+    if (ws_bytes < slam_loss_workspace_bytes(P, views, n_views, n_feat, dec, *opts)) return GS_ECAPACITY;
+    gs_decoder d{};
+    if (dec != nullptr && n_feat > 0) d = *dec;  // without features there is no semantic term
+    return hip_status(launch_slam_loss(out, n_feat, rgb_target, depth_target, labels, dec != nullptr ? &d : nullptr,
+                                       *opts, views, views_dev, n_views, P, grad_out, loss, median, masks, ws,
+                                       reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags,

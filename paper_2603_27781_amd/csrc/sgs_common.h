@@ -144,9 +144,10 @@ hipError_t launch_render_fwd(const float* rec, const float* app, int n, int n_fe
                              int64_t total_pixels, const RasterConst& c, int lds_batch, int persistent,
                              float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s);
 
-size_t slam_loss_workspace_bytes(int64_t P, const gs_view* views_host, int n_views, bool ssim);
+size_t slam_loss_workspace_bytes(int64_t P, const gs_view* views_host, int n_views, int n_feat,
+                                 const gs_decoder* dec, const gs_slam_loss_opts& o);
 hipError_t launch_slam_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t,
-                            const int32_t* labels, const float* decoder, int n_classes, const gs_slam_loss_opts& o,
+                            const int32_t* labels, const gs_decoder* dec, const gs_slam_loss_opts& o,
                             const gs_view* views_host, const gs_view* views_dev, int n_views, int64_t P,
                             float* grad_out, double* loss, float* median, uint8_t* masks, void* ws, hipStream_t s);
 size_t loss_workspace_bytes(int64_t P);

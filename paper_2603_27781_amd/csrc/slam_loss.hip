@@ -39,7 +39,7 @@ constexpr int kSsimIX = kSsimTX + 2 * kSsimR, kSsimIY = kSsimTY + 2 * kSsimR;
 struct SlamParams {
     float w0, w1, w2, lam;
     float tau_obs, tau_unobs, obs_factor, unobs_factor;
-    int use_obs;
+    int use_obs, bce;
 };
 
 struct SsimConst {
@@ -150,21 +150,118 @@ __global__ void __launch_bounds__(256) k_median_select(uint32_t* __restrict__ hi
 // ---------------------------------------------------------------------------
 // 2. per-pixel masks, L1 terms and cross-entropy
 // ---------------------------------------------------------------------------
+// Semantic term of one pixel through the decoder z = W^T f + b (a 1x1
+// convolution standing in for F_cnn, Eq. 8), K <= KC classes, logits in
+// registers.  Returns the term and leaves dz = dterm/dz in z:
+//   CE:  -log p_lab,  dz = p - y;
+//   BCE (Eq. 16): -sum_k [y_k log p_k + (1 - y_k) log(1 - p_k)], each log
+//   clamped at -100 (no gradient through a clamped log); dz_j = p_j (dp_j -
+//   sum_k p_k dp_k) with dp_k the derivative in p_k.
+// A class row of Wt is wavefront-uniform: scalar loads feeding the FMAs.
 template <int F, int KC>
+__device__ __forceinline__ float sem_dz(const float (&fv)[F], const float* __restrict__ Wt,
+                                        const float* __restrict__ bias, int K, int lab, bool bce, float (&z)[KC]) {
+    // z = W^T f + b, then in place z - max (the only per-class state kept,
+    // so that the logits cost one register per class)
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        if (k < K) {
+            const float* wr = Wt + k * F;
+            float acc = bias != nullptr ? bias[k] : 0.0f;
+#pragma unroll
+            for (int f = 0; f < F; ++f) acc = fmaf(wr[f], fv[f], acc);
+            z[k] = acc;
+            m = fmaxf(m, acc);
+        }
+    }
+    float se = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (k < K) {
+            z[k] -= m;
+            se += __expf(z[k]);
+        }
+    const float inv = 1.0f / se, lse = __logf(se);
+    float L = 0.0f;
+    if (!bce) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (k < K) {
+                if (k == lab) L = lse - z[k];
+                z[k] = __expf(z[k]) * inv - (k == lab ? 1.0f : 0.0f);  // dz
+            }
+        return L;
+    }
+    // BCE: p_k, log p_k = z_k - lse, log(1 - p_k) = log(se - e_k) - lse, and
+    // dp_k = dS/dp_k, recomputed from z_k - max where needed
+    auto dpk = [&](float t, bool y, float& pk, float& lp, float& lq) {
+        const float e = __expf(t);
+        pk = e * inv;
+        lp = t - lse;
+        lq = __logf(se - e) - lse;
+        return y ? (lp > -100.0f ? -1.0f / pk : 0.0f) : (lq > -100.0f ? 1.0f / (1.0f - pk) : 0.0f);
+    };
+    float sdp = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (k < K) {
+            const bool y = k == lab;
+            float pk, lp, lq;
+            const float dp = dpk(z[k], y, pk, lp, lq);
+            L -= y ? fmaxf(lp, -100.0f) : fmaxf(lq, -100.0f);
+            sdp = fmaf(pk, dp, sdp);
+        }
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (k < K) {
+            float pk, lp, lq;
+            const float dp = dpk(z[k], k == lab, pk, lp, lq);
+            z[k] = pk * (dp - sdp);  // dz
+        }
+    return L;
+}
+
+// Decoder-gradient staging (dynamic LDS, only when the decoder gradients
+// are wanted): two slots, each f [64][FM] (F padded to the 16-row MFMA
+// tile) and the scaled dz [64][KC] of one wavefront; wavefronts 0-1 use them
+// first, then 2-3, so the area stays at most 2 * 64 * 96 floats (48 KiB).
+template <int F>
+struct DecStage {
+    static constexpr int FM = F <= 16 ? 16 : 32;
+};
+template <int F, int KC>
+constexpr size_t dec_lds_bytes() {
+    return (size_t)2 * kWave * (DecStage<F>::FM + KC) * sizeof(float);
+}
+
+// MODE: kSemCE the fused cross-entropy (no decoder gradients; fewest
+// registers), kSemDz the semantic term through dz (BCE), kSemDzDec the same
+// plus the decoder gradients.
+constexpr int kSemCE = 0, kSemDz = 1, kSemDzDec = 2;
+
+template <int F, int KC, int MODE>
 __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restrict__ out, int64_t P,
                                                             const float* __restrict__ rgb_t,
                                                             const float* __restrict__ depth_t,
                                                             const int32_t* __restrict__ labels,
-                                                            const float* __restrict__ Wt, int K, SlamParams sp,
+                                                            const float* __restrict__ Wt,
+                                                            const float* __restrict__ bias, int K, SlamParams sp,
                                                             const float* __restrict__ med,
                                                             const gs_view* __restrict__ views, int n_views,
                                                             float* __restrict__ grad_out,
                                                             uint8_t* __restrict__ masks,
-                                                            double* __restrict__ partials) {
+                                                            double* __restrict__ partials,
+                                                            float* __restrict__ dec_partials) {
+    extern __shared__ float s_dyn[];
     __shared__ double s_red[3][kSlamThreads / kWave];
-    const int tid = threadIdx.x;
-    double lc = 0.0, ld = 0.0, ls = 0.0;
+    __shared__ float s_db[kSlamThreads / kWave][KC > 0 ? KC : 1];  // per-wavefront bias sums
+    constexpr int FM = DecStage<F>::FM;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int64_t p = (int64_t)blockIdx.x * kSlamThreads + tid;
+    double lc = 0.0, ld = 0.0, ls = 0.0;
+    float fv[F > 0 ? F : 1], dz[KC > 0 ? KC : 1];
+    float dscale = 0.0f;  // w_sem / P_v * M(p) for the decoder gradients (0: no contribution)
     if (p < P) {
         double pc = 0.0, pd = 0.0, ps = 0.0;
         const int v = view_of_pixel(views, n_views, p);
@@ -193,15 +290,29 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
             for (int ch = 0; ch < 4; ++ch) grad_out[ch * P + p] = 0.0f;
         }
         grad_out[4 * P + p] = 0.0f;
-        if (F > 0) {
-            float gf[F > 0 ? F : 1];
+        if constexpr (F > 0) {
+            float gf[F];
 #pragma unroll
             for (int f = 0; f < F; ++f) gf[f] = 0.0f;
+#pragma unroll
+            for (int f = 0; f < F; ++f) fv[f] = 0.0f;
             if (on && K > 0 && sp.w2 != 0.0f) {
-                float fv[F > 0 ? F : 1];
 #pragma unroll
                 for (int f = 0; f < F; ++f) fv[f] = out[(5 + f) * P + p];
-                ps += (double)semantic_ce<F, KC>(fv, Wt, K, labels[p], gf);
+                if constexpr (MODE == kSemCE) {
+                    ps = (double)semantic_ce<F, KC>(fv, Wt, K, labels[p], gf, bias);
+                } else {
+                    ps = (double)sem_dz<F, KC>(fv, Wt, bias, K, labels[p], sp.bce != 0, dz);
+                    // dL/df = W dz
+#pragma unroll
+                    for (int k = 0; k < KC; ++k)
+                        if (k < K) {
+                            const float* wr = Wt + k * F;
+#pragma unroll
+                            for (int f = 0; f < F; ++f) gf[f] = fmaf(wr[f], dz[k], gf[f]);
+                        }
+                    dscale = gs;
+                }
             }
 #pragma unroll
             for (int f = 0; f < F; ++f) grad_out[(5 + f) * P + p] = gs * gf[f];
@@ -210,7 +321,83 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
         ld = pd * ((double)sp.w1 / (double)Pv);
         ls = ps * ((double)sp.w2 / (double)Pv);
     }
-    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    // decoder gradients of the workgroup: dW = sum_p dscale_p f_p dz_p^T and
+    // db = sum_p dscale_p dz_p.  The contraction over a wavefront's 64
+    // pixels runs on MFMA (16x16x4 f32: four pixels per step; A[m][k] = f of
+    // pixel k at row m, B[k][n] = scaled dz of pixel k at class n), the four
+    // wavefronts' tiles and bias sums are then added in a fixed order.
+    if constexpr (MODE == kSemDzDec && F > 0 && KC > 0) {
+        {
+            constexpr int NT = KC / 16, MT = FM / 16;
+            float* sF = s_dyn + (wave & 1) * kWave * (FM + KC);  // [64][FM]
+            float* sZ = sF + kWave * FM;                          // [64][KC]
+            using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+            f4 acc[MT][NT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            const int col = lane & 15, kk = lane >> 4;
+            for (int phase = 0; phase < 2; ++phase) {
+                if ((wave >> 1) == phase) {
+                    const bool c = dscale != 0.0f;
+#pragma unroll
+                    for (int f = 0; f < FM; ++f) sF[lane * FM + f] = (f < F && c) ? fv[f < F ? f : 0] : 0.0f;
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) sZ[lane * KC + k] = (k < K && c) ? dscale * dz[k] : 0.0f;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int st = 0; st < kWave / 4; ++st) {
+                        const int pr = 4 * st + kk;  // the pixel (lane) of k index kk in this step
+                        float a[MT];
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) a[mt] = sF[pr * FM + col + 16 * mt];
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const float bv = sZ[pr * KC + col + 16 * nt];
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt)
+                                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], bv, acc[mt][nt], 0, 0, 0);
+                        }
+                    }
+                    // this wavefront's bias sums, lane n over its 64 rows
+                    if (lane < KC) {
+                        float t = 0.0f;
+                        for (int r = 0; r < kWave; ++r) t += sZ[r * KC + lane];
+                        s_db[wave][lane] = t;
+                    }
+                }
+                __syncthreads();  // the slots are free for the next pair
+            }
+            // D[m][n] with m = 4 (lane / 16) + i, n = lane % 16, per tile, into
+            // the freed staging area as [wave][FM][KC]
+            float* sD = s_dyn + wave * FM * KC;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) sD[(16 * mt + 4 * kk + i) * KC + 16 * nt + col] = acc[mt][nt][i];
+            __syncthreads();
+            const int T = F * K + K;  // this workgroup's partial: dW [F][K], then db [K]
+            float* dst = dec_partials + (size_t)blockIdx.x * T;
+            for (int e = tid; e < F * K; e += kSlamThreads) {
+                const int mm = e / K, nn = e - mm * K;
+                float t = 0.0f;
+#pragma unroll
+                for (int w = 0; w < kSlamThreads / kWave; ++w) t += s_dyn[w * FM * KC + mm * KC + nn];
+                dst[e] = t;
+            }
+            if (tid < K) {
+                float t = 0.0f;
+#pragma unroll
+                for (int w = 0; w < kSlamThreads / kWave; ++w) t += s_db[w][tid];
+                dst[F * K + tid] = t;
+            }
+        }
+    }
     for (int dd = kWave / 2; dd > 0; dd >>= 1) {
         lc += __shfl_xor(lc, dd, kWave);
         ld += __shfl_xor(ld, dd, kWave);
@@ -633,7 +820,7 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 unsigned slam_blocks(int64_t P) { return (unsigned)((P + kSlamThreads - 1) / kSlamThreads); }
 
 struct SlamWs {
-    size_t hist, sel, med, part, spart, stage, wt, mask, maps, total;
+    size_t hist, sel, med, part, spart, stage, wt, mask, maps, dpart, dstage, total;
 };
 
 int ssim_tiles(const gs_view* views, int n_views, SsimTiles* st) {
@@ -649,7 +836,14 @@ int ssim_tiles(const gs_view* views, int n_views, SsimTiles* st) {
     return t;
 }
 
-SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim) {
+// Decoder-gradient reduction: the pixel kernel's block partials, block-major
+// [nblk][T] floats (T = F K + K), are summed in fixed order by chunks of
+// kRowChunk rows (k_rows_stage, doubles [nchunk][T]), then over the chunks
+// (k_rows_final).
+constexpr int kRowChunk = 256;
+int row_chunks(int64_t nblk) { return (int)((nblk + kRowChunk - 1) / kRowChunk); }
+
+SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim, int dec_terms) {
     SlamWs L;
     size_t o = 0;
     L.hist = o;
@@ -672,8 +866,55 @@ SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim) {
     o += align256((size_t)P);
     L.maps = o;
     if (ssim) o += align256((size_t)9 * P * 4);
+    L.dpart = o;
+    o += align256((size_t)nblk * dec_terms * 4);
+    L.dstage = o;
+    o += align256((size_t)row_chunks(nblk) * dec_terms * 8);
     L.total = o;
     return L;
+}
+
+// block (c, g): column t = 64 g + lane of rows [c kRowChunk, (c + 1) kRowChunk);
+// wavefront w takes rows w, w + 4, ... of the chunk, the four sums added in
+// order.
+__global__ void __launch_bounds__(256) k_rows_stage(const float* __restrict__ src, int64_t nrows, int T,
+                                                    double* __restrict__ dst) {
+    __shared__ double s[4][kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int t = blockIdx.y * kWave + lane;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowChunk;
+    double acc = 0.0;
+    if (t < T) {
+        constexpr int U = 16;
+        for (int j0 = 0; j0 < kRowChunk / 4; j0 += U) {
+            float x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t r = r0 + wave + 4 * (j0 + u);
+                x[u] = src[(r < nrows ? r : nrows - 1) * T + t];
+                x[u] = r < nrows ? x[u] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += (double)x[u];
+        }
+    }
+    s[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && t < T) dst[(size_t)blockIdx.x * T + t] = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
+}
+
+__global__ void __launch_bounds__(256) k_rows_final(const double* __restrict__ stage, int nchunk, int F, int K,
+                                                    float* __restrict__ grad_w, float* __restrict__ grad_b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int T = F * K + K;
+    if (t >= T) return;
+    double a = 0.0;
+    for (int c = 0; c < nchunk; ++c) a += stage[(size_t)c * T + t];
+    if (t < F * K) {
+        if (grad_w != nullptr) grad_w[t] = (float)a;
+    } else if (grad_b != nullptr) {
+        grad_b[t - F * K] = (float)a;
+    }
 }
 
 // Workgroups of a persistent SSIM launch: as many as are resident on the
@@ -694,20 +935,38 @@ unsigned ssim_grid(const void* kern, int nitems) {
 
 template <int F, int KC>
 void launch_slam_pixels(unsigned nblk, hipStream_t s, const float* out, int64_t P, const float* rgb_t,
-                        const float* depth_t, const int32_t* labels, const float* Wt, int K, const SlamParams& sp,
-                        const float* med, const gs_view* views, int n_views, float* grad_out, uint8_t* masks,
-                        double* partials) {
-    hipLaunchKernelGGL((k_slam_loss<F, KC>), dim3(nblk), dim3(kSlamThreads), 0, s, out, P, rgb_t, depth_t, labels,
-                       Wt, K, sp, med, views, n_views, grad_out, masks, partials);
+                        const float* depth_t, const int32_t* labels, const float* Wt, const float* bias, int K,
+                        const SlamParams& sp, const float* med, const gs_view* views, int n_views, float* grad_out,
+                        uint8_t* masks, double* partials, float* dec_partials) {
+    // the decoder-gradient path is its own instantiation, so that the plain
+    // loss keeps its register budget
+    const size_t lds = dec_lds_bytes<F, KC>();
+    if (dec_partials != nullptr && F > 0)
+        hipLaunchKernelGGL((k_slam_loss<F, KC, kSemDzDec>), dim3(nblk), dim3(kSlamThreads), lds, s, out, P, rgb_t,
+                           depth_t, labels, Wt, bias, K, sp, med, views, n_views, grad_out, masks, partials,
+                           dec_partials);
+    else if (sp.bce)
+        hipLaunchKernelGGL((k_slam_loss<F, KC, kSemDz>), dim3(nblk), dim3(kSlamThreads), 0, s, out, P, rgb_t, depth_t,
+                           labels, Wt, bias, K, sp, med, views, n_views, grad_out, masks, partials, nullptr);
+    else
+        hipLaunchKernelGGL((k_slam_loss<F, KC, kSemCE>), dim3(nblk), dim3(kSlamThreads), 0, s, out, P, rgb_t, depth_t,
+                           labels, Wt, bias, K, sp, med, views, n_views, grad_out, masks, partials, nullptr);
+}
+
+int dec_terms_of(int F, const gs_decoder* dec) {
+    if (dec == nullptr || F == 0 || dec->n_classes == 0) return 0;
+    if (dec->grad_weight == nullptr && dec->grad_bias == nullptr) return 0;
+    return F * dec->n_classes + dec->n_classes;
 }
 
 template <int F>
 hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* depth_t, const int32_t* labels,
-                         const float* decoder, int K, const gs_slam_loss_opts& o, const gs_view* views_host,
+                         const gs_decoder* dec, const gs_slam_loss_opts& o, const gs_view* views_host,
                          const gs_view* views_dev, int n_views, int64_t P, float* grad_out, double* loss,
                          float* median, uint8_t* masks, char* ws, hipStream_t s) {
     const bool ssim = o.ssim_lambda != 0.0f;
-    const SlamWs L = slam_layout(P, views_host, n_views, ssim);
+    const int dterms = dec_terms_of(F, dec);
+    const SlamWs L = slam_layout(P, views_host, n_views, ssim, dterms);
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
     uint32_t* sel = reinterpret_cast<uint32_t*>(ws + L.sel);
     float* med = reinterpret_cast<float*>(ws + L.med);
@@ -716,6 +975,8 @@ hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* dept
     float* Wt = reinterpret_cast<float*>(ws + L.wt);
     uint8_t* mk = masks != nullptr ? masks : reinterpret_cast<uint8_t*>(ws + L.mask);
     float* maps = reinterpret_cast<float*>(ws + L.maps);
+    float* dpart = dterms > 0 ? reinterpret_cast<float*>(ws + L.dpart) : nullptr;
+    double* dstage = reinterpret_cast<double*>(ws + L.dstage);
 
     // 1. median depth error per view
     hipError_t e = fill_u32(hist, 0u, (int64_t)n_views * (256 + 4), s);  // hist and sel are adjacent
@@ -736,7 +997,7 @@ hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* dept
     hipLaunchKernelGGL(k_median_hist<3>, hg, dim3(kSlamThreads), 0, s, dep, depth_t, views_dev, hist, sel);
     hipLaunchKernelGGL(k_median_select<3>, dim3(n_views), dim3(256), 0, s, hist, sel, med, median);
 
-    // 2. masks, L1 and cross-entropy
+    // 2. masks, L1 and the semantic term (with the decoder gradients' block partials)
     SlamParams sp;
     sp.w0 = o.w_color;
     sp.w1 = o.w_depth;
@@ -747,21 +1008,34 @@ hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* dept
     sp.obs_factor = o.obs_factor;
     sp.unobs_factor = o.unobs_factor;
     sp.use_obs = (o.flags & GS_LOSS_OBS_MASK) != 0;
+    sp.bce = (o.flags & GS_LOSS_BCE) != 0;
+    const int K = dec != nullptr ? dec->n_classes : 0;
     const bool sem = F > 0 && K > 0 && sp.w2 != 0.0f;
     if (sem)
-        hipLaunchKernelGGL(k_transpose_decoder, dim3((unsigned)ceil_div(F * K, 256)), dim3(256), 0, s, decoder, F,
-                           K, Wt);
+        hipLaunchKernelGGL(k_transpose_decoder, dim3((unsigned)ceil_div(F * K, 256)), dim3(256), 0, s, dec->weight,
+                           F, K, Wt);
     const unsigned nblk = slam_blocks(P);
     const int Ke = sem ? K : 0;
-    if (Ke > 64)
-        launch_slam_pixels<F, 0>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, Ke, sp, med, views_dev, n_views,
-                                 grad_out, mk, part);
-    else if (Ke > 32)
-        launch_slam_pixels<F, 64>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, Ke, sp, med, views_dev, n_views,
-                                  grad_out, mk, part);
+    const float* bias = sem ? dec->bias : nullptr;
+    float* dp = sem ? dpart : nullptr;
+    if (Ke > 32)
+        launch_slam_pixels<F, 64>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, bias, Ke, sp, med, views_dev, n_views,
+                                  grad_out, mk, part, dp);
     else
-        launch_slam_pixels<F, 32>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, Ke, sp, med, views_dev, n_views,
-                                  grad_out, mk, part);
+        launch_slam_pixels<F, 32>(nblk, s, out, P, rgb_t, depth_t, labels, Wt, bias, Ke, sp, med, views_dev, n_views,
+                                  grad_out, mk, part, dp);
+    if (dterms > 0) {
+        // dL/dW and dL/db (zero when the semantic term is off)
+        if (!sem) {
+            e = fill_u32(reinterpret_cast<uint32_t*>(dpart), 0u, (int64_t)nblk * dterms, s);
+            if (e != hipSuccess) return e;
+        }
+        const int nch = row_chunks(nblk);
+        hipLaunchKernelGGL(k_rows_stage, dim3((unsigned)nch, (unsigned)ceil_div(dterms, kWave)), dim3(256), 0, s,
+                           dpart, (int64_t)nblk, dterms, dstage);
+        hipLaunchKernelGGL(k_rows_final, dim3((unsigned)ceil_div(dterms, 256)), dim3(256), 0, s, dstage, nch, F,
+                           dec->n_classes, dec->grad_weight, dec->grad_bias);
+    }
 
     // 3. SSIM
     int nssim = 0;
@@ -800,28 +1074,29 @@ hipError_t launch_slam_t(const float* out, const float* rgb_t, const float* dept
 
 }  // namespace
 
-size_t slam_loss_workspace_bytes(int64_t P, const gs_view* views_host, int n_views, bool ssim) {
-    return slam_layout(P, views_host, n_views, ssim).total;
+size_t slam_loss_workspace_bytes(int64_t P, const gs_view* views_host, int n_views, int n_feat,
+                                 const gs_decoder* dec, const gs_slam_loss_opts& o) {
+    return slam_layout(P, views_host, n_views, o.ssim_lambda != 0.0f, dec_terms_of(n_feat, dec)).total;
 }
 
 hipError_t launch_slam_loss(const float* out, int n_feat, const float* rgb_t, const float* depth_t,
-                            const int32_t* labels, const float* decoder, int n_classes, const gs_slam_loss_opts& o,
+                            const int32_t* labels, const gs_decoder* dec, const gs_slam_loss_opts& o,
                             const gs_view* views_host, const gs_view* views_dev, int n_views, int64_t P,
                             float* grad_out, double* loss, float* median, uint8_t* masks, void* ws, hipStream_t s) {
     char* w = static_cast<char*>(ws);
     switch (n_feat) {
         case 0:
-            return launch_slam_t<0>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
-                                    n_views, P, grad_out, loss, median, masks, w, s);
+            return launch_slam_t<0>(out, rgb_t, depth_t, labels, dec, o, views_host, views_dev, n_views, P, grad_out,
+                                    loss, median, masks, w, s);
         case 8:
-            return launch_slam_t<8>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
-                                    n_views, P, grad_out, loss, median, masks, w, s);
+            return launch_slam_t<8>(out, rgb_t, depth_t, labels, dec, o, views_host, views_dev, n_views, P, grad_out,
+                                    loss, median, masks, w, s);
         case 32:
-            return launch_slam_t<32>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
-                                     n_views, P, grad_out, loss, median, masks, w, s);
+            return launch_slam_t<32>(out, rgb_t, depth_t, labels, dec, o, views_host, views_dev, n_views, P, grad_out,
+                                     loss, median, masks, w, s);
         default:
-            return launch_slam_t<16>(out, rgb_t, depth_t, labels, decoder, n_classes, o, views_host, views_dev,
-                                     n_views, P, grad_out, loss, median, masks, w, s);
+            return launch_slam_t<16>(out, rgb_t, depth_t, labels, dec, o, views_host, views_dev, n_views, P,
+                                     grad_out, loss, median, masks, w, s);
     }
 }
 

@@ -239,34 +239,45 @@ class Rasterizer:
         return self.grad_out
 
     def slam_loss(self, rgb_t, depth_t, labels=None, decoder=None, opts=None,
-                  out: Optional[torch.Tensor] = None, masks: bool = True) -> torch.Tensor:
+                  out: Optional[torch.Tensor] = None, masks: bool = True, bias: Optional[torch.Tensor] = None,
+                  decoder_grads: bool = False) -> torch.Tensor:
         """SLAM losses with masks (gs_slam_loss): writes self.grad_out, the
         terms (colour L1, SSIM, depth, semantic, total) to self.slam_terms,
-        the per-view median depth error to self.median and, with masks=True,
-        M_obs | M_unobs << 1 per pixel to self.masks.  `opts` is a
-        GsSlamLossOpts (default: gs_default_slam_loss_opts)."""
+        the per-view median depth error to self.median, with masks=True
+        M_obs | M_unobs << 1 per pixel to self.masks and, with
+        decoder_grads=True, dL/dW and dL/db of the decoder (W [F][K], bias
+        [K] or None) to self.grad_decoder_w / self.grad_decoder_b.  `opts`
+        is a GsSlamLossOpts (default: gs_default_slam_loss_opts)."""
         out = self.out if out is None else out
         L = self.L
         if opts is None:
             opts = _lib.GsSlamLossOpts()
             check(L.gs_default_slam_loss_opts(ctypes.byref(opts)), "gs_default_slam_loss_opts")
-        ssim = 1 if opts.ssim_lambda != 0.0 else 0
+        K = 0 if decoder is None else int(decoder.shape[1])
+        dev = dict(device=self.device)
+        dec = None
+        if decoder is not None:
+            dec = _lib.GsDecoder(decoder.data_ptr(), bias.data_ptr() if bias is not None else None, None, None, K, 0)
+            if decoder_grads:
+                if getattr(self, "grad_decoder_w", None) is None or self.grad_decoder_w.shape != (self.F, K):
+                    self.grad_decoder_w = torch.zeros(max(self.F, 1), K, dtype=torch.float32, **dev)[:self.F]
+                    self.grad_decoder_b = torch.zeros(K, dtype=torch.float32, **dev)
+                dec.grad_weight = self.grad_decoder_w.data_ptr()
+                dec.grad_bias = self.grad_decoder_b.data_ptr()
+        pdec = ctypes.byref(dec) if dec is not None else None
         b = ctypes.c_size_t(0)
-        check(L.gs_slam_loss_workspace(self.views.host, self.views.n, ssim, ctypes.byref(b)),
-              "gs_slam_loss_workspace")
+        check(L.gs_slam_loss_workspace(self.views.host, self.views.n, self.F, pdec, ctypes.byref(opts),
+                                       ctypes.byref(b)), "gs_slam_loss_workspace")
         if getattr(self, "slam_ws", None) is None or self.slam_ws_bytes < b.value:
-            self.slam_ws = torch.empty(b.value + 256, dtype=torch.uint8, device=self.device)
+            self.slam_ws = torch.empty(b.value + 256, dtype=torch.uint8, **dev)
             self.slam_ws_bytes = b.value
         off = (-self.slam_ws.data_ptr()) % 256
         if getattr(self, "slam_terms", None) is None:
-            dev = dict(device=self.device)
             self.slam_terms = torch.zeros(5, dtype=torch.float64, **dev)
             self.median = torch.zeros(self.views.n, dtype=torch.float32, **dev)
             self.masks = torch.zeros(self.views.total_pixels, dtype=torch.uint8, **dev)
-        K = 0 if decoder is None else int(decoder.shape[1])
         check(L.gs_slam_loss(out.data_ptr(), self.F, rgb_t.data_ptr(), depth_t.data_ptr(),
-                             labels.data_ptr() if labels is not None else None,
-                             decoder.data_ptr() if decoder is not None else None, K, ctypes.byref(opts),
+                             labels.data_ptr() if labels is not None else None, pdec, ctypes.byref(opts),
                              self.views.host, self.views.dev_ptr(), self.views.n, self.grad_out.data_ptr(),
                              self.slam_terms.data_ptr(), self.median.data_ptr(),
                              self.masks.data_ptr() if masks else None, self.slam_ws.data_ptr() + off,

@@ -131,25 +131,37 @@ def test_slam_loss_host_side():
     for i, (w, h) in enumerate([(100, 60), (33, 17)]):
         V[i].width, V[i].height, V[i].fx, V[i].fy = w, h, 50.0, 50.0
     L.gs_views_layout(V, 2, 16, None, None)
-    b0, b1 = ctypes.c_size_t(), ctypes.c_size_t()
-    assert L.gs_slam_loss_workspace(V, 2, 0, ctypes.byref(b0)) == 0
-    assert L.gs_slam_loss_workspace(V, 2, 1, ctypes.byref(b1)) == 0
+    b0, b1, b2 = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    dummy = 1 << 20
+    dec = _lib.GsDecoder(dummy, None, None, None, 20, 0)
+    nossim = _lib.GsSlamLossOpts.from_buffer_copy(o)
+    nossim.ssim_lambda = 0.0
+    assert L.gs_slam_loss_workspace(V, 2, 16, ctypes.byref(dec), ctypes.byref(nossim), ctypes.byref(b0)) == 0
+    assert L.gs_slam_loss_workspace(V, 2, 16, ctypes.byref(dec), ctypes.byref(o), ctypes.byref(b1)) == 0
     P = 100 * 60 + 33 * 17
     assert b0.value >= P and b1.value >= b0.value + 9 * 4 * P  # the SSIM maps
-    assert L.gs_slam_loss_workspace(V, 0, 1, ctypes.byref(b1)) == _lib.GS_EINVAL
-    dummy = 1 << 20
+    dg = _lib.GsDecoder(dummy, None, dummy, dummy, 20, 0)
+    assert L.gs_slam_loss_workspace(V, 2, 16, ctypes.byref(dg), ctypes.byref(o), ctypes.byref(b2)) == 0
+    assert b2.value >= b1.value + ((P + 255) // 256) * (16 * 20 + 20) * 4  # decoder-gradient partials
+    assert L.gs_slam_loss_workspace(V, 0, 16, ctypes.byref(dec), ctypes.byref(o), ctypes.byref(b1)) == _lib.GS_EINVAL
+    big = _lib.GsDecoder(dummy, None, None, None, 65, 0)
+    assert L.gs_slam_loss_workspace(V, 2, 16, ctypes.byref(big), ctypes.byref(o), ctypes.byref(b1)) == \
+        _lib.GS_EUNSUPPORTED
+    L.gs_slam_loss_workspace(V, 2, 16, ctypes.byref(dec), ctypes.byref(o), ctypes.byref(b1))
     ws = 1 << 24  # 256-byte aligned
 
-    def call(opts=o, n_feat=16, ws_ptr=ws, ws_bytes=1 << 30, out=dummy, K=20, labels=dummy):
-        return L.gs_slam_loss(out, n_feat, dummy, dummy, labels, dummy, K, ctypes.byref(opts), V, dummy, 2, dummy,
-                              dummy, None, None, ws_ptr, ws_bytes, None)
+    def call(opts=o, n_feat=16, ws_ptr=ws, ws_bytes=1 << 30, out=dummy, d=dec, labels=dummy):
+        return L.gs_slam_loss(out, n_feat, dummy, dummy, labels, ctypes.byref(d) if d is not None else None,
+                              ctypes.byref(opts), V, dummy, 2, dummy, dummy, None, None, ws_ptr, ws_bytes, None)
 
     assert call(n_feat=12) == _lib.GS_EUNSUPPORTED
     assert call(out=None) == _lib.GS_EINVAL
     assert call(labels=None) == _lib.GS_EINVAL
-    assert call(K=10_000) == _lib.GS_EINVAL
+    assert call(d=_lib.GsDecoder(None, None, None, None, 20, 0)) == _lib.GS_EINVAL
+    assert call(d=big) == _lib.GS_EUNSUPPORTED
     assert call(ws_ptr=ws + 16) == _lib.GS_EINVAL
     assert call(ws_bytes=b0.value) == _lib.GS_ECAPACITY  # SSIM on: needs the larger size
+    assert call(d=dg, ws_bytes=b1.value) == _lib.GS_ECAPACITY  # decoder gradients need their partials
     bad = _lib.GsSlamLossOpts.from_buffer_copy(o)
     bad.flags = 4
     assert call(opts=bad) == _lib.GS_EINVAL

@@ -187,3 +187,75 @@ def test_slam_loss_full_size_sampled():
             assert np.max(np.abs(go[:3, p] - gref[:3])) <= TOL_GRAD * scale, (v, q)
             assert np.array_equal(np.sign(go[3, p]), np.sign(gref[3]))
             assert np.max(np.abs(go[5:, p] - gref[5:])) <= 1e-5 * max(np.abs(gref[5:]).max(), 1e-30), (v, q)
+
+
+DEC_CASES = [(8, 5, True, False), (16, 20, False, True), (16, 20, True, True), (32, 40, True, False),
+             (16, 64, False, False), (32, 64, True, True), (16, 33, True, False)]
+
+
+@pytest.mark.parametrize("F,K,bce,use_obs", DEC_CASES)
+def test_slam_loss_decoder_gradients(F, K, bce, use_obs):
+    """Learned decoder z = W^T f + b (bias on), CE or BCE (Eq. 16), with the
+    decoder gradients dL/dW, dL/db (MFMA contraction over the pixels, fixed
+    order sums) against the oracle; the rest of the loss as in mapping."""
+    from paper_2603_27781_amd import _lib
+    sz = SIZES["3views-ragged"]
+    rng = np.random.default_rng(50 + F + K)
+    li = wl.loss_images(rng, sz, F, K)
+    W = wl.decoder_matrix(rng, F, K)
+    b = (rng.normal(0, 0.3, K)).astype(np.float32)
+    o, oo = _opts("masked-ssim" if use_obs else "mapping")
+    if bce:
+        o.flags |= _lib.GS_LOSS_BCE
+        oo.bce = True
+    r = _rasterizer(sz, F)
+    r.slam_loss(_dev(li.rgb_t), _dev(li.depth_t), _dev(li.labels), _dev(W), o, out=_dev(li.out), bias=_dev(b),
+                decoder_grads=True)
+    torch.cuda.synchronize()
+    go, terms = r.grad_out.cpu().numpy(), r.slam_terms.cpu().numpy()
+    gw, gb = r.grad_decoder_w.cpu().numpy(), r.grad_decoder_b.cpu().numpy()
+    gref, tref, mref, medref, gwr, gbr = oracle.slam_loss(li.out, sz, li.rgb_t, li.depth_t, li.labels,
+                                                          W.astype(np.float64), oo, bias=b.astype(np.float64),
+                                                          decoder_grads=True)
+    assert np.array_equal(r.masks.cpu().numpy(), mref)
+    assert rel_err(go[5:], gref[5:]) <= 1e-5, rel_err(go[5:], gref[5:])
+    assert rel_err(go[:3], gref[:3]) <= TOL_GRAD
+    assert terms[3] == pytest.approx(tref[3], rel=1e-5)
+    assert rel_err(gw, gwr) <= 1e-5, rel_err(gw, gwr)
+    assert rel_err(gb, gbr) <= 1e-5, rel_err(gb, gbr)
+    # run-to-run identical (fixed-order sums)
+    w0, b0 = r.grad_decoder_w.clone(), r.grad_decoder_b.clone()
+    r.slam_loss(_dev(li.rgb_t), _dev(li.depth_t), _dev(li.labels), _dev(W), o, out=_dev(li.out), bias=_dev(b),
+                decoder_grads=True)
+    torch.cuda.synchronize()
+    assert torch.equal(r.grad_decoder_w, w0) and torch.equal(r.grad_decoder_b, b0)
+
+
+def test_slam_loss_decoder_full_size():
+    """Eight 1200x680 views, F = 16, 20 classes, BCE under M_obs, no SSIM:
+    the decoder gradients (sums over 6.5 M pixels) and the semantic term
+    against the full FP64 oracle."""
+    from paper_2603_27781_amd import _lib
+    F, K = 16, 20
+    sz = [(1200, 680)] * 8
+    rng = np.random.default_rng(79)
+    li = wl.loss_images(rng, sz, F, K)
+    W = wl.decoder_matrix(rng, F, K)
+    b = (rng.normal(0, 0.3, K)).astype(np.float32)
+    o, oo = _opts("tracking")
+    o.flags |= _lib.GS_LOSS_BCE
+    oo.bce = True
+    r = _rasterizer(sz, F)
+    r.slam_loss(_dev(li.rgb_t), _dev(li.depth_t), _dev(li.labels), _dev(W), o, out=_dev(li.out), bias=_dev(b),
+                decoder_grads=True)
+    torch.cuda.synchronize()
+    gref, tref, mref, _, gwr, gbr = oracle.slam_loss(li.out, sz, li.rgb_t, li.depth_t, li.labels,
+                                                     W.astype(np.float64), oo, bias=b.astype(np.float64),
+                                                     decoder_grads=True)
+    assert np.array_equal(r.masks.cpu().numpy(), mref)
+    terms = r.slam_terms.cpu().numpy()
+    assert terms[3] == pytest.approx(tref[3], rel=1e-5)
+    assert rel_err(r.grad_decoder_w.cpu().numpy(), gwr) <= 1e-5
+    assert rel_err(r.grad_decoder_b.cpu().numpy(), gbr) <= 1e-5
+    go = r.grad_out.cpu().numpy()
+    assert rel_err(go[5:], gref[5:]) <= 1e-5
