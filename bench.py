@@ -333,35 +333,54 @@ def slam_loss_bench(r, rgb_t, dep_t, lab, W, steps, warmup, F, P):
     from paper_2603_27781_amd import _lib
     L = _lib.load()
     res = {}
-    for mode in ("mapping", "tracking"):
+    K = int(W.shape[1]) if W is not None else 0
+    bias = torch.zeros(K, dtype=torch.float32, device="cuda") + 0.1 if K else None
+    # the two uses, then the mapping loss with a learnable decoder (bias, dL/dW
+    # and dL/db), with the CE and with the BCE semantic term
+    for mode in ("mapping", "tracking", "mapping_decoder_grad", "mapping_bce_decoder_grad"):
         o = _lib.GsSlamLossOpts()
         L.gs_default_slam_loss_opts(ctypes.byref(o))
         if mode == "tracking":
             o.ssim_lambda, o.w_sem, o.flags = 0.0, 0.001, _lib.GS_LOSS_OBS_MASK
+        if mode == "mapping_bce_decoder_grad":
+            o.flags = _lib.GS_LOSS_BCE
+        dec = mode.endswith("decoder_grad")
+        if dec and K == 0:
+            continue
+        kw = dict(bias=bias, decoder_grads=True) if dec else {}
         for _ in range(max(warmup, 1)):
-            r.slam_loss(rgb_t, dep_t, lab, W, o)
+            r.slam_loss(rgb_t, dep_t, lab, W, o, **kw)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
         for _ in range(steps):
-            r.slam_loss(rgb_t, dep_t, lab, W, o)
+            r.slam_loss(rgb_t, dep_t, lab, W, o, **kw)
         b.record()
         torch.cuda.synchronize()
         us = a.elapsed_time(b) / steps * 1e3
         res[mode] = {"us": round(us, 2), "Mpixel_per_s": round(P / (us * 1e-6) / 1e6, 1),
                      "terms": [round(x, 6) for x in r.slam_terms.cpu().tolist()]}
+        if dec:
+            res[mode]["grad_decoder_norm"] = round(float(r.grad_decoder_w.norm().item()), 6)
+            res[mode]["extra_us_over_mapping"] = round(us - res["mapping"]["us"], 2)
+            # the contraction dL/dW = sum_p f_p dz_p^T: 2 P F K flops
+            res[mode]["decoder_grad_gflop"] = round(2.0 * P * F * K / 1e9, 3)
     m = r.masks[:P].cpu().numpy()
     res["mask_fraction"] = {"obs": round(float(np.mean(m & 1)), 4), "unobs": round(float(np.mean(m >> 1)), 4)}
     res["median_depth_error"] = [round(x, 6) for x in r.median.cpu().tolist()]
     alg = P * ((5 + F) * 4 + 3 * 4 + 4 + 4 + (5 + F) * 4 + 1)
     res["algorithmic_bytes_per_call"] = int(alg)
     res["roofline"] = {}
-    for mode in ("mapping", "tracking"):
+    for mode in ("mapping", "tracking", "mapping_decoder_grad", "mapping_bce_decoder_grad"):
+        if mode not in res:
+            continue
         gbs = alg / (res[mode]["us"] * 1e-6) / 1e9
         res["roofline"][mode] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
     log(f"slam loss: mapping {res['mapping']['us']:.1f} us, tracking {res['tracking']['us']:.1f} us, "
-        f"masks obs {res['mask_fraction']['obs']}, unobs {res['mask_fraction']['unobs']}")
+        + "".join(f"{m} {res[m]['us']:.1f} us, " for m in ("mapping_decoder_grad", "mapping_bce_decoder_grad")
+                  if m in res)
+        + f"masks obs {res['mask_fraction']['obs']}, unobs {res['mask_fraction']['unobs']}")
     return res
 
 

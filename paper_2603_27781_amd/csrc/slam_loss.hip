@@ -193,47 +193,45 @@ __device__ __forceinline__ float sem_dz(const float (&fv)[F], const float* __res
             }
         return L;
     }
-    // BCE: p_k, log p_k = z_k - lse, log(1 - p_k) = log(se - e_k) - lse, and
-    // dp_k = dS/dp_k, recomputed from z_k - max where needed
-    auto dpk = [&](float t, bool y, float& pk, float& lp, float& lq) {
-        const float e = __expf(t);
-        pk = e * inv;
-        lp = t - lse;
-        lq = __logf(se - e) - lse;
-        return y ? (lp > -100.0f ? -1.0f / pk : 0.0f) : (lq > -100.0f ? 1.0f / (1.0f - pk) : 0.0f);
-    };
+    // BCE: p_k, log p_k = z_k - lse, log(1 - p_k) = log(se - e_k) - lse;
+    // z keeps p_k and one bit per class whether the log that class's
+    // gradient uses is above the clamp, so dp_k = -1/p_k (label) or
+    // 1/(1 - p_k) (other classes, hardware reciprocals) is rebuilt in the
+    // last pass without another exp or log
     float sdp = 0.0f;
+    uint64_t live = 0;
 #pragma unroll
     for (int k = 0; k < KC; ++k)
         if (k < K) {
             const bool y = k == lab;
-            float pk, lp, lq;
-            const float dp = dpk(z[k], y, pk, lp, lq);
+            const float e = __expf(z[k]), pk = e * inv;
+            const float lp = z[k] - lse;            // log p_k
+            const float lq = __logf(se - e) - lse;  // log(1 - p_k)
             L -= y ? fmaxf(lp, -100.0f) : fmaxf(lq, -100.0f);
+            const bool on = y ? lp > -100.0f : lq > -100.0f;
+            const float dp = on ? (y ? -__builtin_amdgcn_rcpf(pk) : __builtin_amdgcn_rcpf(1.0f - pk)) : 0.0f;
             sdp = fmaf(pk, dp, sdp);
+            z[k] = pk;
+            live |= (uint64_t)on << k;
         }
 #pragma unroll
     for (int k = 0; k < KC; ++k)
         if (k < K) {
-            float pk, lp, lq;
-            const float dp = dpk(z[k], k == lab, pk, lp, lq);
+            const float pk = z[k];
+            const float dp = ((live >> k) & 1) ? (k == lab ? -__builtin_amdgcn_rcpf(pk)
+                                                            : __builtin_amdgcn_rcpf(1.0f - pk))
+                                               : 0.0f;
             z[k] = pk * (dp - sdp);  // dz
         }
     return L;
 }
 
 // Decoder-gradient staging (dynamic LDS, only when the decoder gradients
-// are wanted): two slots, each f [64][FM] (F padded to the 16-row MFMA
-// tile) and the scaled dz [64][KC] of one wavefront; wavefronts 0-1 use them
-// first, then 2-3, so the area stays at most 2 * 64 * 96 floats (48 KiB).
-template <int F>
-struct DecStage {
-    static constexpr int FM = F <= 16 ? 16 : 32;
-};
-template <int F, int KC>
-constexpr size_t dec_lds_bytes() {
-    return (size_t)2 * kWave * (DecStage<F>::FM + KC) * sizeof(float);
-}
+// are wanted): one slot per wavefront of 32 pixel rows, f [32][F] then the
+// scaled dz [32][K]; a wavefront stages and contracts its 64 pixels in two
+// halves, so the area is 4 * 32 * (F + K) floats (at most 48 KiB).
+constexpr int kDecRows = kWave / 2;
+inline size_t dec_lds_bytes(int F, int K) { return (size_t)4 * kDecRows * (F + K) * sizeof(float); }
 
 // MODE: kSemCE the fused cross-entropy (no decoder gradients; fewest
 // registers), kSemDz the semantic term through dz (BCE), kSemDzDec the same
@@ -256,7 +254,6 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
     extern __shared__ float s_dyn[];
     __shared__ double s_red[3][kSlamThreads / kWave];
     __shared__ float s_db[kSlamThreads / kWave][KC > 0 ? KC : 1];  // per-wavefront bias sums
-    constexpr int FM = DecStage<F>::FM;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int64_t p = (int64_t)blockIdx.x * kSlamThreads + tid;
     double lc = 0.0, ld = 0.0, ls = 0.0;
@@ -327,75 +324,91 @@ __global__ void __launch_bounds__(kSlamThreads) k_slam_loss(const float* __restr
     // pixel k at row m, B[k][n] = scaled dz of pixel k at class n), the four
     // wavefronts' tiles and bias sums are then added in a fixed order.
     if constexpr (MODE == kSemDzDec && F > 0 && KC > 0) {
-        {
-            constexpr int NT = KC / 16, MT = FM / 16;
-            float* sF = s_dyn + (wave & 1) * kWave * (FM + KC);  // [64][FM]
-            float* sZ = sF + kWave * FM;                          // [64][KC]
-            using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
-            f4 acc[MT][NT];
+        constexpr int MT = (F + 15) / 16, NT = KC / 16;
+        float* sF = s_dyn + wave * kDecRows * (F + K);  // [32][F]
+        float* sZ = sF + kDecRows * F;                  // [32][K]
+        using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+        f4 acc[MT][NT];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            const int col = lane & 15, kk = lane >> 4;
-            for (int phase = 0; phase < 2; ++phase) {
-                if ((wave >> 1) == phase) {
-                    const bool c = dscale != 0.0f;
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        const int col = lane & 15, kk = lane >> 4, row = lane & (kDecRows - 1);
+        const bool c = dscale != 0.0f;
+        float db = 0.0f;  // lane n < K: bias sum of this wavefront, rows in a fixed order
+        for (int half = 0; half < 2; ++half) {
+            if ((lane >> 5) == half) {
 #pragma unroll
-                    for (int f = 0; f < FM; ++f) sF[lane * FM + f] = (f < F && c) ? fv[f < F ? f : 0] : 0.0f;
+                for (int f = 0; f < F; ++f) sF[row * F + f] = c ? fv[f] : 0.0f;
 #pragma unroll
-                    for (int k = 0; k < KC; ++k) sZ[lane * KC + k] = (k < K && c) ? dscale * dz[k] : 0.0f;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int k = 0; k < KC; ++k)
+                    if (k < K) sZ[row * K + k] = c ? dscale * dz[k] : 0.0f;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // 8 steps of four pixels: A[m][k] = f of pixel k at row m, B[k][n]
+            // = scaled dz of pixel k at class n (zero past F and K)
+#pragma unroll 2
+            for (int st = 0; st < kDecRows / 4; ++st) {
+                const int pr = 4 * st + kk;
+                float a[MT];
 #pragma unroll
-                    for (int st = 0; st < kWave / 4; ++st) {
-                        const int pr = 4 * st + kk;  // the pixel (lane) of k index kk in this step
-                        float a[MT];
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) a[mt] = sF[pr * FM + col + 16 * mt];
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt) {
-                            const float bv = sZ[pr * KC + col + 16 * nt];
-#pragma unroll
-                            for (int mt = 0; mt < MT; ++mt)
-                                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], bv, acc[mt][nt], 0, 0, 0);
-                        }
-                    }
-                    // this wavefront's bias sums, lane n over its 64 rows
-                    if (lane < KC) {
-                        float t = 0.0f;
-                        for (int r = 0; r < kWave; ++r) t += sZ[r * KC + lane];
-                        s_db[wave][lane] = t;
-                    }
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int m = col + 16 * mt;
+                    a[mt] = m < F ? sF[pr * F + m] : 0.0f;
                 }
-                __syncthreads();  // the slots are free for the next pair
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int n = col + 16 * nt;
+                    const float bv = n < K ? sZ[pr * K + n] : 0.0f;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], bv, acc[mt][nt], 0, 0, 0);
+                }
             }
-            // D[m][n] with m = 4 (lane / 16) + i, n = lane % 16, per tile, into
-            // the freed staging area as [wave][FM][KC]
-            float* sD = s_dyn + wave * FM * KC;
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) sD[(16 * mt + 4 * kk + i) * KC + 16 * nt + col] = acc[mt][nt][i];
-            __syncthreads();
-            const int T = F * K + K;  // this workgroup's partial: dW [F][K], then db [K]
-            float* dst = dec_partials + (size_t)blockIdx.x * T;
-            for (int e = tid; e < F * K; e += kSlamThreads) {
-                const int mm = e / K, nn = e - mm * K;
-                float t = 0.0f;
-#pragma unroll
-                for (int w = 0; w < kSlamThreads / kWave; ++w) t += s_dyn[w * FM * KC + mm * KC + nn];
-                dst[e] = t;
+            if (lane < K) {
+                float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;  // four chains
+                for (int r = 0; r < kDecRows; r += 4) {
+                    t0 += sZ[r * K + lane];
+                    t1 += sZ[(r + 1) * K + lane];
+                    t2 += sZ[(r + 2) * K + lane];
+                    t3 += sZ[(r + 3) * K + lane];
+                }
+                db += (t0 + t1) + (t2 + t3);
             }
-            if (tid < K) {
-                float t = 0.0f;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (lane < KC) s_db[wave][lane] = db;
+        __syncthreads();  // every wavefront is done with its slot
+        // D[m][n] with m = 4 (lane / 16) + i, n = lane % 16 per tile, into the
+        // freed slots as [wave][F][K]
+        float* sD = s_dyn + wave * F * K;
 #pragma unroll
-                for (int w = 0; w < kSlamThreads / kWave; ++w) t += s_db[w][tid];
-                dst[F * K + tid] = t;
-            }
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int mm = 16 * mt + 4 * kk + i, nn = 16 * nt + col;
+                    if (mm < F && nn < K) sD[mm * K + nn] = acc[mt][nt][i];
+                }
+        __syncthreads();
+        const int T = F * K + K;  // this workgroup's partial: dW [F][K], then db [K]
+        float* dst = dec_partials + (size_t)blockIdx.x * T;
+        for (int e = tid; e < F * K; e += kSlamThreads) {
+            float t = 0.0f;
+#pragma unroll
+            for (int w = 0; w < kSlamThreads / kWave; ++w) t += s_dyn[w * F * K + e];
+            dst[e] = t;
+        }
+        if (tid < K) {
+            float t = 0.0f;
+#pragma unroll
+            for (int w = 0; w < kSlamThreads / kWave; ++w) t += s_db[w][tid];
+            dst[F * K + tid] = t;
         }
     }
     for (int dd = kWave / 2; dd > 0; dd >>= 1) {
@@ -840,7 +853,7 @@ int ssim_tiles(const gs_view* views, int n_views, SsimTiles* st) {
 // [nblk][T] floats (T = F K + K), are summed in fixed order by chunks of
 // kRowChunk rows (k_rows_stage, doubles [nchunk][T]), then over the chunks
 // (k_rows_final).
-constexpr int kRowChunk = 256;
+constexpr int kRowChunk = 512;
 int row_chunks(int64_t nblk) { return (int)((nblk + kRowChunk - 1) / kRowChunk); }
 
 SlamWs slam_layout(int64_t P, const gs_view* views, int n_views, bool ssim, int dec_terms) {
@@ -908,8 +921,16 @@ __global__ void __launch_bounds__(256) k_rows_final(const double* __restrict__ s
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int T = F * K + K;
     if (t >= T) return;
-    double a = 0.0;
-    for (int c = 0; c < nchunk; ++c) a += stage[(size_t)c * T + t];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;  // four chains, fixed order
+    int c = 0;
+    for (; c + 3 < nchunk; c += 4) {
+        a0 += stage[(size_t)c * T + t];
+        a1 += stage[(size_t)(c + 1) * T + t];
+        a2 += stage[(size_t)(c + 2) * T + t];
+        a3 += stage[(size_t)(c + 3) * T + t];
+    }
+    for (; c < nchunk; ++c) a0 += stage[(size_t)c * T + t];
+    const double a = (a0 + a1) + (a2 + a3);
     if (t < F * K) {
         if (grad_w != nullptr) grad_w[t] = (float)a;
     } else if (grad_b != nullptr) {
@@ -940,7 +961,7 @@ void launch_slam_pixels(unsigned nblk, hipStream_t s, const float* out, int64_t 
                         uint8_t* masks, double* partials, float* dec_partials) {
     // the decoder-gradient path is its own instantiation, so that the plain
     // loss keeps its register budget
-    const size_t lds = dec_lds_bytes<F, KC>();
+    const size_t lds = dec_lds_bytes(F, K);
     if (dec_partials != nullptr && F > 0)
         hipLaunchKernelGGL((k_slam_loss<F, KC, kSemDzDec>), dim3(nblk), dim3(kSlamThreads), lds, s, out, P, rgb_t,
                            depth_t, labels, Wt, bias, K, sp, med, views, n_views, grad_out, masks, partials,
