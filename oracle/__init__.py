@@ -307,6 +307,37 @@ def slam_loss(out, wh, rgb_t, depth_t, labels=None, decoder=None, opts: SlamLoss
     return g, terms, masks, med_out
 
 
+def expand(views, masks, rgb_t, depth_t, feat_init, n0: int, capacity: int, F: int):
+    """Adaptive expansion (Sec. 3.3.1-3.3.2): new Gaussians at the pixels with
+    M_unobs and a valid depth.  Returns (count of candidates, dict of FP64
+    SoA planes with `capacity` columns; only columns [n0, n0 + count) capped
+    at capacity are written)."""
+    L = lib()
+    va = views_array(views, np.float64)
+    out = {"mu": np.zeros((3, capacity)), "log_scale": np.zeros((3, capacity)), "quat": np.zeros((4, capacity)),
+           "logit": np.zeros(capacity), "color": np.zeros((3, capacity)), "feat": np.zeros((max(F, 1), capacity))}
+    fi = np.ascontiguousarray(feat_init if F > 0 else np.zeros((1, 1)), np.float64)
+    L.orc_expand.restype = ctypes.c_int64
+    cnt = L.orc_expand(ctypes.c_int(F), ctypes.c_int(len(views)), _p(va), _p(np.ascontiguousarray(masks, np.uint8)),
+                       _p(np.ascontiguousarray(rgb_t, np.float64)), _p(np.ascontiguousarray(depth_t, np.float64)),
+                       _p(fi), ctypes.c_int64(n0), ctypes.c_int64(capacity), _p(out["mu"]), _p(out["log_scale"]),
+                       _p(out["quat"]), _p(out["logit"]), _p(out["color"]), _p(out["feat"]))
+    return int(cnt), out
+
+
+def dsr(log_scale, w_big: float = 0.01, w_small: float = 0.001):
+    """Depth-adaptive scale regularisation, Eq. (12), over the 3n per-axis
+    scales; returns (dict of L_big, L_small, loss, mu, sigma, n_big, n_small;
+    gradient with respect to log_scale, FP64 [3][n])."""
+    ls = np.ascontiguousarray(log_scale, np.float32)
+    g = np.zeros(ls.shape, np.float64)
+    o = np.zeros(7)
+    lib().orc_dsr(ctypes.c_int64(ls.size // 3), _p(ls), ctypes.c_double(w_big), ctypes.c_double(w_small), _p(g),
+                  _p(o))
+    keys = ("L_big", "L_small", "loss", "mu", "sigma", "n_big", "n_small")
+    return dict(zip(keys, o.tolist())), g
+
+
 GRAD_PARAMS = 1
 GRAD_POSE = 2
 

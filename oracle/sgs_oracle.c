@@ -1241,3 +1241,110 @@ void orc_slam_loss2(int F, int K, int V, const int32_t* wh, const int64_t* norm_
     terms[3] = T[3];
     terms[4] = T[0] + T[1] + T[2] + T[3];
 }
+
+/* ========================================================================= */
+/* Map growth and scale regularisation (Sec. 3.3.1-3.3.2).                    */
+/* ========================================================================= */
+
+/* Adaptive expansion (Sec. 3.3.1 with the initialisation of Sec. 3.3.2):
+ * every pixel with M_unobs (masks bit 1) and an observed depth D* > 0 adds
+ * one Gaussian, in (view, row, column) order, appended at index n0, n0 + 1,
+ * ... while below `capacity`:
+ *   mean: the pixel centre (u + 1/2, v + 1/2) unprojected at D*:
+ *     x_c = ((u + 1/2 - cx) / fx * D*, (v + 1/2 - cy) / fy * D*, D*),
+ *     mu = R^T (x_c - t) for the view's world-to-camera [R|t];
+ *   colour: the observed colour C*(p); features: feat_init[.][p] (random
+ *   numbers drawn by the caller); opacity 0.5 (logit 0); log-scale
+ *   log(D* / fx) on all three axes; rotation the identity (1, 0, 0, 0).
+ * Arrays are structure-of-arrays with `capacity` columns.  Returns the number
+ * of candidate pixels (the new count is min(n0 + that, capacity)). */
+int64_t orc_expand(int F, int V, const double* views, const uint8_t* masks, const double* rgb_t,
+                   const double* depth_t, const double* feat_init, int64_t n0, int64_t capacity, double* mu,
+                   double* ls, double* quat, double* logit, double* color, double* feat) {
+    int64_t P = 0;
+    for (int v = 0; v < V; ++v) P += (int64_t)views[VSTRIDE * v] * (int64_t)views[VSTRIDE * v + 1];
+    int64_t base = 0, cnt = 0;
+    for (int v = 0; v < V; ++v) {
+        const double* vw = views + VSTRIDE * v;
+        const int W = (int)vw[0], H = (int)vw[1];
+        const double fx = vw[2], fy = vw[3], cx = vw[4], cy = vw[5];
+        const double* R = vw + 6;
+        const double* t = vw + 15;
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                const int64_t p = base + (int64_t)y * W + x;
+                const double d = depth_t[p];
+                if (!((masks[p] >> 1) & 1) || !((float)d > 0.0f)) continue;
+                const int64_t i = n0 + cnt++;
+                if (i >= capacity) continue;
+                const double xc[3] = {(x + 0.5 - cx) / fx * d, (y + 0.5 - cy) / fy * d, d};
+                const double r[3] = {xc[0] - t[0], xc[1] - t[1], xc[2] - t[2]};
+                for (int a = 0; a < 3; ++a) {
+                    mu[(size_t)a * capacity + i] = R[a] * r[0] + R[3 + a] * r[1] + R[6 + a] * r[2];
+                    ls[(size_t)a * capacity + i] = log(d / fx);
+                    color[(size_t)a * capacity + i] = rgb_t[(size_t)a * P + p];
+                }
+                quat[i] = 1.0;
+                quat[(size_t)capacity + i] = 0.0;
+                quat[(size_t)2 * capacity + i] = 0.0;
+                quat[(size_t)3 * capacity + i] = 0.0;
+                logit[i] = 0.0;
+                for (int f = 0; f < F; ++f) feat[(size_t)f * capacity + i] = feat_init[(size_t)f * P + p];
+            }
+        base += (int64_t)W * H;
+    }
+    return cnt;
+}
+
+/* Depth-adaptive scale regularisation, Eq. (12), over the 3n per-axis
+ * scales s = exp(log s) (binary32, by the decision-path exponential dec_expf
+ * as in the projection, so that both sides hold the same samples):
+ *   mu_s, sigma_s = mean and population standard deviation of the samples,
+ *   s_big = mu_s + 2 sigma_s, s_small = mu_s - 2 sigma_s,
+ *   L_big = mean of s over the samples with s > s_big,
+ *   L_small = mean of -log s over the samples with s < s_small,
+ * each 0 when its set is empty; loss = w_big L_big + w_small L_small.
+ * The thresholds and counts are constants of the gradient (they only move
+ * the set boundaries): d loss / d log s = w_big s / n_big on the big set,
+ * -w_small / n_small on the small set; added into grad_ls (may be NULL).
+ * out[7] = (L_big, L_small, loss, mu_s, sigma_s, n_big, n_small). */
+void orc_dsr(int64_t n, const float* log_scale, double w_big, double w_small, double* grad_ls, double* out) {
+    const int64_t m = 3 * n;
+    double sum = 0.0;
+    for (int64_t j = 0; j < m; ++j) sum += (double)dec_expf(log_scale[j]);
+    const double mean = m > 0 ? sum / (double)m : 0.0;
+    double ss = 0.0;
+    for (int64_t j = 0; j < m; ++j) {
+        const double e = (double)dec_expf(log_scale[j]) - mean;
+        ss += e * e;
+    }
+    const double sd = m > 0 ? sqrt(ss / (double)m) : 0.0;
+    const double big = mean + 2.0 * sd, small = mean - 2.0 * sd;
+    double sb = 0.0, sm = 0.0;
+    int64_t nb = 0, ns = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        const double s = (double)dec_expf(log_scale[j]);
+        if (s > big) {
+            sb += s;
+            ++nb;
+        }
+        if (s < small) {
+            sm += -log(s);
+            ++ns;
+        }
+    }
+    const double Lb = nb > 0 ? sb / (double)nb : 0.0, Ls = ns > 0 ? sm / (double)ns : 0.0;
+    if (grad_ls)
+        for (int64_t j = 0; j < m; ++j) {
+            const double s = (double)dec_expf(log_scale[j]);
+            if (s > big) grad_ls[j] += w_big * s / (double)nb;
+            if (s < small) grad_ls[j] += -w_small / (double)ns;
+        }
+    out[0] = Lb;
+    out[1] = Ls;
+    out[2] = w_big * Lb + w_small * Ls;
+    out[3] = mean;
+    out[4] = sd;
+    out[5] = (double)nb;
+    out[6] = (double)ns;
+}
