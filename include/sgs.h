@@ -305,6 +305,57 @@ int gs_slam_loss(const float* out, int32_t n_feat, const float* rgb_target, cons
                  uint8_t* masks, void* ws, size_t ws_bytes, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * gs_expand -- adaptive Gaussian expansion, Sec. 3.3.1 (which pixels: the
+ * unobserved-region mask, Eq. 11) with the initialisation of Sec. 3.3.2.
+ * Every pixel p with M_unobs (bit 1 of masks, as gs_slam_loss writes it)
+ * and an observed depth D*(p) > 0 adds one Gaussian, appended in pixel order
+ * (views back to back, rows, columns) at index n, n + 1, ... while below
+ * `capacity`:
+ *   mean     the pixel centre (u + 1/2, v + 1/2) unprojected at D*:
+ *            x_c = ((u + 1/2 - cx)/fx D*, (v + 1/2 - cy)/fy D*, D*),
+ *            mu = R^T (x_c - t) for the view's world-to-camera [R|t];
+ *   colour   the observed colour rgb_target[.][p];
+ *   feature  feat_init[.][p] (random values drawn by the caller, the paper's
+ *            random semantic coefficients), n_feat rows;
+ *   opacity  0.5 (logit 0); log-scale log(D* / fx) on all three axes;
+ *   rotation the identity quaternion (1, 0, 0, 0).
+ * dst: the parameter planes (device), each with `capacity` columns.
+ * n_dev (device int64, in/out): the current Gaussian count on entry,
+ * min(count + candidates, capacity) on exit.  candidates_dev (device int64,
+ * may be NULL): the number of candidate pixels.  Nothing is read back on the
+ * host, so the call can be captured in a graph.  ws: gs_expand_workspace
+ * bytes, 256-byte aligned.  Errors: GS_EINVAL (null pointer, bad views),
+ * GS_ECAPACITY (ws too small), GS_EUNSUPPORTED (n_feat).
+ * --------------------------------------------------------------------------- */
+typedef gs_gaussian_grads gs_gaussian_planes; /* writable parameter planes */
+
+int gs_expand_workspace(int64_t total_pixels, size_t* bytes);
+int gs_expand(const uint8_t* masks, const float* rgb_target, const float* depth_target, const float* feat_init,
+              int32_t n_feat, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+              const gs_gaussian_planes* dst, int64_t capacity, int64_t* n_dev, int64_t* candidates_dev, void* ws,
+              size_t ws_bytes, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_dsr -- depth-adaptive scale regularisation, Sec. 3.3.2, Eq. (12), over
+ * the 3n per-axis scales s = exp(log s) of log_scale [3][n] (device; the
+ * exponential is the projection's decision-path one, so the samples are the
+ * same bits as any implementation of that sequence):
+ *   mu_s, sigma_s: their mean and population standard deviation;
+ *   L_big   = mean of s over {s > mu_s + 2 sigma_s},
+ *   L_small = mean of -log s over {s < mu_s - 2 sigma_s} (0 for empty sets);
+ *   loss    = w_big L_big + w_small L_small (Supp. C.1: 0.01, 0.001).
+ * grad_log_scale [3][n] (device, may be NULL) is ACCUMULATED (+=) with
+ * d loss / d log s, the sets and their counts held: w_big s / n_big on the
+ * big set, -w_small / n_small on the small set.  out[7] (device double) =
+ * (L_big, L_small, loss, mu_s, sigma_s, n_big, n_small).  Every sum is in a
+ * fixed order (deterministic).  ws: gs_dsr_workspace bytes, 256-byte
+ * aligned.  Errors: GS_EINVAL (n < 1, null pointer), GS_ECAPACITY.
+ * --------------------------------------------------------------------------- */
+int gs_dsr_workspace(int64_t n, size_t* bytes);
+int gs_dsr(const float* log_scale, int64_t n, float w_big, float w_small, float* grad_log_scale, double* out,
+           void* ws, size_t ws_bytes, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
  * gs_render_bwd -- backward of gs_render_fwd.  Re-traverses each pixel's list
  * from `last` down, rebuilding T_i = T_{i+1} / (1 - alpha_i), and forms
  *   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),

@@ -24,8 +24,8 @@ EXPORTS = [
     "gs_default_config", "gs_views_layout", "gs_app_stride", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
     "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
     "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_pose_grad_workspace",
-    "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_error_string",
-    "gs_last_hip_error", "gs_version",
+    "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_expand_workspace",
+    "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_error_string", "gs_last_hip_error", "gs_version",
 ]
 GS_LOSS_OBS_MASK, GS_LOSS_BCE = 1, 2
 
@@ -117,6 +117,11 @@ def load() -> ctypes.CDLL:
     L.gs_slam_loss.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, P(GsDecoder), P(GsSlamLossOpts),
                                P(GsView), c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_size_t, c_void_p]
+    L.gs_expand_workspace.argtypes = [c_int64, P(c_size_t)]
+    L.gs_expand.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, P(GsView), c_void_p, c_int32,
+                            P(GsGaussianGrads), c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.gs_dsr_workspace.argtypes = [c_int64, P(c_size_t)]
+    L.gs_dsr.argtypes = [c_void_p, c_int64, c_float, c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.gs_error_string.argtypes = [ctypes.c_int]
     L.gs_error_string.restype = ctypes.c_char_p
     L.gs_last_hip_error.restype = ctypes.c_char_p

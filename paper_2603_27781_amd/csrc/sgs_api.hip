@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "sgs_common.h"
+#include "growth.h"
 
 using namespace sgs;
 
@@ -272,6 +273,44 @@ int gs_slam_loss(const float* out, int32_t n_feat, const float* rgb_target, cons
     return hip_status(launch_slam_loss(out, n_feat, rgb_target, depth_target, labels, dec != nullptr ? &d : nullptr,
                                        *opts, views, views_dev, n_views, P, grad_out, loss, median, masks, ws,
                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_expand_workspace(int64_t total_pixels, size_t* bytes) {
+    if (!bytes || total_pixels < 1) return GS_EINVAL;
+    *bytes = expand_workspace_bytes(total_pixels);
+    return GS_OK;
+}
+
+int gs_expand(const uint8_t* masks, const float* rgb_target, const float* depth_target, const float* feat_init,
+              int32_t n_feat, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+              const gs_gaussian_planes* dst, int64_t capacity, int64_t* n_dev, int64_t* candidates_dev, void* ws,
+              size_t ws_bytes, gs_stream stream) {
+    if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
+    int64_t P = 0;
+    int st = check_views(views, views_dev, n_views, 0, &P, nullptr);
+    if (st) return st;
+    if (!masks || !rgb_target || !depth_target || !dst || !n_dev || !ws || capacity < 1) return GS_EINVAL;
+    if (!dst->mu || !dst->log_scale || !dst->quat || !dst->opacity_logit || !dst->color) return GS_EINVAL;
+    if (n_feat > 0 && (!dst->feat || !feat_init)) return GS_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return GS_EINVAL;
+    if (ws_bytes < expand_workspace_bytes(P)) return GS_ECAPACITY;
+    return hip_status(launch_expand(masks, rgb_target, depth_target, feat_init, n_feat, P, views_dev, n_views, n_dev,
+                                    capacity, candidates_dev, *dst, ws, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_dsr_workspace(int64_t n, size_t* bytes) {
+    if (!bytes || n < 1) return GS_EINVAL;
+    *bytes = dsr_workspace_bytes(n);
+    return GS_OK;
+}
+
+int gs_dsr(const float* log_scale, int64_t n, float w_big, float w_small, float* grad_log_scale, double* out,
+           void* ws, size_t ws_bytes, gs_stream stream) {
+    if (!log_scale || !out || !ws || n < 1 || n > (1ll << 40)) return GS_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return GS_EINVAL;
+    if (ws_bytes < dsr_workspace_bytes(n)) return GS_ECAPACITY;
+    return hip_status(launch_dsr(log_scale, n, w_big, w_small, grad_log_scale, out, ws,
+                                 reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags,

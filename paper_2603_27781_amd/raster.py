@@ -382,3 +382,46 @@ class RasterizeFunction(torch.autograd.Function):
 
 def rasterize(rast: Rasterizer, xi, mu, log_scale, quat, logit, color, feat) -> torch.Tensor:
     return RasterizeFunction.apply(rast, xi, mu, log_scale, quat, logit, color, feat)
+
+
+# ---------------------------------------------------------------------------
+# map growth and scale regularisation (Sec. 3.3.1-3.3.2)
+# ---------------------------------------------------------------------------
+def expand(views: Views, masks, rgb_t, depth_t, feat_init, planes: dict, capacity: int, n_dev: torch.Tensor,
+           n_feat: int, candidates: Optional[torch.Tensor] = None) -> None:
+    """gs_expand: appends Gaussians for the pixels with M_unobs and a valid
+    depth to `planes` (device tensors mu [3][cap], log_scale [3][cap],
+    quat [4][cap], logit [cap], color [3][cap], feat [F][cap]); n_dev (int64
+    device scalar) is the count, updated on the device."""
+    L = _lib.load()
+    b = ctypes.c_size_t(0)
+    check(L.gs_expand_workspace(views.total_pixels, ctypes.byref(b)), "gs_expand_workspace")
+    ws = torch.empty(b.value + 256, dtype=torch.uint8, device=masks.device)
+    off = (-ws.data_ptr()) % 256
+    dst = GsGaussianGrads(planes["mu"].data_ptr(), planes["log_scale"].data_ptr(), planes["quat"].data_ptr(),
+                          planes["logit"].data_ptr(), planes["color"].data_ptr(),
+                          planes["feat"].data_ptr() if n_feat > 0 else None)
+    check(L.gs_expand(masks.data_ptr(), rgb_t.data_ptr(), depth_t.data_ptr(),
+                      feat_init.data_ptr() if feat_init is not None else None, n_feat, views.host, views.dev_ptr(),
+                      views.n, ctypes.byref(dst), capacity, n_dev.data_ptr(),
+                      candidates.data_ptr() if candidates is not None else None, ws.data_ptr() + off, b.value,
+                      _stream()), "gs_expand")
+
+
+def dsr(log_scale: torch.Tensor, w_big: float = 0.01, w_small: float = 0.001,
+        grad_log_scale: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """gs_dsr: Eq. (12) over log_scale [3][n]; returns the device double[7]
+    (L_big, L_small, loss, mu, sigma, n_big, n_small) and accumulates the
+    gradient into grad_log_scale when given."""
+    L = _lib.load()
+    n = log_scale.shape[-1]
+    b = ctypes.c_size_t(0)
+    check(L.gs_dsr_workspace(n, ctypes.byref(b)), "gs_dsr_workspace")
+    ws = torch.empty(b.value + 256, dtype=torch.uint8, device=log_scale.device)
+    off = (-ws.data_ptr()) % 256
+    out = torch.zeros(7, dtype=torch.float64, device=log_scale.device)
+    check(L.gs_dsr(log_scale.data_ptr(), n, w_big, w_small,
+                   grad_log_scale.data_ptr() if grad_log_scale is not None else None, out.data_ptr(),
+                   ws.data_ptr() + off, b.value, _stream()), "gs_dsr")
+    return out
+
