@@ -300,6 +300,11 @@ def main():
     if not args.no_slam:
         slam = slam_loss_bench(r, rgb_t, dep_t, lab, W, args.steps, args.warmup, F, P)
 
+    # ------------------------------------------------ map growth, DSR
+    growth = None
+    if not args.no_slam:
+        growth = growth_bench(r, g, w, rgb_t, dep_t, args.steps, F, P)
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
@@ -317,7 +322,7 @@ def main():
                    "lds_batch_bwd": cfg.lds_batch_bwd},
         "per_view": per_view, "other_launch_mode": other,
         "entry_us": {k: round(v, 2) for k, v in kern_us.items()},
-        "roofline": roofline, "cpu_baseline": cpu, "slam_loss": slam,
+        "roofline": roofline, "cpu_baseline": cpu, "slam_loss": slam, "growth": growth,
     }
     print(json.dumps(rec), flush=True)
 
@@ -381,6 +386,59 @@ def slam_loss_bench(r, rgb_t, dep_t, lab, W, steps, warmup, F, P):
         + "".join(f"{m} {res[m]['us']:.1f} us, " for m in ("mapping_decoder_grad", "mapping_bce_decoder_grad")
                   if m in res)
         + f"masks obs {res['mask_fraction']['obs']}, unobs {res['mask_fraction']['unobs']}")
+    return res
+
+
+def growth_bench(r, g, w, rgb_t, dep_t, steps, F, P):
+    """gs_expand on the masks the SLAM loss left (M_unobs of the bench batch,
+    random features drawn here) into planes with room for every pixel, and
+    gs_dsr over the workload's 1M Gaussians (3M scales) with its gradient.
+    Times from HIP events over `steps` calls; algorithmic bytes: expansion
+    reads the mask byte and depth of every pixel and writes 4(14 + F) B per
+    new Gaussian from 4(3 + F) B of colour and features read; DSR reads the
+    3n log-scales once and read-modify-writes the gradient."""
+    import torch
+    from paper_2603_27781_amd import raster
+    n = w.scene.n
+    cap = n + P
+    planes = {"mu": torch.zeros(3, cap, device="cuda"), "log_scale": torch.zeros(3, cap, device="cuda"),
+              "quat": torch.zeros(4, cap, device="cuda"), "logit": torch.zeros(cap, device="cuda"),
+              "color": torch.zeros(3, cap, device="cuda"), "feat": torch.zeros(max(F, 1), cap, device="cuda")}
+    rng = np.random.default_rng(1234)
+    feat_init = torch.from_numpy(rng.normal(size=(max(F, 1), P)).astype(np.float32)).cuda()
+    n_dev = torch.tensor([n], dtype=torch.int64, device="cuda")
+    cand = torch.zeros(1, dtype=torch.int64, device="cuda")
+    masks = r.masks[:P]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    raster.expand(r.views, masks, rgb_t, dep_t, feat_init, planes, cap, n_dev, F, cand)  # warm-up
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        n_dev.fill_(n)
+        raster.expand(r.views, masks, rgb_t, dep_t, feat_init, planes, cap, n_dev, F, cand)
+    b.record()
+    torch.cuda.synchronize()
+    us_e = a.elapsed_time(b) / steps * 1e3
+    added = int(cand.item())
+    ls = g.log_scale.reshape(3, -1)
+    grad = torch.zeros_like(ls)
+    raster.dsr(ls, 0.01, 0.001, grad)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        out = raster.dsr(ls, 0.01, 0.001, grad)
+    b.record()
+    torch.cuda.synchronize()
+    us_d = a.elapsed_time(b) / steps * 1e3
+    o = out.cpu().tolist()
+    alg_e = P * (1 + 4) + added * (4 * (14 + F) + 4 * (3 + F))
+    alg_d = 3 * n * 4 + 3 * n * 8
+    res = {"expand": {"us": round(us_e, 2), "new_gaussians": added, "algorithmic_bytes": int(alg_e),
+                      "hbm_frac": round(alg_e / (us_e * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+           "dsr": {"us": round(us_d, 2), "gaussians": n, "L_big": round(o[0], 6), "L_small": round(o[1], 6),
+                   "n_big": int(o[5]), "n_small": int(o[6]), "algorithmic_bytes": int(alg_d),
+                   "hbm_frac": round(alg_d / (us_d * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
+    log(f"growth: expand {us_e:.1f} us ({added} new), dsr {us_d:.1f} us")
     return res
 
 
