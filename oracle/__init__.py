@@ -338,6 +338,34 @@ def dsr(log_scale, w_big: float = 0.01, w_small: float = 0.001):
     return dict(zip(keys, o.tolist())), g
 
 
+def adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on FP64 arrays (bias-corrected at step t >= 1)."""
+    arrs = [np.ascontiguousarray(a, np.float64) for a in (p, g, m, v)]
+    lib().orc_adam(ctypes.c_int64(arrs[0].size), _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), _p(arrs[3]),
+                   ctypes.c_double(lr), ctypes.c_double(b1), ctypes.c_double(b2), ctypes.c_double(eps), ctypes.c_int(t))
+    return arrs[0], arrs[2], arrs[3]
+
+
+def se3_exp(xi) -> np.ndarray:
+    """3x4 [R|t] = Exp(xi), xi = (rho, phi)."""
+    x = np.ascontiguousarray(xi, np.float64)
+    out = np.zeros(12)
+    lib().orc_se3_exp(_p(x), _p(out))
+    return out.reshape(3, 4)
+
+
+def pose_step(Rt, grad, m, v, lr_rho, lr_phi, t, b1=0.9, b2=0.999, eps=1e-8):
+    """Tracking pose step for V views: Adam on the twist, then T <- Exp(dxi) T."""
+    R = np.ascontiguousarray(Rt, np.float64).reshape(-1, 12).copy()
+    gg = np.ascontiguousarray(grad, np.float64).reshape(-1, 6)
+    mm = np.ascontiguousarray(m, np.float64).reshape(-1, 6).copy()
+    vv = np.ascontiguousarray(v, np.float64).reshape(-1, 6).copy()
+    lib().orc_pose_step(ctypes.c_int(R.shape[0]), _p(R), _p(gg), _p(mm), _p(vv), ctypes.c_double(lr_rho),
+                        ctypes.c_double(lr_phi), ctypes.c_double(b1), ctypes.c_double(b2), ctypes.c_double(eps),
+                        ctypes.c_int(t))
+    return R.reshape(-1, 3, 4), mm, vv
+
+
 GRAD_PARAMS = 1
 GRAD_POSE = 2
 

@@ -1348,3 +1348,85 @@ void orc_dsr(int64_t n, const float* log_scale, double w_big, double w_small, do
     out[5] = (double)nb;
     out[6] = (double)ns;
 }
+
+/* ========================================================================= */
+/* Optimiser steps of the SLAM loop (Supp. C.1 learning rates).              */
+/* ========================================================================= */
+
+/* Adam (Kingma and Ba, 2015) on n values with bias correction at step t
+ * (from 1): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+ * p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+void orc_adam(int64_t n, double* p, const double* g, double* m, double* v, double lr, double b1, double b2,
+              double eps, int t) {
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* SE(3) exponential of a twist (rho, phi) (translation first) as a 3x4
+ * [R|t]: R = I + (sin th / th) [phi]x + ((1 - cos th) / th^2) [phi]x^2,
+ * t = (I + ((1 - cos th) / th^2) [phi]x + ((th - sin th) / th^3) [phi]x^2) rho,
+ * th = |phi| (series near 0). */
+void orc_se3_exp(const double* xi, double* Rt) {
+    const double* rho = xi;
+    const double* phi = xi + 3;
+    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2], th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-4) {
+        A = 1.0 - th2 / 6.0;
+        B = 0.5 - th2 / 24.0;
+        C = 1.0 / 6.0 - th2 / 120.0;
+    } else {
+        A = sin(th) / th;
+        B = (1.0 - cos(th)) / th2;
+        C = (th - sin(th)) / (th2 * th);
+    }
+    const double K[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
+    double K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += K[3 * i + k] * K[3 * k + j];
+            K2[3 * i + j] = s;
+        }
+    for (int i = 0; i < 3; ++i) {
+        double tv = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double I = i == j ? 1.0 : 0.0;
+            Rt[4 * i + j] = I + A * K[3 * i + j] + B * K2[3 * i + j];
+            tv += (I + B * K[3 * i + j] + C * K2[3 * i + j]) * rho[j];
+        }
+        Rt[4 * i + 3] = tv;
+    }
+}
+
+/* Tracking's pose step for V views: Adam on each view's twist gradient
+ * (per-component learning rate lr_rho for the translation part, lr_phi for
+ * the rotation part), then the left update T <- Exp(dxi) T of the view's
+ * world-to-camera [R|t] (Rt [V][12], row-major 3x4). */
+void orc_pose_step(int V, double* Rt, const double* grad, double* m, double* v, double lr_rho, double lr_phi,
+                   double b1, double b2, double eps, int t) {
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int w = 0; w < V; ++w) {
+        double dxi[6];
+        for (int k = 0; k < 6; ++k) {
+            const int i = 6 * w + k;
+            m[i] = b1 * m[i] + (1.0 - b1) * grad[i];
+            v[i] = b2 * v[i] + (1.0 - b2) * grad[i] * grad[i];
+            dxi[k] = -(k < 3 ? lr_rho : lr_phi) * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+        }
+        double E[12], T[12];
+        orc_se3_exp(dxi, E);
+        memcpy(T, Rt + 12 * w, sizeof(T));
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 4; ++j) {
+                double s = j == 3 ? E[4 * i + 3] : 0.0;
+                for (int k = 0; k < 3; ++k) s += E[4 * i + k] * T[4 * k + j];
+                Rt[12 * w + 4 * i + j] = s;
+            }
+        }
+    }
+}
