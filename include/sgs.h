@@ -356,6 +356,36 @@ int gs_dsr(const float* log_scale, int64_t n, float w_big, float w_small, float*
            void* ws, size_t ws_bytes, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * gs_adam_step -- one Adam step (Kingma and Ba 2015, bias-corrected at step
+ * `step` >= 1) over up to 8 parameter groups in one launch, each with its
+ * own learning rate (Supp. C.1 gives the per-attribute rates of mapping):
+ *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+ *   p <- p - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * groups is a HOST array; every pointer in it is device memory (param, m, v
+ * updated in place; grad read).  Binary32 throughout.
+ * gs_pose_step -- tracking's pose update (Sec. 3.4): Adam as above on each
+ * view's twist gradient twist_grad [V][6] = dL/d(rho, phi) (learning rate
+ * lr_rho for rho, lr_phi for phi; m, v [V][6] device state), then the left
+ * update T <- Exp(dxi) T of the view's world-to-camera [R|t], written in
+ * place into views_dev (the records the other kernels read), so an
+ * iteration needs no host round trip.  Errors: GS_EINVAL.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    float* param;
+    const float* grad;
+    float* m;
+    float* v;
+    int64_t n;
+    float lr;
+    int32_t reserved;
+} gs_adam_group;
+
+int gs_adam_step(const gs_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps, int32_t step,
+                 gs_stream stream);
+int gs_pose_step(gs_view* views_dev, int32_t n_views, const float* twist_grad, float* m, float* v, float lr_rho,
+                 float lr_phi, float beta1, float beta2, float eps, int32_t step, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
  * gs_render_bwd -- backward of gs_render_fwd.  Re-traverses each pixel's list
  * from `last` down, rebuilding T_i = T_{i+1} / (1 - alpha_i), and forms
  *   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),

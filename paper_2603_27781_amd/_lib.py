@@ -25,7 +25,8 @@ EXPORTS = [
     "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
     "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_pose_grad_workspace",
     "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_expand_workspace",
-    "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_error_string", "gs_last_hip_error", "gs_version",
+    "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_adam_step", "gs_pose_step", "gs_error_string",
+    "gs_last_hip_error", "gs_version",
 ]
 GS_LOSS_OBS_MASK, GS_LOSS_BCE = 1, 2
 
@@ -56,6 +57,11 @@ class GsSlamLossOpts(ctypes.Structure):
     _fields_ = [("w_color", c_float), ("w_depth", c_float), ("w_sem", c_float), ("ssim_lambda", c_float),
                 ("tau_obs", c_float), ("tau_unobs", c_float), ("obs_factor", c_float), ("unobs_factor", c_float),
                 ("flags", c_uint32)]
+
+
+class GsAdamGroup(ctypes.Structure):
+    _fields_ = [("param", c_void_p), ("grad", c_void_p), ("m", c_void_p), ("v", c_void_p), ("n", c_int64),
+                ("lr", c_float), ("reserved", c_int32)]
 
 
 class GsDecoder(ctypes.Structure):
@@ -122,6 +128,9 @@ def load() -> ctypes.CDLL:
                             P(GsGaussianGrads), c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.gs_dsr_workspace.argtypes = [c_int64, P(c_size_t)]
     L.gs_dsr.argtypes = [c_void_p, c_int64, c_float, c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.gs_adam_step.argtypes = [ctypes.c_void_p, c_int32, c_float, c_float, c_float, c_int32, c_void_p]
+    L.gs_pose_step.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float, c_float,
+                               c_float, c_int32, c_void_p]
     L.gs_error_string.argtypes = [ctypes.c_int]
     L.gs_error_string.restype = ctypes.c_char_p
     L.gs_last_hip_error.restype = ctypes.c_char_p

@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgs.so")
 SOURCES = ["sgs_api.hip", "project.hip", "binsort.hip", "render_fwd.hip", "render_bwd.hip", "loss.hip",
-           "project_bwd.hip", "slam_loss.hip", "growth.hip"]
+           "project_bwd.hip", "slam_loss.hip", "growth.hip", "optim.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,0 +1,17 @@
+// Launchers of the optimiser kernels (optim.hip).
+#pragma once
+
+#include <cmath>
+
+#include "sgs_common.h"
+
+namespace sgs {
+
+constexpr int kAdamGroups = 8;
+
+hipError_t launch_adam(const gs_adam_group* groups, int n_groups, float b1, float b2, float eps, int step,
+                       hipStream_t s);
+hipError_t launch_pose_step(gs_view* views_dev, int n_views, const float* grad, float* m, float* v, float lr_rho,
+                            float lr_phi, float b1, float b2, float eps, int step, hipStream_t s);
+
+}  // namespace sgs

@@ -7,6 +7,7 @@
 
 #include "sgs_common.h"
 #include "growth.h"
+#include "optim.h"
 
 using namespace sgs;
 
@@ -311,6 +312,23 @@ int gs_dsr(const float* log_scale, int64_t n, float w_big, float w_small, float*
     if (ws_bytes < dsr_workspace_bytes(n)) return GS_ECAPACITY;
     return hip_status(launch_dsr(log_scale, n, w_big, w_small, grad_log_scale, out, ws,
                                  reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_adam_step(const gs_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps, int32_t step,
+                 gs_stream stream) {
+    if (!groups || n_groups < 1 || n_groups > kAdamGroups || step < 1) return GS_EINVAL;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f)) return GS_EINVAL;
+    for (int k = 0; k < n_groups; ++k)
+        if (!groups[k].param || !groups[k].grad || !groups[k].m || !groups[k].v || groups[k].n < 0) return GS_EINVAL;
+    return hip_status(launch_adam(groups, n_groups, beta1, beta2, eps, step, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_pose_step(gs_view* views_dev, int32_t n_views, const float* twist_grad, float* m, float* v, float lr_rho,
+                 float lr_phi, float beta1, float beta2, float eps, int32_t step, gs_stream stream) {
+    if (!views_dev || !twist_grad || !m || !v || n_views < 1 || n_views > GS_MAX_VIEWS || step < 1) return GS_EINVAL;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f)) return GS_EINVAL;
+    return hip_status(launch_pose_step(views_dev, n_views, twist_grad, m, v, lr_rho, lr_phi, beta1, beta2, eps, step,
+                                       reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags,

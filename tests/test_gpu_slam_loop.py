@@ -1,0 +1,154 @@
+"""The SLAM loop's device steps and iterations (Sec. 3.3-3.4, Supp. C.1).
+
+  - gs_adam_step against the oracle's Adam (several groups and steps):
+    binary32 against FP64, 1e-5 relative;
+  - gs_pose_step against the oracle's pose step (Adam on the twist, then
+    T <- Exp(dxi) T): 1e-5;
+  - tracking (40 iterations from the constant-velocity guess of a slightly
+    wrong pose) brings the pose close to the one the targets were rendered
+    at, and a mapping run lowers the mapping loss of a perturbed map:
+    properties of the loop (its FP64 counterpart would take minutes per
+    iteration on the host).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_27781_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_adam_step_parity():
+    from paper_2603_27781_amd import _lib, raster
+    L = _lib.load()
+    rng = np.random.default_rng(4)
+    sizes, lrs = [1000, 37, 70_001], [0.01, 0.05, 0.0001]
+    ps = [rng.normal(size=n).astype(np.float32) for n in sizes]
+    dp = [_dev(p) for p in ps]
+    dm = [torch.zeros(n, device="cuda") for n in sizes]
+    dv = [torch.zeros(n, device="cuda") for n in sizes]
+    ref = [(p.astype(np.float64), np.zeros(n), np.zeros(n)) for p, n in zip(ps, sizes)]
+    for t in range(1, 4):
+        gs = [rng.normal(size=n).astype(np.float32) for n in sizes]
+        dg = [_dev(x) for x in gs]
+        groups = (_lib.GsAdamGroup * 3)(*[_lib.GsAdamGroup(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                                           p.numel(), lr, 0)
+                                          for p, g, m, v, lr in zip(dp, dg, dm, dv, lrs)])
+        assert L.gs_adam_step(ctypes.cast(groups, ctypes.c_void_p), 3, 0.9, 0.999, 1e-8, t, raster._stream()) == 0
+        ref = [oracle.adam(p, g.astype(np.float64), m, v, float(np.float32(lr)), t)
+               for (p, m, v), g, lr in zip(ref, gs, lrs)]
+        torch.cuda.synchronize()
+        for (p, m, v), d in zip(ref, dp):
+            got = d.cpu().numpy()
+            assert np.max(np.abs(got - p)) <= 1e-5 * np.max(np.abs(p)), t
+
+
+def test_pose_step_parity():
+    from paper_2603_27781_amd import _lib, raster
+    L = _lib.load()
+    rng = np.random.default_rng(6)
+    V = 3
+    views = [wl.make_view(32, 24, 30.0, wl.se3_exp(rng.normal(size=6) * 0.3)) for _ in range(V)]
+    Vw = raster.Views(views, 16)
+    Rt = np.stack([np.asarray(v.Rt, np.float32).astype(np.float64) for v in views])
+    m = torch.zeros(V, 6, device="cuda")
+    v = torch.zeros(V, 6, device="cuda")
+    mr, vr = np.zeros((V, 6)), np.zeros((V, 6))
+    for t in range(1, 3):
+        g = rng.normal(size=(V, 6)).astype(np.float32)
+        assert L.gs_pose_step(Vw.dev_ptr(), V, _dev(g).data_ptr(), m.data_ptr(), v.data_ptr(), 0.002, 0.0004, 0.9,
+                              0.999, 1e-8, t, raster._stream()) == 0
+        Rt, mr, vr = oracle.pose_step(Rt, g.astype(np.float64), mr, vr, float(np.float32(0.002)),
+                                      float(np.float32(0.0004)), t)
+    torch.cuda.synchronize()
+    got = Vw.dev.view(torch.float32)[:, 6:18].cpu().numpy().reshape(V, 3, 4)
+    assert np.max(np.abs(got - Rt)) <= 1e-5
+
+
+def _small_world(seed=71, n=4000, F=8, K=6):
+    w = wl.tiny_scene(seed, n, F=F, W=64, H=48, f=50.0, log_scale_mu=-2.6, spread=1.2)
+    rng = np.random.default_rng(seed)
+    W = wl.decoder_matrix(rng, F, K)
+    return w, W
+
+
+def _render_targets(scene, view, K, seed):
+    from paper_2603_27781_amd import raster
+    cfg = raster.Config()
+    r = raster.Rasterizer(scene.n, scene.n_feat, raster.Views([view], cfg.tile), cfg)
+    g = raster.Gaussians.from_numpy(scene)
+    r.ensure_capacity(g)
+    out = r.forward(g).clone()
+    rng = np.random.default_rng(seed)
+    lab = _dev(rng.integers(0, K, out.shape[1]).astype(np.int32))
+    return out[:3].contiguous(), out[3].contiguous(), lab
+
+
+def test_tracking_recovers_the_pose():
+    from paper_2603_27781_amd import raster, slam
+    w, Wd = _small_world()
+    view = w.views[0]
+    T_gt = np.vstack([np.asarray(view.Rt, np.float64), [0, 0, 0, 1]])
+    rgb, dep, lab = _render_targets(w.scene, view, Wd.shape[1], 1)
+    # previous two poses: the truth moved back by a small constant velocity
+    dxi = np.array([0.01, -0.008, 0.006, 0.004, -0.006, 0.005])
+    T_prev = wl.se3_exp(-dxi) @ T_gt
+    T_prev2 = wl.se3_exp(-2 * dxi) @ T_gt
+    # a wrong start: 2.7 cm and 0.011 rad off (40 Adam steps at the paper's
+    # rates move at most 8 cm and 0.016 rad)
+    T0 = wl.se3_exp(np.array([0.02, 0.015, -0.01, 0.008, -0.006, 0.004])) @ T_gt
+    cfg = raster.Config()
+    r = raster.Rasterizer(w.scene.n, w.scene.n_feat, raster.Views([view], cfg.tile), cfg)
+    g = raster.Gaussians.from_numpy(w.scene)
+    r.ensure_capacity(g, slack=2.0)
+    tr = slam.Tracker(r, g, _dev(Wd))
+
+    def err(T):
+        D = T @ np.linalg.inv(T_gt)
+        ang = np.arccos(np.clip((np.trace(D[:3, :3]) - 1) / 2, -1, 1))
+        return np.linalg.norm(D[:3, 3]), ang
+
+    e0 = err(T0)
+    T = tr.track(rgb, dep, lab, T0, iters=40)
+    e1 = err(T)
+    _, _, over = r.instance_counts()
+    assert not over
+    assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1], (e0, e1)
+    # constant velocity itself (Eq. 19) predicts the uniform motion exactly
+    assert np.allclose(slam.constant_velocity(T_prev, T_prev2), T_gt, atol=1e-9)
+
+
+def test_mapping_lowers_the_loss():
+    from paper_2603_27781_amd import raster, slam
+    w, Wd = _small_world(seed=72)
+    view = w.views[0]
+    T = np.vstack([np.asarray(view.Rt, np.float64), [0, 0, 0, 1]])
+    rgb, dep, lab = _render_targets(w.scene, view, Wd.shape[1], 2)
+    start = wl.perturbed_copy(np.random.default_rng(5), w.scene)
+    cfg = raster.Config()
+    r = raster.Rasterizer(start.n, start.n_feat, raster.Views([view], cfg.tile), cfg)
+    g = raster.Gaussians.from_numpy(start)
+    r.ensure_capacity(g, slack=2.0)
+    mp = slam.Mapper(r, g, _dev(Wd))
+    losses = []
+    for k in range(30):
+        mp.iteration(rgb, dep, lab, T)
+        losses.append(float(r.slam_terms[4].item()))
+    _, _, over = r.instance_counts()
+    assert not over
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.8 * losses[0], losses
+    # RSKM: the current frame every t_opt-th iteration, uniform otherwise
+    rng = np.random.default_rng(0)
+    picks = [slam.rskm_pick(rng, 5, 4, k, 3) for k in range(300)]
+    assert all(picks[k] == 4 for k in range(0, 300, 3))
+    others = [picks[k] for k in range(300) if k % 3]
+    assert set(others) == {0, 1, 2, 3, 4}
