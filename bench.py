@@ -305,6 +305,11 @@ def main():
     if not args.no_slam:
         growth = growth_bench(r, g, w, rgb_t, dep_t, args.steps, F, P)
 
+    # ------------------------------------------- tracking / mapping iterations
+    slam_iter = None
+    if not args.no_slam:
+        slam_iter = slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, args.steps)
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
@@ -322,7 +327,7 @@ def main():
                    "lds_batch_bwd": cfg.lds_batch_bwd},
         "per_view": per_view, "other_launch_mode": other,
         "entry_us": {k: round(v, 2) for k, v in kern_us.items()},
-        "roofline": roofline, "cpu_baseline": cpu, "slam_loss": slam, "growth": growth,
+        "roofline": roofline, "cpu_baseline": cpu, "slam_loss": slam, "growth": growth, "slam_iteration": slam_iter,
     }
     print(json.dumps(rec), flush=True)
 
@@ -439,6 +444,53 @@ def growth_bench(r, g, w, rgb_t, dep_t, steps, F, P):
                    "n_big": int(o[5]), "n_small": int(o[6]), "algorithmic_bytes": int(alg_d),
                    "hbm_frac": round(alg_d / (us_d * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
     log(f"growth: expand {us_e:.1f} us ({added} new), dsr {us_d:.1f} us")
+    return res
+
+
+def slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, steps):
+    """One tracking iteration (render, tracking loss under M_obs, pose-only
+    backward, twist, Adam + SE(3) update) and one mapping iteration (render,
+    mapping loss with SSIM, full backward, DSR, Adam on every parameter) on
+    the first view of the workload with all its Gaussians, the shapes of the
+    paper's per-iteration times (one 1200x680 Replica frame).  HIP events
+    over `steps` eager iterations each (no graph: the host loop as written)."""
+    import torch
+    from paper_2603_27781_amd import raster, slam
+    v0 = w.views[0]
+    P0 = v0.width * v0.height
+    V1 = raster.Views([v0], cfg.tile)
+    r = raster.Rasterizer(g.n, g.n_feat, V1, cfg)
+    r.ensure_capacity(g, slack=1.5)
+    rgb1, dep1, lab1 = rgb_t[:, :P0].contiguous(), dep_t[:P0].contiguous(), lab[:P0].contiguous()
+    T = np.vstack([np.asarray(v0.Rt, np.float64), [0, 0, 0, 1]])
+    tr = slam.Tracker(r, g, W)
+    tr.set_pose(T)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tr.iteration(rgb1, dep1, lab1, 1)
+    torch.cuda.synchronize()
+    a.record()
+    for k in range(steps):
+        tr.iteration(rgb1, dep1, lab1, k + 2)
+    b.record()
+    torch.cuda.synchronize()
+    ms_t = a.elapsed_time(b) / steps
+    gm = raster.Gaussians(*(t.clone() for t in g.tensors()))
+    mp = slam.Mapper(r, gm, W)
+    mp.iteration(rgb1, dep1, lab1, T)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        mp.iteration(rgb1, dep1, lab1, T)
+    b.record()
+    torch.cuda.synchronize()
+    ms_m = a.elapsed_time(b) / steps
+    _, _, over = r.instance_counts()
+    res = {"view": f"{v0.width}x{v0.height}", "gaussians": g.n, "tracking_ms_per_iter": round(ms_t, 3),
+           "mapping_ms_per_iter": round(ms_m, 3), "capacity_overflow": bool(over),
+           "paper_rtx3090_ms_per_iter": {"tracking": 89, "mapping": 55}}
+    log(f"slam iterations: tracking {ms_t:.3f} ms, mapping {ms_m:.3f} ms per iteration")
+    del r, tr, mp, gm
+    torch.cuda.empty_cache()
     return res
 
 
