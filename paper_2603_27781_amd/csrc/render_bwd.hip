@@ -519,7 +519,9 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <
     __shared__ int s_tile;
     __shared__ int s_max;
     if (!persistent) {
-        bwd_tile<TS, F, B, PARAMS>(blockIdx.x, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, T_final,
+        const int t = tile_of_block<TS>(blockIdx.x, total_tiles);
+        if (t < 0) return;
+        bwd_tile<TS, F, B, PARAMS>(t, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, T_final,
                                    last, grad_out, records, s_g0, s_g1, s_app, &s_max, s_acc);
         return;
     }
@@ -689,7 +691,7 @@ hipError_t launch_bwd_t(const float* rec, const float* app, int n, const int32_t
                         const RasterConst& c, int persistent, const float* T_final, const int32_t* last,
                         const float* grad_out, float* records, int32_t* queue, hipStream_t s) {
     auto kern = k_render_bwd<TS, F, B, PARAMS>;
-    unsigned grid = (unsigned)total_tiles;
+    unsigned grid = total_tiles > 0 ? tile_grid<TS>(total_tiles) : 0u;
     if (persistent) {
         int dev = 0, cus = 0, per_cu = 0;
         (void)hipGetDevice(&dev);
@@ -698,7 +700,7 @@ hipError_t launch_bwd_t(const float* rec, const float* app, int n, const int32_t
         if (per_cu < 1) per_cu = 1;
         if (cus < 1) cus = 1;  // a failed query still drains the queue, with fewer workgroups
         const unsigned cap = (unsigned)(cus * per_cu);
-        grid = cap < grid ? cap : grid;
+        grid = cap < (unsigned)total_tiles ? cap : (unsigned)total_tiles;
         hipLaunchKernelGGL(k_reset_queue_bwd, dim3(1), dim3(64), 0, s, queue);
     }
     if (grid == 0) return hipGetLastError();

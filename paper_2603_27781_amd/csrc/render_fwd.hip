@@ -177,7 +177,9 @@ __global__ void __launch_bounds__(TS* TS) k_render_fwd(const float4* __restrict_
     __shared__ float4 s_app[B * AV];
     __shared__ int s_tile;
     if (!persistent) {
-        fwd_tile<TS, F, B>(blockIdx.x, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, out, T_final, last, s_g0,
+        const int t = tile_of_block<TS>(blockIdx.x, total_tiles);
+        if (t < 0) return;
+        fwd_tile<TS, F, B>(t, rec, app, n, inst, inst_gid, ranges, views, n_views, P, c, out, T_final, last, s_g0,
                            s_g1, s_app);
         return;
     }
@@ -202,7 +204,7 @@ hipError_t launch_fwd_t(const float* rec, const float* app, int n, const int32_t
                         const gs_view* views, int n_views, int total_tiles, int64_t P, const RasterConst& c,
                         int persistent, float* out, float* T_final, int32_t* last, int32_t* queue, hipStream_t s) {
     auto kern = k_render_fwd<TS, F, B>;
-    unsigned grid = (unsigned)total_tiles;
+    unsigned grid = total_tiles > 0 ? tile_grid<TS>(total_tiles) : 0u;
     if (persistent) {
         int dev = 0, cus = 0, per_cu = 0;
         (void)hipGetDevice(&dev);
@@ -211,7 +213,7 @@ hipError_t launch_fwd_t(const float* rec, const float* app, int n, const int32_t
         if (per_cu < 1) per_cu = 1;
         if (cus < 1) cus = 1;  // a failed query still drains the queue, with fewer workgroups
         unsigned cap = (unsigned)(cus * per_cu);
-        grid = cap < grid ? cap : grid;
+        grid = cap < (unsigned)total_tiles ? cap : (unsigned)total_tiles;
         hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, queue);
     }
     if (grid == 0) return hipGetLastError();

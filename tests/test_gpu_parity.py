@@ -202,6 +202,16 @@ def test_loss_grad_class_counts(K):
     _loss_case("tiny-F8", K=K)
 
 
+@pytest.mark.parametrize("name,K", [("tiny3views-F16", 1), ("tiny3views-F16", 16), ("tiny3views-F16", 17),
+                                    ("cfg2-160x120-20k-F16", 20), ("tiny3views-F16", 33), ("tiny-F32", 16),
+                                    ("tiny-F32", 32)])
+def test_loss_grad_class_counts_wide_features(name, K):
+    """Class counts with 16 and 32 feature channels (one class: the gradient
+    is exactly zero), on views whose pixel counts leave partial wavefronts and
+    workgroups that straddle two views."""
+    _loss_case(name, K=K)
+
+
 def _loss_case(name, K):
     """The loss of a synthetic render (seeded; not the GPU's render, so that
     no oracle input comes from the device) on the case's views."""
