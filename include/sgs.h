@@ -449,6 +449,16 @@ int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* v
                    const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, size_t grad2d_bytes,
                    gs_gaussian_grads* grads, gs_stream stream);
 
+/* gs_project_bwd_write -- gs_project_bwd that WRITES *grads instead of adding
+ * to them: every plane of every Gaussian is written, zeros where no view
+ * contributes, so a caller whose step starts from cleared gradients (one
+ * batched launch over all its views) need not clear them first, and the
+ * planes are not read.  Same arguments, layout and errors as gs_project_bwd;
+ * the values equal those of gs_project_bwd on cleared planes, bit for bit. */
+int gs_project_bwd_write(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                         const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d,
+                         size_t grad2d_bytes, gs_gaussian_grads* grads, gs_stream stream);
+
 /* ---------------------------------------------------------------------------
  * gs_pose_grad -- Supp. B.1 written as a twist of the left perturbation
  * T(xi) = Exp(xi) T_CW, xi = (rho, phi):

@@ -23,7 +23,8 @@ GS_GRAD_PARAMS, GS_GRAD_POSE = 1, 2
 EXPORTS = [
     "gs_default_config", "gs_views_layout", "gs_app_stride", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
     "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
-    "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_pose_grad_workspace",
+    "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_project_bwd_write",
+    "gs_pose_grad_workspace",
     "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_expand_workspace",
     "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_adam_step", "gs_pose_step", "gs_error_string",
     "gs_last_hip_error", "gs_version",
@@ -115,6 +116,7 @@ def load() -> ctypes.CDLL:
                                     c_uint32, c_void_p, c_size_t, c_void_p]
     L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
                                  c_size_t, P(GsGaussianGrads), c_void_p]
+    L.gs_project_bwd_write.argtypes = L.gs_project_bwd.argtypes
     L.gs_pose_grad_workspace.argtypes = [c_int32, c_int32, P(c_size_t)]
     L.gs_pose_grad.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
                                c_void_p, c_size_t, c_void_p, c_void_p]

@@ -47,16 +47,15 @@ class MappingStep:
         return self.r.ensure_capacity(self.g, slack)
 
     def run(self) -> None:
-        """One eager step: zero grads, project, bin, render, loss, backward."""
+        """One eager step: project, bin, render, loss, backward; the
+        projection backward writes the parameter gradients (one launch sums
+        every view), so they need no clearing first."""
         r = self.r
-        if self.grads is not None:
-            for t in self.grads.tensors():
-                t.zero_()
         r.project(self.g)
         r.bin_sort()
         r.render_fwd()
         r.loss_grad(self.rgb_t, self.depth_t, self.labels, self.decoder, self.weights)
-        r.render_bwd(self.g, r.grad_out, self.flags, self.grads)
+        r.render_bwd(self.g, r.grad_out, self.flags, self.grads, write=True)
         if self.flags & _lib.GS_GRAD_POSE:
             r.pose_grad(self.g)
 

@@ -139,7 +139,22 @@ __device__ __forceinline__ bool nonzero(const float4 a, const float4 b) {
 constexpr int kPbThreads = 256;
 constexpr int kPbViewFloats = 16;  // Rt (12), fx, fy, 2 unused
 
-template <int F>
+// Zero mean, log-scale and quaternion gradients of Gaussian i (the write
+// mode, for a Gaussian whose views contribute nothing to them).
+__device__ __forceinline__ void write_zero_geometry(const GradPtrs& out, int n, int i) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        out.mu[(size_t)k * n + i] = 0.0f;
+        out.log_scale[(size_t)k * n + i] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out.quat[(size_t)k * n + i] = 0.0f;
+}
+
+// ACC: add to the gradient planes; otherwise write them, zeros included for
+// Gaussians no view touches (the caller need not clear them first).  Written
+// as 0 + value, so both give the same bits from cleared planes.
+template <int F, bool ACC>
 __global__ void __launch_bounds__(kPbThreads) k_project_bwd(GaussPtrs g, const gs_view* __restrict__ views,
                                                             int n_views, float blur,
                                                             const int32_t* __restrict__ touched,
@@ -172,11 +187,11 @@ __global__ void __launch_bounds__(kPbThreads) k_project_bwd(GaussPtrs g, const g
     for (int q = 0; q < GA4; ++q) ga[q] = grad_app[(size_t)i * GA4 + q];
     const float lg = g.logit[i];
     float oc[3], of[F > 0 ? F : 1];
-    const float ol = out.logit[i];
+    const float ol = ACC ? out.logit[i] : 0.0f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) oc[k] = out.color[(size_t)k * n + i];
+    for (int k = 0; k < 3; ++k) oc[k] = ACC ? out.color[(size_t)k * n + i] : 0.0f;
 #pragma unroll
-    for (int f = 0; f < F; ++f) of[f] = out.feat[(size_t)f * n + i];
+    for (int f = 0; f < F; ++f) of[f] = ACC ? out.feat[(size_t)f * n + i] : 0.0f;
     const float* gaf = reinterpret_cast<const float*>(ga);
     const float o = 1.0f / (1.0f + __expf(-lg));
     out.logit[i] = ol + gaf[0] * o * (1.0f - o);
@@ -184,7 +199,10 @@ __global__ void __launch_bounds__(kPbThreads) k_project_bwd(GaussPtrs g, const g
     for (int k = 0; k < 3; ++k) out.color[(size_t)k * n + i] = oc[k] + gaf[1 + k];
 #pragma unroll
     for (int f = 0; f < F; ++f) out.feat[(size_t)f * n + i] = of[f] + gaf[4 + f];
-    if (mask == 0) return;
+    if (mask == 0) {
+        if constexpr (!ACC) write_zero_geometry(out, n, i);
+        return;
+    }
 
     Gauss G;
     load_gauss(g, i, G);
@@ -207,15 +225,18 @@ __global__ void __launch_bounds__(kPbThreads) k_project_bwd(GaussPtrs g, const g
         backward_view(G, f, Rt, fx, fy, g0, g1, dM, dp, D);
         for (int k = 0; k < 3; ++k) dmu[k] += Rt[k] * dp[0] + Rt[4 + k] * dp[1] + Rt[8 + k] * dp[2];
     }
-    if (!any) return;
-    for (int k = 0; k < 3; ++k) out.mu[(size_t)k * n + i] += dmu[k];
+    if (!any) {
+        if constexpr (!ACC) write_zero_geometry(out, n, i);
+        return;
+    }
+    for (int k = 0; k < 3; ++k) out.mu[(size_t)k * n + i] = (ACC ? out.mu[(size_t)k * n + i] : 0.0f) + dmu[k];
     // M = R diag(s)
     float dR[9];
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) dR[3 * r + k] = dM[3 * r + k] * G.s[k];
     for (int k = 0; k < 3; ++k) {
         const float ds = dM[k] * G.R[k] + dM[3 + k] * G.R[3 + k] + dM[6 + k] * G.R[6 + k];
-        out.log_scale[(size_t)k * n + i] += ds * G.s[k];
+        out.log_scale[(size_t)k * n + i] = (ACC ? out.log_scale[(size_t)k * n + i] : 0.0f) + ds * G.s[k];
     }
     // rotation of the unit quaternion (w, x, y, z): dR_ab / dq
     const float w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
@@ -229,7 +250,8 @@ __global__ void __launch_bounds__(kPbThreads) k_project_bwd(GaussPtrs g, const g
                    y * dR[7]);
     const float dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
     const float iq = 1.0f / G.qn;
-    for (int k = 0; k < 4; ++k) out.quat[(size_t)k * n + i] += (dq[k] - G.q[k] * dot) * iq;
+    for (int k = 0; k < 4; ++k)
+        out.quat[(size_t)k * n + i] = (ACC ? out.quat[(size_t)k * n + i] : 0.0f) + (dq[k] - G.q[k] * dot) * iq;
 }
 
 // Twist contributions per (view, Gaussian), reduced per block in FP64.
@@ -317,13 +339,13 @@ __global__ void __launch_bounds__(256) k_pose_final(const double* __restrict__ p
 
 hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
                               const int32_t* touched, const float* grad_geo, const float* grad_app,
-                              const GradPtrs& out, hipStream_t s) {
+                              const GradPtrs& out, bool accumulate, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    auto kern = k_project_bwd<16>;
+    auto kern = accumulate ? k_project_bwd<16, true> : k_project_bwd<16, false>;
     switch (g.n_feat) {
-        case 0: kern = k_project_bwd<0>; break;
-        case 8: kern = k_project_bwd<8>; break;
-        case 32: kern = k_project_bwd<32>; break;
+        case 0: kern = accumulate ? k_project_bwd<0, true> : k_project_bwd<0, false>; break;
+        case 8: kern = accumulate ? k_project_bwd<8, true> : k_project_bwd<8, false>; break;
+        case 32: kern = accumulate ? k_project_bwd<32, true> : k_project_bwd<32, false>; break;
         case 16: break;
         default: return hipErrorInvalidValue;
     }

@@ -408,9 +408,9 @@ int gs_render_bwd(const gs_gaussians* g, const float* rec, const float* app, con
                              grad2d, grad2d_bytes_, stream);
 }
 
-int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
-                   const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, size_t grad2d_bytes_,
-                   gs_gaussian_grads* grads, gs_stream stream) {
+static int project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                       const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, size_t grad2d_bytes_,
+                       gs_gaussian_grads* grads, bool accumulate, gs_stream stream) {
     int st = check_gauss(g, false);
     if (st) return st;
     if ((st = check_config(cfg))) return st;
@@ -430,7 +430,19 @@ int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* v
     const float* geo = grad2d;
     const float* appg = grad2d + (size_t)n_views * g->n * 8;
     return hip_status(launch_project_bwd(gauss_ptrs(g), views_dev, n_views, make_const(cfg), tiles_touched, geo, appg,
-                                         o, reinterpret_cast<hipStream_t>(stream)));
+                                         o, accumulate, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_project_bwd(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                   const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, size_t grad2d_bytes_,
+                   gs_gaussian_grads* grads, gs_stream stream) {
+    return project_bwd(g, views, views_dev, n_views, cfg, tiles_touched, grad2d, grad2d_bytes_, grads, true, stream);
+}
+
+int gs_project_bwd_write(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                         const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d,
+                         size_t grad2d_bytes_, gs_gaussian_grads* grads, gs_stream stream) {
+    return project_bwd(g, views, views_dev, n_views, cfg, tiles_touched, grad2d, grad2d_bytes_, grads, false, stream);
 }
 
 int gs_pose_grad_workspace(int32_t n, int32_t n_views, size_t* bytes) {

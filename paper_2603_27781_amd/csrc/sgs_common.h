@@ -166,9 +166,11 @@ hipError_t launch_reduce_records(const float* records, const int32_t* pair_first
                                  int n_feat, int n_views, int64_t capacity, bool params, float* grad_geo,
                                  float* grad_app, hipStream_t s);
 
+// accumulate: add to the planes of out; otherwise write every plane of every
+// Gaussian (zeros where no view contributes).
 hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
                               const int32_t* touched, const float* grad_geo, const float* grad_app,
-                              const GradPtrs& out, hipStream_t s);
+                              const GradPtrs& out, bool accumulate, hipStream_t s);
 
 size_t pose_workspace_bytes(int n, int n_views);
 hipError_t launch_pose_grad(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,

@@ -284,12 +284,13 @@ class Rasterizer:
                              self.slam_ws_bytes, _stream()), "gs_slam_loss")
         return self.grad_out
 
-    def render_bwd(self, g: Gaussians, grad_out: torch.Tensor, flags: int, grads: Optional[Gaussians]) -> None:
+    def render_bwd(self, g: Gaussians, grad_out: torch.Tensor, flags: int, grads: Optional[Gaussians],
+                   write: bool = False) -> None:
         """Backward of the compositing into the 2D gradient buffer and, with
-        GS_GRAD_PARAMS, of the projection into `grads` (+=)."""
+        GS_GRAD_PARAMS, of the projection into `grads` (+=, or = with write)."""
         self.render_bwd_2d(g, grad_out, flags)
         if flags & _lib.GS_GRAD_PARAMS:
-            self.project_bwd(g, grads)
+            self.project_bwd(g, grads, write)
 
     def render_bwd_2d(self, g: Gaussians, grad_out: torch.Tensor, flags: int) -> None:
         check(self.L.gs_render_bwd(ctypes.byref(g.c()), self.rec.data_ptr(), self.app.data_ptr(),
@@ -317,11 +318,13 @@ class Rasterizer:
                                        self.grad2d.data_ptr(), self.grad2d.numel() * 4, _stream()),
               "gs_reduce_records")
 
-    def project_bwd(self, g: Gaussians, grads: Gaussians) -> None:
+    def project_bwd(self, g: Gaussians, grads: Gaussians, write: bool = False) -> None:
+        """gs_project_bwd (adds to `grads`), or gs_project_bwd_write (writes them)."""
         gc = _grads_c(grads)
-        check(self.L.gs_project_bwd(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
-                                    ctypes.byref(self.cc), self.touched.data_ptr(), self.grad2d.data_ptr(),
-                                    self.grad2d.numel() * 4, ctypes.byref(gc), _stream()), "gs_project_bwd")
+        fn = self.L.gs_project_bwd_write if write else self.L.gs_project_bwd
+        check(fn(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc),
+                 self.touched.data_ptr(), self.grad2d.data_ptr(), self.grad2d.numel() * 4, ctypes.byref(gc),
+                 _stream()), "gs_project_bwd_write" if write else "gs_project_bwd")
 
     def pose_grad(self, g: Gaussians) -> torch.Tensor:
         check(self.L.gs_pose_grad(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,

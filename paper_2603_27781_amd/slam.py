@@ -118,13 +118,12 @@ class Mapper:
     def iteration(self, rgb_t, depth_t, labels, T: np.ndarray) -> torch.Tensor:
         r, g = self.r, self.g
         r.views.set_poses(torch.from_numpy(np.ascontiguousarray(T[:3, :4], np.float32)).to(r.device))
-        for t in self.grads.tensors():
-            t.zero_()
         r.project(g)
         r.bin_sort()
         r.render_fwd()
         r.slam_loss(rgb_t, depth_t, labels, self.decoder, self.opts, masks=True)
-        r.render_bwd(g, r.grad_out, _lib.GS_GRAD_PARAMS, self.grads)
+        # the projection backward writes the gradients; DSR then adds to them
+        r.render_bwd(g, r.grad_out, _lib.GS_GRAD_PARAMS, self.grads, write=True)
         dsr_out = raster.dsr(g.log_scale, self.w_big, self.w_small, self.grads.log_scale)
         self.step += 1
         names = ("mu", "log_scale", "quat", "logit", "color", "feat")

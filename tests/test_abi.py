@@ -101,6 +101,8 @@ def test_validation_rejects_before_any_launch():
                            None) == _lib.GS_ECAPACITY
     assert L.gs_project_bwd(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, dummy, 1 << 30, None,
                             None) == _lib.GS_EINVAL
+    assert L.gs_project_bwd_write(ctypes.byref(g), V, dummy, 1, ctypes.byref(cfg), dummy, dummy, 1 << 30, None,
+                                  None) == _lib.GS_EINVAL
     # the two halves of gs_render_bwd validate on their own
     assert L.gs_render_bwd_records(ctypes.byref(g), dummy, dummy, dummy, dummy, 100, dummy, V, dummy, 1,
                                    ctypes.byref(cfg), dummy, dummy, dummy, 4, dummy, 1 << 30, dummy,

@@ -288,6 +288,34 @@ def test_backward_launch_shapes(tile, lds_batch, persistent, lds_batch_bwd):
     _check_grads(*out, flags=3)
 
 
+@pytest.mark.parametrize("name", ["tiny3views-F16", "cfg1-64x64-2k", "tiny-F32"])
+def test_project_bwd_write_equals_add_on_cleared(name):
+    """gs_project_bwd_write into planes full of garbage gives, bit for bit,
+    what gs_project_bwd adds to cleared planes, zeros included for Gaussians
+    no view touches (ten moved far behind every camera)."""
+    from paper_2603_27781_amd import _lib
+    scene, views, r, g, cfg = _render(name, 16)
+    g.mu[:, :10] = torch.tensor([0.0, 0.0, -1e3], device="cuda")[:, None]
+    r.project(g)
+    r.bin_sort()
+    r.render_fwd()
+    rng = np.random.default_rng(5)
+    go = torch.from_numpy(rng.normal(size=r.out.shape).astype(np.float32) * 1e-2).cuda()
+    r.render_bwd_2d(g, go, _lib.GS_GRAD_PARAMS)
+    added = g.zeros_like()
+    r.project_bwd(g, added)
+    written = g.zeros_like()
+    for t in written.tensors():
+        t.copy_(torch.from_numpy(rng.normal(size=tuple(t.shape)).astype(np.float32) * 1e3))
+    r.project_bwd(g, written, write=True)
+    torch.cuda.synchronize()
+    untouched = (r.touched.view(len(views), -1) == 0).all(dim=0).cpu().numpy()
+    assert untouched.any()
+    for a, b in zip(added.tensors(), written.tensors()):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+    assert np.all(written.mu.cpu().numpy()[:, untouched] == 0)
+
+
 @pytest.mark.parametrize("flags", [3, 2])
 def test_backward_split_entry_points(flags):
     """gs_render_bwd_records followed by gs_reduce_records gives the grad2d of
