@@ -450,7 +450,8 @@ def slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, steps):
     mapping loss with SSIM, full backward, DSR, Adam on every parameter) on
     the first view of the workload with all its Gaussians, the shapes of the
     paper's per-iteration times (one 1200x680 Replica frame).  HIP events
-    over `steps` eager iterations each (no graph: the host loop as written)."""
+    over `steps` eager iterations each (the host loop as written), and over
+    `steps` replays of the tracking iteration captured in a HIP graph."""
     import torch
     from paper_2603_27781_amd import raster, slam
     v0 = w.views[0]
@@ -471,6 +472,18 @@ def slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, steps):
     b.record()
     torch.cuda.synchronize()
     ms_t = a.elapsed_time(b) / steps
+    # the same iteration captured once in a HIP graph and replayed
+    tr.capture(rgb1, dep1, lab1)
+    tr.set_pose(T)
+    tr.step.zero_()
+    tr.graph.replay()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        tr.graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms_tg = a.elapsed_time(b) / steps
     gm = raster.Gaussians(*(t.clone() for t in g.tensors()))
     mp = slam.Mapper(r, gm, W)
     mp.iteration(rgb1, dep1, lab1, T)
@@ -483,9 +496,11 @@ def slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, steps):
     ms_m = a.elapsed_time(b) / steps
     _, _, over = r.instance_counts()
     res = {"view": f"{v0.width}x{v0.height}", "gaussians": g.n, "tracking_ms_per_iter": round(ms_t, 3),
-           "mapping_ms_per_iter": round(ms_m, 3), "capacity_overflow": bool(over),
+           "tracking_graph_ms_per_iter": round(ms_tg, 3), "mapping_ms_per_iter": round(ms_m, 3),
+           "capacity_overflow": bool(over),
            "paper_rtx3090_ms_per_iter": {"tracking": 89, "mapping": 55}}
-    log(f"slam iterations: tracking {ms_t:.3f} ms, mapping {ms_m:.3f} ms per iteration")
+    log(f"slam iterations: tracking {ms_t:.3f} ms ({ms_tg:.3f} ms as graph replays), mapping {ms_m:.3f} ms "
+        "per iteration")
     del r, tr, mp, gm
     torch.cuda.empty_cache()
     return res

@@ -384,6 +384,14 @@ int gs_adam_step(const gs_adam_group* groups, int32_t n_groups, float beta1, flo
                  gs_stream stream);
 int gs_pose_step(gs_view* views_dev, int32_t n_views, const float* twist_grad, float* m, float* v, float lr_rho,
                  float lr_phi, float beta1, float beta2, float eps, int32_t step, gs_stream stream);
+/* gs_pose_step_dev -- gs_pose_step with Adam's step count in device memory:
+ * each call takes t = *step_dev + 1 (int32, device), stores t back and uses
+ * it for the bias corrections, so an iteration captured in a HIP graph
+ * replays with the right step.  The caller clears *step_dev at the start of a
+ * tracking run (with a kernel, not a memset, if that is captured too).  The
+ * same update as gs_pose_step at step t.  Errors: GS_EINVAL. */
+int gs_pose_step_dev(gs_view* views_dev, int32_t n_views, const float* twist_grad, float* m, float* v, float lr_rho,
+                     float lr_phi, float beta1, float beta2, float eps, int32_t* step_dev, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
  * gs_render_bwd -- backward of gs_render_fwd.  Re-traverses each pixel's list

@@ -26,7 +26,7 @@ EXPORTS = [
     "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_project_bwd_write",
     "gs_pose_grad_workspace",
     "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_expand_workspace",
-    "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_adam_step", "gs_pose_step", "gs_error_string",
+    "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_adam_step", "gs_pose_step", "gs_pose_step_dev", "gs_error_string",
     "gs_last_hip_error", "gs_version",
 ]
 GS_LOSS_OBS_MASK, GS_LOSS_BCE = 1, 2
@@ -133,6 +133,8 @@ def load() -> ctypes.CDLL:
     L.gs_adam_step.argtypes = [ctypes.c_void_p, c_int32, c_float, c_float, c_float, c_int32, c_void_p]
     L.gs_pose_step.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float, c_float,
                                c_float, c_int32, c_void_p]
+    L.gs_pose_step_dev.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,
+                                   c_float, c_float, c_void_p, c_void_p]
     L.gs_error_string.argtypes = [ctypes.c_int]
     L.gs_error_string.restype = ctypes.c_char_p
     L.gs_last_hip_error.restype = ctypes.c_char_p

@@ -69,9 +69,24 @@ __device__ void se3_exp(const float* xi, float* E) {
     }
 }
 
+// step_dev (may be null): the Adam step count in device memory; the kernel
+// takes t = *step_dev + 1, stores it back and forms the bias corrections
+// from it (in double, as the host does), in place of c1 and c2.  One block.
 __global__ void k_pose_step(gs_view* __restrict__ views, int n_views, const float* __restrict__ grad,
                             float* __restrict__ m, float* __restrict__ v, float lr_rho, float lr_phi, float b1,
-                            float b2, float eps, float c1, float c2) {
+                            float b2, float eps, float c1, float c2, int32_t* __restrict__ step_dev) {
+    __shared__ float s_c[2];
+    if (step_dev != nullptr) {
+        if (threadIdx.x == 0) {
+            const int t = *step_dev + 1;
+            *step_dev = t;
+            s_c[0] = (float)(1.0 - pow((double)b1, (double)t));
+            s_c[1] = (float)(1.0 - pow((double)b2, (double)t));
+        }
+        __syncthreads();
+        c1 = s_c[0];
+        c2 = s_c[1];
+    }
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= n_views) return;
     float dxi[6];
@@ -119,11 +134,11 @@ hipError_t launch_adam(const gs_adam_group* groups, int n_groups, float b1, floa
 }
 
 hipError_t launch_pose_step(gs_view* views_dev, int n_views, const float* grad, float* m, float* v, float lr_rho,
-                            float lr_phi, float b1, float b2, float eps, int step, hipStream_t s) {
-    const float c1 = (float)(1.0 - std::pow((double)b1, (double)step));
-    const float c2 = (float)(1.0 - std::pow((double)b2, (double)step));
-    hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(64), 0, s, views_dev, n_views, grad, m, v, lr_rho, lr_phi, b1, b2,
-                       eps, c1, c2);
+                            float lr_phi, float b1, float b2, float eps, int step, int32_t* step_dev, hipStream_t s) {
+    const float c1 = step_dev ? 1.0f : (float)(1.0 - std::pow((double)b1, (double)step));
+    const float c2 = step_dev ? 1.0f : (float)(1.0 - std::pow((double)b2, (double)step));
+    hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(kAdamPoseThreads), 0, s, views_dev, n_views, grad, m, v, lr_rho,
+                       lr_phi, b1, b2, eps, c1, c2, step_dev);
     return hipGetLastError();
 }
 

@@ -328,7 +328,15 @@ int gs_pose_step(gs_view* views_dev, int32_t n_views, const float* twist_grad, f
     if (!views_dev || !twist_grad || !m || !v || n_views < 1 || n_views > GS_MAX_VIEWS || step < 1) return GS_EINVAL;
     if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f)) return GS_EINVAL;
     return hip_status(launch_pose_step(views_dev, n_views, twist_grad, m, v, lr_rho, lr_phi, beta1, beta2, eps, step,
-                                       reinterpret_cast<hipStream_t>(stream)));
+                                       nullptr, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_pose_step_dev(gs_view* views_dev, int32_t n_views, const float* twist_grad, float* m, float* v, float lr_rho,
+                     float lr_phi, float beta1, float beta2, float eps, int32_t* step_dev, gs_stream stream) {
+    if (!views_dev || !twist_grad || !m || !v || !step_dev || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f)) return GS_EINVAL;
+    return hip_status(launch_pose_step(views_dev, n_views, twist_grad, m, v, lr_rho, lr_phi, beta1, beta2, eps, 0,
+                                       step_dev, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_render_bwd_workspace(int32_t n, int32_t n_feat, int32_t n_views, int64_t capacity, uint32_t flags,

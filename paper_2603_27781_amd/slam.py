@@ -68,7 +68,9 @@ class Tracker:
         dev = dict(device=r.device)
         self.m = torch.zeros(1, 6, dtype=torch.float32, **dev)
         self.v = torch.zeros(1, 6, dtype=torch.float32, **dev)
+        self.step = torch.zeros(1, dtype=torch.int32, **dev)  # Adam's step count (graph mode)
         self.opts = _opts("tracking")
+        self.graph = None
 
     def set_pose(self, T: np.ndarray) -> None:
         self.r.views.set_poses(torch.from_numpy(np.ascontiguousarray(T[:3, :4], np.float32)).to(self.r.device))
@@ -77,7 +79,9 @@ class Tracker:
         Rt = self.r.views.dev.view(torch.float32)[0, 6:18].cpu().numpy().reshape(3, 4).astype(np.float64)
         return np.vstack([Rt, [0, 0, 0, 1]])
 
-    def iteration(self, rgb_t, depth_t, labels, step: int) -> None:
+    def iteration(self, rgb_t, depth_t, labels, step: Optional[int]) -> None:
+        """One iteration; step None takes Adam's step count from self.step on
+        the device (gs_pose_step_dev), as a captured iteration must."""
         r, g = self.r, self.g
         r.project(g)
         r.bin_sort()
@@ -86,16 +90,43 @@ class Tracker:
         r.render_bwd(g, r.grad_out, _lib.GS_GRAD_POSE, None)
         tw = r.pose_grad(g)
         L = _lib.load()
-        check(L.gs_pose_step(r.views.dev_ptr(), 1, tw.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), TRACK_LR_RHO,
-                             TRACK_LR_PHI, ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS, step, raster._stream()),
-              "gs_pose_step")
+        args = (r.views.dev_ptr(), 1, tw.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), TRACK_LR_RHO, TRACK_LR_PHI,
+                ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+        if step is None:
+            check(L.gs_pose_step_dev(*args, self.step.data_ptr(), raster._stream()), "gs_pose_step_dev")
+        else:
+            check(L.gs_pose_step(*args, step, raster._stream()), "gs_pose_step")
 
-    def track(self, rgb_t, depth_t, labels, T_init: np.ndarray, iters: int = TRACK_ITERS) -> np.ndarray:
+    def capture(self, rgb_t, depth_t, labels) -> None:
+        """Captures one iteration (device step count) in a HIP graph for
+        replay by track(..., graph=True); the targets' buffers are baked in.
+        One eager iteration first sets up the lazily allocated workspaces; the
+        state it changes is reset by track."""
+        self.iteration(rgb_t, depth_t, labels, None)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.iteration(rgb_t, depth_t, labels, None)
+        torch.cuda.synchronize()
+        self.graph_targets = (rgb_t, depth_t, labels)
+
+    def track(self, rgb_t, depth_t, labels, T_init: np.ndarray, iters: int = TRACK_ITERS,
+              graph: bool = False) -> np.ndarray:
+        """Frame-to-model tracking from T_init; with graph, the iterations
+        are replays of a captured one (captured on first use with these
+        targets, which must then stay the same buffers)."""
+        if graph and (self.graph is None or any(a is not b for a, b in zip(self.graph_targets,
+                                                                           (rgb_t, depth_t, labels)))):
+            self.capture(rgb_t, depth_t, labels)
         self.set_pose(T_init)
         self.m.zero_()
         self.v.zero_()
+        self.step.zero_()
         for k in range(1, iters + 1):
-            self.iteration(rgb_t, depth_t, labels, k)
+            if graph:
+                self.graph.replay()
+            else:
+                self.iteration(rgb_t, depth_t, labels, k)
         return self.pose()
 
 

@@ -4,9 +4,11 @@
     binary32 against FP64, 1e-5 relative;
   - gs_pose_step against the oracle's pose step (Adam on the twist, then
     T <- Exp(dxi) T): 1e-5;
+  - gs_pose_step_dev (the step count in device memory) against gs_pose_step;
   - tracking (40 iterations from the constant-velocity guess of a slightly
     wrong pose) brings the pose close to the one the targets were rendered
-    at, and a mapping run lowers the mapping loss of a perturbed map:
+    at, eagerly and as replays of a captured iteration alike, and a mapping
+    run lowers the mapping loss of a perturbed map:
     properties of the loop (its FP64 counterpart would take minutes per
     iteration on the host).
 """
@@ -73,6 +75,33 @@ def test_pose_step_parity():
     assert np.max(np.abs(got - Rt)) <= 1e-5
 
 
+def test_pose_step_dev_matches_host_step():
+    """gs_pose_step_dev with the step count in device memory (0 before the
+    first call) gives gs_pose_step's update at t = 1, 2, 3 and leaves 3."""
+    from paper_2603_27781_amd import _lib, raster
+    L = _lib.load()
+    rng = np.random.default_rng(8)
+    V = 2
+    views = [wl.make_view(32, 24, 30.0, wl.se3_exp(rng.normal(size=6) * 0.3)) for _ in range(V)]
+    Va, Vb = raster.Views(views, 16), raster.Views(views, 16)
+    ma, va = torch.zeros(V, 6, device="cuda"), torch.zeros(V, 6, device="cuda")
+    mb, vb = torch.zeros(V, 6, device="cuda"), torch.zeros(V, 6, device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for t in range(1, 4):
+        gr = _dev(rng.normal(size=(V, 6)).astype(np.float32))
+        assert L.gs_pose_step(Va.dev_ptr(), V, gr.data_ptr(), ma.data_ptr(), va.data_ptr(), 0.002, 0.0004, 0.9,
+                              0.999, 1e-8, t, raster._stream()) == 0
+        assert L.gs_pose_step_dev(Vb.dev_ptr(), V, gr.data_ptr(), mb.data_ptr(), vb.data_ptr(), 0.002, 0.0004, 0.9,
+                                  0.999, 1e-8, step.data_ptr(), raster._stream()) == 0
+    torch.cuda.synchronize()
+    assert int(step.item()) == 3
+    a = Va.dev.view(torch.float32)[:, 6:18].cpu().numpy()
+    b = Vb.dev.view(torch.float32)[:, 6:18].cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-7
+    assert L.gs_pose_step_dev(Vb.dev_ptr(), V, gr.data_ptr(), mb.data_ptr(), vb.data_ptr(), 0.002, 0.0004, 0.9,
+                              0.999, 1e-8, None, raster._stream()) == _lib.GS_EINVAL
+
+
 def _small_world(seed=71, n=4000, F=8, K=6):
     w = wl.tiny_scene(seed, n, F=F, W=64, H=48, f=50.0, log_scale_mu=-2.6, spread=1.2)
     rng = np.random.default_rng(seed)
@@ -122,6 +151,12 @@ def test_tracking_recovers_the_pose():
     _, _, over = r.instance_counts()
     assert not over
     assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1], (e0, e1)
+    # the same run as replays of one captured iteration (device step count),
+    # twice in a row: the compositing backward may differ from the eager run
+    # in the last bits only
+    for _ in range(2):
+        Tg = tr.track(rgb, dep, lab, T0, iters=40, graph=True)
+        assert np.max(np.abs(Tg - T)) <= 1e-5, np.max(np.abs(Tg - T))
     # constant velocity itself (Eq. 19) predicts the uniform motion exactly
     assert np.allclose(slam.constant_velocity(T_prev, T_prev2), T_gt, atol=1e-9)
 
