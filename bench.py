@@ -464,6 +464,7 @@ def slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, steps):
     tr = slam.Tracker(r, g, W)
     tr.set_pose(T)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tr.refresh()
     tr.iteration(rgb1, dep1, lab1, 1)
     torch.cuda.synchronize()
     a.record()

@@ -140,12 +140,15 @@ __global__ void __launch_bounds__(kProjThreads) k_project(GaussPtrs g, const gs_
     }
 
     // every plane is read up front with an in-range index (one batch of
-    // independent loads per thread, no branches between them)
+    // independent loads per thread, no branches between them; the
+    // appearance planes only when their records are wanted, a uniform test)
     const int ic = valid ? i : n - 1;
     float av[AS];
+    if (app != nullptr) {
 #pragma unroll
-    for (int k = 0; k < AS; ++k)
-        av[k] = k < 3 ? g.color[(size_t)k * n + ic] : (k < 3 + F ? g.feat[(size_t)(k - 3) * n + ic] : 0.0f);
+        for (int k = 0; k < AS; ++k)
+            av[k] = k < 3 ? g.color[(size_t)k * n + ic] : (k < 3 + F ? g.feat[(size_t)(k - 3) * n + ic] : 0.0f);
+    }
     const float logit = g.logit[ic];
     const float m0 = g.mu[ic], m1 = g.mu[(size_t)n + ic], m2 = g.mu[2 * (size_t)n + ic];
     const float q0 = g.quat[ic], q1 = g.quat[(size_t)n + ic], q2 = g.quat[2 * (size_t)n + ic],

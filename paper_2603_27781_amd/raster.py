@@ -199,10 +199,13 @@ class Rasterizer:
         return inst
 
     # -------------------------------------------------------------------- calls
-    def project(self, g: Gaussians) -> None:
+    def project(self, g: Gaussians, write_app: bool = True) -> None:
+        """gs_project; write_app False keeps the appearance records of the
+        previous call (for a map whose colours and features have not changed)."""
         check(self.L.gs_project(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
                                 ctypes.byref(self.cc), self.rec.data_ptr(), self.rect.data_ptr(),
-                                self.touched.data_ptr(), self.app.data_ptr(), _stream()), "gs_project")
+                                self.touched.data_ptr(), self.app.data_ptr() if write_app else None, _stream()),
+              "gs_project")
 
     def bin_sort(self) -> None:
         check(self.L.gs_bin_sort(self.rect.data_ptr(), self.touched.data_ptr(), self.rec.data_ptr(), self.n,

@@ -5,7 +5,8 @@ Host orchestration only: every computation is a call into libsgs (render,
 SLAM loss, backward, pose gradient, optimiser steps, expansion, DSR), with
 the state (Gaussian planes, Adam moments, poses) in device memory.
 
-  Tracker.track   -- frame-to-model tracking (Sec. 3.4): the pose starts
+  Tracker.track   -- frame-to-model tracking (Sec. 3.4; the map is frozen, so
+      the appearance records are written once per call): the pose starts
       from the constant-velocity prediction T_t = T_{t-1} T_{t-2}^-1 T_{t-1}
       (Eq. 19) and is refined for `iters` iterations of: render, tracking
       loss (every term under M_obs, Eq. 21), pose-only backward, twist
@@ -83,7 +84,7 @@ class Tracker:
         """One iteration; step None takes Adam's step count from self.step on
         the device (gs_pose_step_dev), as a captured iteration must."""
         r, g = self.r, self.g
-        r.project(g)
+        r.project(g, write_app=False)  # the map is frozen: appearance records from refresh()
         r.bin_sort()
         r.render_fwd()
         r.slam_loss(rgb_t, depth_t, labels, self.decoder, self.opts, masks=True)
@@ -97,11 +98,17 @@ class Tracker:
         else:
             check(L.gs_pose_step(*args, step, raster._stream()), "gs_pose_step")
 
+    def refresh(self) -> None:
+        """Writes the appearance records of the current map (colours and
+        features, which tracking does not change), once per tracked frame."""
+        self.r.project(self.g)
+
     def capture(self, rgb_t, depth_t, labels) -> None:
         """Captures one iteration (device step count) in a HIP graph for
         replay by track(..., graph=True); the targets' buffers are baked in.
         One eager iteration first sets up the lazily allocated workspaces; the
         state it changes is reset by track."""
+        self.refresh()
         self.iteration(rgb_t, depth_t, labels, None)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
@@ -122,6 +129,7 @@ class Tracker:
         self.m.zero_()
         self.v.zero_()
         self.step.zero_()
+        self.refresh()
         for k in range(1, iters + 1):
             if graph:
                 self.graph.replay()

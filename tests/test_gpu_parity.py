@@ -288,6 +288,25 @@ def test_backward_launch_shapes(tile, lds_batch, persistent, lds_batch_bwd):
     _check_grads(*out, flags=3)
 
 
+@pytest.mark.parametrize("name", ["tiny3views-F16", "tiny-F32"])
+def test_project_without_appearance_records(name):
+    """gs_project with a null appearance buffer writes the same records,
+    rectangles and tile counts, and leaves the appearance records alone."""
+    scene, views, r, g, cfg = _render(name, 16)
+    rec, rect, touched, app = (t.clone() for t in (r.rec, r.rect, r.touched, r.app))
+    r.app.fill_(7.0)
+    r.rec.zero_()
+    r.project(g, write_app=False)
+    torch.cuda.synchronize()
+    assert torch.all(r.app == 7.0)
+    vis = (touched > 0).cpu().numpy()
+    assert np.array_equal(r.touched.cpu().numpy(), touched.cpu().numpy())
+    assert np.array_equal(r.rec.view(len(views) * scene.n, 8).cpu().numpy()[vis],
+                          rec.view(len(views) * scene.n, 8).cpu().numpy()[vis])
+    assert np.array_equal(r.rect.view(len(views) * scene.n, -1).cpu().numpy()[vis],
+                          rect.view(len(views) * scene.n, -1).cpu().numpy()[vis])
+
+
 @pytest.mark.parametrize("name", ["tiny3views-F16", "cfg1-64x64-2k", "tiny-F32"])
 def test_project_bwd_write_equals_add_on_cleared(name):
     """gs_project_bwd_write into planes full of garbage gives, bit for bit,
