@@ -59,6 +59,7 @@ CASES = {
     "stacked600-F16": _stacked,
     "empty-view-F8": _with_empty_view,
     "40views-F8": _many_views,
+    "64views-F8": lambda: _many_views(seed=68, V=64),  # the most views a batch may hold (mask bit 63)
 }
 
 
