@@ -3,13 +3,12 @@
 //
 // Two stable sorts replace one wide-key sort:
 //   1. the visible (view, Gaussian) pairs, compacted in (view, index) order,
-//      are radix-sorted by the binary32 bits of their camera depth (4 passes
-//      of 8 bits; the last pass also writes each sorted pair's tile count);
-//   2. each pair, in that depth order, emits one instance per tile of its
-//      rectangle, keyed by global tile id, and the instances are radix-sorted
-//      by tile id (ceil(log2 tiles) bits).
-// Because both sorts are stable and the compaction preserves the index order,
-// the final order is (view, tile, depth bits, Gaussian index).
+//      each emit one instance per tile of their rectangle, keyed by global
+//      tile id, and the instances are radix-sorted by tile id (ceil(log2
+//      tiles) bits; stable, so each tile's list stays in index order);
+//   2. each tile's list is sorted by the binary32 bits of its pairs' camera
+//      depth, one workgroup per tile (stable counting passes in LDS).
+// So the final order is (view, tile, depth bits, Gaussian index).
 //
 // Every count that the host does not know (visible pairs, instances) stays on
 // the device; grids are sized for the capacity and blocks beyond the count
@@ -487,7 +486,7 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t*
 // Order-preserving compaction of the visible pairs in three steps: the
 // visible count of each run of CV_RUN consecutive pairs, an exclusive scan
 // of those counts (one block), then each run ranks its pairs with ballots
-// and writes (depth bits, pair index) at its offset.
+// and writes (tile count, pair index) at its offset.
 constexpr int CV_THREADS = 256;
 constexpr int CV_RUN = 2048;
 
@@ -513,9 +512,8 @@ __global__ void __launch_bounds__(CV_THREADS) k_count_visible(const int32_t* __r
 }
 
 __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* __restrict__ touched,
-                                                                const float4* __restrict__ rec,
                                                                 const uint32_t* __restrict__ run_offs, int64_t vn,
-                                                                uint32_t* __restrict__ keys,
+                                                                uint32_t* __restrict__ counts,
                                                                 uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_w[CV_THREADS / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -537,7 +535,7 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
         }
         if (vis) {
             const uint32_t p = off + (uint32_t)__popcll(m & lt);
-            keys[p] = __float_as_uint(rec[2 * i + 1].z);  // camera depth, positive: bits are monotone
+            counts[p] = (uint32_t)touched[i];
             vals[p] = (uint32_t)i;
         }
         run += tot;
@@ -545,7 +543,7 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
     }
 }
 
-// Emission: the visible pair at depth-sorted position i writes one instance
+// Emission: the visible pair at compacted position i writes one instance
 // per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1
 // (row-major over the rectangle): key = global tile id (the first tile-sort
 // pass attaches the emission index as the value).  inst_gid[e] keeps the Gaussian of emission index e,
@@ -645,13 +643,232 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ins
     if (i == I - 1 || keys[i + 1] != k) ranges[k].y = (int)(i + 1);
 }
 
+// Per-tile depth order.  The visible pairs are emitted in (view, index)
+// order and the tile sort is stable, so each tile's instances arrive in
+// Gaussian-index order; a stable sort of each tile's list by the binary32
+// bits of its pair's camera depth (positive, so the bits order like the
+// values) leaves them in (depth, index) order, the order the forward and
+// backward walk.  Four stable counting passes over 8-bit digits.  Lists are
+// short (about 140 instances at the 8 x 1200x680, 1M-Gaussian workload, the
+// longest a few hundred), so one 64-thread workgroup sorts a list of up to
+// kTsShort in LDS, many of them in flight per CU; a second kernel takes
+// the longer lists (each workgroup finds those among kTslTiles tiles at a
+// time) with 256 threads, in LDS up to kTsLong and otherwise in
+// global memory (the tile's slices of the sorted tile keys, whose values
+// are all the tile's own id and are written back, and of the tile sort's
+// ping-pong arrays, unused by then).
+constexpr int kTsShort = 512, kTsLong = 2048;
+constexpr int kTslTiles = 64;  // tiles a long-list workgroup scans per stride
+
+template <int NT>
+struct SegSortLds {
+    uint32_t next[256];             // next output position per digit
+    uint32_t wcnt[NT / kWave][256];  // per chunk: each wavefront's count per digit
+    uint32_t tmp[NT / kWave];
+};
+
+// One stable counting pass of the whole block over the digit at `shift`:
+// (kin, vin) -> (kout, vout), L items, every array in LDS or every array in
+// global memory.  Chunks of NT items: ranks within a wavefront from ballots,
+// wavefronts in order, chunks in order.  Thread tid keeps the digits
+// tid * DPT .. tid * DPT + DPT - 1 of the tables.
+template <int NT>
+__device__ void seg_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int L, int shift,
+                         SegSortLds<NT>& S) {
+    constexpr int DPT = 256 / NT, NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) S.next[tid * DPT + q] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int c0 = 0; c0 < L; c0 += NT) {
+        // one LDS atomic per run of equal digits in a wavefront (the keys of
+        // a tile share most of their high bits)
+        const int i = c0 + tid;
+        const bool valid = i < L;
+        const uint32_t d = valid ? (kin[i] >> shift) & 0xffu : 0u;
+        const uint64_t peers = match_digit(d, valid);
+        if (valid && (peers & lt) == 0) atomicAdd(&S.next[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    uint32_t c[DPT], sum = 0;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        c[q] = S.next[tid * DPT + q];
+        sum += c[q];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive<NT>(sum, S.tmp, &tot);  // barriers inside
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        S.next[tid * DPT + q] = run;
+        run += c[q];
+    }
+    for (int c0 = 0; c0 < L; c0 += NT) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int q = 0; q < DPT; ++q) S.wcnt[w][tid * DPT + q] = 0;
+        __syncthreads();
+        const int i = c0 + tid;
+        const bool valid = i < L;
+        const uint32_t k = valid ? kin[i] : 0u, v = valid ? vin[i] : 0u;
+        const uint32_t d = (k >> shift) & 0xffu;
+        const uint64_t peers = match_digit(d, valid);
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) S.wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t o = S.next[d] + rank;
+            for (int w = 0; w < wave; ++w) o += S.wcnt[w][d];
+            kout[o] = k;
+            vout[o] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            uint32_t add = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) add += S.wcnt[w][tid * DPT + q];
+            S.next[tid * DPT + q] += add;
+        }
+    }
+}
+
+// OR of v over the block (every thread gets it).
+template <int NT>
+__device__ __forceinline__ uint32_t block_or(uint32_t v, uint32_t* s_tmp) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v |= (uint32_t)__shfl_xor((int)v, d, kWave);
+    if (lane == 0) s_tmp[wave] = v;
+    __syncthreads();
+    uint32_t r = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) r |= s_tmp[w];
+    __syncthreads();
+    return r;
+}
+
+// The list of tile t in LDS (L <= LMAX): depth keys gathered, a counting
+// pass per byte in which the keys differ, the emission indices written back
+// in order.
+template <int NT, int LMAX>
+__device__ void tile_sort_lds(int t, int2 rg, const gs_view* __restrict__ views, int n_views, int n,
+                              const float4* __restrict__ rec, const int32_t* __restrict__ inst_gid,
+                              int32_t* __restrict__ inst, uint32_t (&s_k)[2][LMAX], uint32_t (&s_v)[2][LMAX],
+                              SegSortLds<NT>& S) {
+    const int L = rg.y - rg.x;
+    const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
+    uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
+    uint32_t diff = 0;  // bits in which some key differs from the first
+    for (int i = threadIdx.x; i < L; i += NT) {
+        const uint32_t e = einst[i];
+        s_k[0][i] = __float_as_uint(rec[2 * (vbase + (size_t)inst_gid[e]) + 1].z);
+        s_v[0][i] = e;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < L; i += NT) diff |= s_k[0][i] ^ s_k[0][0];
+    const uint32_t any = block_or<NT>(diff, S.tmp);
+    // a byte every key shares is a pass that would leave the order as it is
+    int b = 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        if (((any >> (8 * p)) & 0xffu) == 0) continue;  // uniform across the block
+        seg_pass<NT>(s_k[b], s_v[b], s_k[b ^ 1], s_v[b ^ 1], L, 8 * p, S);
+        __syncthreads();
+        b ^= 1;
+    }
+    for (int i = threadIdx.x; i < L; i += NT) einst[i] = s_v[b][i];
+}
+
+constexpr int TSS_THREADS = kWave;  // short lists: one wavefront per tile
+constexpr int TSL_THREADS = 256;    // long lists
+
+__global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __restrict__ ranges,
+                                                                  const gs_view* __restrict__ views, int n_views,
+                                                                  int n, const float4* __restrict__ rec,
+                                                                  const int32_t* __restrict__ inst_gid,
+                                                                  int32_t* __restrict__ inst) {
+    __shared__ uint32_t s_k[2][kTsShort];
+    __shared__ uint32_t s_v[2][kTsShort];
+    __shared__ SegSortLds<TSS_THREADS> S;
+    const int t = blockIdx.x;
+    const int2 rg = ranges[t];
+    const int L = rg.y - rg.x;
+    if (L <= 1 || L > kTsShort) return;  // uniform across the block
+    tile_sort_lds<TSS_THREADS, kTsShort>(t, rg, views, n_views, n, rec, inst_gid, inst, s_k, s_v, S);
+}
+
+// The lists longer than kTsShort; each workgroup walks the tiles with a
+// stride of the grid (few tiles have such lists).
+__global__ void __launch_bounds__(TSL_THREADS) k_tile_sort_long(const int2* __restrict__ ranges, int total_tiles,
+                                                                 const gs_view* __restrict__ views, int n_views,
+                                                                 int n, const float4* __restrict__ rec,
+                                                                 const int32_t* __restrict__ inst_gid,
+                                                                 uint32_t* __restrict__ tile_keys,
+                                                                 int32_t* __restrict__ inst,
+                                                                 uint32_t* __restrict__ gk,
+                                                                 uint32_t* __restrict__ gv) {
+    __shared__ uint32_t s_k[2][kTsLong];
+    __shared__ uint32_t s_v[2][kTsLong];
+    __shared__ SegSortLds<TSL_THREADS> S;
+    __shared__ int s_long[kTslTiles];
+    __shared__ int s_nlong;
+    for (int base = blockIdx.x * kTslTiles; base < total_tiles; base += gridDim.x * kTslTiles) {
+        // the tiles of this stride with long lists, found together
+        const int tt = base + (int)threadIdx.x;
+        const bool lng = (int)threadIdx.x < kTslTiles && tt < total_tiles && ranges[tt].y - ranges[tt].x > kTsShort;
+        if (threadIdx.x == 0) s_nlong = 0;
+        __syncthreads();
+        if (lng) s_long[atomicAdd(&s_nlong, 1)] = tt;
+        __syncthreads();
+        const int nlong = s_nlong;
+        for (int j = 0; j < nlong; ++j) {
+            const int t = s_long[j];
+            const int2 rg = ranges[t];
+            const int L = rg.y - rg.x;
+            if (L <= kTsLong) {
+                tile_sort_lds<TSL_THREADS, kTsLong>(t, rg, views, n_views, n, rec, inst_gid, inst, s_k, s_v, S);
+                __syncthreads();
+                continue;
+            }
+            // in global memory: (depth bits, emission index) start in
+            // (tile_keys, inst) and ping-pong with the scratch slices; after
+            // four passes they are back
+            const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
+            uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
+            uint32_t* bk = tile_keys + rg.x;
+            uint32_t* ak = gk + rg.x;
+            uint32_t* av = gv + rg.x;
+            for (int i = threadIdx.x; i < L; i += TSL_THREADS)
+                bk[i] = __float_as_uint(rec[2 * (vbase + (size_t)inst_gid[einst[i]]) + 1].z);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                // the previous pass's global writes are complete and visible
+                // to the whole block (and not stale in this CU's cache)
+                // before they are read
+                __threadfence();
+                __syncthreads();
+                if (p & 1) seg_pass<TSL_THREADS>(ak, av, bk, einst, L, 8 * p, S);
+                else seg_pass<TSL_THREADS>(bk, einst, ak, av, L, 8 * p, S);
+            }
+            __threadfence();
+            __syncthreads();
+            for (int i = threadIdx.x; i < L; i += TSL_THREADS) bk[i] = (uint32_t)t;
+            __syncthreads();
+        }
+        __syncthreads();  // s_long and s_nlong are reused by the next stride
+    }
+}
+
 struct WsLayout {
-    size_t vis_k0, vis_v0, vis_k1, vis_v1, pos, inst_k2, inst_v2, hist, sums, status, tickets, cnt, total;
+    size_t vis_k0, vis_v0, inst_k2, inst_v2, hist, sums, status, tickets, cnt, total;
     int64_t spine_tiles, n_status;
 };
 
 constexpr int kMaxPasses = 4;            // radix passes per sort (32-bit keys)
-constexpr int kTickets = 2 * kMaxPasses; // one per radix pass: depth sort, then tile sort
+constexpr int kTickets = kMaxPasses;     // one per radix pass of the tile sort
 
 WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -665,14 +882,11 @@ WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     // scan (runs are the shorter, so there are more of them)
     const int64_t vt = (vn + CV_RUN - 1) / CV_RUN > 0 ? (vn + CV_RUN - 1) / CV_RUN : 1;
     static_assert(CV_RUN <= LB_TILE, "the run counts need at least as many words as the tile totals");
-    // look-back status words: 2 x kMaxPasses radix spines
-    L.n_status = 2 * kMaxPasses * L.spine_tiles;
+    // look-back status words: kMaxPasses radix spines
+    L.n_status = kMaxPasses * L.spine_tiles;
     size_t o = 0;
     L.vis_k0 = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
     L.vis_v0 = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
-    L.vis_k1 = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
-    L.vis_v1 = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
-    L.pos = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
     L.inst_k2 = o; o += al(4 * (size_t)cap);
     L.inst_v2 = o; o += al(4 * (size_t)cap);
     L.hist = o; o += al(4 * (size_t)(256 * nblk + 1));
@@ -696,9 +910,6 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     char* w = static_cast<char*>(ws);
     uint32_t* vis_k0 = reinterpret_cast<uint32_t*>(w + L.vis_k0);
     uint32_t* vis_v0 = reinterpret_cast<uint32_t*>(w + L.vis_v0);
-    uint32_t* vis_k1 = reinterpret_cast<uint32_t*>(w + L.vis_k1);
-    uint32_t* vis_v1 = reinterpret_cast<uint32_t*>(w + L.vis_v1);
-    uint32_t* pos = reinterpret_cast<uint32_t*>(w + L.pos);
     uint32_t* ik2 = reinterpret_cast<uint32_t*>(w + L.inst_k2);
     uint32_t* iv2 = reinterpret_cast<uint32_t*>(w + L.inst_v2);
     uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
@@ -707,42 +918,27 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
     int64_t* cnt = reinterpret_cast<int64_t*>(w + L.cnt);  // [0] n_vis [1] n_inst [2] clamped
     const int64_t vn = (int64_t)n * n_views;
-    uint64_t* st_depth = status;
-    uint64_t* st_tile = st_depth + kMaxPasses * L.spine_tiles;
     hipError_t e;
 
     // 0. zero the scan state and the counts, and clear the per-tile ranges
     hipLaunchKernelGGL(k_bin_reset, dim3(64), dim3(256), 0, s, status, L.n_status, tickets, kTickets,
                        reinterpret_cast<uint32_t*>(ranges), 2 * (int64_t)total_tiles);
-    // 1. order-preserving compaction of the visible pairs, key = depth bits
+    // 1. order-preserving compaction of the visible pairs: (tile count, pair)
     if (vn > 0) {
         const unsigned nrun = (unsigned)((vn + CV_RUN - 1) / CV_RUN);
         hipLaunchKernelGGL(k_count_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched, vn, sums);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_THREADS), 0, s, sums, (int)nrun, &cnt[0]);
-        hipLaunchKernelGGL(k_compact_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched,
-                           reinterpret_cast<const float4*>(rec), sums, vn, vis_k0, vis_v0);
+        hipLaunchKernelGGL(k_compact_visible, dim3(nrun), dim3(CV_THREADS), 0, s, touched, sums, vn, vis_k0, vis_v0);
     } else {
         e = fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 8, s);
         if (e != hipSuccess) return e;
     }
-    // 2. stable sort of the visible pairs by depth (32 bits, 4 passes); the
-    //    last pass also writes each sorted pair's tile count
-    if (vn > 0) {
-        uint32_t *ki = vis_k0, *vi = vis_v0, *ko = vis_k1, *vo = vis_v1;
-        for (int p = 0; p < 4; ++p) {
-            e = radix_pass(SrcKV{ki, vi}, &cnt[0], vn, 8 * p, hist, st_depth + p * L.spine_tiles, &tickets[p],
-                           nullptr, ko, vo, touched, p == 3 ? pos : nullptr, s);
-            if (e != hipSuccess) return e;
-            uint32_t* t = ki; ki = ko; ko = t;
-            t = vi; vi = vo; vo = t;
-        }  // four passes: the sorted pairs end in (vis_k0, vis_v0)
-    }
-    // 3. instance offsets in depth order (in place over the tile counts),
+    // 2. instance offsets in pair order (in place over the tile counts),
     //    total instance count and the counts
-    e = exclusive_scan_long(LoadU32{pos}, &cnt[0], vn, sums, pos, &cnt[1], s,
+    e = exclusive_scan_long(LoadU32{vis_k0}, &cnt[0], vn, sums, vis_k0, &cnt[1], s,
                             CountsOut{counts, &cnt[2], &cnt[0], capacity});
     if (e != hipSuccess) return e;
-    // 4. emission, then stable sort by global tile id
+    // 3. emission, then stable sort by global tile id
     int bits = 1;
     while ((1ll << bits) < (int64_t)total_tiles) ++bits;
     const int passes = (bits + 7) / 8;
@@ -752,16 +948,27 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     uint32_t* ok = (passes % 2 == 0) ? ik2 : reinterpret_cast<uint32_t*>(tile_keys);
     uint32_t* ov = (passes % 2 == 0) ? iv2 : reinterpret_cast<uint32_t*>(inst);
     if (vn > 0) {
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, vis_v0, pos, &cnt[0],
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, vis_v0, vis_k0, &cnt[0],
                            reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, inst_gid,
                            pair_first);
     }
-    e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, st_tile, L.spine_tiles, &tickets[kMaxPasses], s);
+    e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, status, L.spine_tiles, tickets, s);
     if (e != hipSuccess) return e;
-    // 5. per-tile [start, end) (the ranges were cleared in step 0)
+    // 4. per-tile [start, end) (the ranges were cleared in step 0), then each
+    //    tile's list in depth order
     if (capacity > 0) {
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s,
                            reinterpret_cast<const uint32_t*>(tile_keys), &cnt[2], reinterpret_cast<int2*>(ranges));
+        if (total_tiles > 0) {
+            const int2* rg = reinterpret_cast<const int2*>(ranges);
+            const float4* rc = reinterpret_cast<const float4*>(rec);
+            hipLaunchKernelGGL(k_tile_sort_short, dim3((unsigned)total_tiles), dim3(TSS_THREADS), 0, s, rg, views_dev,
+                               n_views, n, rc, inst_gid, inst);
+            const int lgw = (total_tiles + kTslTiles - 1) / kTslTiles;
+            const unsigned lg = (unsigned)(lgw < 1024 ? lgw : 1024);
+            hipLaunchKernelGGL(k_tile_sort_long, dim3(lg), dim3(TSL_THREADS), 0, s, rg, total_tiles, views_dev,
+                               n_views, n, rc, inst_gid, tile_keys, inst, ik2, iv2);
+        }
     }
     return hipGetLastError();
 }

@@ -27,6 +27,13 @@ def _stacked():
     return w.scene, w.views
 
 
+def _stacked_long():
+    """3000 large Gaussians over a 32x32 image: tile lists of thousands of
+    instances, longer than the per-tile depth sort holds in LDS."""
+    w = wl.tiny_scene(69, 3000, F=8, W=32, H=32, f=30.0, log_scale_mu=-1.6, spread=0.15)
+    return w.scene, w.views
+
+
 def _with_empty_view():
     """A batch whose second view faces away from every Gaussian."""
     w = wl.tiny_scene(66, 250, F=8, W=36, H=28, f=30.0)
@@ -60,6 +67,7 @@ CASES = {
     "empty-view-F8": _with_empty_view,
     "40views-F8": _many_views,
     "64views-F8": lambda: _many_views(seed=68, V=64),  # the most views a batch may hold (mask bit 63)
+    "stacked3000-F8": _stacked_long,
 }
 
 
@@ -163,7 +171,10 @@ def test_render_fwd_parity(name, tile, lds_batch, persistent):
     print(name, tile, "flagged", flagged, rep)
 
 
-@pytest.mark.parametrize("name", list(CASES))
+# stacked3000: thousands of Gaussians at nearly equal depths, whose binary32
+# depth order differs from the FP64 one for many pairs (a different but
+# equally valid composite); the binary32-geometry parity above covers it
+@pytest.mark.parametrize("name", [c for c in CASES if c != "stacked3000-F8"])
 def test_render_fwd_parity_fp64_geometry(name):
     """Against the all-FP64 oracle: same value tolerances, wider threshold
     margins (the binary32 mean is ~3e-5 px off), at most 2% of pixels."""
