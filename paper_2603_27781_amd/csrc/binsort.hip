@@ -648,15 +648,15 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ins
 // Gaussian-index order; a stable sort of each tile's list by the binary32
 // bits of its pair's camera depth (positive, so the bits order like the
 // values) leaves them in (depth, index) order, the order the forward and
-// backward walk.  Four stable counting passes over 8-bit digits.  Lists are
-// short (about 140 instances at the 8 x 1200x680, 1M-Gaussian workload, the
-// longest a few hundred), so one 64-thread workgroup sorts a list of up to
-// kTsShort in LDS, many of them in flight per CU; a second kernel takes
-// the longer lists (each workgroup finds those among kTslTiles tiles at a
-// time) with 256 threads, in LDS up to kTsLong and otherwise in
-// global memory (the tile's slices of the sorted tile keys, whose values
-// are all the tile's own id and are written back, and of the tile sort's
-// ping-pong arrays, unused by then).
+// backward walk.  Lists are short (about 140 instances at the 8 x
+// 1200x680, 1M-Gaussian workload, the longest a few hundred), so one
+// wavefront ranks a list of up to kTsShort (k_tile_sort_short), many of
+// them in flight per CU; a second kernel takes the longer lists (each
+// workgroup finds those among kTslTiles tiles at a time) with 256 threads
+// and stable counting passes over 8-bit digits, in LDS up to kTsLong and
+// otherwise in global memory (the tile's slices of the sorted tile keys,
+// whose values are all the tile's own id and are written back, and of the
+// tile sort's ping-pong arrays, unused by then).
 constexpr int kTsShort = 512, kTsLong = 2048;
 constexpr int kTslTiles = 64;  // tiles a long-list workgroup scans per stride
 
@@ -785,19 +785,70 @@ __device__ void tile_sort_lds(int t, int2 rg, const gs_view* __restrict__ views,
 constexpr int TSS_THREADS = kWave;  // short lists: one wavefront per tile
 constexpr int TSL_THREADS = 256;    // long lists
 
-__global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __restrict__ ranges,
-                                                                  const gs_view* __restrict__ views, int n_views,
-                                                                  int n, const float4* __restrict__ rec,
+// Ranks of the (at most 64 R) instances of a short list: the sorted position
+// of each is the number of instances with a smaller (depth bits, list
+// position) pair -- the pairs are distinct, so this is the stable order --
+// counted by the wavefront against every key, read from LDS as a broadcast.
+template <int R>
+__device__ __forceinline__ void tile_ranks(const uint64_t* __restrict__ s_key, int L, const uint64_t (&k)[8],
+                                           uint32_t (&rank)[8]) {
+#pragma unroll 4
+    for (int j = 0; j < L; ++j) {
+        const uint64_t kj = s_key[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) rank[r] += kj < k[r] ? 1u : 0u;
+    }
+}
+
+// Tiles in the XCD-aware order of the compositing launches (tile_of_block):
+// neighbouring lists gather the same Gaussians' ids and depths.
+__global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __restrict__ ranges, int total_tiles,
+                                                                  int run, const gs_view* __restrict__ views,
+                                                                  int n_views, int n, const float4* __restrict__ rec,
                                                                   const int32_t* __restrict__ inst_gid,
                                                                   int32_t* __restrict__ inst) {
-    __shared__ uint32_t s_k[2][kTsShort];
-    __shared__ uint32_t s_v[2][kTsShort];
-    __shared__ SegSortLds<TSS_THREADS> S;
-    const int t = blockIdx.x;
+    static_assert(kTsShort == 8 * kWave, "eight keys per lane");
+    __shared__ uint64_t s_key[kTsShort];
+    uint32_t* s_out = reinterpret_cast<uint32_t*>(s_key);  // reused once the ranks are known
+    const int t = tile_of_block(blockIdx.x, total_tiles, run);
+    if (t < 0) return;
     const int2 rg = ranges[t];
     const int L = rg.y - rg.x;
-    if (L <= 1 || L > kTsShort) return;  // uniform across the block
-    tile_sort_lds<TSS_THREADS, kTsShort>(t, rg, views, n_views, n, rec, inst_gid, inst, s_k, s_v, S);
+    if (L <= 1 || L > kTsShort) return;  // uniform across the wavefront
+    const int lane = threadIdx.x;
+    const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
+    uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
+    uint64_t k[8];
+    uint32_t e[8], rank[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = r * kWave + lane;
+        k[r] = ~0ull;
+        e[r] = 0u;
+        rank[r] = 0u;
+        if (i < L) {
+            e[r] = einst[i];
+            k[r] = ((uint64_t)__float_as_uint(rec[2 * (vbase + (size_t)inst_gid[e[r]]) + 1].z) << 32) | (uint32_t)i;
+            s_key[i] = k[r];
+        }
+    }
+    __syncthreads();
+    switch ((L + kWave - 1) / kWave) {
+        case 1: tile_ranks<1>(s_key, L, k, rank); break;
+        case 2: tile_ranks<2>(s_key, L, k, rank); break;
+        case 3: tile_ranks<3>(s_key, L, k, rank); break;
+        case 4: tile_ranks<4>(s_key, L, k, rank); break;
+        case 5: tile_ranks<5>(s_key, L, k, rank); break;
+        case 6: tile_ranks<6>(s_key, L, k, rank); break;
+        case 7: tile_ranks<7>(s_key, L, k, rank); break;
+        default: tile_ranks<8>(s_key, L, k, rank); break;
+    }
+    __syncthreads();  // every lane is done reading the keys
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        if (r * kWave + lane < L) s_out[rank[r]] = e[r];
+    __syncthreads();
+    for (int i = lane; i < L; i += kWave) einst[i] = s_out[i];
 }
 
 // The lists longer than kTsShort; each workgroup walks the tiles with a
@@ -962,8 +1013,9 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
         if (total_tiles > 0) {
             const int2* rg = reinterpret_cast<const int2*>(ranges);
             const float4* rc = reinterpret_cast<const float4*>(rec);
-            hipLaunchKernelGGL(k_tile_sort_short, dim3((unsigned)total_tiles), dim3(TSS_THREADS), 0, s, rg, views_dev,
-                               n_views, n, rc, inst_gid, inst);
+            const int run = tile_run(tile);
+            hipLaunchKernelGGL(k_tile_sort_short, dim3(tile_grid(total_tiles, run)), dim3(TSS_THREADS), 0, s, rg,
+                               total_tiles, run, views_dev, n_views, n, rc, inst_gid, inst);
             const int lgw = (total_tiles + kTslTiles - 1) / kTslTiles;
             const unsigned lg = (unsigned)(lgw < 1024 ? lgw : 1024);
             hipLaunchKernelGGL(k_tile_sort_long, dim3(lg), dim3(TSL_THREADS), 0, s, rg, total_tiles, views_dev,

@@ -10,30 +10,6 @@ namespace sgs {
 constexpr float kQ = -0.72134752044448170f;
 constexpr float kLn2 = 0.69314718055994531f;
 
-// Tile order of the one-workgroup-per-tile launches.  Workgroup b runs on
-// XCD b mod 8, and each XCD has its own L2; neighbouring tiles share most of
-// their Gaussians, so the tiles go to the XCDs in runs of about 32 k pixels
-// of consecutive tiles (the runs dealt round-robin), and the tiles an XCD
-// has in flight are neighbours whose shared Gaussian records come from its
-// own L2 instead of each being fetched again by another XCD.
-constexpr int kXcds = 8;
-template <int TS>
-__host__ __device__ constexpr int tile_run() { return 32768 / (TS * TS) > 8 ? 32768 / (TS * TS) : 8; }
-template <int TS>
-inline unsigned tile_grid(int total_tiles) {
-    const int runs = (total_tiles + tile_run<TS>() - 1) / tile_run<TS>();
-    return (unsigned)((runs + kXcds - 1) / kXcds * kXcds * tile_run<TS>());
-}
-// The tile of workgroup b of a tile_grid launch, or -1 (no tile: exit).
-template <int TS>
-__device__ __forceinline__ int tile_of_block(int b, int total_tiles) {
-    constexpr int R = tile_run<TS>();
-    const int x = b & (kXcds - 1), r = b / kXcds;
-    const int round = r / R;
-    const int t = (round * kXcds + x) * R + (r - round * R);
-    return t < total_tiles ? t : -1;
-}
-
 template <int F>
 struct AppRec {
     static constexpr int stride = ((3 + F) + 3) / 4 * 4;  // floats per Gaussian

@@ -42,6 +42,35 @@ struct GradPtrs {
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Tile order of the one-workgroup-per-tile launches.  Workgroup b runs on
+// XCD b mod 8, and each XCD has its own L2; neighbouring tiles share most of
+// their Gaussians, so the tiles go to the XCDs in runs of about 32 k pixels
+// of consecutive tiles (the runs dealt round-robin), and the tiles an XCD
+// has in flight are neighbours whose shared Gaussian records come from its
+// own L2 instead of each being fetched again by another XCD.
+constexpr int kXcds = 8;
+// Run length, in tiles, for tile side ts.
+__host__ __device__ constexpr int tile_run(int ts) { return 32768 / (ts * ts) > 8 ? 32768 / (ts * ts) : 8; }
+inline unsigned tile_grid(int total_tiles, int run) {
+    const int runs = (total_tiles + run - 1) / run;
+    return (unsigned)((runs + kXcds - 1) / kXcds * kXcds * run);
+}
+// The tile of workgroup b of a tile_grid launch, or -1 (no tile: exit).
+__device__ __forceinline__ int tile_of_block(int b, int total_tiles, int run) {
+    const int x = b & (kXcds - 1), r = b / kXcds;
+    const int round = r / run;
+    const int t = (round * kXcds + x) * run + (r - round * run);
+    return t < total_tiles ? t : -1;
+}
+template <int TS>
+inline unsigned tile_grid(int total_tiles) {
+    return tile_grid(total_tiles, tile_run(TS));
+}
+template <int TS>
+__device__ __forceinline__ int tile_of_block(int b, int total_tiles) {
+    return tile_of_block(b, total_tiles, tile_run(TS));
+}
+
 // Index of the view owning global tile t (views sorted by tile_offset).
 __device__ inline int view_of_tile(const gs_view* views, int n_views, int t) {
     int v = 0;
