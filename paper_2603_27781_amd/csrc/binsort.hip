@@ -361,16 +361,12 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(Src src, const int64_
 // per digit a prefix over the rows and wavefronts, then over the digits),
 // the tile is reordered by digit in LDS, and each digit's run of keys is
 // written to its global position as consecutive addresses, instead of every
-// key going to a different place.  touched_out (may be null): also writes
-// touched[value] at each output position (the last depth pass, so that the
-// instance offsets scan a plain array in sorted order).
+// key going to a different place.
 template <class Src>
 __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int64_t* count_dev, int64_t n_max,
                                                               int shift, const uint32_t* __restrict__ offs,
                                                               int nblk, uint32_t* __restrict__ keys_out,
-                                                              uint32_t* __restrict__ vals_out,
-                                                              const int32_t* __restrict__ touched,
-                                                              uint32_t* __restrict__ touched_out) {
+                                                              uint32_t* __restrict__ vals_out) {
     constexpr int SLOTS = RS_ITEMS * RS_WAVES;  // (row, wavefront) slots of a tile
     __shared__ uint32_t s_base[256];             // next global position per digit
     __shared__ uint32_t s_lstart[256];           // first tile position per digit
@@ -432,7 +428,6 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int
                 const uint32_t g = s_base[d] + (p - s_lstart[d]);
                 keys_out[g] = kk;
                 vals_out[g] = vv;
-                if (touched_out != nullptr) touched_out[g] = (uint32_t)touched[vv];
             }
         }
         __syncthreads();
@@ -446,14 +441,14 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int
 template <class Src>
 hipError_t radix_pass(Src src, const int64_t* count_dev, int64_t n_max, int shift, uint32_t* hist,
                       uint64_t* status, uint32_t* ticket, int64_t* total, uint32_t* ko, uint32_t* vo,
-                      const int32_t* touched, uint32_t* touched_out, hipStream_t s) {
+                      hipStream_t s) {
     const int nblk = rs_blocks(n_max);
     hipLaunchKernelGGL(k_radix_hist<Src>, dim3(nblk), dim3(RS_THREADS), 0, s, src, count_dev, n_max, shift, hist,
                        nblk);
     hipError_t e = exclusive_scan(LoadU32{hist}, nullptr, (int64_t)256 * nblk, status, ticket, hist, total, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_radix_scatter<Src>, dim3(nblk), dim3(RS_THREADS), 0, s, src, count_dev, n_max, shift, hist,
-                       nblk, ko, vo, touched, touched_out);
+                       nblk, ko, vo);
     return hipGetLastError();
 }
 
@@ -469,10 +464,9 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t*
     uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
     for (int p = 0; p < passes; ++p) {
         hipError_t e = (p == 0) ? radix_pass(SrcKI{ki}, count_dev, n_max, 0, hist, status, tickets, nullptr, ko,
-                                             vo, nullptr, nullptr, s)
+                                             vo, s)
                                 : radix_pass(SrcKV{ki, vi}, count_dev, n_max, 8 * p, hist,
-                                             status + p * spine_tiles, tickets + p, nullptr, ko, vo, nullptr,
-                                             nullptr, s);
+                                             status + p * spine_tiles, tickets + p, nullptr, ko, vo, s);
         if (e != hipSuccess) return e;
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
