@@ -160,11 +160,11 @@ int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views
  * gs_bin_sort -- tile binning and depth sort (Sec. 3.2.1: tile-based
  * rasterization of Gaussians sorted in depth order).  Every visible
  * (view, Gaussian) pair emits one instance per tile of its rectangle; the
- * instances are sorted by (global tile id, binary32 depth, Gaussian index)
- * with the library's own device radix sorts (visible pairs by depth, then
- * instances by tile, both stable).
- * An instance is identified by its emission index e (pairs in depth order,
- * each pair's tiles row by row), so the instances of one pair occupy the
+ * instances are sorted by (global tile id, binary32 depth, Gaussian index):
+ * a stable device radix sort of the instances by tile, then each tile's
+ * list by depth (its Gaussian-index order kept among equal depths).
+ * An instance is identified by its emission index e (pairs in (view, index)
+ * order, each pair's tiles row by row), so the instances of one pair occupy the
  * contiguous range [pair_first[pair], pair_first[pair] + tiles_touched[pair]).
  *   tile_keys[capacity]     global tile id of each sorted instance
  *   inst[capacity]          emission index of each sorted instance
