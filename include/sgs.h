@@ -485,6 +485,27 @@ int gs_pose_grad(const gs_gaussians* g, const gs_view* views, const gs_view* vie
                  const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, void* ws,
                  size_t ws_bytes, float* twist, gs_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * gs_pose_grad_noalloc -- gs_pose_grad without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight tracking loops, harnesses that forbid allocation).  It computes the
+ * same twist with the same kernels, bit for bit; the per-block partial sums
+ * go to a fixed scratch array of GS_NOALLOC_SCRATCH_BYTES in the library's
+ * own device memory (one copy per GPU, held until the process ends; nothing
+ * is allocated or freed by the call).  Every partial is written before it is
+ * read, so the array needs no clearing, but all calls on one GPU share it:
+ * calls that overlap in time on one GPU (two streams, two host threads)
+ * race and must be ordered by the caller.  The first call on each device
+ * looks the array's address up (hipGetSymbolAddress); make that first call
+ * outside stream capture.  Errors: as gs_pose_grad, and GS_ECAPACITY when
+ * gs_pose_grad_workspace(n, n_views) exceeds GS_NOALLOC_SCRATCH_BYTES
+ * (e.g. beyond 2M Gaussians at 16 views); nothing is launched then.
+ * --------------------------------------------------------------------------- */
+enum { GS_NOALLOC_SCRATCH_BYTES = 8 << 20 };
+int gs_pose_grad_noalloc(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                         const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, float* twist,
+                         gs_stream stream);
+
 /* Static description of a status code. */
 const char* gs_error_string(int status);
 /* Text of the last HIP error seen by this thread (empty if none). */

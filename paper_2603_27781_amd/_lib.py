@@ -26,10 +26,11 @@ EXPORTS = [
     "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_project_bwd_write",
     "gs_pose_grad_workspace",
     "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_expand_workspace",
-    "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_adam_step", "gs_pose_step", "gs_pose_step_dev", "gs_error_string",
+    "gs_expand", "gs_dsr_workspace", "gs_dsr", "gs_adam_step", "gs_pose_step", "gs_pose_step_dev", "gs_pose_grad_noalloc", "gs_error_string",
     "gs_last_hip_error", "gs_version",
 ]
 GS_LOSS_OBS_MASK, GS_LOSS_BCE = 1, 2
+GS_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class GsGaussians(ctypes.Structure):
@@ -120,6 +121,8 @@ def load() -> ctypes.CDLL:
     L.gs_pose_grad_workspace.argtypes = [c_int32, c_int32, P(c_size_t)]
     L.gs_pose_grad.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
                                c_void_p, c_size_t, c_void_p, c_void_p]
+    L.gs_pose_grad_noalloc.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p,
+                                       c_void_p, c_void_p, c_void_p]
     L.gs_default_slam_loss_opts.argtypes = [P(GsSlamLossOpts)]
     L.gs_slam_loss_workspace.argtypes = [P(GsView), c_int32, c_int32, P(GsDecoder), P(GsSlamLossOpts), P(c_size_t)]
     L.gs_slam_loss.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, P(GsDecoder), P(GsSlamLossOpts),

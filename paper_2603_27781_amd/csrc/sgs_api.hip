@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "sgs_common.h"
 #include "growth.h"
@@ -97,6 +98,38 @@ GaussPtrs gauss_ptrs(const gs_gaussians* g) {
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Scratch of gs_pose_grad_noalloc (the per-block partial twist sums), a
+// file-scope device array: every GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in for the symbol): its device
+// address is looked up once per device with hipGetSymbolAddress and kept in
+// g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)GS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+int scratch_ptr(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e);
+    if (dev < 0 || dev >= kMaxDevices) return GS_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e);
+        if (!p) return GS_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GS_OK;
+}
 
 size_t grad2d_bytes(int n, int n_feat, int n_views) {
     return ((size_t)n_views * n * 8 + (size_t)n * (4 + n_feat)) * sizeof(float);
@@ -469,6 +502,24 @@ int gs_pose_grad(const gs_gaussians* g, const gs_view* views, const gs_view* vie
     if (!tiles_touched || !grad2d || !ws || !twist) return GS_EINVAL;
     if (ws_bytes < pose_workspace_bytes(g->n, n_views)) return GS_ECAPACITY;
     if (!aligned16(grad2d) || (reinterpret_cast<uintptr_t>(ws) & 15u) != 0) return GS_EINVAL;
+    return hip_status(launch_pose_grad(gauss_ptrs(g), views_dev, n_views, make_const(cfg), tiles_touched, grad2d, ws,
+                                       twist, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_pose_grad_noalloc(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
+                         const gs_config* cfg, const int32_t* tiles_touched, const float* grad2d, float* twist,
+                         gs_stream stream) {
+    int st = check_gauss(g, false);
+    if (st) return st;
+    if ((st = check_config(cfg))) return st;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, nullptr))) return st;
+    if (!tiles_touched || !grad2d || !twist) return GS_EINVAL;
+    if (!aligned16(grad2d)) return GS_EINVAL;
+    if (pose_workspace_bytes(g->n, n_views) > kScratchBytes) return GS_ECAPACITY;
+    void* ws = nullptr;
+    if ((st = scratch_ptr(&ws))) return st;
+    // k_pose_partial writes every partial k_pose_final reads, so the scratch
+    // needs no clearing between calls.
     return hip_status(launch_pose_grad(gauss_ptrs(g), views_dev, n_views, make_const(cfg), tiles_touched, grad2d, ws,
                                        twist, reinterpret_cast<hipStream_t>(stream)));
 }

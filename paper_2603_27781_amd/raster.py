@@ -329,7 +329,15 @@ class Rasterizer:
                  self.touched.data_ptr(), self.grad2d.data_ptr(), self.grad2d.numel() * 4, ctypes.byref(gc),
                  _stream()), "gs_project_bwd_write" if write else "gs_project_bwd")
 
-    def pose_grad(self, g: Gaussians) -> torch.Tensor:
+    def pose_grad(self, g: Gaussians, noalloc: bool = False) -> torch.Tensor:
+        """gs_pose_grad into self.twist; noalloc=True calls
+        gs_pose_grad_noalloc (the library's own scratch, no workspace)."""
+        if noalloc:
+            check(self.L.gs_pose_grad_noalloc(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(),
+                                              self.views.n, ctypes.byref(self.cc), self.touched.data_ptr(),
+                                              self.grad2d.data_ptr(), self.twist.data_ptr(), _stream()),
+                  "gs_pose_grad_noalloc")
+            return self.twist
         check(self.L.gs_pose_grad(ctypes.byref(g.c()), self.views.host, self.views.dev_ptr(), self.views.n,
                                   ctypes.byref(self.cc), self.touched.data_ptr(), self.grad2d.data_ptr(),
                                   self.pose_ws.data_ptr(), self.pose_ws.numel() * 8, self.twist.data_ptr(),
