@@ -70,10 +70,9 @@ class Cfg:
 
     def array(self) -> np.ndarray:
         amin = float(np.float32(self.alpha_min))
-        kbox = 2.0 * math.log(1.0 / amin)
         lmin = math.log(amin / (1.0 - amin))
         return np.array([self.z_near, self.blur, self.guard, self.alpha_min, self.alpha_max,
-                         self.T_min, kbox, lmin], dtype=np.float32)
+                         self.T_min, 0.0, lmin], dtype=np.float32)
 
 
 def views_array(views, dtype=np.float32, poses64: Optional[List[np.ndarray]] = None) -> np.ndarray:
@@ -371,12 +370,17 @@ GRAD_POSE = 2
 
 
 def backward(scene, views, cfg: Cfg, grad_out: np.ndarray, bins=None, flags=GRAD_PARAMS | GRAD_POSE,
-             tile_mask=None, s64=None, poses64=None):
-    """FP64 backward of <grad_out, render> to every parameter and the pose."""
+             tile_mask=None, s64=None, poses64=None, decisions="fp64"):
+    """FP64 backward of <grad_out, render> to every parameter and the pose.
+    decisions="fp32" takes each pixel's contributor set and stop (the
+    alpha_min / T_min decisions) on the binary32 decision geometry, as
+    render(geometry="fp32") does, while every value and derivative stays on
+    the FP64 projection."""
     L = lib()
     bins = bin_instances(scene, views, cfg) if bins is None else bins
     s64 = scene64(scene) if s64 is None else s64
     proj = project64(scene, views, cfg, s64, poses64)
+    dproj = project32(scene, views, cfg, bins["dec"]) if decisions == "fp32" else None
     F, n, V = scene.n_feat, scene.n, len(views)
     vis = np.ascontiguousarray((bins["dec"]["touched"] > 0).astype(np.uint8))
     r = {
@@ -390,7 +394,7 @@ def backward(scene, views, cfg: Cfg, grad_out: np.ndarray, bins=None, flags=GRAD
     L.orc_backward(ctypes.c_int(n), ctypes.c_int(F), _p(s64["mu"]), _p(s64["log_scale"]), _p(s64["quat"]),
                    _p(s64["logit"]), _p(s64["color"]), _p(s64["feat"]), ctypes.c_int(V),
                    _p(views_array(views, np.float64, poses64)), _p(cfg.array()), ctypes.c_int(cfg.tile),
-                   _p(np.ascontiguousarray(bins["ranges"])), _p(gids), _p(proj),
+                   _p(np.ascontiguousarray(bins["ranges"])), _p(gids), _p(proj), _p(dproj),
                    _p(np.ascontiguousarray(grad_out, np.float64)), _p(tm), _p(vis), ctypes.c_int(flags),
                    _p(r["grad2d"]), _p(r["gapp"]), _p(r["mu"]), _p(r["log_scale"]), _p(r["quat"]),
                    _p(r["logit"]), _p(r["color"]), _p(r["feat"]), _p(r["gcam"]), _p(r["Gcam"]),
@@ -416,6 +420,23 @@ def dec_exp(x: np.ndarray) -> np.ndarray:
     y = np.zeros_like(x)
     L.orc_dec_exp(ctypes.c_int(x.size), _p(x), _p(y))
     return y
+
+
+def dec_log(x: np.ndarray) -> np.ndarray:
+    """The decision path's binary32 natural logarithm (positive normal x)."""
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.zeros_like(x)
+    lib().orc_dec_log(ctypes.c_int(x.size), _p(x), _p(y))
+    return y
+
+
+def box_k(logit: np.ndarray, alpha_min: float = 1.0 / 255.0) -> np.ndarray:
+    """Squared box radius (in standard deviations) of each opacity logit on
+    the decision path, 2 ln(o / alpha_min) + 2^-8; 0 where o <= alpha_min."""
+    x = np.ascontiguousarray(logit, np.float32)
+    k = np.zeros_like(x)
+    lib().orc_box_k(ctypes.c_int(x.size), _p(x), ctypes.c_float(float(np.float32(alpha_min))), _p(k))
+    return k
 
 
 def num_threads() -> int:

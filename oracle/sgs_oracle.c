@@ -43,10 +43,10 @@
 #include <omp.h>
 #endif
 
-/* cfg layout (float[8]): z_near, blur, guard, alpha_min, alpha_max, T_min, kbox, logit_min
- * kbox      = (float)(2*ln(1/alpha_min))          squared box radius in std-devs
- * logit_min = (float)ln(alpha_min/(1-alpha_min))  opacity cull threshold        */
-enum { C_ZNEAR = 0, C_BLUR, C_GUARD, C_AMIN, C_AMAX, C_TMIN, C_KBOX, C_LOGITMIN };
+/* cfg layout (float[8]): z_near, blur, guard, alpha_min, alpha_max, T_min, (unused), logit_min
+ * logit_min = (float)ln(alpha_min/(1-alpha_min))  opacity cull threshold
+ * The box size is per Gaussian (box_k below).                                  */
+enum { C_ZNEAR = 0, C_BLUR, C_GUARD, C_AMIN, C_AMAX, C_TMIN, C_UNUSED, C_LOGITMIN };
 
 /* view layout: [W, H, fx, fy, cx, cy, R00..R22, t0, t1, t2] = 18 values */
 #define VSTRIDE 18
@@ -81,6 +81,47 @@ static float dec_expf(float x) {
     return ldexpf(p, (int)n);
 }
 
+/* Natural logarithm of a positive normal binary32 y on the decision path.
+ * Reduction: y = m * 2^e with m in [sqrt(1/2), sqrt(2)) -- frexp gives m in
+ * [1/2, 1), and m below sqrt(1/2) is doubled (e lowered by one).  With
+ * f = m - 1 (exact in that range) and s = f / (2 + f), ln m = 2 atanh(s),
+ * whose odd series 2s (1 + z/3 + z^2/5 + z^3/7 + z^4/9 + z^5/11), z = s^2,
+ * is truncated after the z^5 term (|s| < 0.172, so the next term is below
+ * 1e-9 relative).  ln y = e ln2_hi + (ln m + e ln2_lo), with ln 2 split in
+ * a short head (e * head exact) and a tail. */
+static float dec_logf(float y) {
+    int e;
+    float m = frexpf(y, &e);
+    if (m < 0x1.6a09e6p-1f) {   /* binary32 sqrt(1/2) */
+        m = m + m;
+        e = e - 1;
+    }
+    float f = m - 1.0f;
+    float s = f / (2.0f + f);
+    float z = s * s;
+    float series = 0x1.745d18p-4f;            /* 1/11 */
+    series = 0x1.c71c72p-4f + z * series;     /* 1/9  */
+    series = 0x1.24924ap-3f + z * series;     /* 1/7  */
+    series = 0x1.99999ap-3f + z * series;     /* 1/5  */
+    series = 0x1.555556p-2f + z * series;     /* 1/3  */
+    float two_s = s + s;
+    float ln_m = two_s + (two_s * z) * series;
+    float fe = (float)e;
+    return fe * 0x1.62e4p-1f + (ln_m + fe * 0x1.7f7d1cp-20f);
+}
+
+/* Squared box radius, in standard deviations, of a Gaussian with opacity
+ * logit l (reading R5): alpha = o exp(-q/2) reaches alpha_min only where
+ * q <= 2 ln(o / alpha_min), o = sigmoid(l) evaluated on the decision path;
+ * 2^-8 is added so that the box also holds the pairs whose binary32 alpha
+ * rounds up to alpha_min.  Returns 0 when o / alpha_min <= 1 (culled). */
+static float box_k(float logit, float alpha_min) {
+    float o = 1.0f / (1.0f + dec_expf(-logit));
+    float y = o / alpha_min;
+    if (!(y > 1.0f)) return 0.0f;
+    return 2.0f * dec_logf(y) + 0x1p-8f;
+}
+
 /* One (view, Gaussian) pair on the binary32 decision path.
  * Returns 1 if visible, 0 if culled.  rec = (mx, my, A, B, C, d, rx, ry). */
 static int decide_one(const float* mu, const float* ls, const float* q, float logit,
@@ -89,6 +130,8 @@ static int decide_one(const float* mu, const float* ls, const float* q, float lo
     const float* R = vw + 6;
     const float* t = vw + 15;
     if (!(logit > cfg[C_LOGITMIN])) return 0;
+    const float k = box_k(logit, cfg[C_AMIN]);
+    if (!(k > 0.0f)) return 0;
     float p0 = ((R[0] * mu[0] + R[1] * mu[1]) + R[2] * mu[2]) + t[0];
     float p1 = ((R[3] * mu[0] + R[4] * mu[1]) + R[5] * mu[2]) + t[1];
     float p2 = ((R[6] * mu[0] + R[7] * mu[1]) + R[8] * mu[2]) + t[2];
@@ -142,8 +185,8 @@ static int decide_one(const float* mu, const float* ls, const float* q, float lo
     rec[3] = -b / det;
     rec[4] = a / det;
     rec[5] = p2;
-    rec[6] = sqrtf(cfg[C_KBOX] * a) * 0x1.004p+0f;
-    rec[7] = sqrtf(cfg[C_KBOX] * c) * 0x1.004p+0f;
+    rec[6] = sqrtf(k * a) * 0x1.004p+0f;
+    rec[7] = sqrtf(k * c) * 0x1.004p+0f;
     return 1;
 }
 
@@ -392,6 +435,7 @@ typedef struct {
     const double* color;   /* [3][n] */
     const double* feat;    /* [F][n] */
     const proj_t* proj;    /* [V][n] */
+    const proj_t* dproj;   /* [V][n] geometry the alpha_min / T_min decisions are taken on */
     int64_t* tile_base;
     int64_t* pix_base;
 } scene_ctx;
@@ -467,7 +511,7 @@ static void setup_ctx(scene_ctx* s, int n, int F, const double* color, const dou
                       const double* views, const float* cfg, int tile, const int32_t* ranges,
                       const int32_t* gids, const proj_t* proj) {
     s->V = V; s->n = n; s->F = F; s->tile = tile; s->views = views; s->cfg = cfg;
-    s->ranges = ranges; s->gids = gids; s->color = color; s->feat = feat; s->proj = proj;
+    s->ranges = ranges; s->gids = gids; s->color = color; s->feat = feat; s->proj = proj; s->dproj = proj;
     s->tile_base = (int64_t*)malloc(sizeof(int64_t) * (V > 0 ? V : 1));
     s->pix_base = (int64_t*)malloc(sizeof(int64_t) * (V + 1));
     int64_t tb = 0, pb = 0;
@@ -587,7 +631,11 @@ void orc_loss(int F, int K, int V, const int64_t* pix_count, const double* out, 
  * transmittance before every included Gaussian (no division), then the
  * gradient is accumulated in reverse with per-channel suffix sums
  *   dL/dalpha_i = sum_ch g_ch (x_i,ch T_i - S_ch / (1 - alpha_i)),
- *   S_ch = sum_{j > i} x_j,ch alpha_j T_j. */
+ *   S_ch = sum_{j > i} x_j,ch alpha_j T_j.
+ * Which Gaussians are included (alpha >= alpha_min) and where the pixel
+ * stops (T (1 - alpha) < T_min) is decided on s->dproj; every value comes
+ * from s->proj (the two are the same unless a caller asks for decisions on
+ * another geometry). */
 static void pixel_backward(const scene_ctx* s, int v, int u, int w_, const double* gpix,
                            double* inst_acc, int32_t beg, int32_t end) {
     const double amin = s->cfg[C_AMIN], amax = s->cfg[C_AMAX], tmin = s->cfg[C_TMIN];
@@ -597,15 +645,16 @@ static void pixel_backward(const scene_ctx* s, int v, int u, int w_, const doubl
     int cap = 64, m = 0;
     int32_t* ks = (int32_t*)malloc(sizeof(int32_t) * cap);
     double* Ts = (double*)malloc(sizeof(double) * cap);
-    double T = 1.0;
+    double T = 1.0, Td = 1.0;
     for (int32_t k = beg; k < end; ++k) {
-        const proj_t* pr = s->proj + (size_t)v * s->n + s->gids[k];
+        const size_t o = (size_t)v * s->n + s->gids[k];
         double raw, G, dx, dy;
         int qc;
-        double a = pair_alpha(pr, px, py, amax, &raw, &G, &dx, &dy, &qc);
-        if (a < amin) continue;
-        double Tn = T * (1.0 - a);
-        if (Tn < tmin) break;
+        double ad = pair_alpha(s->dproj + o, px, py, amax, &raw, &G, &dx, &dy, &qc);
+        if (ad < amin) continue;
+        double Tdn = Td * (1.0 - ad);
+        if (Tdn < tmin) break;
+        double a = pair_alpha(s->proj + o, px, py, amax, &raw, &G, &dx, &dy, &qc);
         if (m == cap) {
             cap *= 2;
             ks = (int32_t*)realloc(ks, sizeof(int32_t) * cap);
@@ -614,7 +663,8 @@ static void pixel_backward(const scene_ctx* s, int v, int u, int w_, const doubl
         ks[m] = k;
         Ts[m] = T;
         ++m;
-        T = Tn;
+        T = T * (1.0 - a);
+        Td = Tdn;
     }
     double S[5 + 256];
     for (int ch = 0; ch < NC; ++ch) S[ch] = 0.0;
@@ -755,12 +805,13 @@ static void project_backward(const geom_t* g, const double* vw, const double* g2
 void orc_backward(int n, int F, const double* mu, const double* ls, const double* quat,
                   const double* logit, const double* color, const double* feat, int V,
                   const double* views, const float* cfg, int tile, const int32_t* ranges,
-                  const int32_t* gids, const double* proj, const double* grad_out,
+                  const int32_t* gids, const double* proj, const double* dproj, const double* grad_out,
                   const uint8_t* tile_mask, const uint8_t* vis, int flags,
                   double* grad2d, double* gapp, double* dmu, double* dls, double* dq, double* dlogit,
                   double* dcolor, double* dfeat, double* gcam, double* Gcam, double* twist) {
     scene_ctx s;
     setup_ctx(&s, n, F, color, feat, V, views, cfg, tile, ranges, gids, (const proj_t*)proj);
+    if (dproj) s.dproj = (const proj_t*)dproj;
     const int64_t P = s.pix_base[V];
     const int NC = 5 + F, IS = IA + F, GA = 4 + F;
     int64_t total_tiles = 0;
@@ -913,6 +964,15 @@ void orc_geom(const double* mu, const double* ls, const double* q, double logit,
 /* The decision-path exponential, exposed for its accuracy pin. */
 void orc_dec_exp(int n, const float* x, float* y) {
     for (int i = 0; i < n; ++i) y[i] = dec_expf(x[i]);
+}
+
+/* test hooks of the decision-path logarithm and box size */
+void orc_dec_log(int n, const float* x, float* y) {
+    for (int i = 0; i < n; ++i) y[i] = dec_logf(x[i]);
+}
+
+void orc_box_k(int n, const float* logit, float alpha_min, float* k) {
+    for (int i = 0; i < n; ++i) k[i] = box_k(logit[i], alpha_min);
 }
 
 /* ========================================================================= */

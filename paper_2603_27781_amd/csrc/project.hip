@@ -25,7 +25,7 @@ constexpr int kViewFloats = 20;
 constexpr int kProjThreads = 256;
 constexpr int kProjWaves = kProjThreads / kWave;
 constexpr int kProjRing = 128;  // queued (view, lane) entries per wavefront
-constexpr int kProjG = 13;      // per-Gaussian values shared in LDS: M (9), opacity, mean (3)
+constexpr int kProjG = 14;      // per-Gaussian values shared in LDS: M (9), opacity, mean (3), box k
 
 // Camera-frame position p = R mu + t (one rounding per operation, fixed order).
 __device__ __forceinline__ void cam_point(const float* R, float m0, float m1, float m2, float& p0, float& p1,
@@ -44,8 +44,8 @@ __device__ __forceinline__ float guard_limit(float guard, int extent, float foca
 // rectangle; writes the pair's record and rectangle when it is visible and
 // returns its tile count (0 when culled).
 __device__ __forceinline__ int32_t project_pair(const float* vw, const float* Mg, float op, float m0, float m1,
-                                                float m2, const RasterConst& c, size_t o, float4* __restrict__ rec,
-                                                uint2* __restrict__ rect) {
+                                                float m2, float kbox, const RasterConst& c, size_t o,
+                                                float4* __restrict__ rec, uint2* __restrict__ rect) {
     const float* R = vw;
     const float fx = vw[12], fy = vw[13], cx = vw[14], cy = vw[15], limx = vw[16], limy = vw[17];
     const float txm1 = vw[18], tym1 = vw[19];
@@ -78,8 +78,8 @@ __device__ __forceinline__ int32_t project_pair(const float* vw, const float* Mg
     const float cc = ((U10 * U10 + U11 * U11) + U12 * U12) + c.blur;
     const float det = a * cc - b * b;
     if (!((det > 0.0f) && (det < INFINITY))) return 0;
-    const float rx = sqrtf(c.kbox * a) * 0x1.004p+0f;
-    const float ry = sqrtf(c.kbox * cc) * 0x1.004p+0f;
+    const float rx = sqrtf(kbox * a) * 0x1.004p+0f;
+    const float ry = sqrtf(kbox * cc) * 0x1.004p+0f;
     // tile rectangle (inclusive); tile is a power of two so the scale is exact
     const float inv = 1.0f / (float)c.tile;
     float fx0 = floorf((mx - rx) * inv), fx1 = floorf((mx + rx) * inv);
@@ -163,7 +163,9 @@ __global__ void __launch_bounds__(kProjThreads) k_project(GaussPtrs g, const gs_
     }
 
     const float n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
-    const bool alive = valid && (logit > c.logit_min) && (n2 > 0.0f) && (n2 < INFINITY);
+    // opacity-aware box (R5): the decision-path k, <= 0 for o <= alpha_min
+    const float kbox = valid ? dec_box_k(logit, c.alpha_min) : 0.0f;
+    const bool alive = valid && (logit > c.logit_min) && (kbox > 0.0f) && (n2 > 0.0f) && (n2 < INFINITY);
     if (alive) {
         // rotation of the unit quaternion and M = R S (Eq. 2)
         const float nrm = sqrtf(n2);
@@ -194,6 +196,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project(GaussPtrs g, const gs_
         s_g[10][tid] = m0;
         s_g[11][tid] = m1;
         s_g[12][tid] = m2;
+        s_g[13][tid] = kbox;
     }
     __syncthreads();
 
@@ -210,7 +213,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project(GaussPtrs g, const gs_
             for (int k = 0; k < 9; ++k) Mg[k] = s_g[k][col];
             const size_t o = (size_t)v * n + gbase + gl;
             touched[o] = project_pair(s_vw + v * kViewFloats, Mg, s_g[9][col], s_g[10][col], s_g[11][col],
-                                      s_g[12][col], c, o, rec, rect);
+                                      s_g[12][col], s_g[13][col], c, o, rec, rect);
         }
     };
     int head = 0, tail = 0;

@@ -47,7 +47,6 @@ RasterConst make_const(const gs_config* c) {
     k.alpha_max = c->alpha_max;
     k.T_min = c->T_min;
     const double am = (double)c->alpha_min;
-    k.kbox = (float)(2.0 * std::log(1.0 / am));
     k.logit_min = (float)std::log(am / (1.0 - am));
     k.tile = c->tile;
     return k;

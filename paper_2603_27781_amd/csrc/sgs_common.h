@@ -15,7 +15,6 @@ constexpr int kWave = 64;
 // Constants of the rasterizer derived on the host from gs_config.
 struct RasterConst {
     float z_near, blur, guard, alpha_min, alpha_max, T_min;
-    float kbox;       // (float)(2 ln(1/alpha_min)): squared box radius in std-devs
     float logit_min;  // (float)ln(alpha_min / (1 - alpha_min)): opacity cull
     int32_t tile;
 };

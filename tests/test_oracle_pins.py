@@ -126,6 +126,79 @@ def test_jacobian_matches_finite_difference_of_projection(orc):
     assert np.allclose(got, S, rtol=1e-6, atol=1e-14)
 
 
+def test_dec_log_accuracy(orc):
+    """The decision path's binary32 logarithm against the FP64 library log:
+    within 2 ulp of the result everywhere, exact at 1."""
+    rng = np.random.default_rng(5)
+    x = np.concatenate([1.0 + rng.uniform(0, 1e-3, 4000), rng.uniform(1.0, 300.0, 40000),
+                        np.exp(rng.uniform(-80, 80, 40000)), [1.0, 2.0, 255.0, 0.5, 1e-30, 1e30]]).astype(np.float32)
+    y = orc.dec_log(x).astype(np.float64)
+    ref = np.log(x.astype(np.float64))
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(y - ref) <= 2.0 * ulp), float(np.max(np.abs(y - ref) / ulp))
+    assert y[x == 1.0].tolist() == [0.0] * int(np.sum(x == 1.0))
+
+
+def test_box_k_is_twice_log_opacity_over_alpha_min(orc):
+    """R5: the squared box radius is 2 ln(o / alpha_min) (+ 2^-8), from the
+    opacity o = sigmoid(logit); 0 (culled) where o <= alpha_min."""
+    rng = np.random.default_rng(6)
+    amin = float(np.float32(1.0 / 255.0))
+    lmin = math.log(amin / (1 - amin))
+    logit = np.concatenate([rng.normal(0, 3, 20000), lmin + rng.normal(0, 1e-3, 2000), [60.0, -60.0, 0.0]])
+    logit = logit.astype(np.float32)
+    k = orc.box_k(logit).astype(np.float64)
+    o = 1.0 / (1.0 + np.exp(-logit.astype(np.float64)))
+    ref = 2.0 * np.log(o / amin) + 2.0 ** -8
+    clear_in = o > amin * (1 + 1e-5)
+    clear_out = o < amin * (1 - 1e-5)
+    assert np.all(np.abs(k[clear_in] - ref[clear_in]) <= 1e-6 * np.maximum(1.0, ref[clear_in]))
+    assert np.all(k[clear_out] == 0.0)
+    # an opaque Gaussian's box: 2 ln(1/alpha_min) = 2 ln 255
+    assert k[-3] == pytest.approx(2 * math.log(255.0) + 2.0 ** -8, rel=1e-6)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_tile_rectangle_edges_follow_the_r5_box(orc, tile):
+    """Both edges of every visible pair's tile rectangle are where R5 puts
+    them, from FP64 quantities: the box [m - r, m + r] with r = sqrt(k Sigma2D_xx)
+    (1 + 2^-10), k = 2 ln(o / alpha_min) (+ 2^-8), mean, Sigma2D and o from
+    the FP64 projection, touches tiles floor((m - r)/tile) .. floor((m + r)/tile),
+    clamped to the grid.  The FP64 box is bracketed (r without the padding,
+    less 1e-3 px, and with it, plus 1e-3 px) to absorb binary32 rounding; a
+    rectangle even one tile too wide or too narrow on either side fails."""
+    w = wl.config1(scale=0.5)
+    views = w.views + [wl.make_view(53, 37, 40.0, wl.se3_exp(np.array([0.1, -0.05, 0.2, 0.05, 0.1, -0.03])))]
+    cfg = orc.Cfg(tile=tile)
+    dec = orc.decide(w.scene, views, cfg)
+    proj = orc.project64(w.scene, views, cfg)
+    amin = float(np.float32(cfg.alpha_min))
+    checked = 0
+    for vi, v in enumerate(views):
+        vis = dec["touched"][vi] > 0
+        mx, my, A, B, C, o = (proj[vi][vis][:, k] for k in range(6))
+        det = A * C - B * B
+        sxx, syy = C / det, A / det
+        kk = 2.0 * np.log(o / amin)
+        ntx, nty = (v.width + tile - 1) // tile, (v.height + tile - 1) // tile
+        rect = dec["rect"][vi][vis]
+        for m, sig, lim, lo_col, hi_col in ((mx, sxx, ntx, 0, 2), (my, syy, nty, 1, 3)):
+            r_lo = np.sqrt(kk * sig) - 1e-3
+            r_hi = np.sqrt((kk + 2.0 ** -8) * sig) * (1 + 2.0 ** -10) + 1e-3
+            cl = lambda t: np.clip(t, 0, lim - 1)
+            lo0, lo1 = cl(np.floor((m - r_hi) / tile)), cl(np.floor((m - r_lo) / tile))
+            hi0, hi1 = cl(np.floor((m + r_lo) / tile)), cl(np.floor((m + r_hi) / tile))
+            assert np.all((rect[:, lo_col] >= lo0) & (rect[:, lo_col] <= lo1))
+            assert np.all((rect[:, hi_col] >= hi0) & (rect[:, hi_col] <= hi1))
+            # the bracket is narrow: it leaves a choice for few pairs
+            assert np.mean(lo0 != lo1) < 0.01 and np.mean(hi0 != hi1) < 0.01
+        checked += int(vis.sum())
+        # opacity cull: o <= alpha_min is never visible
+        o_all = 1.0 / (1.0 + np.exp(-w.scene.logit.astype(np.float64)))
+        assert not np.any(dec["touched"][vi][o_all <= amin])
+    assert checked > 500
+
+
 def test_decision_path_agrees_with_fp64(orc):
     w = wl.config1(scale=0.25)
     cfg = orc.Cfg()
@@ -457,3 +530,21 @@ def test_loss_gradient_matches_torch_cross_entropy(orc):
     assert terms[3] == pytest.approx(float(tot), rel=1e-12)
     assert np.max(np.abs(g - o.grad.numpy())) < 1e-15
     assert np.all(g[4] == 0)
+
+
+def test_backward_decision_geometry_changes_only_decisions(orc):
+    """Taking the alpha_min / T_min decisions on the binary32 decision
+    geometry leaves every value on the FP64 projection: where both
+    geometries give every pixel the same contributors and stop (the 64x64,
+    2,000-Gaussian workload), the gradients are the same bits."""
+    w = wl.config1()
+    cfg = orc.Cfg(tile=16)
+    bins = orc.bin_instances(w.scene, w.views, cfg)
+    r64 = orc.render(w.scene, w.views, cfg, bins=bins)
+    r32 = orc.render(w.scene, w.views, cfg, bins=bins, geometry="fp32")
+    assert np.array_equal(r64["ncontrib"], r32["ncontrib"]) and np.array_equal(r64["last"], r32["last"])
+    go = np.random.default_rng(3).normal(size=r64["out"].shape) * 1e-2
+    a = orc.backward(w.scene, w.views, cfg, go, bins=bins)
+    b = orc.backward(w.scene, w.views, cfg, go, bins=bins, decisions="fp32")
+    for k in ("grad2d", "mu", "log_scale", "quat", "logit", "color", "feat", "twist"):
+        assert np.array_equal(a[k], b[k]), k
