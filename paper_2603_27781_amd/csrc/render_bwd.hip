@@ -6,8 +6,13 @@
 // transmittance before every contributor by division, T_i = T_{i+1}/(1-a_i),
 // instead of storing it.  With g the pixel's upstream gradient (5+F
 // channels) and x_i the Gaussian's channel values (colour, depth, 1, f),
-//   dL/dalpha_i = T_i (g . x_i) - S_i / (1 - alpha_i),
-//   S_i = sum_{j>i} (g . x_j) alpha_j T_j      (one scalar per pixel),
+//   dL/dalpha_i = T_i (g . x_i) - sum_{j>i} (g . x_j) alpha_j T_j / (1 - alpha_i)
+//               = T_i ((g . x_i) - R_i),
+//   R_i = sum_{j>i} (g . x_j) alpha_j prod_{i<k<j} (1 - alpha_k)
+// (one scalar per pixel), accumulated from the back as
+// R_{i-1} = R_i + alpha_i ((g . x_i) - R_i): a convex combination per step,
+// with no division by 1 - alpha_i, so the error of the rebuilt T_i scales
+// the (small) difference instead of two large terms before they cancel;
 // then through alpha = min(alpha_max, o 2^q'), q' = A'dx^2 + B2'dx dy + C'dy^2,
 // to the projected mean, the conic, the opacity, and linearly to colour,
 // depth and feature.  The 10+F per-Gaussian values of the 64 pixels of a
@@ -243,7 +248,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 #pragma unroll
         for (int ch = 0; ch < 5 + F; ++ch) g[ch] = inside ? grad_out[ch * P + p] : 0.0f;
     }
-    float Sg = 0.0f;
+    float Rg = 0.0f;  // R of the Gaussian about to be visited
     const float log2_amin = __log2f(c.alpha_min);
     const float amin = c.alpha_min, amax = c.alpha_max;
 
@@ -419,8 +424,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 // multipliers, so a step without contributors adds zeros.
                 {
                     const float ac = contrib ? a : 0.0f;
-                    const float ra = __builtin_amdgcn_rcpf(1.0f - ac);
-                    T = T * ra;  // transmittance before this Gaussian
+                    T = T * __builtin_amdgcn_rcpf(1.0f - ac);  // transmittance before this Gaussian
                     const float w = ac * T;
                     // g . x over the 5+F channels of this lane's pixel
                     float gx;
@@ -447,8 +451,9 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 #pragma unroll
                         for (int f = 0; f < F; ++f) gx = fmaf(g[5 + f], xs[3 + f], gx);
                     }
-                    const float dA = fmaf(T, gx, -Sg * ra);
-                    Sg = fmaf(gx, w, Sg);
+                    const float dg = gx - Rg;
+                    const float dA = T * dg;
+                    Rg = fmaf(ac, dg, Rg);
                     const float hm = (contrib && unc) ? dA : 0.0f;
                     const float h = hm * a;
                     float val[NBF];
@@ -592,7 +597,9 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
         const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
         s_start[wave][lane] = start;
         s_first[wave][lane] = first;
-        float geo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // the pair's records are summed in FP64: a Gaussian spanning many
+        // tiles adds many partials of both signs (float only at the end)
+        double geo[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int carry = -1;  // owner of the last record before the current 64
         for (int base = 0; base < total; base += kWave) {
             // owner of record base + lane: the last lane with records whose
@@ -632,7 +639,7 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
                     rr[4 * q + 3] = a.w;
                 }
 #pragma unroll
-                for (int q = 0; q < 6; ++q) geo[q] += rr[q];
+                for (int q = 0; q < 6; ++q) geo[q] += (double)rr[q];
                 if (PARAMS) {
 #pragma unroll
                     for (int q = 0; q < NA; ++q) appacc[q] += rr[6 + q];
@@ -641,8 +648,8 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
         }
         if (vis) {
             float4* gg = reinterpret_cast<float4*>(grad_geo + pair * 8);
-            gg[0] = make_float4(geo[0], geo[1], geo[2], geo[3]);
-            gg[1] = make_float4(geo[4], geo[5], 0.f, 0.f);
+            gg[0] = make_float4((float)geo[0], (float)geo[1], (float)geo[2], (float)geo[3]);
+            gg[1] = make_float4((float)geo[4], (float)geo[5], 0.f, 0.f);
         }
         // the next round reuses this wavefront's LDS
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
