@@ -7,68 +7,10 @@ import pytest
 
 import oracle
 from paper_2603_27781_amd import workloads as wl
-from gpu_common import (MARGIN, TOL_GRAD, chan_scales, compare_render, gpu_setup, oracle_cfg, rel_err)
+from gpu_common import (CASES, MARGIN, TOL_GRAD, chan_scales, compare_render, gpu_setup, oracle_cfg, rel_err)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-
-def _multi_view_tiny(seed=61, n=300, F=16):
-    w = wl.tiny_scene(seed, n, F=F, W=53, H=37, f=40.0)
-    v2 = wl.make_view(29, 21, 25.0, wl.se3_exp(np.array([0.02, -0.01, 0.03, 0.01, 0.03, -0.02])))
-    v3 = wl.make_view(64, 48, 50.0, wl.se3_exp(np.array([-0.05, 0.02, 0.0, -0.02, 0.01, 0.04])))
-    return w.scene, w.views + [v2, v3]
-
-
-def _stacked():
-    """600 large Gaussians in a small region: every tile list spans several
-    LDS batches and most pixels stop at T_min."""
-    w = wl.tiny_scene(65, 600, F=16, W=48, H=40, f=40.0, log_scale_mu=-1.6, spread=0.15)
-    return w.scene, w.views
-
-
-def _stacked_long():
-    """3000 large Gaussians over a 32x32 image: tile lists of thousands of
-    instances, longer than the per-tile depth sort holds in LDS."""
-    w = wl.tiny_scene(69, 3000, F=8, W=32, H=32, f=30.0, log_scale_mu=-1.6, spread=0.15)
-    return w.scene, w.views
-
-
-def _with_empty_view():
-    """A batch whose second view faces away from every Gaussian."""
-    w = wl.tiny_scene(66, 250, F=8, W=36, H=28, f=30.0)
-    away = wl.make_view(32, 24, 30.0, wl.se3_exp(np.array([0.0, 0.0, 0.0, 0.0, np.pi, 0.0])))
-    return w.scene, w.views + [away]
-
-
-def _many_views(seed=67, n=300, F=8, V=40):
-    """40 small views of mixed sizes and poses (some seeing little): more
-    views than lanes of a wavefront's projection queue drains at once, view
-    masks past bit 31 in the projection backward, and the record
-    reduction's cross-lane sum over 64 lanes per Gaussian."""
-    w = wl.tiny_scene(seed, n, F=F, W=24, H=20, f=25.0)
-    rng = np.random.default_rng(seed)
-    views = list(w.views)
-    for _ in range(V - 1):
-        xi = rng.normal(size=6) * np.array([0.05, 0.05, 0.05, 0.2, 0.2, 0.1])
-        views.append(wl.make_view(int(rng.integers(12, 33)), int(rng.integers(10, 25)),
-                                  float(rng.uniform(18.0, 35.0)), wl.se3_exp(xi)))
-    return w.scene, views
-
-
-CASES = {
-    "tiny3views-F16": lambda: _multi_view_tiny(),
-    "cfg1-64x64-2k": lambda: (wl.config1().scene, wl.config1().views),
-    "cfg2-160x120-20k-F16": lambda: (lambda w: (w.scene, w.views))(wl.config2(n=20_000, width=160, height=120)),
-    "tiny-F8": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(62, 200, F=8, W=40, H=40, f=35.0)),
-    "tiny-F32": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(63, 200, F=32, W=40, H=24, f=35.0)),
-    "tiny-F0": lambda: (lambda w: (w.scene, w.views))(wl.tiny_scene(64, 200, F=0, W=40, H=40, f=35.0)),
-    "stacked600-F16": _stacked,
-    "empty-view-F8": _with_empty_view,
-    "40views-F8": _many_views,
-    "64views-F8": lambda: _many_views(seed=68, V=64),  # the most views a batch may hold (mask bit 63)
-    "stacked3000-F8": _stacked_long,
-}
 
 
 def _project(name, tile):
@@ -162,13 +104,18 @@ def _render(name, tile, lds_batch=256, persistent=0, lds_batch_bwd=0):
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("tile,lds_batch,persistent", [(16, 256, 0), (8, 64, 0), (32, 128, 1)])
 def test_render_fwd_parity(name, tile, lds_batch, persistent):
-    """Against the oracle on the binary32 projected geometry: pixels within
-    2e-5 (alpha) / 2e-4 (T) of a threshold are counted, at most 2e-4 P."""
+    """Against the oracle on the binary32 projected geometry, every pixel:
+    RGB, opacity, T within 1e-5, depth and features within 1e-4 of the
+    channel max, the last contributor equal.  A pixel off tolerance is
+    excused only as a flipped threshold decision (a decision within 1e-5
+    (alpha) / 1e-4 (T) of its threshold, the deviation within the flip
+    bound), at most 1e-5 P of them: none at these sizes."""
     scene, views, r, g, cfg = _render(name, tile, lds_batch, persistent)
     ref = oracle.render(scene, views, oracle_cfg(cfg), geometry="fp32")
-    flagged, rep = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref,
+    excused, rep = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref,
                                   scales=chan_scales(scene, float(ref["proj"][..., 6].max())), cfg=cfg)
-    print(name, tile, "flagged", flagged, rep)
+    rep.pop("_excused_mask")
+    print(name, tile, "excused", excused, rep)
 
 
 # stacked3000: thousands of Gaussians at nearly equal depths, whose binary32
@@ -176,14 +123,16 @@ def test_render_fwd_parity(name, tile, lds_batch, persistent):
 # equally valid composite); the binary32-geometry parity above covers it
 @pytest.mark.parametrize("name", [c for c in CASES if c != "stacked3000-F8"])
 def test_render_fwd_parity_fp64_geometry(name):
-    """Against the all-FP64 oracle: same value tolerances, wider threshold
-    margins (the binary32 mean is ~3e-5 px off), at most 2% of pixels."""
+    """Against the all-FP64 oracle: the same tolerances on every pixel; the
+    threshold margins that can excuse a pixel are 1e-3 (the binary32 mean is
+    ~3e-5 px off the FP64 one), and at most 5e-3 P pixels may be excused."""
     scene, views, r, g, cfg = _render(name, 16)
     ref = oracle.render(scene, views, oracle_cfg(cfg), geometry="fp64")
-    flagged, rep = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref,
+    excused, rep = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref,
                                   geometry="fp64", scales=chan_scales(scene, float(ref["proj"][..., 6].max())),
                                   cfg=cfg)
-    print(name, "flagged", flagged, rep)
+    rep.pop("_excused_mask")
+    print(name, "excused", excused, rep)
 
 
 @pytest.mark.parametrize("name", ["cfg1-64x64-2k", "tiny3views-F16"])
@@ -446,9 +395,9 @@ def _single(scene, views):
     r.ensure_capacity(g)
     r.forward(g)
     ref = oracle.render(scene, views, oracle_cfg(cfg), geometry="fp32")
-    flagged, _ = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref,
+    excused, _ = compare_render(r.out.cpu().numpy(), r.T_final.cpu().numpy(), r.last.cpu().numpy(), ref,
                                 scales=chan_scales(scene, float(ref["proj"][..., 6].max())), cfg=cfg)
-    return flagged <= 2
+    return excused == 0
 
 
 def test_abi_rejects_bad_arguments_without_launching():
