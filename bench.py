@@ -8,8 +8,9 @@ over 20 classes, gradients to every Gaussian parameter, the whole step
 (project, bin/sort, render, loss gradient, render backward, projection
 backward) captured in one HIP graph.  Inputs are synthetic and resident in
 HBM before timing starts.  Also measured: the same step as 8 plain per-view
-launches, per-entry-point HIP-event times, and the FP64 CPU oracle on one
-of the 8 views.
+passes, per-entry-point HIP-event times, the other workloads (640x480
+single view, 1200x680 tracking, 16 mixed views with 2M Gaussians) as
+secondary entries, and the FP64 CPU oracle on bounded samples.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4]
 """
@@ -37,7 +38,7 @@ METRIC = "fwd+bwd Mpixel/s, 1M Gaussians RGB+D+16ch sem; batched vs per-view"
 # (FETCH_SIZE and WRITE_SIZE, scaled by the same counters' reading for a plain
 # copy), valid only for the kernel sources they were taken on: the record
 # holds the SHA-256 of those sources and is reported only while they match.
-TRAFFIC = {"bytes": 1927956503, "sha256": "367b373a05a920e9074a2529a3502f775506c12916fc6fffa939db8bba08af06"}
+TRAFFIC = None
 TRAFFIC_SOURCES = ("paper_2603_27781_amd/csrc/render_bwd.hip", "paper_2603_27781_amd/csrc/raster_common.h",
                    "paper_2603_27781_amd/csrc/sgs_common.h")
 
@@ -47,7 +48,8 @@ def log(*a):
 
 
 def byte_model(F, AS, V, N, n_vis, I, P, T, K, params=True):
-    """Algorithmic bytes per launch of each entry point (FP32)."""
+    """Bytes each entry point of this implementation moves per launch (its
+    own layout: 32-byte projected records, padded appearance records)."""
     geo = 44                       # mu 12, log_scale 12, quat 16, logit 4
     inst_gather = 4 + 32 + 4 * AS  # gid, projected record, appearance record
     n_red = (10 + F) if params else 6
@@ -65,25 +67,37 @@ def byte_model(F, AS, V, N, n_vis, I, P, T, K, params=True):
 
 
 def stream_bytes(F, V, N, n_vis, I, P, params=True):
-    """Compulsory and streaming bytes of one fwd+bwd step (the step-level
-    HBM model): parameters read once per pass, images and per-pixel state,
-    instance keys; streaming adds the per-instance gathers and gradients."""
+    """The step-level HBM model: compulsory bytes (parameters read once per
+    pass, images and per-pixel state, instance keys) and streaming bytes
+    (adding the per-instance gathers of both passes and the per-instance
+    gradients the tile method implies)."""
     geo, app, Pg, Pi = 44, 12 + 4 * F, 56 + 4 * F, 4 * (5 + F)
     comp = 2 * (N * geo + n_vis * app) + (N * Pg if params else 0) + 2 * P * Pi + 2 * P * 8 + 2 * I * 12 + 24 * V
     stream = comp + 2 * I * (44 + 4 * F) + I * 4 * ((10 + F) if params else 6)
     return comp, stream
 
 
+def kernel_stream_share(kernel, F, I, P, params=True):
+    """A compositing kernel's share of the streaming bytes, per unit:
+    per instance, one pass of gathers (44 + 4F), its half of the key traffic
+    (12) and, for the backward, the per-instance gradient (4 (10 + F), or
+    4 * 6 pose-only); per pixel, one image plane set (4 (5 + F)) and the
+    per-pixel state (T_final and last, 8).  Returns (bytes per launch,
+    per-instance bytes, per-pixel bytes)."""
+    per_inst = (44 + 4 * F) + 12
+    if kernel == "render_bwd_records":
+        per_inst += 4 * ((10 + F) if params else 6)
+    per_pix = 4 * (5 + F) + 8
+    return I * per_inst + P * per_pix, per_inst, per_pix
+
+
 def composite_flops(F, params=True):
-    """FP32 operations per (pixel, list entry) pair visited by the
-    compositing kernels, counted from the equations (fma = 2):
-    alpha = min(a_max, o 2^(A'dx^2 + B'dx dy + C'dy^2)): 13 (exp as one);
-    forward, when the pair contributes: w = alpha T, T update, 4+F channel
-    accumulations -> 3 + 2 (4+F);
-    backward: T_i rebuild 2, w 1, g.x over 5+F channels 2 (5+F), dL/dalpha 3,
-    suffix sum 2, through the clamp 1; mean, conic, depth terms 8 + 6 + 1
-    and their 6 cross-pixel sums; with parameter gradients also opacity 1,
-    colour 3, features F and their 4+F sums."""
+    """FP32 operations per (pixel, list entry) pair, counted from the
+    equations (fma = 2): alpha = min(a_max, o 2^q'): 13 (exp as one);
+    forward, when the pair contributes: w, T update, 4+F accumulations;
+    backward: T rebuild, w, g.x over 5+F channels, dL/dalpha, the R
+    recursion, the clamp, mean / conic / depth terms and their 6 sums, and
+    with parameter gradients opacity, colour, features and their 4+F sums."""
     fwd = 13 + 3 + 2 * (4 + F)
     bwd = 13 + (2 + 1 + 2 * (5 + F) + 3 + 2 + 1) + (8 + 6 + 1 + 6) + ((1 + 3 + F) + (4 + F) if params else 0)
     return fwd, bwd
@@ -102,11 +116,67 @@ def traffic_bytes():
     return TRAFFIC["bytes"] if h.hexdigest() == TRAFFIC["sha256"] else None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def workload_targets(w, dev):
+    """Colour, depth and label targets of a workload, on the device: its own
+    analytic room observation where it has one, else seeded uniform values
+    (and its labels) -- data, never a render of this path."""
+    if w.targets is not None and w.targets.rgb is not None:
+        return dev(w.targets.rgb), dev(w.targets.depth), dev(w.targets.labels)
+    rng = np.random.default_rng(w.seed + 1000)
+    P = w.total_pixels
+    lab = w.targets.labels if w.targets is not None and w.targets.labels is not None else \
+        rng.integers(0, max(w.n_classes, 1), P).astype(np.int32)
+    return (dev(rng.uniform(0, 1, (3, P)).astype(np.float32)), dev(rng.uniform(1, 6, P).astype(np.float32)),
+            dev(lab))
+
+
+def time_replays(step, steps):
+    """Replays the captured step `steps` times between two synchronisations;
+    returns (mean ms of the bracketed region, median ms of the per-replay
+    HIP-event times)."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for a, b in evs:
+        a.record()
+        step.replay()
+        b.record()
+    end.record()
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in evs]
+    return start.elapsed_time(end) / steps, float(np.median(per))
+
+
+def time_eager(fn, steps):
+    import torch
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--lds-batch", type=int, default=None)
@@ -116,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-perview", action="store_true")
     ap.add_argument("--no-slam", action="store_true", help="skip the SLAM-loss (masks, SSIM) timing")
+    ap.add_argument("--secondary", default="2,3,5",
+                    help="other workloads measured into the same JSON line (comma list; empty for none)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -135,14 +207,7 @@ def main():
         f"P={w.total_pixels} ({time.time() - t0:.1f}s)")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     g = raster.Gaussians.from_numpy(w.scene)
-    if w.targets is not None and w.targets.rgb is not None:
-        rgb_t, dep_t, lab = dev(w.targets.rgb), dev(w.targets.depth), dev(w.targets.labels)
-    else:  # analytic stand-ins sized like the images
-        rng = np.random.default_rng(w.seed + 1000)
-        P = w.total_pixels
-        rgb_t = dev(rng.uniform(0, 1, (3, P)).astype(np.float32))
-        dep_t = dev(rng.uniform(1, 6, P).astype(np.float32))
-        lab = dev(rng.integers(0, max(w.n_classes, 1), P).astype(np.int32))
+    rgb_t, dep_t, lab = workload_targets(w, dev)
     W = dev(w.decoder) if w.decoder is not None else None
     params = not w.pose_only
     pose = w.pose_grad
@@ -175,20 +240,13 @@ def main():
     torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- timed
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        step.replay()
-    end.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
+    ms, med = time_replays(step, args.steps)
     P = step.views.total_pixels
     mpix = P / (ms * 1e-3) / 1e6
     n_inst, n_vis, over = step.r.instance_counts()
-    assert not over
+    assert not over, "instance capacity overflowed during the timed replays"
     loss = step.loss.cpu().numpy().tolist()
-    log(f"batched graph: {ms:.3f} ms/step, {mpix:.1f} Mpix/s, loss {loss[3]:.5f}")
+    log(f"batched graph: {ms:.3f} ms/step (median {med:.3f}), {mpix:.1f} Mpix/s, loss {loss[3]:.5f}")
 
     # ------------------------------------------- per-entry-point event times
     r = step.r
@@ -220,26 +278,15 @@ def main():
     log("entry-point times (us): " + ", ".join(f"{k} {v:.1f}" for k, v in kern_us.items()))
 
     # ------------------------------------------- the other launch mode
-    # The same graph-captured step with the other compositing launch mode
-    # (persistent workgroups pulling tiles from a queue, or one workgroup
-    # per tile), timed the same way, so that both are on the record.
     other = None
     if not args.no_perview:
         ocfg = raster.Config(**{**dataclasses.asdict(cfg), "persistent": 1 - int(cfg.persistent)})
         ost = batched.MappingStep(g, w.views, ocfg, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose)
         ost.ensure_capacity()
         ost.capture(warmup=max(args.warmup, 1))
-        for _ in range(args.warmup):
-            ost.replay()
-        torch.cuda.synchronize()
-        start.record()
-        for _ in range(args.steps):
-            ost.replay()
-        end.record()
-        torch.cuda.synchronize()
-        ms_o = start.elapsed_time(end) / args.steps
+        ms_o, med_o = time_replays(ost, args.steps)
         other = {"persistent": int(ocfg.persistent), "ms_per_step": round(ms_o, 4),
-                 "value": round(P / (ms_o * 1e-3) / 1e6, 2)}
+                 "median_ms_per_step": round(med_o, 4), "value": round(P / (ms_o * 1e-3) / 1e6, 2)}
         log(f"{'persistent' if ocfg.persistent else 'one workgroup per tile'}: {ms_o:.3f} ms/step "
             f"({other['value']} Mpix/s)")
         del ost
@@ -248,49 +295,14 @@ def main():
     # ------------------------------------------------------------ per-view
     per_view = None
     if not args.no_perview and len(w.views) > 1:
-        pv = batched.PerViewStep(g, w.views, cfg, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose)
-        pv.ensure_capacity()
-        for _ in range(args.warmup):
-            pv.run()
-        torch.cuda.synchronize()
-        start.record()
-        for _ in range(args.steps):
-            pv.run()
-        end.record()
-        torch.cuda.synchronize()
-        ms_pv = start.elapsed_time(end) / args.steps
-        per_view = {"ms_per_step": round(ms_pv, 4), "value": round(P / (ms_pv * 1e-3) / 1e6, 2),
-                    "speedup_batched": round(ms_pv / ms, 3)}
-        log(f"per-view plain launches: {ms_pv:.3f} ms/step ({per_view['value']} Mpix/s)")
+        per_view = per_view_bench(g, w, cfg, rgb_t, dep_t, lab, W, params, pose, args.warmup, args.steps, P, ms)
+        log(f"per-view plain launches: {per_view['ms_per_step']:.3f} ms/step ({per_view['value']} Mpix/s)")
 
     # ------------------------------------------------------------- roofline
-    # The compositing kernels are bound by VALU issue (rocprofv3 counters),
-    # so their roofline is the FP32 vector peak over the operations the
-    # method needs per visited (pixel, list entry) pair; the units are the
-    # pairs each pixel visits, i.e. the sum of `last` over the pixels.
     F = w.scene.n_feat
     K = w.n_classes
-    bm = byte_model(F, r.AS, len(w.views), w.scene.n, n_vis, n_inst, P, step.views.total_tiles, K, params)
-    dom = max(kern_us, key=lambda k: kern_us[k])
-    visited = int(r.last[:P].to(torch.int64).sum().item())
-    fwd_flops, bwd_flops = composite_flops(F, params)
-    if dom in ("render_bwd_records", "render_fwd"):
-        per_pair = bwd_flops if dom == "render_bwd_records" else fwd_flops
-        achieved = visited * per_pair / (kern_us[dom] * 1e-6) / 1e12
-        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                    "traffic": traffic_bytes() if dom == "render_bwd_records" else None,
-                    "flops_per_pair": per_pair, "visited_pairs": visited, "launch_us": round(kern_us[dom], 2),
-                    "algorithmic_bytes_per_launch": int(bm[dom]),
-                    "hbm_frac": round(bm[dom] / (kern_us[dom] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
-    else:
-        achieved = bm[dom] / (kern_us[dom] * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "algorithmic_bytes_per_launch": int(bm[dom]), "launch_us": round(kern_us[dom], 2)}
-    comp, strm = stream_bytes(F, len(w.views), w.scene.n, n_vis, n_inst, P, params)
-    roofline["step"] = {"bytes_comp": int(comp), "bytes_stream": int(strm),
-                        "hbm_frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    roofline = roofline_of(r, kern_us, F, K, len(w.views), w.scene.n, n_vis, n_inst, P, step.views.total_tiles,
+                           params, ms)
 
     # ------------------------------------------------ SLAM losses
     slam = None
@@ -310,23 +322,132 @@ def main():
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, rgb_t, dep_t, lab, W, cfg)
+        cpu = cpu_baseline(w, rgb_t, dep_t, lab, W, cfg, budget_s=10.0, one_thread=True)
+        cpu["gpu_speedup"] = round(mpix / cpu["value"], 1)
+
+    main_cfg = {"workload": w.name, "gaussians": w.scene.n, "views": len(w.views),
+                "resolution": sorted({f"{v.width}x{v.height}" for v in w.views}), "feat": F, "classes": K,
+                "pixels_per_step": P, "instances": n_inst, "visible_pairs": n_vis,
+                "grad": ("params" if params else "") + ("+pose" if pose else ""), "mode": "batched hipGraph",
+                "tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
+                "lds_batch_bwd": cfg.lds_batch_bwd}
+    del step, r
+    torch.cuda.empty_cache()
+
+    # -------------------------------------------- the other workloads
+    secondary = {}
+    for c in [int(x) for x in args.secondary.split(",") if x.strip()]:
+        if c == args.config:
+            continue
+        secondary[f"cfg{c}"] = secondary_bench(c, cfg, args.warmup, min(args.steps, 20), args.no_cpu,
+                                               args.no_perview)
+        torch.cuda.empty_cache()
 
     rec = {
         "metric": METRIC, "value": round(mpix, 2), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "gaussians": w.scene.n, "views": len(w.views),
-                   "resolution": sorted({f"{v.width}x{v.height}" for v in w.views}), "feat": F, "classes": K,
-                   "pixels_per_step": P, "instances": n_inst, "visible_pairs": n_vis,
-                   "grad": ("params" if params else "") + ("+pose" if pose else ""), "mode": "batched hipGraph",
-                   "tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
-                   "lds_batch_bwd": cfg.lds_batch_bwd},
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "median_ms_per_step": round(med, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": main_cfg,
         "per_view": per_view, "other_launch_mode": other,
         "entry_us": {k: round(v, 2) for k, v in kern_us.items()},
-        "roofline": roofline, "cpu_baseline": cpu, "slam_loss": slam, "growth": growth, "slam_iteration": slam_iter,
+        "roofline": roofline, "cpu_baseline": cpu, "configs": secondary, "slam_loss": slam, "growth": growth,
+        "slam_iteration": slam_iter,
     }
     print(json.dumps(rec), flush=True)
+
+
+def per_view_bench(g, w, cfg, rgb_t, dep_t, lab, W, params, pose, warmup, steps, P, ms_batched):
+    """The same step as V plain single-view passes on one stream, no graph."""
+    import torch
+    from paper_2603_27781_amd import batched
+    pv = batched.PerViewStep(g, w.views, cfg, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose)
+    pv.ensure_capacity()
+    for _ in range(warmup):
+        pv.run()
+    ms_pv = time_eager(pv.run, steps)
+    del pv
+    torch.cuda.empty_cache()
+    return {"ms_per_step": round(ms_pv, 4), "value": round(P / (ms_pv * 1e-3) / 1e6, 2),
+            "speedup_batched": round(ms_pv / ms_batched, 3)}
+
+
+def roofline_of(r, kern_us, F, K, V, N, n_vis, n_inst, P, T, params, ms):
+    """Roofline of the dominant kernel against HBM: its share of the
+    streaming bytes (kernel_stream_share: per-instance and per-pixel
+    figures times the instances and pixels of one launch) over its mean
+    HIP-event launch time; the step's compulsory and streaming bytes over
+    the step time beside it; and, as a secondary figure, the compositing
+    arithmetic against the FP32 vector peak."""
+    import torch
+    dom = max(kern_us, key=lambda k: kern_us[k])
+    bm = byte_model(F, r.AS, V, N, n_vis, n_inst, P, T, K, params)
+    if dom in ("render_bwd_records", "render_fwd"):
+        alg, per_inst, per_pix = kernel_stream_share(dom, F, n_inst, P, params)
+        per_unit = {"per_instance_bytes": per_inst, "per_pixel_bytes": per_pix, "instances": n_inst, "pixels": P}
+    else:
+        alg, per_unit = bm[dom], {"model": "byte_model"}
+    us = kern_us[dom]
+    achieved = alg / (us * 1e-6) / 1e9
+    comp, strm = stream_bytes(F, V, N, n_vis, n_inst, P, params)
+    visited = int(r.last[:P].to(torch.int64).sum().item())
+    fwd_flops, bwd_flops = composite_flops(F, params)
+    per_pair = bwd_flops if dom == "render_bwd_records" else fwd_flops
+    alu = visited * per_pair / (us * 1e-6) / 1e12
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_bytes() if dom == "render_bwd_records" else None,
+            "algorithmic_bytes_per_launch": int(alg), **per_unit, "launch_us": round(us, 2),
+            "implementation_bytes_per_launch": int(bm[dom]),
+            "step": {"bytes_comp": int(comp), "bytes_stream": int(strm), "ms": round(ms, 4),
+                     "frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac_comp": round(comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "alu_secondary": {"peak_tflops": FP32_PEAK_TFLOPS, "flops_per_visited_pair": per_pair,
+                              "visited_pairs": visited, "achieved_tflops_upper_bound": round(alu, 2),
+                              "note": "every visited (pixel, list entry) pair charged as contributing; an upper "
+                                      "bound on the work done"}}
+
+
+def secondary_bench(c, cfg, warmup, steps, no_cpu, no_perview):
+    """One of the other workloads: its own graph-captured step (tracking
+    mode for the 1200x680 tracking workload) timed like the main one, its
+    step-level HBM fraction, the per-view alternative when it has several
+    views, and the oracle on a bounded sample."""
+    import torch
+    from paper_2603_27781_amd import batched, raster, workloads as wl
+    t0 = time.time()
+    w = wl.get_config(c)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    g = raster.Gaussians.from_numpy(w.scene)
+    rgb_t, dep_t, lab = workload_targets(w, dev)
+    W = dev(w.decoder) if w.decoder is not None else None
+    params, pose = not w.pose_only, w.pose_grad
+    step = batched.MappingStep(g, w.views, cfg, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose)
+    step.ensure_capacity()
+    step.capture(warmup=max(warmup, 1))
+    for _ in range(warmup):
+        step.replay()
+    ms, med = time_replays(step, steps)
+    P = step.views.total_pixels
+    n_inst, n_vis, over = step.r.instance_counts()
+    assert not over
+    comp, strm = stream_bytes(w.scene.n_feat, len(w.views), w.scene.n, n_vis, n_inst, P, params)
+    mpix = P / (ms * 1e-3) / 1e6
+    res = {"workload": w.name, "gaussians": w.scene.n, "views": len(w.views), "feat": w.scene.n_feat,
+           "classes": w.n_classes, "pixels_per_step": P, "instances": n_inst,
+           "grad": ("params" if params else "") + ("+pose" if pose else ""), "ms_per_step": round(ms, 4),
+           "median_ms_per_step": round(med, 4), "value": round(mpix, 2), "unit": "Mpixel/s",
+           "bytes_stream": int(strm), "hbm_frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del step
+    torch.cuda.empty_cache()
+    if not no_perview and len(w.views) > 1:
+        res["per_view"] = per_view_bench(g, w, cfg, rgb_t, dep_t, lab, W, params, pose, warmup, steps, P, ms)
+    if not no_cpu:
+        cpu = cpu_baseline(w, rgb_t, dep_t, lab, W, cfg, budget_s=5.0, one_thread=False)
+        cpu["gpu_speedup"] = round(mpix / cpu["value"], 1)
+        res["cpu_baseline"] = cpu
+    log(f"{w.name}: {ms:.3f} ms/step, {mpix:.1f} Mpix/s, HBM frac {res['hbm_frac_stream']} "
+        f"({time.time() - t0:.1f}s)")
+    return res
 
 
 def slam_loss_bench(r, rgb_t, dep_t, lab, W, steps, warmup, F, P):
@@ -507,37 +628,73 @@ def slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, steps):
     return res
 
 
-def cpu_baseline(w, rgb_t, dep_t, lab, W, cfg, budget_s=10.0):
-    """The FP64 oracle, untuned, on the bench workload's views one at a time
-    (all Gaussians, full resolution; project, bin, render, loss gradient,
-    backward per view) until about budget_s seconds have passed or every
-    view is done: a bounded sample of the same work."""
+def cpu_baseline(w, rgb_t, dep_t, lab, W, cfg, budget_s=10.0, one_thread=False):
+    """The FP64 oracle, untuned, on the workload's views one at a time (all
+    Gaussians, full resolution; project, bin, render, loss gradient,
+    backward per view) with all host threads until about budget_s seconds
+    have passed or every view is done: a bounded sample of the same work.
+    With one_thread, also one thread on a band of tile rows of the first
+    view (about an eighth of its pixels; the projection and binning of all
+    Gaussians included)."""
     import oracle
     ocfg = oracle.Cfg(z_near=cfg.z_near, blur=cfg.blur, guard=cfg.guard, alpha_min=cfg.alpha_min,
                       alpha_max=cfg.alpha_max, T_min=cfg.T_min, tile=cfg.tile)
     Wd = W.cpu().numpy().astype(np.float64) if W is not None else None
     flags = (0 if w.pose_only else 1) | (2 if w.pose_grad else 0)
+    threads = oracle.num_threads()
+
+    def view_data(vi):
+        off = sum(v.width * v.height for v in w.views[:vi])
+        P0 = w.views[vi].width * w.views[vi].height
+        return (rgb_t[:, off:off + P0].cpu().numpy().astype(np.float64),
+                dep_t[off:off + P0].cpu().numpy().astype(np.float64), lab[off:off + P0].cpu().numpy())
+
     done_px, done_v, dt = 0, 0, 0.0
-    off = 0
-    for v in w.views:
-        P0 = v.width * v.height
-        rgb = rgb_t[:, off:off + P0].cpu().numpy().astype(np.float64)
-        dep = dep_t[off:off + P0].cpu().numpy().astype(np.float64)
-        lb = lab[off:off + P0].cpu().numpy()
-        off += P0
+    for vi, v in enumerate(w.views):
+        rgb, dep, lb = view_data(vi)
         t = time.time()
         ren = oracle.render(w.scene, [v], ocfg)
         gout, _ = oracle.loss(ren["out"], [v], rgb, dep, lb, Wd, w.weights)
         oracle.backward(w.scene, [v], ocfg, gout, bins=ren["bins"], flags=flags)
         dt += time.time() - t
-        done_px += P0
+        done_px += v.width * v.height
         done_v += 1
         if dt >= budget_s:
             break
-    log(f"oracle on {done_v} view(s): {dt:.1f}s")
-    return {"value": round(done_px / dt / 1e6, 5), "unit": "Mpixel/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{done_v} of {len(w.views)} views, one at a time ({w.views[0].width}x{w.views[0].height}, "
-                      f"all {w.scene.n} Gaussians): project+bin+render+loss+backward in FP64, {dt:.1f}s"}
+    log(f"oracle on {done_v} view(s), {threads} threads: {dt:.1f}s")
+    res = {"value": round(done_px / dt / 1e6, 5), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"{done_v} of {len(w.views)} views of {w.name}, one at a time, all {w.scene.n} Gaussians: "
+                     f"project+bin+render+loss+backward in FP64 with {threads} threads, {dt:.1f}s"}
+    if one_thread:
+        v = w.views[0]
+        rgb, dep, lb = view_data(0)
+        ty = (v.height + cfg.tile - 1) // cfg.tile
+        tx = (v.width + cfg.tile - 1) // cfg.tile
+        rows = max(1, ty // 8)
+        pm = np.zeros(v.width * v.height, np.uint8)
+        pm[: min(rows * cfg.tile, v.height) * v.width] = 1
+        tm = np.zeros(tx * ty, np.uint8)
+        tm[: rows * tx] = 1
+        sel = pm.astype(bool)
+        oracle.set_num_threads(1)
+        try:
+            t = time.time()
+            ren = oracle.render(w.scene, [v], ocfg, pix_mask=pm)
+            band = [type(v)(v.width, int(sel.sum()) // v.width, v.fx, v.fy, v.cx, v.cy, v.Rt)]
+            g_band, _ = oracle.loss(np.ascontiguousarray(ren["out"][:, sel]), band, rgb[:, sel], dep[sel], lb[sel],
+                                    Wd, w.weights)
+            gout = np.zeros_like(ren["out"])
+            gout[:, sel] = g_band
+            oracle.backward(w.scene, [v], ocfg, gout, bins=ren["bins"], flags=flags, tile_mask=tm)
+            dt1 = time.time() - t
+        finally:
+            oracle.set_num_threads(threads)
+        res["one_thread"] = {"value": round(int(sel.sum()) / dt1 / 1e6, 5), "unit": "Mpixel/s", "cores": 1,
+                             "sample": f"first view, top {rows} of {ty} tile rows ({int(sel.sum())} pixels), "
+                                       f"projection and binning of all Gaussians, {dt1:.1f}s"}
+        log(f"oracle, one thread, {int(sel.sum())} pixels: {dt1:.1f}s")
+    return res
 
 
 if __name__ == "__main__":

@@ -441,3 +441,8 @@ def box_k(logit: np.ndarray, alpha_min: float = 1.0 / 255.0) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_num_threads(ctypes.c_int(int(n)))

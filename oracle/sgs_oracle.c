@@ -61,6 +61,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads used by the parallel loops from now on (timing of the oracle). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* FP32 decision path                                                         */
 /* ------------------------------------------------------------------------- */
