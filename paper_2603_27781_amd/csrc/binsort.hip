@@ -642,17 +642,21 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ins
 // Gaussian-index order; a stable sort of each tile's list by the binary32
 // bits of its pair's camera depth (positive, so the bits order like the
 // values) leaves them in (depth, index) order, the order the forward and
-// backward walk.  Lists are short (about 140 instances at the 8 x
-// 1200x680, 1M-Gaussian workload, the longest a few hundred), so one
-// wavefront ranks a list of up to kTsShort (k_tile_sort_short), many of
-// them in flight per CU; a second kernel takes the longer lists (each
-// workgroup finds those among kTslTiles tiles at a time) with 256 threads
-// and stable counting passes over 8-bit digits, in LDS up to kTsLong and
-// otherwise in global memory (the tile's slices of the sorted tile keys,
-// whose values are all the tile's own id and are written back, and of the
-// tile sort's ping-pong arrays, unused by then).
-constexpr int kTsShort = 512, kTsLong = 2048;
-constexpr int kTslTiles = 64;  // tiles a long-list workgroup scans per stride
+// backward walk.  The sort key of the instance at list position i is
+// (depth bits << 32 | i): distinct keys, so any correct sort is the stable
+// one.  A list is cut into runs of 64 keys, one key per lane; each run is
+// sorted across the lanes of a wavefront by a bitonic network; the rank of
+// a key among up to eight runs (a chunk of 512) is its lane plus, for every
+// other run, the number of that run's keys below it (a 6-step binary search
+// in LDS); chunks of a longer list merge the same way (9-step searches in
+// the other sorted chunks).  k_tile_sort_short gives each list of up to
+// kTsShort one wavefront; k_tile_sort_long gives each longer list a
+// workgroup, in LDS up to kTsLong, and beyond that (rare) stable counting
+// passes over 8-bit digits in global memory (the tile's slices of the
+// sorted tile keys, whose values are all the tile's own id and are written
+// back, and of the tile sort's ping-pong arrays, unused by then).
+constexpr int kTsShort = 512, kTsLong = 4096;
+constexpr int kTsChunk = 512;  // keys a wavefront sorts at once (8 runs of 64)
 
 template <int NT>
 struct SegSortLds {
@@ -729,69 +733,87 @@ __device__ void seg_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kou
     }
 }
 
-// OR of v over the block (every thread gets it).
-template <int NT>
-__device__ __forceinline__ uint32_t block_or(uint32_t v, uint32_t* s_tmp) {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) v |= (uint32_t)__shfl_xor((int)v, d, kWave);
-    if (lane == 0) s_tmp[wave] = v;
-    __syncthreads();
-    uint32_t r = 0;
-#pragma unroll
-    for (int w = 0; w < NT / kWave; ++w) r |= s_tmp[w];
-    __syncthreads();
-    return r;
-}
-
-// The list of tile t in LDS (L <= LMAX): depth keys gathered, a counting
-// pass per byte in which the keys differ, the emission indices written back
-// in order.
-template <int NT, int LMAX>
-__device__ void tile_sort_lds(int t, int2 rg, const gs_view* __restrict__ views, int n_views, int n,
-                              const float4* __restrict__ rec, const int32_t* __restrict__ inst_gid,
-                              int32_t* __restrict__ inst, uint32_t (&s_k)[2][LMAX], uint32_t (&s_v)[2][LMAX],
-                              SegSortLds<NT>& S) {
-    const int L = rg.y - rg.x;
-    const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
-    uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
-    uint32_t diff = 0;  // bits in which some key differs from the first
-    for (int i = threadIdx.x; i < L; i += NT) {
-        const uint32_t e = einst[i];
-        s_k[0][i] = __float_as_uint(rec[2 * (vbase + (size_t)inst_gid[e]) + 1].z);
-        s_v[0][i] = e;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < L; i += NT) diff |= s_k[0][i] ^ s_k[0][0];
-    const uint32_t any = block_or<NT>(diff, S.tmp);
-    // a byte every key shares is a pass that would leave the order as it is
-    int b = 0;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        if (((any >> (8 * p)) & 0xffu) == 0) continue;  // uniform across the block
-        seg_pass<NT>(s_k[b], s_v[b], s_k[b ^ 1], s_v[b ^ 1], L, 8 * p, S);
-        __syncthreads();
-        b ^= 1;
-    }
-    for (int i = threadIdx.x; i < L; i += NT) einst[i] = s_v[b][i];
-}
-
 constexpr int TSS_THREADS = kWave;  // short lists: one wavefront per tile
-constexpr int TSL_THREADS = 256;    // long lists
+constexpr int TSL_THREADS = 256;    // long lists: one workgroup per tile
+constexpr uint64_t kNoKey = ~0ull;  // padding, above every real key
 
-// Ranks of the (at most 64 R) instances of a short list: the sorted position
-// of each is the number of instances with a smaller (depth bits, list
-// position) pair -- the pairs are distinct, so this is the stable order --
-// counted by the wavefront against every key, read from LDS as a broadcast.
-template <int R>
-__device__ __forceinline__ void tile_ranks(const uint64_t* __restrict__ s_key, int L, const uint64_t (&k)[8],
-                                           uint32_t (&rank)[8]) {
-#pragma unroll 4
-    for (int j = 0; j < L; ++j) {
-        const uint64_t kj = s_key[j];
+// Lane-crossing exchange of a 64-bit key.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of one key per lane: afterwards lane l holds the l-th
+// smallest of the wavefront's 64 keys.  In each compare-exchange step the
+// lane with the bit clear keeps the smaller key inside an ascending block
+// (and the larger inside a descending one).
+__device__ __forceinline__ uint64_t wave_bitonic_u64(uint64_t x, int lane) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) rank[r] += kj < k[r] ? 1u : 0u;
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint64_t y = shfl_xor_u64(x, j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & size) == 0);
+            x = keep_min ? (y < x ? y : x) : (y > x ? y : x);
+        }
     }
+    return x;
+}
+
+// Number of keys of the sorted array a[0 .. 2^LOG) below `key`
+// (branch-free binary search; a is padded with kNoKey).
+template <int LOG>
+__device__ __forceinline__ int count_below(const uint64_t* a, uint64_t key) {
+    int p = 0;
+#pragma unroll
+    for (int s = 1 << (LOG - 1); s > 0; s >>= 1) p += a[p + s - 1] < key ? s : 0;
+    return p + (a[p] < key ? 1 : 0);
+}
+
+// One wavefront sorts the keys k[0 .. R) (run r holds list positions
+// r*64 .. r*64+63, kNoKey past the end): every run across the lanes, the
+// runs stored in s_run, then each key's rank among all R runs.  Returns, in
+// k[r], the sorted keys of run r and, in rank[r], their ranks in the chunk.
+template <int R>
+__device__ __forceinline__ void wave_sort_chunk(uint64_t (&k)[8], int (&rank)[8], uint64_t* s_run, int lane) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        k[r] = wave_bitonic_u64(k[r], lane);
+        s_run[r * kWave + lane] = k[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int rk = lane;
+#pragma unroll
+        for (int r2 = 0; r2 < R; ++r2)
+            if (r2 != r) rk += count_below<6>(s_run + r2 * kWave, k[r]);
+        rank[r] = rk;
+    }
+}
+
+// Runs R of a chunk of n keys, dispatched to a compile-time count.
+__device__ __forceinline__ void wave_sort_chunk_n(int n, uint64_t (&k)[8], int (&rank)[8], uint64_t* s_run,
+                                                  int lane) {
+    switch ((n + kWave - 1) / kWave) {
+        case 1: wave_sort_chunk<1>(k, rank, s_run, lane); break;
+        case 2: wave_sort_chunk<2>(k, rank, s_run, lane); break;
+        case 3: wave_sort_chunk<3>(k, rank, s_run, lane); break;
+        case 4: wave_sort_chunk<4>(k, rank, s_run, lane); break;
+        case 5: wave_sort_chunk<5>(k, rank, s_run, lane); break;
+        case 6: wave_sort_chunk<6>(k, rank, s_run, lane); break;
+        case 7: wave_sort_chunk<7>(k, rank, s_run, lane); break;
+        default: wave_sort_chunk<8>(k, rank, s_run, lane); break;
+    }
+}
+
+// Sort key of list position i of the tile: (depth bits << 32) | i.
+__device__ __forceinline__ uint64_t depth_key(const float4* __restrict__ rec, size_t vbase,
+                                              const int32_t* __restrict__ inst_gid, uint32_t e, int i) {
+    return ((uint64_t)__float_as_uint(rec[2 * (vbase + (size_t)inst_gid[e]) + 1].z) << 32) | (uint32_t)i;
 }
 
 // Tiles in the XCD-aware order of the compositing launches (tile_of_block):
@@ -800,54 +822,128 @@ __global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __r
                                                                   int run, const gs_view* __restrict__ views,
                                                                   int n_views, int n, const float4* __restrict__ rec,
                                                                   const int32_t* __restrict__ inst_gid,
-                                                                  int32_t* __restrict__ inst) {
-    static_assert(kTsShort == 8 * kWave, "eight keys per lane");
-    __shared__ uint64_t s_key[kTsShort];
-    uint32_t* s_out = reinterpret_cast<uint32_t*>(s_key);  // reused once the ranks are known
+                                                                  int32_t* __restrict__ inst,
+                                                                  uint32_t* __restrict__ long_list,
+                                                                  uint32_t* __restrict__ long_count) {
+    static_assert(kTsShort == kTsChunk && kTsChunk == 8 * kWave, "a short list is one chunk of eight runs");
+    __shared__ uint64_t s_run[kTsChunk];
+    __shared__ uint32_t s_e[kTsShort];
     const int t = tile_of_block(blockIdx.x, total_tiles, run);
     if (t < 0) return;
     const int2 rg = ranges[t];
     const int L = rg.y - rg.x;
-    if (L <= 1 || L > kTsShort) return;  // uniform across the wavefront
+    if (L > kTsShort) {  // uniform across the wavefront: left to k_tile_sort_long
+        if (threadIdx.x == 0) long_list[atomicAdd(long_count, 1u)] = (uint32_t)t;
+        return;
+    }
+    if (L <= 1) return;
     const int lane = threadIdx.x;
     const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
     uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
     uint64_t k[8];
-    uint32_t e[8], rank[8];
+    int rank[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int i = r * kWave + lane;
-        k[r] = ~0ull;
-        e[r] = 0u;
-        rank[r] = 0u;
+        k[r] = kNoKey;
         if (i < L) {
-            e[r] = einst[i];
-            k[r] = ((uint64_t)__float_as_uint(rec[2 * (vbase + (size_t)inst_gid[e[r]]) + 1].z) << 32) | (uint32_t)i;
-            s_key[i] = k[r];
+            const uint32_t e = einst[i];
+            s_e[i] = e;
+            k[r] = depth_key(rec, vbase, inst_gid, e, i);
         }
     }
+    wave_sort_chunk_n(L, k, rank, s_run, lane);
+    // s_e was written by other lanes of this (only) wavefront
     __syncthreads();
-    switch ((L + kWave - 1) / kWave) {
-        case 1: tile_ranks<1>(s_key, L, k, rank); break;
-        case 2: tile_ranks<2>(s_key, L, k, rank); break;
-        case 3: tile_ranks<3>(s_key, L, k, rank); break;
-        case 4: tile_ranks<4>(s_key, L, k, rank); break;
-        case 5: tile_ranks<5>(s_key, L, k, rank); break;
-        case 6: tile_ranks<6>(s_key, L, k, rank); break;
-        case 7: tile_ranks<7>(s_key, L, k, rank); break;
-        default: tile_ranks<8>(s_key, L, k, rank); break;
-    }
-    __syncthreads();  // every lane is done reading the keys
 #pragma unroll
     for (int r = 0; r < 8; ++r)
-        if (r * kWave + lane < L) s_out[rank[r]] = e[r];
-    __syncthreads();
-    for (int i = lane; i < L; i += kWave) einst[i] = s_out[i];
+        if (r * kWave < L && k[r] != kNoKey) einst[rank[r]] = s_e[(uint32_t)k[r]];
 }
 
-// The lists longer than kTsShort; each workgroup walks the tiles with a
-// stride of the grid (few tiles have such lists).
-__global__ void __launch_bounds__(TSL_THREADS) k_tile_sort_long(const int2* __restrict__ ranges, int total_tiles,
+// One long list (tile t, more than kTsShort instances), by the whole block.
+__device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_view* __restrict__ views,
+                               int n_views, int n, const float4* __restrict__ rec,
+                               const int32_t* __restrict__ inst_gid, uint32_t* __restrict__ tile_keys,
+                               int32_t* __restrict__ inst, uint32_t* __restrict__ gk, uint32_t* __restrict__ gv,
+                               uint64_t (&s_sorted)[kTsLong], uint64_t (&s_run)[TSL_THREADS / kWave][kTsChunk],
+                               uint32_t (&s_e)[kTsLong], SegSortLds<TSL_THREADS>& S) {
+    constexpr int NW = TSL_THREADS / kWave;
+    const int2 rg = ranges[t];
+    const int L = rg.y - rg.x;
+    const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
+    uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (L <= kTsLong) {
+        const int nchunk = (L + kTsChunk - 1) / kTsChunk;
+        for (int c = wave; c < nchunk; c += NW) {
+            const int c0 = c * kTsChunk;
+            const int nc = min(kTsChunk, L - c0);
+            uint64_t k[8];
+            int rank[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int i = c0 + r * kWave + lane;
+                k[r] = kNoKey;
+                if (i < L) {
+                    const uint32_t e = einst[i];
+                    s_e[i] = e;
+                    k[r] = depth_key(rec, vbase, inst_gid, e, i);
+                }
+            }
+            wave_sort_chunk_n(nc, k, rank, s_run[wave], lane);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (r * kWave + lane < nc) s_sorted[c0 + rank[r]] = k[r];
+            // pad the last chunk to a full 512 for the searches
+            for (int i = nc + lane; i < kTsChunk; i += kWave) s_sorted[c0 + i] = kNoKey;
+            // s_run is rewritten by this wavefront's next chunk
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < L; j += TSL_THREADS) {
+            const uint64_t key = s_sorted[j];
+            const int c = j / kTsChunk;
+            int pos = j - c * kTsChunk;
+            for (int c2 = 0; c2 < nchunk; ++c2)
+                if (c2 != c) pos += count_below<9>(s_sorted + c2 * kTsChunk, key);
+            einst[pos] = s_e[(uint32_t)key];
+        }
+        return;
+    }
+    // in global memory: (depth bits, emission index) start in (tile_keys,
+    // inst) and ping-pong with the scratch slices; after four passes they
+    // are back
+    uint32_t* bk = tile_keys + rg.x;
+    uint32_t* ak = gk + rg.x;
+    uint32_t* av = gv + rg.x;
+    for (int i = threadIdx.x; i < L; i += TSL_THREADS)
+        bk[i] = __float_as_uint(rec[2 * (vbase + (size_t)inst_gid[einst[i]]) + 1].z);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        // the previous pass's global writes are complete and visible to the
+        // whole block (and not stale in this CU's cache) before they are read
+        __threadfence();
+        __syncthreads();
+        if (p & 1) seg_pass<TSL_THREADS>(ak, av, bk, einst, L, 8 * p, S);
+        else seg_pass<TSL_THREADS>(bk, einst, ak, av, L, 8 * p, S);
+    }
+    __threadfence();
+    __syncthreads();
+    for (int i = threadIdx.x; i < L; i += TSL_THREADS) bk[i] = (uint32_t)t;
+}
+
+// The lists longer than kTsShort, which k_tile_sort_short listed in
+// long_list: a fixed grid of workgroups walks the list, one tile each at a
+// time.  Up to kTsLong: each wavefront sorts chunks of 512 (wave_sort_chunk)
+// into s_sorted (the last chunk padded with kNoKey), then every key's place
+// is its rank in its chunk plus, for each other chunk, the number of that
+// chunk's keys below it.  Beyond kTsLong: stable counting passes over the
+// four bytes of the depth bits in global memory.
+__global__ void __launch_bounds__(TSL_THREADS) k_tile_sort_long(const int2* __restrict__ ranges,
+                                                                 const uint32_t* __restrict__ long_list,
+                                                                 const uint32_t* __restrict__ long_count,
                                                                  const gs_view* __restrict__ views, int n_views,
                                                                  int n, const float4* __restrict__ rec,
                                                                  const int32_t* __restrict__ inst_gid,
@@ -855,65 +951,26 @@ __global__ void __launch_bounds__(TSL_THREADS) k_tile_sort_long(const int2* __re
                                                                  int32_t* __restrict__ inst,
                                                                  uint32_t* __restrict__ gk,
                                                                  uint32_t* __restrict__ gv) {
-    __shared__ uint32_t s_k[2][kTsLong];
-    __shared__ uint32_t s_v[2][kTsLong];
+    __shared__ uint64_t s_sorted[kTsLong];
+    __shared__ uint64_t s_run[TSL_THREADS / kWave][kTsChunk];
+    __shared__ uint32_t s_e[kTsLong];
     __shared__ SegSortLds<TSL_THREADS> S;
-    __shared__ int s_long[kTslTiles];
-    __shared__ int s_nlong;
-    for (int base = blockIdx.x * kTslTiles; base < total_tiles; base += gridDim.x * kTslTiles) {
-        // the tiles of this stride with long lists, found together
-        const int tt = base + (int)threadIdx.x;
-        const bool lng = (int)threadIdx.x < kTslTiles && tt < total_tiles && ranges[tt].y - ranges[tt].x > kTsShort;
-        if (threadIdx.x == 0) s_nlong = 0;
-        __syncthreads();
-        if (lng) s_long[atomicAdd(&s_nlong, 1)] = tt;
-        __syncthreads();
-        const int nlong = s_nlong;
-        for (int j = 0; j < nlong; ++j) {
-            const int t = s_long[j];
-            const int2 rg = ranges[t];
-            const int L = rg.y - rg.x;
-            if (L <= kTsLong) {
-                tile_sort_lds<TSL_THREADS, kTsLong>(t, rg, views, n_views, n, rec, inst_gid, inst, s_k, s_v, S);
-                __syncthreads();
-                continue;
-            }
-            // in global memory: (depth bits, emission index) start in
-            // (tile_keys, inst) and ping-pong with the scratch slices; after
-            // four passes they are back
-            const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
-            uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
-            uint32_t* bk = tile_keys + rg.x;
-            uint32_t* ak = gk + rg.x;
-            uint32_t* av = gv + rg.x;
-            for (int i = threadIdx.x; i < L; i += TSL_THREADS)
-                bk[i] = __float_as_uint(rec[2 * (vbase + (size_t)inst_gid[einst[i]]) + 1].z);
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                // the previous pass's global writes are complete and visible
-                // to the whole block (and not stale in this CU's cache)
-                // before they are read
-                __threadfence();
-                __syncthreads();
-                if (p & 1) seg_pass<TSL_THREADS>(ak, av, bk, einst, L, 8 * p, S);
-                else seg_pass<TSL_THREADS>(bk, einst, ak, av, L, 8 * p, S);
-            }
-            __threadfence();
-            __syncthreads();
-            for (int i = threadIdx.x; i < L; i += TSL_THREADS) bk[i] = (uint32_t)t;
-            __syncthreads();
-        }
-        __syncthreads();  // s_long and s_nlong are reused by the next stride
+    const uint32_t count = *long_count;
+    for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        sort_long_list((int)long_list[idx], ranges, views, n_views, n, rec, inst_gid, tile_keys, inst, gk, gv,
+                       s_sorted, s_run, s_e, S);
+        __syncthreads();  // the LDS is reused by the next tile
     }
 }
 
+
 struct WsLayout {
-    size_t vis_k0, vis_v0, inst_k2, inst_v2, hist, sums, status, tickets, cnt, total;
+    size_t vis_k0, vis_v0, inst_k2, inst_v2, hist, sums, status, tickets, cnt, long_list, total;
     int64_t spine_tiles, n_status;
 };
 
 constexpr int kMaxPasses = 4;            // radix passes per sort (32-bit keys)
-constexpr int kTickets = kMaxPasses;     // one per radix pass of the tile sort
+constexpr int kTickets = kMaxPasses + 1; // one per radix pass of the tile sort, then the long-list count
 
 WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -939,6 +996,8 @@ WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     L.status = o; o += al(8 * (size_t)L.n_status);
     L.tickets = o; o += al(4 * (size_t)kTickets);
     L.cnt = o; o += al(8 * 4);
+    // tiles with more than kTsShort instances: at most capacity / (kTsShort + 1)
+    L.long_list = o; o += al(4 * (size_t)(cap / (kTsShort + 1) + 1));
     L.total = o;
     return L;
 }
@@ -1008,12 +1067,14 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
             const int2* rg = reinterpret_cast<const int2*>(ranges);
             const float4* rc = reinterpret_cast<const float4*>(rec);
             const int run = tile_run(tile);
+            uint32_t* long_list = reinterpret_cast<uint32_t*>(w + L.long_list);
+            uint32_t* long_count = tickets + kMaxPasses;
             hipLaunchKernelGGL(k_tile_sort_short, dim3(tile_grid(total_tiles, run)), dim3(TSS_THREADS), 0, s, rg,
-                               total_tiles, run, views_dev, n_views, n, rc, inst_gid, inst);
-            const int lgw = (total_tiles + kTslTiles - 1) / kTslTiles;
-            const unsigned lg = (unsigned)(lgw < 1024 ? lgw : 1024);
-            hipLaunchKernelGGL(k_tile_sort_long, dim3(lg), dim3(TSL_THREADS), 0, s, rg, total_tiles, views_dev,
-                               n_views, n, rc, inst_gid, tile_keys, inst, ik2, iv2);
+                               total_tiles, run, views_dev, n_views, n, rc, inst_gid, inst, long_list, long_count);
+            const int64_t max_long = capacity / (kTsShort + 1) + 1;
+            const unsigned lg = (unsigned)(max_long < 1024 ? max_long : 1024);
+            hipLaunchKernelGGL(k_tile_sort_long, dim3(lg), dim3(TSL_THREADS), 0, s, rg, long_list, long_count,
+                               views_dev, n_views, n, rc, inst_gid, tile_keys, inst, ik2, iv2);
         }
     }
     return hipGetLastError();

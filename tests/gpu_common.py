@@ -138,6 +138,13 @@ def _stacked_long():
     return w.scene, w.views
 
 
+def _stacked_longest():
+    """5000 large Gaussians over a 32x32 image: tile lists longer than the
+    per-tile depth sort merges in LDS (global-memory counting passes)."""
+    w = wl.tiny_scene(70, 5000, F=8, W=32, H=32, f=30.0, log_scale_mu=-1.6, spread=0.12)
+    return w.scene, w.views
+
+
 def _with_empty_view():
     """A batch whose second view faces away from every Gaussian."""
     w = wl.tiny_scene(66, 250, F=8, W=36, H=28, f=30.0)
@@ -172,6 +179,7 @@ CASES = {
     "40views-F8": _many_views,
     "64views-F8": lambda: _many_views(seed=68, V=64),  # the most views a batch may hold (mask bit 63)
     "stacked3000-F8": _stacked_long,
+    "stacked5000-F8": _stacked_longest,
 }
 
 
