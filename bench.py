@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--no-slam", action="store_true", help="skip the SLAM-loss (masks, SSIM) timing")
     ap.add_argument("--secondary", default="2,3,5",
                     help="other workloads measured into the same JSON line (comma list; empty for none)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="secondary workloads in the main launch configuration instead of an autotuned one")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -339,8 +341,8 @@ def main():
     for c in [int(x) for x in args.secondary.split(",") if x.strip()]:
         if c == args.config:
             continue
-        secondary[f"cfg{c}"] = secondary_bench(c, cfg, args.warmup, min(args.steps, 20), args.no_cpu,
-                                               args.no_perview)
+        secondary[f"cfg{c}"] = secondary_bench(c, args.warmup, min(args.steps, 20), args.no_cpu,
+                                               args.no_perview, not args.no_tune)
         torch.cuda.empty_cache()
 
     rec = {
@@ -407,13 +409,14 @@ def roofline_of(r, kern_us, F, K, V, N, n_vis, n_inst, P, T, params, ms):
                                       "bound on the work done"}}
 
 
-def secondary_bench(c, cfg, warmup, steps, no_cpu, no_perview):
+def secondary_bench(c, warmup, steps, no_cpu, no_perview, tune=True):
     """One of the other workloads: its own graph-captured step (tracking
-    mode for the 1200x680 tracking workload) timed like the main one, its
+    mode for the 1200x680 tracking workload) in the launch configuration the
+    autotuner picks for it (or the main one), timed like the main one, its
     step-level HBM fraction, the per-view alternative when it has several
     views, and the oracle on a bounded sample."""
     import torch
-    from paper_2603_27781_amd import batched, raster, workloads as wl
+    from paper_2603_27781_amd import autotune, batched, raster, workloads as wl
     t0 = time.time()
     w = wl.get_config(c)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -421,6 +424,10 @@ def secondary_bench(c, cfg, warmup, steps, no_cpu, no_perview):
     rgb_t, dep_t, lab = workload_targets(w, dev)
     W = dev(w.decoder) if w.decoder is not None else None
     params, pose = not w.pose_only, w.pose_grad
+    if tune:
+        cfg = autotune.tune(g, w.views, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose, cache=None)
+    else:
+        cfg = raster.Config(**batched.BENCH_CONFIG)
     step = batched.MappingStep(g, w.views, cfg, rgb_t, dep_t, lab, W, w.weights, params=params, pose=pose)
     step.ensure_capacity()
     step.capture(warmup=max(warmup, 1))
@@ -436,7 +443,9 @@ def secondary_bench(c, cfg, warmup, steps, no_cpu, no_perview):
            "classes": w.n_classes, "pixels_per_step": P, "instances": n_inst,
            "grad": ("params" if params else "") + ("+pose" if pose else ""), "ms_per_step": round(ms, 4),
            "median_ms_per_step": round(med, 4), "value": round(mpix, 2), "unit": "Mpixel/s",
-           "bytes_stream": int(strm), "hbm_frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+           "bytes_stream": int(strm), "hbm_frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "launch": {"tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
+                      "lds_batch_bwd": cfg.lds_batch_bwd, "autotuned": bool(tune)}}
     del step
     torch.cuda.empty_cache()
     if not no_perview and len(w.views) > 1:

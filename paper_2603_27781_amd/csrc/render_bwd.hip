@@ -502,10 +502,12 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 }
 
 // Occupancy: the kernel is latency-bound (LDS reads and cross-lane steps on
-// every Gaussian), so with up to 16 feature channels the register budget is
-// capped at five wavefronts per SIMD (the values fit without spills).
+// every Gaussian), so the register budget is capped at five wavefronts per
+// SIMD with up to 16 feature channels and at four with 32 (with 64
+// Gaussians per LDS batch, which keeps the LDS from capping it at three):
+// the values fit without spills.
 template <int TS, int F, int B, bool PARAMS>
-__global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <= 16 ? 5 : 1, 8))) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
+__global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <= 16 ? 5 : 4, 8))) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
                                                        int n, const int32_t* __restrict__ inst,
                                                        const int32_t* __restrict__ inst_gid,
                                                        const int2* __restrict__ ranges,
