@@ -242,11 +242,12 @@ def main():
     torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- timed
+    step.r.clear_trouble()
     ms, med = time_replays(step, args.steps)
     P = step.views.total_pixels
     mpix = P / (ms * 1e-3) / 1e6
-    n_inst, n_vis, over = step.r.instance_counts()
-    assert not over, "instance capacity overflowed during the timed replays"
+    n_inst, n_vis, over, gave_up = step.r.instance_counts()
+    assert not step.r.trouble(), "a replay overflowed the instance capacity or gave up a scan wait"
     loss = step.loss.cpu().numpy().tolist()
     log(f"batched graph: {ms:.3f} ms/step (median {med:.3f}), {mpix:.1f} Mpix/s, loss {loss[3]:.5f}")
 
@@ -433,10 +434,11 @@ def secondary_bench(c, warmup, steps, no_cpu, no_perview, tune=True):
     step.capture(warmup=max(warmup, 1))
     for _ in range(warmup):
         step.replay()
+    step.r.clear_trouble()
     ms, med = time_replays(step, steps)
     P = step.views.total_pixels
-    n_inst, n_vis, over = step.r.instance_counts()
-    assert not over
+    n_inst, n_vis, over, gave_up = step.r.instance_counts()
+    assert not step.r.trouble(), "a replay overflowed the instance capacity or gave up a scan wait"
     comp, strm = stream_bytes(w.scene.n_feat, len(w.views), w.scene.n, n_vis, n_inst, P, params)
     mpix = P / (ms * 1e-3) / 1e6
     res = {"workload": w.name, "gaussians": w.scene.n, "views": len(w.views), "feat": w.scene.n_feat,
@@ -625,7 +627,7 @@ def slam_iteration_bench(g, w, rgb_t, dep_t, lab, W, cfg, steps):
     b.record()
     torch.cuda.synchronize()
     ms_m = a.elapsed_time(b) / steps
-    _, _, over = r.instance_counts()
+    over = r.trouble()
     res = {"view": f"{v0.width}x{v0.height}", "gaussians": g.n, "tracking_ms_per_iter": round(ms_t, 3),
            "tracking_graph_ms_per_iter": round(ms_tg, 3), "mapping_ms_per_iter": round(ms_m, 3),
            "capacity_overflow": bool(over),

@@ -172,11 +172,22 @@ int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views
  *                           (so inst_gid[inst[k]] is the k-th sorted Gaussian)
  *   pair_first[V][n]        first emission index of each visible pair
  *   tile_ranges[T_total][2] [start, end) of every global tile in the sorted list
- *   counts[4] (int64)       [0] instances, [1] visible pairs,
+ *   counts[5] (int64)       [0] instances, [1] visible pairs,
  *                           [2] 1 if the instance count exceeded capacity
  *                           (the lists are then truncated: read counts after
  *                           the stream completes and call again with
- *                           capacity >= counts[0]), [3] reserved.
+ *                           capacity >= counts[0]),
+ *                           [3] 1 if a wait of the device sort's single-pass
+ *                           scan gave up (a block's predecessor never
+ *                           published within the spin limit): the later
+ *                           binning kernels then stand down, every tile list
+ *                           is left empty and the call's results must be
+ *                           discarded (call again),
+ *                           [4] sticky: set whenever [2] or [3] is set, by
+ *                           every call, and cleared only by the caller (write
+ *                           0 to it), so that one check after many calls (a
+ *                           tracking run, a batch of mapping iterations)
+ *                           shows whether any of them was truncated.
  * ws / ws_bytes: workspace of at least gs_bin_sort_workspace(...) bytes,
  * 256-byte aligned.  Instance counts must stay below 2^31.
  * --------------------------------------------------------------------------- */

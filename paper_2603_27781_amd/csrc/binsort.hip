@@ -25,6 +25,8 @@
 // totals first, and each tile then sums the totals before it itself; the
 // compaction counts runs, scans the run counts in one block and ranks
 // inside a run with ballots.
+#include <cstdlib>
+
 #include "sgs_common.h"
 
 namespace sgs {
@@ -128,17 +130,33 @@ __device__ __forceinline__ uint64_t lb_read(const uint64_t* st) {
     return __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Where a look-back that gave up is recorded: the call's flag and the
+// caller's sticky flag (the low words of counts[3] and counts[4]), and how
+// many reads a wait may take.
+struct LbGiveUp {
+    uint32_t* flag;
+    uint32_t* sticky;
+    int spin_limit;
+};
+
 // Exclusive prefix of tile `tile` (> 0) from the status words of the tiles
 // before it; called by one whole wavefront, which reads 64 of them at a
 // time, newest first.  Positions before tile 0 count as an inclusive 0.
-__device__ uint32_t lb_lookback(const uint64_t* status, int tile) {
+// A predecessor that has not published after gu.spin_limit further reads is
+// counted as 0 -- a short prefix -- and the give-up is recorded, so that the
+// binning's later kernels stand down and the caller sees it.
+__device__ uint32_t lb_lookback(const uint64_t* status, int tile, LbGiveUp gu) {
     const int lane = threadIdx.x & (kWave - 1);
     uint32_t prefix = 0;
     for (int j = tile - 1;; j -= kWave) {
         const int k = j - lane;
         uint64_t s = k >= 0 ? lb_read(status + k) : LB_INC;
-        for (int spin = 0; __any((s >> 62) == 0) && spin < LB_SPIN_MAX; ++spin)
+        for (int spin = 0; __any((s >> 62) == 0) && spin < gu.spin_limit; ++spin)
             if ((s >> 62) == 0) s = lb_read(status + k);
+        if (__any((s >> 62) == 0) && lane == 0) {
+            atomicOr(gu.flag, 1u);
+            atomicOr(gu.sticky, 1u);
+        }
         const uint64_t inc = __ballot((s >> 62) == 2);
         uint32_t v = (uint32_t)s;
         if (inc != 0 && lane > __builtin_ctzll(inc)) v = 0;  // stop at the nearest inclusive prefix
@@ -153,7 +171,7 @@ __device__ uint32_t lb_lookback(const uint64_t* status, int tile) {
 // the exclusive prefix of this thread's items (excl added to the tile's
 // prefix) and the tile's total; all threads of the block call it.
 __device__ __forceinline__ uint32_t lb_block(uint32_t acc, int tile, uint64_t* status, uint32_t* s_tmp,
-                                             uint32_t* s_prefix, uint32_t* tile_total) {
+                                             uint32_t* s_prefix, uint32_t* tile_total, LbGiveUp gu) {
     uint32_t tot;
     const uint32_t excl = block_exclusive<LB_THREADS>(acc, s_tmp, &tot);
     if (threadIdx.x < kWave) {
@@ -163,7 +181,7 @@ __device__ __forceinline__ uint32_t lb_block(uint32_t acc, int tile, uint64_t* s
             if (lane == 0) lb_publish(status, LB_INC, tot);
         } else {
             if (lane == 0) lb_publish(status + tile, LB_AGG, tot);
-            prefix = lb_lookback(status, tile);
+            prefix = lb_lookback(status, tile, gu);
             if (lane == 0) lb_publish(status + tile, LB_INC, prefix + tot);
         }
         if (lane == 0) *s_prefix = prefix;
@@ -181,7 +199,7 @@ __device__ __forceinline__ int lb_ticket(uint32_t* ticket, int* s_tile) {
 
 // Instance bookkeeping written by the last tile of the instance-offset scan.
 struct CountsOut {
-    int64_t* counts;         // (instances, visible pairs, overflow flag, 0)
+    int64_t* counts;         // (instances, visible pairs, overflow, look-back gave up, sticky)
     int64_t* n_clamped;      // min(instances, capacity)
     const int64_t* n_vis;
     int64_t capacity;
@@ -240,6 +258,7 @@ __global__ void __launch_bounds__(LB_THREADS) k_tile_scan(Load ld, const int64_t
             co.counts[1] = *co.n_vis;
             co.counts[2] = I > co.capacity ? 1 : 0;
             co.counts[3] = 0;
+            if (I > co.capacity) co.counts[4] |= 1;  // sticky: only the caller clears it
             *co.n_clamped = I < co.capacity ? I : co.capacity;
         }
     }
@@ -251,7 +270,7 @@ __global__ void __launch_bounds__(LB_THREADS) k_tile_scan(Load ld, const int64_t
 template <class Load>
 __global__ void __launch_bounds__(LB_THREADS) k_scan_lb(Load ld, const int64_t* count_dev, int64_t n_max,
                                                         uint64_t* status, uint32_t* ticket, uint32_t* out,
-                                                        int64_t* total) {
+                                                        int64_t* total, LbGiveUp gu) {
     __shared__ uint32_t s_tmp[LB_THREADS / kWave];
     __shared__ uint32_t s_prefix;
     __shared__ int s_tile;
@@ -268,7 +287,7 @@ __global__ void __launch_bounds__(LB_THREADS) k_scan_lb(Load ld, const int64_t* 
         acc += v[k];
     }
     uint32_t tot;
-    uint32_t run = lb_block(acc, tile, status, s_tmp, &s_prefix, &tot);
+    uint32_t run = lb_block(acc, tile, status, s_tmp, &s_prefix, &tot, gu);
 #pragma unroll
     for (int k = 0; k < LB_ITEMS; ++k) {
         if (base + k < count) out[base + k] = run;
@@ -280,10 +299,10 @@ __global__ void __launch_bounds__(LB_THREADS) k_scan_lb(Load ld, const int64_t* 
 // Single-pass scan for short inputs (few tiles: the look-back stays short).
 template <class Load>
 hipError_t exclusive_scan(Load ld, const int64_t* count_dev, int64_t n_max, uint64_t* status, uint32_t* ticket,
-                          uint32_t* out, int64_t* total, hipStream_t s) {
+                          uint32_t* out, int64_t* total, LbGiveUp gu, hipStream_t s) {
     const int64_t nt = lb_tiles(n_max);
     hipLaunchKernelGGL(k_scan_lb<Load>, dim3((unsigned)(nt > 0 ? nt : 1)), dim3(LB_THREADS), 0, s, ld, count_dev,
-                       n_max, status, ticket, out, total);
+                       n_max, status, ticket, out, total, gu);
     return hipGetLastError();
 }
 
@@ -366,7 +385,8 @@ template <class Src>
 __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int64_t* count_dev, int64_t n_max,
                                                               int shift, const uint32_t* __restrict__ offs,
                                                               int nblk, uint32_t* __restrict__ keys_out,
-                                                              uint32_t* __restrict__ vals_out) {
+                                                              uint32_t* __restrict__ vals_out,
+                                                              const uint32_t* __restrict__ gave_up) {
     constexpr int SLOTS = RS_ITEMS * RS_WAVES;  // (row, wavefront) slots of a tile
     __shared__ uint32_t s_base[256];             // next global position per digit
     __shared__ uint32_t s_lstart[256];           // first tile position per digit
@@ -378,6 +398,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int
     int64_t lo, hi;
     rs_chunk(eff_count(count_dev, n_max), nblk, lo, hi);
     if (lo >= hi) return;  // uniform across the block
+    if (*gave_up) return;  // the digit offsets are not to be trusted (uniform)
     s_base[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int64_t t0 = lo; t0 < hi; t0 += RS_TILE) {
@@ -426,8 +447,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int
                 const uint32_t kk = s_key[p], vv = s_val[p];
                 const uint32_t d = (kk >> shift) & 0xffu;
                 const uint32_t g = s_base[d] + (p - s_lstart[d]);
-                keys_out[g] = kk;
-                vals_out[g] = vv;
+                if (g < n_max) {
+                    keys_out[g] = kk;
+                    vals_out[g] = vv;
+                }
             }
         }
         __syncthreads();
@@ -440,15 +463,15 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(Src src, const int
 // keys that took part), then the stable scatter.
 template <class Src>
 hipError_t radix_pass(Src src, const int64_t* count_dev, int64_t n_max, int shift, uint32_t* hist,
-                      uint64_t* status, uint32_t* ticket, int64_t* total, uint32_t* ko, uint32_t* vo,
+                      uint64_t* status, uint32_t* ticket, int64_t* total, uint32_t* ko, uint32_t* vo, LbGiveUp gu,
                       hipStream_t s) {
     const int nblk = rs_blocks(n_max);
     hipLaunchKernelGGL(k_radix_hist<Src>, dim3(nblk), dim3(RS_THREADS), 0, s, src, count_dev, n_max, shift, hist,
                        nblk);
-    hipError_t e = exclusive_scan(LoadU32{hist}, nullptr, (int64_t)256 * nblk, status, ticket, hist, total, s);
+    hipError_t e = exclusive_scan(LoadU32{hist}, nullptr, (int64_t)256 * nblk, status, ticket, hist, total, gu, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_radix_scatter<Src>, dim3(nblk), dim3(RS_THREADS), 0, s, src, count_dev, n_max, shift, hist,
-                       nblk, ko, vo);
+                       nblk, ko, vo, gu.flag);
     return hipGetLastError();
 }
 
@@ -459,14 +482,14 @@ hipError_t radix_pass(Src src, const int64_t* count_dev, int64_t n_max, int shif
 // and ticket tickets[p] (all zeroed beforehand).
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t* vals2, const int64_t* count_dev,
                       int64_t n_max, int passes, uint32_t* hist, uint64_t* status, int64_t spine_tiles,
-                      uint32_t* tickets, hipStream_t s) {
+                      uint32_t* tickets, LbGiveUp gu, hipStream_t s) {
     if (n_max <= 0) return hipSuccess;
     uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
     for (int p = 0; p < passes; ++p) {
         hipError_t e = (p == 0) ? radix_pass(SrcKI{ki}, count_dev, n_max, 0, hist, status, tickets, nullptr, ko,
-                                             vo, s)
+                                             vo, gu, s)
                                 : radix_pass(SrcKV{ki, vi}, count_dev, n_max, 8 * p, hist,
-                                             status + p * spine_tiles, tickets + p, nullptr, ko, vo, s);
+                                             status + p * spine_tiles, tickets + p, nullptr, ko, vo, gu, s);
         if (e != hipSuccess) return e;
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -628,10 +651,13 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
     }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_inst, int2* __restrict__ ranges) {
+// Per-tile [start, end) of the sorted instances; nothing (every range left
+// empty) when a look-back of the sort gave up.
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_inst, int2* __restrict__ ranges,
+                         const uint32_t* __restrict__ gave_up) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t I = *n_inst;
-    if (i >= I) return;
+    if (i >= I || *gave_up) return;
     const uint32_t k = keys[i];
     if (i == 0 || keys[i - 1] != k) ranges[k].x = (int)i;
     if (i == I - 1 || keys[i + 1] != k) ranges[k].y = (int)(i + 1);
@@ -824,12 +850,13 @@ __global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __r
                                                                   const int32_t* __restrict__ inst_gid,
                                                                   int32_t* __restrict__ inst,
                                                                   uint32_t* __restrict__ long_list,
-                                                                  uint32_t* __restrict__ long_count) {
+                                                                  uint32_t* __restrict__ long_count,
+                                                                  const uint32_t* __restrict__ gave_up) {
     static_assert(kTsShort == kTsChunk && kTsChunk == 8 * kWave, "a short list is one chunk of eight runs");
     __shared__ uint64_t s_run[kTsChunk];
     __shared__ uint32_t s_e[kTsShort];
     const int t = tile_of_block(blockIdx.x, total_tiles, run);
-    if (t < 0) return;
+    if (t < 0 || *gave_up) return;  // after a look-back gave up the lists are not sorted (and none is long)
     const int2 rg = ranges[t];
     const int L = rg.y - rg.x;
     if (L > kTsShort) {  // uniform across the wavefront: left to k_tile_sort_long
@@ -1006,6 +1033,15 @@ WsLayout ws_layout(int n, int n_views, int64_t capacity) {
 
 size_t binsort_workspace_bytes(int n, int n_views, int64_t capacity) { return ws_layout(n, n_views, capacity).total; }
 
+// Reads a look-back wait may take before it gives up (LB_SPIN_MAX, or the
+// value of SGS_LOOKBACK_SPIN, which tests set to force the give-up path).
+int lookback_spin_limit() {
+    const char* v = std::getenv("SGS_LOOKBACK_SPIN");
+    if (v == nullptr || *v == 0) return LB_SPIN_MAX;
+    const long x = std::strtol(v, nullptr, 10);
+    return x < 0 ? 0 : (x > LB_SPIN_MAX ? LB_SPIN_MAX : (int)x);
+}
+
 hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const float* rec, int n,
                           const gs_view* views_dev, int n_views, int total_tiles, int tile, void* ws,
                           int64_t capacity, uint32_t* tile_keys, int32_t* inst, int32_t* inst_gid,
@@ -1056,13 +1092,20 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
                            reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, inst_gid,
                            pair_first);
     }
-    e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, status, L.spine_tiles, tickets, s);
+    // a look-back that waits past the spin limit (SGS_LOOKBACK_SPIN overrides
+    // it, for tests) records the give-up in counts[3] and counts[4]
+    LbGiveUp gu;
+    gu.flag = reinterpret_cast<uint32_t*>(counts + 3);
+    gu.sticky = reinterpret_cast<uint32_t*>(counts + 4);
+    gu.spin_limit = lookback_spin_limit();
+    e = radix_sort(ek, ev, ok, ov, &cnt[2], capacity, passes, hist, status, L.spine_tiles, tickets, gu, s);
     if (e != hipSuccess) return e;
     // 4. per-tile [start, end) (the ranges were cleared in step 0), then each
     //    tile's list in depth order
     if (capacity > 0) {
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s,
-                           reinterpret_cast<const uint32_t*>(tile_keys), &cnt[2], reinterpret_cast<int2*>(ranges));
+                           reinterpret_cast<const uint32_t*>(tile_keys), &cnt[2], reinterpret_cast<int2*>(ranges),
+                           gu.flag);
         if (total_tiles > 0) {
             const int2* rg = reinterpret_cast<const int2*>(ranges);
             const float4* rc = reinterpret_cast<const float4*>(rec);
@@ -1070,7 +1113,8 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
             uint32_t* long_list = reinterpret_cast<uint32_t*>(w + L.long_list);
             uint32_t* long_count = tickets + kMaxPasses;
             hipLaunchKernelGGL(k_tile_sort_short, dim3(tile_grid(total_tiles, run)), dim3(TSS_THREADS), 0, s, rg,
-                               total_tiles, run, views_dev, n_views, n, rc, inst_gid, inst, long_list, long_count);
+                               total_tiles, run, views_dev, n_views, n, rc, inst_gid, inst, long_list, long_count,
+                               gu.flag);
             const int64_t max_long = capacity / (kTsShort + 1) + 1;
             const unsigned lg = (unsigned)(max_long < 1024 ? max_long : 1024);
             hipLaunchKernelGGL(k_tile_sort_long, dim3(lg), dim3(TSL_THREADS), 0, s, rg, long_list, long_count,

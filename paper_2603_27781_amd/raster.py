@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-from typing import List, Optional, Sequence
+from typing import List, NamedTuple, Optional, Sequence
 
 import numpy as np
 import torch
@@ -120,6 +120,13 @@ class Views:
         return ctypes.c_void_p(self.dev.data_ptr())
 
 
+class BinCounts(NamedTuple):
+    instances: int
+    visible_pairs: int
+    overflow: bool
+    lookback_gave_up: bool
+
+
 class Rasterizer:
     """Buffers and calls of one fwd+bwd pass for a fixed workload shape."""
 
@@ -135,7 +142,7 @@ class Rasterizer:
         self.rect = torch.empty(V * n * 2, dtype=torch.int32, **dev)
         self.touched = torch.empty(V * n, dtype=torch.int32, **dev)
         self.app = torch.empty(n * self.AS, dtype=torch.float32, **dev)
-        self.counts = torch.zeros(4, dtype=torch.int64, **dev)
+        self.counts = torch.zeros(5, dtype=torch.int64, **dev)
         self.ranges = torch.empty(views.total_tiles * 2, dtype=torch.int32, **dev)
         self.out = torch.empty(5 + n_feat, P, dtype=torch.float32, **dev)
         self.T_final = torch.empty(P, dtype=torch.float32, **dev)
@@ -179,10 +186,20 @@ class Rasterizer:
         """Gaussian index of each of the first `count` sorted instances."""
         return self.inst_gid[self.inst[:count].long()]
 
-    def instance_counts(self):
-        """(instances, visible pairs, overflow) -- synchronises."""
+    def instance_counts(self) -> "BinCounts":
+        """(instances, visible pairs, capacity overflow, look-back gave up)
+        of the last bin_sort -- synchronises."""
         c = self.counts.cpu().tolist()
-        return int(c[0]), int(c[1]), bool(c[2])
+        return BinCounts(int(c[0]), int(c[1]), bool(c[2]), bool(c[3]))
+
+    def trouble(self) -> bool:
+        """Whether any bin_sort since the last clear_trouble() overflowed its
+        capacity or gave up a scan wait (the sticky flag) -- synchronises."""
+        return bool(self.counts[4].item())
+
+    def clear_trouble(self) -> None:
+        """Clears the sticky flag (a fill kernel: safe inside a graph)."""
+        self.counts[4:5].zero_()
 
     def ensure_capacity(self, g: Gaussians, slack: float = 1.25) -> int:
         """Run projection + binning once and size the instance buffers to the
@@ -190,11 +207,13 @@ class Rasterizer:
         capturing a graph, and again if the scene changes a lot)."""
         self.project(g)
         self.bin_sort()
-        inst, _, over = self.instance_counts()
+        inst, _, over, gave_up = self.instance_counts()
         want = int(inst * slack) + 1024
         if over or inst > self.capacity or self.capacity > 2 * want:
             self.set_capacity(want)
             self.project(g)
+            self.bin_sort()
+        elif gave_up:
             self.bin_sort()
         return inst
 

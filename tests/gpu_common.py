@@ -298,8 +298,8 @@ def step_oracle_parity(snap, r, scene, views, cfg, rgb_t, dep_t, lab, W, weights
     dec = bins["dec"]
     touched = r.touched.view(V, n).cpu().numpy()
     assert np.array_equal(touched, dec["touched"])
-    inst, nvis, over = snap["counts"]
-    assert not over and inst == bins["count"] and nvis == int((touched > 0).sum())
+    inst, nvis, over, gave_up = snap["counts"]
+    assert not over and not gave_up and inst == bins["count"] and nvis == int((touched > 0).sum())
     assert np.array_equal(r.keys[:inst].cpu().numpy().view(np.uint32), bins["keys"])
     assert np.array_equal(r.sorted_gids(inst).cpu().numpy(), bins["gids"])
     assert np.array_equal(r.ranges.view(-1, 2).cpu().numpy(), bins["ranges"])

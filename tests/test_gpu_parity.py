@@ -59,9 +59,9 @@ def test_project_bit_exact(name, tile):
 def test_bin_sort_bit_exact(name, tile):
     scene, views, r, g, cfg, dec = _project(name, tile)
     r.bin_sort()
-    inst, nvis, over = r.instance_counts()
+    inst, nvis, over, gave_up = r.instance_counts()
     ref = oracle.bin_instances(scene, views, oracle_cfg(cfg), dec=dec)
-    assert not over
+    assert not over and not gave_up
     assert inst == ref["count"]
     assert nvis == int((dec["touched"] > 0).sum())
     assert np.array_equal(r.keys[:inst].cpu().numpy().view(np.uint32), ref["keys"])
@@ -84,7 +84,7 @@ def test_bin_sort_capacity_overflow_is_reported():
     r, g, cfg = gpu_setup(scene, views, {"tile": 16}, capacity=1000)
     r.project(g)
     r.bin_sort()
-    inst, _, over = r.instance_counts()
+    inst, _, over, _ = r.instance_counts()
     assert over and inst > 1000
     assert r.ensure_capacity(g) == inst
     r.bin_sort()
@@ -419,3 +419,40 @@ def test_abi_rejects_bad_arguments_without_launching():
                        r.keys.data_ptr(), r.inst.data_ptr(), r.inst_gid.data_ptr(), r.pair_first.data_ptr(),
                        r.ranges.data_ptr(), r.counts.data_ptr(), None)
     assert st == _lib.GS_ECAPACITY
+
+
+def test_lookback_give_up_is_reported_and_the_binning_stands_down(monkeypatch):
+    """A wait of the sort's single-pass scan that gives up -- forced from the
+    host with SGS_LOOKBACK_SPIN=0, so a block never waits for a predecessor
+    that has not published yet, and every kernel still exits normally -- is
+    reported in counts[3] and in the sticky counts[4]; the later binning
+    kernels then stand down and leave every tile list empty (the render is
+    background).  Without the override the next call bins bit-exactly."""
+    scene, views = CASES["cfg2-160x120-20k-F16"]()
+    # a large capacity: 1024 radix blocks, so each digit scan runs over 128 tiles
+    r, g, cfg = gpu_setup(scene, views, {"tile": 16}, capacity=8_000_000)
+    r.project(g)
+    monkeypatch.setenv("SGS_LOOKBACK_SPIN", "0")
+    seen = []
+    for _ in range(5):
+        r.clear_trouble()
+        r.bin_sort()
+        c = r.instance_counts()
+        seen.append(c.lookback_gave_up)
+        if c.lookback_gave_up:
+            assert r.trouble() and not c.overflow
+            assert not r.ranges.any()
+            r.render_fwd()
+            torch.cuda.synchronize()
+            assert float(r.out.abs().max()) == 0.0 and float(r.T_final.min()) == 1.0
+    assert any(seen), "no wait gave up in five calls with a spin limit of 0"
+    monkeypatch.delenv("SGS_LOOKBACK_SPIN")
+    r.clear_trouble()
+    r.bin_sort()
+    c = r.instance_counts()
+    assert not c.lookback_gave_up and not c.overflow and not r.trouble()
+    ref = oracle.bin_instances(scene, views, oracle_cfg(cfg))
+    assert c.instances == ref["count"]
+    assert np.array_equal(r.keys[:c.instances].cpu().numpy().view(np.uint32), ref["keys"])
+    assert np.array_equal(r.sorted_gids(c.instances).cpu().numpy(), ref["gids"])
+    assert np.array_equal(r.ranges.view(-1, 2).cpu().numpy(), ref["ranges"])
