@@ -128,9 +128,27 @@ int gs_default_config(gs_config* cfg);
 /* Host helper: fills pixel_offset / tile_offset of a HOST array of views for
  * the given tile size and returns the totals.  Every entry point takes the
  * views twice: `views` (host, for sizes and offsets) and `views_dev`
- * (device copy of the same array, read by the kernels), which must agree. */
+ * (device copy of the same array, read by the kernels), which must agree in
+ * everything but the poses (gs_views_check compares them on the device). */
 int gs_views_layout(gs_view* views, int32_t n_views, int32_t tile, int64_t* total_pixels,
                     int32_t* total_tiles);
+
+/* gs_views_check -- for callers that keep the two copies of their views
+ * themselves (the pinhole cameras of Sec. 3.2.1): counts, on the device,
+ * the views whose device copy differs, bit for bit, from the host array in
+ * a field the entry points take from the host array -- width, height,
+ * pixel_offset and, when tile > 0, tile_offset, which size their grids and
+ * buffer extents -- or in the intrinsics fx, fy, cx, cy, and writes the
+ * count to *mismatch_dev (one device int32, written whatever the count, so
+ * nothing needs clearing; graph-capturable).  The poses Rt are not
+ * compared: the kernels read them from the device copy only, and a caller
+ * may update them there between graph replays.  Asynchronous; read
+ * *mismatch_dev after the stream completes.  GS_EINVAL for a null pointer,
+ * n_views outside [1, GS_MAX_VIEWS], a tile other than 0, 8, 16 or 32, or a
+ * host array not laid out by gs_views_layout (for this tile; tile 0 checks
+ * the pixel offsets only); nothing is launched then. */
+int gs_views_check(const gs_view* views, const gs_view* views_dev, int32_t n_views, int32_t tile,
+                   int32_t* mismatch_dev, gs_stream stream);
 
 /* Floats per Gaussian of the appearance record written by gs_project:
  * (c0, c1, c2, f0 .. f_{F-1}) padded to a multiple of 4. */

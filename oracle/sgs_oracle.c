@@ -120,8 +120,10 @@ static float dec_logf(float y) {
 }
 
 /* Squared box radius, in standard deviations, of a Gaussian with opacity
- * logit l (reading R5): alpha = o exp(-q/2) reaches alpha_min only where
- * q <= 2 ln(o / alpha_min), o = sigmoid(l) evaluated on the decision path;
+ * logit l (the box that decides which tiles a Gaussian is binned to, so
+ * that tiled rendering equals per-pixel rendering): alpha = o exp(-q/2)
+ * reaches alpha_min only where q <= 2 ln(o / alpha_min), o = sigmoid(l)
+ * evaluated on the decision path;
  * 2^-8 is added so that the box also holds the pairs whose binary32 alpha
  * rounds up to alpha_min.  Returns 0 when o / alpha_min <= 1 (culled). */
 static float box_k(float logit, float alpha_min) {

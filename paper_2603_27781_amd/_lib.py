@@ -21,7 +21,7 @@ GS_GRAD_PARAMS, GS_GRAD_POSE = 1, 2
 
 # symbols declared in include/sgs.h (checked by the ABI test)
 EXPORTS = [
-    "gs_default_config", "gs_views_layout", "gs_app_stride", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
+    "gs_default_config", "gs_views_layout", "gs_views_check", "gs_app_stride", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
     "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
     "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_project_bwd_write",
     "gs_pose_grad_workspace",
@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
     P = ctypes.POINTER
     L.gs_default_config.argtypes = [P(GsConfig)]
     L.gs_views_layout.argtypes = [P(GsView), c_int32, c_int32, P(c_int64), P(c_int32)]
+    L.gs_views_check.argtypes = [P(GsView), c_void_p, c_int32, c_int32, c_void_p, c_void_p]
     L.gs_app_stride.argtypes = [c_int32]
     L.gs_app_stride.restype = c_int32
     L.gs_project.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,

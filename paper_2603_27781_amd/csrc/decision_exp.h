@@ -54,7 +54,7 @@ __device__ __forceinline__ float dec_log(float y) {
 }
 
 // Squared box radius in standard deviations of a Gaussian of opacity logit
-// l (R5): alpha = o exp(-q/2) >= alpha_min needs q <= 2 ln(o / alpha_min),
+// l: alpha = o exp(-q/2) >= alpha_min needs q <= 2 ln(o / alpha_min),
 // with o = 1 / (1 + exp(-l)) taken on the decision path; plus 2^-8 so that
 // the box covers the binary32 rounding of q and alpha at any opacity.
 // Returns a value <= 0 when o / alpha_min <= 1 (the pair is culled).

@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project(GaussPtrs g, const gs_
     }
 
     const float n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
-    // opacity-aware box (R5): the decision-path k, <= 0 for o <= alpha_min
+    // opacity-aware box: the decision-path k, <= 0 for o <= alpha_min
     const float kbox = valid ? dec_box_k(logit, c.alpha_min) : 0.0f;
     const bool alive = valid && (logit > c.logit_min) && (kbox > 0.0f) && (n2 > 0.0f) && (n2 < INFINITY);
     if (alive) {

@@ -134,6 +134,32 @@ size_t grad2d_bytes(int n, int n_feat, int n_views) {
     return ((size_t)n_views * n * 8 + (size_t)n * (4 + n_feat)) * sizeof(float);
 }
 
+// The fields of up to GS_MAX_VIEWS host views that gs_views_check compares,
+// passed by value to its kernel (2.3 KB of kernel arguments).
+struct ViewFields {
+    int32_t width[GS_MAX_VIEWS], height[GS_MAX_VIEWS], tile_offset[GS_MAX_VIEWS];
+    int64_t pixel_offset[GS_MAX_VIEWS];
+    float fx[GS_MAX_VIEWS], fy[GS_MAX_VIEWS], cx[GS_MAX_VIEWS], cy[GS_MAX_VIEWS];
+};
+
+__device__ __forceinline__ bool same_bits(float a, float b) { return __float_as_uint(a) == __float_as_uint(b); }
+
+// One wavefront, one lane per view: the number of views whose device copy
+// differs from the host fields, written by lane 0 whatever it is.
+__global__ void __launch_bounds__(kWave) k_views_check(ViewFields h, const gs_view* __restrict__ d, int n,
+                                                       int check_tiles, int32_t* __restrict__ mismatch) {
+    const int v = threadIdx.x;
+    bool bad = false;
+    if (v < n) {
+        const gs_view& w = d[v];
+        bad = w.width != h.width[v] || w.height != h.height[v] || w.pixel_offset != h.pixel_offset[v] ||
+              (check_tiles && w.tile_offset != h.tile_offset[v]) || !same_bits(w.fx, h.fx[v]) ||
+              !same_bits(w.fy, h.fy[v]) || !same_bits(w.cx, h.cx[v]) || !same_bits(w.cy, h.cy[v]);
+    }
+    const uint64_t m = __ballot(bad);
+    if (v == 0) *mismatch = (int32_t)__popcll(m);
+}
+
 }  // namespace
 
 extern "C" {
@@ -171,6 +197,29 @@ int gs_views_layout(gs_view* views, int32_t n_views, int32_t tile, int64_t* tota
 }
 
 int32_t gs_app_stride(int32_t n_feat) { return n_feat < 0 ? -1 : (int32_t)app_stride(n_feat); }
+
+int gs_views_check(const gs_view* views, const gs_view* views_dev, int32_t n_views, int32_t tile,
+                   int32_t* mismatch_dev, gs_stream stream) {
+    if (!mismatch_dev || (tile != 0 && !pow2_tile(tile))) return GS_EINVAL;
+    const int st = check_views(views, views_dev, n_views, tile, nullptr, nullptr);
+    if (st) return st;
+    static_assert(GS_MAX_VIEWS <= kWave, "one lane per view");
+    ViewFields h;
+    std::memset(&h, 0, sizeof(h));
+    for (int v = 0; v < n_views; ++v) {
+        h.width[v] = views[v].width;
+        h.height[v] = views[v].height;
+        h.tile_offset[v] = views[v].tile_offset;
+        h.pixel_offset[v] = views[v].pixel_offset;
+        h.fx[v] = views[v].fx;
+        h.fy[v] = views[v].fy;
+        h.cx[v] = views[v].cx;
+        h.cy[v] = views[v].cy;
+    }
+    hipLaunchKernelGGL(k_views_check, dim3(1), dim3(kWave), 0, (hipStream_t)stream, h, views_dev, (int)n_views,
+                       tile > 0 ? 1 : 0, mismatch_dev);
+    return hip_status(hipGetLastError());
+}
 
 int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,
                const gs_config* cfg, float* rec, uint32_t* rect, int32_t* tiles_touched, float* app,

@@ -119,6 +119,15 @@ class Views:
     def dev_ptr(self):
         return ctypes.c_void_p(self.dev.data_ptr())
 
+    def check(self) -> int:
+        """Number of views whose device copy differs from the host array in
+        the sizes, offsets or intrinsics (gs_views_check; the poses are not
+        compared) -- synchronises."""
+        out = torch.full((1,), -1, dtype=torch.int32, device=self.dev.device)
+        check(_lib.load().gs_views_check(self.host, self.dev_ptr(), self.n, self.tile,
+                                         ctypes.c_void_p(out.data_ptr()), _stream()), "gs_views_check")
+        return int(out.item())
+
 
 class BinCounts(NamedTuple):
     instances: int

@@ -167,3 +167,22 @@ def test_slam_loss_host_side():
     bad = _lib.GsSlamLossOpts.from_buffer_copy(o)
     bad.flags = 4
     assert call(opts=bad) == _lib.GS_EINVAL
+
+
+def test_views_check_rejects_before_any_launch():
+    """gs_views_check refuses null pointers, view counts outside [1, 64],
+    unsupported tiles and host arrays not laid out back to back, on the host
+    (the dummy device pointers are never dereferenced)."""
+    L = _lib.load()
+    V = (_lib.GsView * 2)()
+    for i in range(2):
+        V[i].width, V[i].height, V[i].fx, V[i].fy = 40, 30, 50.0, 50.0
+    assert L.gs_views_layout(V, 2, 16, None, None) == 0
+    dummy = 1 << 20
+    assert L.gs_views_check(V, None, 2, 16, dummy, None) == _lib.GS_EINVAL
+    assert L.gs_views_check(V, dummy, 2, 16, None, None) == _lib.GS_EINVAL
+    assert L.gs_views_check(V, dummy, 0, 16, dummy, None) == _lib.GS_EINVAL
+    assert L.gs_views_check(V, dummy, 65, 16, dummy, None) == _lib.GS_EINVAL
+    assert L.gs_views_check(V, dummy, 2, 12, dummy, None) == _lib.GS_EINVAL
+    V[1].tile_offset += 1
+    assert L.gs_views_check(V, dummy, 2, 16, dummy, None) == _lib.GS_EINVAL

@@ -421,6 +421,27 @@ def test_abi_rejects_bad_arguments_without_launching():
     assert st == _lib.GS_ECAPACITY
 
 
+def test_views_check_counts_the_views_whose_copies_differ():
+    """gs_views_check: 0 when the device copy equals the host array, 0 after
+    the poses change on the device only (the poses are not compared), and
+    one per view whose size, offset or intrinsics differ."""
+    _scene, views = CASES["tiny3views-F16"]()
+    from paper_2603_27781_amd import raster
+    vw = raster.Views(views, 16)
+    assert vw.check() == 0
+    Rts = torch.from_numpy(np.stack([np.asarray(v.Rt, np.float32) for v in views]) * 1.01).cuda()
+    vw.set_poses(Rts)
+    assert vw.check() == 0
+    words = vw.dev.view(torch.int32)
+    words[1, 0] += 1  # width of view 1
+    assert vw.check() == 1
+    words[1, 0] -= 1
+    vw.dev.view(torch.float32)[2, 4] += 0.5  # cx of view 2
+    assert vw.check() == 1
+    words[0, 1] += 3  # height of view 0
+    assert vw.check() == 2
+
+
 def test_lookback_give_up_is_reported_and_the_binning_stands_down(monkeypatch):
     """A wait of the sort's single-pass scan that gives up -- forced from the
     host with SGS_LOOKBACK_SPIN=0, so a block never waits for a predecessor

@@ -140,8 +140,9 @@ def test_dec_log_accuracy(orc):
 
 
 def test_box_k_is_twice_log_opacity_over_alpha_min(orc):
-    """R5: the squared box radius is 2 ln(o / alpha_min) (+ 2^-8), from the
-    opacity o = sigmoid(logit); 0 (culled) where o <= alpha_min."""
+    """The opacity-aware box: its squared radius is 2 ln(o / alpha_min)
+    (+ 2^-8), from the opacity o = sigmoid(logit); 0 (culled) where
+    o <= alpha_min."""
     rng = np.random.default_rng(6)
     amin = float(np.float32(1.0 / 255.0))
     lmin = math.log(amin / (1 - amin))
@@ -159,9 +160,9 @@ def test_box_k_is_twice_log_opacity_over_alpha_min(orc):
 
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
-def test_tile_rectangle_edges_follow_the_r5_box(orc, tile):
-    """Both edges of every visible pair's tile rectangle are where R5 puts
-    them, from FP64 quantities: the box [m - r, m + r] with r = sqrt(k Sigma2D_xx)
+def test_tile_rectangle_edges_follow_the_opacity_aware_box(orc, tile):
+    """Both edges of every visible pair's tile rectangle are where the
+    opacity-aware box puts them, from FP64 quantities: the box [m - r, m + r] with r = sqrt(k Sigma2D_xx)
     (1 + 2^-10), k = 2 ln(o / alpha_min) (+ 2^-8), mean, Sigma2D and o from
     the FP64 projection, touches tiles floor((m - r)/tile) .. floor((m + r)/tile),
     clamped to the grid.  The FP64 box is bracketed (r without the padding,
