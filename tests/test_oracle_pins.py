@@ -162,10 +162,10 @@ def test_box_k_is_twice_log_opacity_over_alpha_min(orc):
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_tile_rectangle_edges_follow_the_opacity_aware_box(orc, tile):
     """Both edges of every visible pair's tile rectangle are where the
-    opacity-aware box puts them, from FP64 quantities: the box [m - r, m + r] with r = sqrt(k Sigma2D_xx)
-    (1 + 2^-10), k = 2 ln(o / alpha_min) (+ 2^-8), mean, Sigma2D and o from
-    the FP64 projection, touches tiles floor((m - r)/tile) .. floor((m + r)/tile),
-    clamped to the grid.  The FP64 box is bracketed (r without the padding,
+    opacity-aware box puts them, from FP64 quantities: the box [m - r, m + r]
+    with r = sqrt(k Sigma2D_xx) (1 + 2^-10), k = 2 ln(o / alpha_min)
+    (+ 2^-8), mean, Sigma2D and o from the FP64 projection, touches tiles
+    floor((m - r)/tile) .. floor((m + r)/tile), clamped to the grid.  The FP64 box is bracketed (r without the padding,
     less 1e-3 px, and with it, plus 1e-3 px) to absorb binary32 rounding; a
     rectangle even one tile too wide or too narrow on either side fails."""
     w = wl.config1(scale=0.5)
@@ -198,6 +198,50 @@ def test_tile_rectangle_edges_follow_the_opacity_aware_box(orc, tile):
         o_all = 1.0 / (1.0 + np.exp(-w.scene.logit.astype(np.float64)))
         assert not np.any(dec["touched"][vi][o_all <= amin])
     assert checked > 500
+
+
+def test_culls_follow_the_near_plane_guard_and_opacity_rules(orc):
+    """Which pairs survive the culls, against the rules evaluated in FP64:
+    camera depth > z_near; |x/z| <= guard (W/2)/fx and |y/z| <= guard
+    (H/2)/fy; opacity o > alpha_min.  Each Gaussian sits a relative 1e-4
+    (1e-3 in the logit) inside or outside one boundary; the scales are large
+    (0.5 m), so every Gaussian reaches the image and only a cull can drop
+    it."""
+    W, H, f = 64, 48, 40.0
+    view = wl.make_view(W, H, f, np.eye(4))
+    cfg = orc.Cfg()
+    limx, limy = cfg.guard * (W / 2) / f, cfg.guard * (H / 2) / f
+    amin = float(np.float32(cfg.alpha_min))
+    lmin = math.log(amin / (1.0 - amin))
+    eps = 1e-4
+    pts, logit = [], []
+    for z in (cfg.z_near * (1 + eps), cfg.z_near * (1 - eps), 0.5, 3.0):
+        pts.append((0.0, 0.0, z))
+        logit.append(0.0)
+    for sgn in (1.0, -1.0):
+        for fac in (1 - eps, 1 + eps):
+            pts.append((sgn * limx * fac * 3.0, 0.0, 3.0))
+            pts.append((0.0, sgn * limy * fac * 3.0, 3.0))
+            logit += [0.0, 0.0]
+    for dl in (1e-3, -1e-3, 0.5, -0.5):
+        pts.append((0.1, -0.1, 2.0))
+        logit.append(lmin + dl)
+    n = len(pts)
+    mu = np.array(pts, np.float64).T
+    logit = np.array(logit, np.float64)
+    sc = wl.Scene(mu.astype(np.float32), np.full((3, n), math.log(0.5), np.float32),
+                  np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, n)),
+                  logit.astype(np.float32), np.full((3, n), 0.5, np.float32), np.zeros((2, n), np.float32))
+    # the rules, in FP64, on the binary32 inputs
+    m = sc.mu.astype(np.float64)
+    z = m[2]
+    o = 1.0 / (1.0 + np.exp(-sc.logit.astype(np.float64)))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        expect = (z > cfg.z_near) & (np.abs(m[0] / z) <= limx) & (np.abs(m[1] / z) <= limy) & (o > amin)
+    dec = orc.decide(sc, [view], cfg)
+    got = dec["touched"][0] > 0
+    assert expect.sum() >= 8 and (~expect).sum() >= 7
+    assert np.array_equal(got, expect), (np.nonzero(got != expect)[0], got, expect)
 
 
 def test_decision_path_agrees_with_fp64(orc):
