@@ -528,7 +528,7 @@ int gs_pose_grad(const gs_gaussians* g, const gs_view* views, const gs_view* vie
  * looks the array's address up (hipGetSymbolAddress); make that first call
  * outside stream capture.  Errors: as gs_pose_grad, and GS_ECAPACITY when
  * gs_pose_grad_workspace(n, n_views) exceeds GS_NOALLOC_SCRATCH_BYTES
- * (e.g. beyond 2M Gaussians at 16 views); nothing is launched then.
+ * (beyond about 22M Gaussians at 16 views); nothing is launched then.
  * --------------------------------------------------------------------------- */
 enum { GS_NOALLOC_SCRATCH_BYTES = 8 << 20 };
 int gs_pose_grad_noalloc(const gs_gaussians* g, const gs_view* views, const gs_view* views_dev, int32_t n_views,

@@ -254,56 +254,83 @@ __global__ void __launch_bounds__(kPbThreads) k_project_bwd(GaussPtrs g, const g
         out.quat[(size_t)k * n + i] = (ACC ? out.quat[(size_t)k * n + i] : 0.0f) + (dq[k] - G.q[k] * dot) * iq;
 }
 
-// Twist contributions per (view, Gaussian), reduced per block in FP64.
-__global__ void __launch_bounds__(256) k_pose_partial(GaussPtrs g, const gs_view* __restrict__ views, float blur,
-                                                      const int32_t* __restrict__ touched,
-                                                      const float4* __restrict__ grad_geo,
-                                                      double* __restrict__ partials, int nblk) {
-    __shared__ double s_red[6][256 / kWave];
+// Twist contributions per (view, Gaussian), reduced per block in FP64.  A
+// block takes kPoseChunk consecutive Gaussians of one view.  Few pairs are
+// visible (under a tenth at the mapping workloads), so the block first lists
+// the pairs with a nonzero 2D gradient in LDS, in index order (thread t
+// screens Gaussians t, t + 256, ..., each round coalesced, ranked with
+// ballots and per-wavefront counts), and then its threads take the listed
+// pairs, entry e by thread e mod 256: every lane of the projection backward
+// works on a visible pair instead of one in ten.  Each thread sums its
+// entries in list order and the block sums the threads in a fixed order.
+constexpr int kPoseThreads = 256;
+constexpr int kPoseGPT = 8;  // Gaussians screened per thread
+constexpr int kPoseChunk = kPoseThreads * kPoseGPT;
+__global__ void __launch_bounds__(kPoseThreads) k_pose_partial(GaussPtrs g, const gs_view* __restrict__ views,
+                                                               float blur, const int32_t* __restrict__ touched,
+                                                               const float4* __restrict__ grad_geo,
+                                                               double* __restrict__ partials, int nblk) {
+    __shared__ int s_list[kPoseChunk];
+    __shared__ uint32_t s_tmp[kPoseThreads / kWave];
+    __shared__ double s_red[6][kPoseThreads / kWave];
     const int n = g.n;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int base = blockIdx.x * kPoseChunk;
+    uint32_t count = 0;
+    for (int k = 0; k < kPoseGPT; ++k) {
+        const int i = base + k * kPoseThreads + tid;
+        bool keep = false;
+        if (i < n && touched[(size_t)v * n + i] > 0) {
+            const size_t o = (size_t)v * n + i;
+            keep = nonzero(grad_geo[2 * o], grad_geo[2 * o + 1]);
+        }
+        uint32_t tot;
+        const uint32_t rank = block_exclusive<kPoseThreads>(keep ? 1u : 0u, s_tmp, &tot);
+        if (keep) s_list[count + rank] = i;
+        count += tot;
+    }
+    __syncthreads();
     double tw[6] = {0, 0, 0, 0, 0, 0};
-    if (i < n && touched[(size_t)v * n + i] > 0) {
+    const gs_view& vw = views[v];
+    for (uint32_t e = tid; e < count; e += kPoseThreads) {
+        const int i = s_list[e];
         const size_t o = (size_t)v * n + i;
         const float4 g0 = grad_geo[2 * o], g1 = grad_geo[2 * o + 1];
-        if (nonzero(g0, g1)) {
-            Gauss G;
-            load_gauss(g, i, G);
-            const float mu[3] = {g.mu[i], g.mu[(size_t)n + i], g.mu[2 * (size_t)n + i]};
-            const gs_view& vw = views[v];
-            Fwd f;
-            forward(G, mu, vw.Rt, vw.fx, vw.fy, blur, f);
-            float dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            float dp[3], D[3];
-            backward_view(G, f, vw.Rt, vw.fx, vw.fy, g0, g1, dM, dp, D);
-            // G_c = J^T D J with J = [[j00, 0, j02], [0, j11, j12]]
-            const float J0[3] = {f.j00, 0.f, f.j02}, J1[3] = {0.f, f.j11, f.j12};
-            float Gc[9];
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b)
-                    Gc[3 * a + b] = J0[a] * (D[0] * J0[b] + D[1] * J1[b]) + J1[a] * (D[1] * J0[b] + D[2] * J1[b]);
-            // Sigma_c = W W^T, W = R_CW M
-            const float* Rt = vw.Rt;
-            float Wm[9];
-            for (int r = 0; r < 3; ++r)
-                for (int k = 0; k < 3; ++k)
-                    Wm[3 * r + k] = Rt[4 * r] * G.M[k] + Rt[4 * r + 1] * G.M[3 + k] + Rt[4 * r + 2] * G.M[6 + k];
-            float Sc[9];
-            for (int r = 0; r < 3; ++r)
-                for (int k = 0; k < 3; ++k)
-                    Sc[3 * r + k] = Wm[3 * r] * Wm[3 * k] + Wm[3 * r + 1] * Wm[3 * k + 1] + Wm[3 * r + 2] * Wm[3 * k + 2];
-            // antisymmetric part A = Sc G - G Sc, entries (1,2), (2,0), (0,1)
-            auto SG = [&](int r, int k) { return Sc[3 * r] * Gc[k] + Sc[3 * r + 1] * Gc[3 + k] + Sc[3 * r + 2] * Gc[6 + k]; };
-            auto GS = [&](int r, int k) { return Gc[3 * r] * Sc[k] + Gc[3 * r + 1] * Sc[3 + k] + Gc[3 * r + 2] * Sc[6 + k]; };
-            const float* p = f.p;
-            tw[0] = dp[0];
-            tw[1] = dp[1];
-            tw[2] = dp[2];
-            tw[3] = (double)(p[1] * dp[2] - p[2] * dp[1]) + 2.0 * (double)(SG(1, 2) - GS(1, 2));
-            tw[4] = (double)(p[2] * dp[0] - p[0] * dp[2]) + 2.0 * (double)(SG(2, 0) - GS(2, 0));
-            tw[5] = (double)(p[0] * dp[1] - p[1] * dp[0]) + 2.0 * (double)(SG(0, 1) - GS(0, 1));
-        }
+        Gauss G;
+        load_gauss(g, i, G);
+        const float mu[3] = {g.mu[i], g.mu[(size_t)n + i], g.mu[2 * (size_t)n + i]};
+        Fwd f;
+        forward(G, mu, vw.Rt, vw.fx, vw.fy, blur, f);
+        float dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        float dp[3], D[3];
+        backward_view(G, f, vw.Rt, vw.fx, vw.fy, g0, g1, dM, dp, D);
+        // G_c = J^T D J with J = [[j00, 0, j02], [0, j11, j12]]
+        const float J0[3] = {f.j00, 0.f, f.j02}, J1[3] = {0.f, f.j11, f.j12};
+        float Gc[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                Gc[3 * a + b] = J0[a] * (D[0] * J0[b] + D[1] * J1[b]) + J1[a] * (D[1] * J0[b] + D[2] * J1[b]);
+        // Sigma_c = W W^T, W = R_CW M
+        const float* Rt = vw.Rt;
+        float Wm[9];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k)
+                Wm[3 * r + k] = Rt[4 * r] * G.M[k] + Rt[4 * r + 1] * G.M[3 + k] + Rt[4 * r + 2] * G.M[6 + k];
+        float Sc[9];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k)
+                Sc[3 * r + k] = Wm[3 * r] * Wm[3 * k] + Wm[3 * r + 1] * Wm[3 * k + 1] + Wm[3 * r + 2] * Wm[3 * k + 2];
+        // antisymmetric part A = Sc G - G Sc, entries (1,2), (2,0), (0,1)
+        auto SG = [&](int r, int k) { return Sc[3 * r] * Gc[k] + Sc[3 * r + 1] * Gc[3 + k] + Sc[3 * r + 2] * Gc[6 + k]; };
+        auto GS = [&](int r, int k) { return Gc[3 * r] * Sc[k] + Gc[3 * r + 1] * Sc[3 + k] + Gc[3 * r + 2] * Sc[6 + k]; };
+        const float* p = f.p;
+        tw[0] += dp[0];
+        tw[1] += dp[1];
+        tw[2] += dp[2];
+        tw[3] += (double)(p[1] * dp[2] - p[2] * dp[1]) + 2.0 * (double)(SG(1, 2) - GS(1, 2));
+        tw[4] += (double)(p[2] * dp[0] - p[0] * dp[2]) + 2.0 * (double)(SG(2, 0) - GS(2, 0));
+        tw[5] += (double)(p[0] * dp[1] - p[1] * dp[0]) + 2.0 * (double)(SG(0, 1) - GS(0, 1));
     }
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (int k = 0; k < 6; ++k) {
@@ -356,15 +383,15 @@ hipError_t launch_project_bwd(const GaussPtrs& g, const gs_view* views_dev, int 
 }
 
 size_t pose_workspace_bytes(int n, int n_views) {
-    const size_t nblk = (size_t)ceil_div(n > 0 ? n : 1, 256);
+    const size_t nblk = (size_t)ceil_div(n > 0 ? n : 1, kPoseChunk);
     return nblk * (size_t)n_views * 6 * sizeof(double);
 }
 
 hipError_t launch_pose_grad(const GaussPtrs& g, const gs_view* views_dev, int n_views, const RasterConst& c,
                             const int32_t* touched, const float* grad_geo, void* ws, float* twist, hipStream_t s) {
-    const int nblk = ceil_div(g.n > 0 ? g.n : 1, 256);
+    const int nblk = ceil_div(g.n > 0 ? g.n : 1, kPoseChunk);
     double* partials = static_cast<double*>(ws);
-    hipLaunchKernelGGL(k_pose_partial, dim3((unsigned)nblk, (unsigned)n_views), dim3(256), 0, s, g, views_dev,
+    hipLaunchKernelGGL(k_pose_partial, dim3((unsigned)nblk, (unsigned)n_views), dim3(kPoseThreads), 0, s, g, views_dev,
                        c.blur, touched, reinterpret_cast<const float4*>(grad_geo), partials, nblk);
     hipLaunchKernelGGL(k_pose_final, dim3((unsigned)n_views), dim3(256), 0, s, partials, nblk, twist);
     return hipGetLastError();

@@ -544,9 +544,9 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <
 }
 
 // Sum of the records of every (view, Gaussian) pair (contiguous emission
-// indices, fixed order).  One lane per (Gaussian, view) pair: the VP lanes of
-// a Gaussian are adjacent in one wavefront (VP a power of two, VP <= 64; with
-// more views than VP the lanes take views vl, vl + VP, ... in rounds).  Few
+// indices, fixed order).  VP lanes per Gaussian, adjacent in one wavefront
+// (VP a power of two, VP <= 64; the launcher uses VP <= 2); with more views
+// than VP the lanes take views vl, vl + VP, ... in rounds.  Few
 // pairs are visible and their record counts vary widely, so a wavefront
 // flattens the records of its pairs (an exclusive scan of the counts) and
 // loads them 64 at a time, one record per lane (consecutive records of a
@@ -793,8 +793,14 @@ hipError_t launch_render_bwd(const float* rec, const float* app, int n, int n_fe
 template <int F>
 hipError_t launch_reduce_t(bool params, const float* records, const int32_t* pair_first, const int32_t* touched,
                            int n, int n_views, int64_t capacity, float* grad_geo, float* grad_app, hipStream_t s) {
+    // two lanes per Gaussian, the views taken in rounds: a wavefront then
+    // covers 32 consecutive Gaussians, so its pair loads are two coalesced
+    // runs and its records two contiguous ranges of emission indices (the
+    // instances of consecutive visible pairs of one view are adjacent).  A
+    // lane per view was as fast at 8 views and F = 16 (147 against 149 us)
+    // and much slower at 16 views and F = 32 (809 against 599 us).
     int vp_log2 = 0;
-    while ((1 << vp_log2) < n_views && vp_log2 < 6) ++vp_log2;
+    while ((1 << vp_log2) < n_views && vp_log2 < 1) ++vp_log2;
     const int64_t lanes = (int64_t)n << vp_log2;
     const dim3 grid((unsigned)((lanes + 255) / 256));
     if (params)

@@ -61,7 +61,9 @@ def test_workspace_queries():
     assert L.gs_render_bwd_workspace(1000, 12, 2, 5000, 1, ctypes.byref(b), ctypes.byref(b2)) == _lib.GS_EUNSUPPORTED
     assert L.gs_bin_sort_workspace(1000, 2, 5000, ctypes.byref(b)) == 0 and b.value > 5 * 2000 * 4
     assert L.gs_bin_sort_workspace(0, 2, 5000, ctypes.byref(b)) == _lib.GS_EINVAL
-    assert L.gs_pose_grad_workspace(1000, 2, ctypes.byref(b)) == 0 and b.value == 4 * 2 * 6 * 8
+    # per-block FP64 partials (6 per view), a block per 2048 Gaussians
+    assert L.gs_pose_grad_workspace(1000, 2, ctypes.byref(b)) == 0 and b.value == 1 * 2 * 6 * 8
+    assert L.gs_pose_grad_workspace(5000, 3, ctypes.byref(b)) == 0 and b.value == 3 * 3 * 6 * 8
 
 
 def test_validation_rejects_before_any_launch():

@@ -72,7 +72,7 @@ def test_pose_grad_noalloc_refuses_sizes_beyond_its_scratch():
     small = wl.tiny_scene(83, 200, F=8, W=32, H=24, f=30.0)
     r, g = _case(small.scene, small.views, 3)
     gc = g.c()
-    gc.n = 1 << 30  # gs_pose_grad_workspace(2^30, 1) is 192 MiB, beyond the scratch; refused on the host
+    gc.n = 1 << 30  # gs_pose_grad_workspace(2^30, 1) is 24 MiB, beyond the scratch; refused on the host
     b = ctypes.c_size_t(0)
     assert L.gs_pose_grad_workspace(gc.n, 1, ctypes.byref(b)) == _lib.GS_OK
     assert b.value > _lib.GS_NOALLOC_SCRATCH_BYTES
