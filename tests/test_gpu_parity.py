@@ -372,6 +372,84 @@ def test_autograd_function_matches_direct_calls():
     assert torch.allclose(xi.grad, tw, rtol=1e-4, atol=1e-6 * float(tw.abs().max()))
 
 
+def test_parameter_gradients_match_fp64_central_differences():
+    """The backward behind torch.autograd (raster.rasterize) against FP64
+    central finite differences of the oracle's forward render, for four
+    coordinates of every parameter tensor (means, log-scales, quaternions,
+    opacity logits, colours, features) of visible Gaussians and all six
+    twist components, on L = sum(wgt * out) with seeded weights.  The
+    binary32 decisions are held: a step counts only if no pixel's contributor
+    set or last contributor moves, else it is halved.  Tolerance: 1e-3 of
+    the tensor's largest |gradient|."""
+    import scipy.linalg
+    from paper_2603_27781_amd import raster
+    w = wl.tiny_scene(31, 40, F=8)
+    r, g, cfg = gpu_setup(w.scene, w.views, {"tile": 16})
+    r.ensure_capacity(g)
+    params = [t.clone().requires_grad_(True) for t in g.tensors()]
+    xi = torch.zeros(1, 6, device="cuda", requires_grad=True)
+    out = raster.rasterize(r, xi, *params)
+    wgt = np.random.default_rng(3).normal(size=tuple(out.shape))
+    (out * torch.from_numpy(wgt.astype(np.float32)).cuda()).sum().backward()
+    ocfg = oracle_cfg(cfg)
+    bins = oracle.bin_instances(w.scene, w.views, ocfg)
+
+    def lin(s64=None, poses64=None):
+        ro = oracle.render(w.scene, w.views, ocfg, bins=bins, s64=s64, poses64=poses64)
+        return float(np.sum(wgt * ro["out"])), (ro["last"].copy(), ro["ncontrib"].copy())
+
+    _, key0 = lin()
+    s0 = oracle.scene64(w.scene)
+    rng = np.random.default_rng(4)
+    vis = np.nonzero(bins["dec"]["touched"][0] > 0)[0]
+    checked = 0
+    for nm, p in zip(("mu", "log_scale", "quat", "logit", "color", "feat"), params):
+        grad = p.grad.cpu().numpy().astype(np.float64)
+        scale = max(float(np.max(np.abs(grad))), 1e-30)
+        for _ in range(4):
+            i = int(rng.choice(vis))
+            idx = (int(rng.integers(0, s0[nm].shape[0])), i) if s0[nm].ndim == 2 else (i,)
+            x = s0[nm][idx]
+            h = 1e-6 * max(1.0, abs(x))
+            fd = None
+            while h > 1e-9:
+                sp = {k: v.copy() for k, v in s0.items()}
+                sm = {k: v.copy() for k, v in s0.items()}
+                sp[nm][idx] = x + h
+                sm[nm][idx] = x - h
+                lp, kp = lin(s64=sp)
+                lm, km = lin(s64=sm)
+                if all(np.array_equal(a, c) for a, c in zip(kp + km, key0 + key0)):
+                    fd = (lp - lm) / (2 * h)
+                    break
+                h *= 0.5
+            if fd is None:
+                continue
+            assert abs(grad[idx] - fd) <= 1e-3 * scale, (nm, idx, grad[idx], fd, scale)
+            checked += 1
+    assert checked >= 20
+    # the twist: left perturbation Exp(xi) T_CW
+    T0 = np.eye(4)
+    T0[:3] = np.asarray(w.views[0].Rt, np.float32).astype(np.float64)
+
+    def hat(v):
+        M = np.zeros((4, 4))
+        M[:3, :3] = np.array([[0, -v[5], v[4]], [v[5], 0, -v[3]], [-v[4], v[3], 0]])
+        M[:3, 3] = v[:3]
+        return M
+
+    tw = xi.grad.cpu().numpy()[0].astype(np.float64)
+    fd6 = np.zeros(6)
+    for k in range(6):
+        e6 = np.zeros(6)
+        e6[k] = 1e-6
+        lp, kp = lin(poses64=[scipy.linalg.expm(hat(e6)) @ T0])
+        lm, km = lin(poses64=[scipy.linalg.expm(hat(-e6)) @ T0])
+        assert all(np.array_equal(a, c) for a, c in zip(kp + km, key0 + key0))
+        fd6[k] = (lp - lm) / 2e-6
+    assert rel_err(tw, fd6) <= 1e-3, (tw, fd6)
+
+
 def test_edge_cases_empty_and_single():
     # every Gaussian behind the camera: nothing visible, background 0, T = 1
     w = wl.tiny_scene(71, 50, F=8)
