@@ -674,8 +674,8 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* n_ins
 // sorted across the lanes of a wavefront by a bitonic network; the rank of
 // a key among up to eight runs (a chunk of 512) is its lane plus, for every
 // other run, the number of that run's keys below it (a 6-step binary search
-// in LDS); chunks of a longer list merge the same way (9-step searches in
-// the other sorted chunks).  k_tile_sort_short gives each list of up to
+// in LDS); chunks of a longer list merge the same way (8- or 9-step
+// searches in the other sorted chunks).  k_tile_sort_short gives each list of up to
 // kTsShort one wavefront; k_tile_sort_long gives each longer list a
 // workgroup, in LDS up to kTsLong, and beyond that (rare) stable counting
 // passes over 8-bit digits in global memory (the tile's slices of the
@@ -901,17 +901,22 @@ __device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_
     uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     if (L <= kTsLong) {
-        const int nchunk = (L + kTsChunk - 1) / kTsChunk;
+        // chunks of 256 keys (four runs) up to 1024, so that all four
+        // wavefronts sort; of 512 beyond, where more chunks would make the
+        // final merge's searches the larger cost
+        const bool small = L <= 4 * (kTsChunk / 2);
+        const int CH = small ? kTsChunk / 2 : kTsChunk;
+        const int nchunk = (L + CH - 1) / CH;
         for (int c = wave; c < nchunk; c += NW) {
-            const int c0 = c * kTsChunk;
-            const int nc = min(kTsChunk, L - c0);
+            const int c0 = c * CH;
+            const int nc = min(CH, L - c0);
             uint64_t k[8];
             int rank[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 const int i = c0 + r * kWave + lane;
                 k[r] = kNoKey;
-                if (i < L) {
+                if (r * kWave < CH && i < L) {
                     const uint32_t e = einst[i];
                     s_e[i] = e;
                     k[r] = depth_key(rec, vbase, inst_gid, e, i);
@@ -921,8 +926,8 @@ __device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_
 #pragma unroll
             for (int r = 0; r < 8; ++r)
                 if (r * kWave + lane < nc) s_sorted[c0 + rank[r]] = k[r];
-            // pad the last chunk to a full 512 for the searches
-            for (int i = nc + lane; i < kTsChunk; i += kWave) s_sorted[c0 + i] = kNoKey;
+            // pad the last chunk to a full CH for the searches
+            for (int i = nc + lane; i < CH; i += kWave) s_sorted[c0 + i] = kNoKey;
             // s_run is rewritten by this wavefront's next chunk
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -931,10 +936,12 @@ __device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_
         __syncthreads();
         for (int j = threadIdx.x; j < L; j += TSL_THREADS) {
             const uint64_t key = s_sorted[j];
-            const int c = j / kTsChunk;
-            int pos = j - c * kTsChunk;
-            for (int c2 = 0; c2 < nchunk; ++c2)
-                if (c2 != c) pos += count_below<9>(s_sorted + c2 * kTsChunk, key);
+            const int c = j / CH;
+            int pos = j - c * CH;
+            for (int c2 = 0; c2 < nchunk; ++c2) {
+                if (c2 == c) continue;
+                pos += small ? count_below<8>(s_sorted + c2 * CH, key) : count_below<9>(s_sorted + c2 * CH, key);
+            }
             einst[pos] = s_e[(uint32_t)key];
         }
         return;
@@ -963,8 +970,9 @@ __device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_
 
 // The lists longer than kTsShort, which k_tile_sort_short listed in
 // long_list: a fixed grid of workgroups walks the list, one tile each at a
-// time.  Up to kTsLong: each wavefront sorts chunks of 512 (wave_sort_chunk)
-// into s_sorted (the last chunk padded with kNoKey), then every key's place
+// time.  Up to kTsLong: each wavefront sorts chunks (wave_sort_chunk) of 256
+// keys for lists up to 1024, else of 512, into s_sorted (the last chunk
+// padded with kNoKey), then every key's place
 // is its rank in its chunk plus, for each other chunk, the number of that
 // chunk's keys below it.  Beyond kTsLong: stable counting passes over the
 // four bytes of the depth bits in global memory.
