@@ -49,9 +49,12 @@ __device__ __forceinline__ int mask_select(uint64_t m, int if_set, int if_clear)
 // alpha of one (pixel, Gaussian) pair.  The forward and the backward kernels
 // both call this with the same staged values, so every alpha_min / T_min
 // decision of the backward reproduces the forward exactly.
-//   G = 2^min(q', 0) (the Gaussian factor), returns min(alpha_max, o G) as a
-// median of three (o G >= 0; one instruction with alpha_max in a scalar
-// register; a NaN product stays NaN and so fails every alpha test).
+//   G = 2^q' (the Gaussian factor), returns min(alpha_max, o G) as a median
+// of three (o G >= 0; one instruction with alpha_max in a scalar register; a
+// NaN product stays NaN and so fails every alpha test).  q' <= 0 for the
+// positive definite conic; its binary32 evaluation can land above 0 only by
+// its rounding error, where G then exceeds 1 by as little as it would fall
+// short of the true value below 0, so q' is not clamped.
 // qx, qy: the derivatives of q' along dx and dy, 2A'dx + B2'dy and
 // B2'dx + 2C'dy, formed from the intermediates of q' (the forward does not
 // read them, so they cost it nothing).
@@ -65,7 +68,6 @@ __device__ __forceinline__ float pair_alpha(const float4& g0, const float4& g1, 
     float q = fmaf(adx, dx, dy * v);
     qx = fmaf(2.0f, adx, g0.w * dy);
     qy = v + cdy;
-    q = fminf(q, 0.0f);
     G = __builtin_amdgcn_exp2f(q);
     const float a = g1.y * G;
     unclamped = a < amax;

@@ -200,6 +200,37 @@ struct Pow2<1> {
     static constexpr int value = 1;
 };
 
+// Geometry record values of one instance from its moments.  With h the
+// per-pixel factor dL/dalpha * alpha (zero where alpha is clamped or the
+// pixel does not contribute) and (u, v) a pixel centre from the tile origin
+// (x0, y0), the backward accumulates S = sum_p h {1, u, v, u^2, u v, v^2} in
+// slots 0-4 and 6.  With the staged g0 = (mx, my, A', B2'),
+// g1 = (C', o, ...), dx = u - mu, dy = v - mv (mu = mx - x0, mv = my - y0):
+//   sum h dx = Su - mu S1,  sum h dx^2 = Suu - 2 mu Su + mu^2 S1, ...
+// and the record holds -ln2 sum h dq'/ddx, -ln2 sum h dq'/ddy (mean),
+// -1/2 sum h dx^2, -sum h dx dy, -1/2 sum h dy^2 (conic), and
+// sum h / o = sum dL/dalpha * G (opacity, alpha = o G where unclamped).
+// The coordinates are bounded by the tile size: for a mean inside the tile
+// the expansion's terms exceed the per-pixel h dx^2 by at most about the
+// squared tile size (that many units in the last place of the sums, far
+// inside the gradient tolerance); for a mean outside, (u - mu)^2 is itself of
+// the order of the terms and nothing cancels.
+__device__ __forceinline__ void moments_to_geometry(const float4& g0, const float4& g1, float x0, float y0,
+                                                    float* r) {
+    const float s1 = r[0], su = r[1], sv = r[2], suu = r[3], suv = r[4], svv = r[6];
+    const float mu = g0.x - x0, mv = g0.y - y0;
+    const float sdx = fmaf(-mu, s1, su), sdy = fmaf(-mv, s1, sv);
+    const float sxx = fmaf(-mu, sdx, fmaf(-mu, su, suu));
+    const float sxy = fmaf(-mu, sdy, fmaf(-mv, su, suv));
+    const float syy = fmaf(-mv, sdy, fmaf(-mv, sv, svv));
+    r[0] = -kLn2 * fmaf(2.0f * g0.z, sdx, g0.w * sdy);
+    r[1] = -kLn2 * fmaf(g0.w, sdx, 2.0f * g1.x * sdy);
+    r[2] = -0.5f * sxx;
+    r[3] = -sxy;
+    r[4] = -0.5f * syy;
+    r[6] = s1 / g1.y;
+}
+
 template <int TS, int F, int B, bool PARAMS>
 __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, const float4* __restrict__ app, int n,
                                          const int32_t* __restrict__ inst, const int32_t* __restrict__ inst_gid,
@@ -248,7 +279,15 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 #pragma unroll
         for (int ch = 0; ch < 5 + F; ++ch) g[ch] = inside ? grad_out[ch * P + p] : 0.0f;
     }
-    float Rg = 0.0f;  // R of the Gaussian about to be visited
+    // R of the Gaussian about to be visited.  With parameter gradients the
+    // opacity channel (x = 1 for every Gaussian) is left out of g . x and R
+    // starts at -g_opacity instead: R + g_opacity is then the full R, and
+    // g . x - R is unchanged.
+    float Rg = PARAMS ? -g[0] : 0.0f;
+    // pixel centre relative to the tile origin: the coordinates of the
+    // moments that carry the geometry gradients with parameter gradients
+    const float lu = (float)(sbx + (lane & 7)) + 0.5f, lv = (float)(sby + (lane >> 3)) + 0.5f;
+    const float tile_x0 = (float)(tx * TS), tile_y0 = (float)(ty * TS);
     const float log2_amin = __log2f(c.alpha_min);
     const float amin = c.alpha_min, amax = c.alpha_max;
 
@@ -310,11 +349,13 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     // (bits 2, 0, 1, 3) and the sum of the linear channels over the 16 lanes
     // of a row group run as one ORD 1 butterfly over NC values per lane:
     // the two geometry values still open after bits 5 and 4, then the NL
-    // linear channels.  Value index -> record slot and scale of this lane:
+    // linear channels.  The six geometry values are the moments (see
+    // moments_to_geometry), accumulated in slots 0-4 and 6 and turned into
+    // the record's values when it is written.  Value index -> record slot of
+    // this lane:
     constexpr int NC = Pow2<2 + NL>::value;
     const int cs = Butterfly<NC, 1>::slot(lane);
     int cslot = -1;
-    float cscale = 1.0f;
     {
         const int b5 = (lane >> 5) & 1;
         int gi = -1;  // geometry value index
@@ -322,7 +363,6 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
         else if (cs == 1 && !b4) gi = 1 + 4 * b5;
         if (gi >= 0) {
             cslot = gi < 5 ? gi : 6;
-            cscale = gi < 2 ? -kLn2 : (gi == 2 || gi == 4 ? -0.5f : (gi == 3 ? -1.0f : 1.0f));
         } else if (cs >= 2 && cs < 2 + NL) {
             const int ch = 4 * (cs - 2) + q4;
             cslot = ch == 0 ? 5 : 6 + ch;
@@ -387,6 +427,10 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     const float* sa = reinterpret_cast<const float*>(s_app) + j * AV * 4;
 #pragma unroll
                     for (int m = 0; m < NL; ++m) xs[m] = sa[xidx[m]];
+                    // issue these loads at the top of the step (the g . x
+                    // below waits on them; left alone, the scheduler sinks
+                    // some past the exponential)
+                    __builtin_amdgcn_sched_barrier(0);
                 } else {
 #pragma unroll
                     for (int qq = 0; qq < AV; ++qq) {
@@ -401,15 +445,15 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 float dx, dy, G, qx, qy;
                 bool unc;
                 const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc, qx, qy);
-                // qx, qy (the derivatives of q' along dx and dy, up to the
-                // factors the record scales apply) are kept here by an empty
-                // statement (no instruction): sunk further down they would
-                // keep g0 and g1 alive, and g0 and g1 are dead from here --
-                // the next candidate's geometry is loaded into them (no
-                // register copies at the end of the step), unconditionally
-                // with a clamped index (a conditional load becomes a pointer
-                // select that leaves LDS addressing)
-                __asm__ volatile("" : "+v"(qx), "+v"(qy));
+                // Without parameter gradients qx, qy (the derivatives of q'
+                // along dx and dy, up to the factors the record scales apply)
+                // are kept here by an empty statement (no instruction): sunk
+                // further down they would keep g0 and g1 alive.  g0 and g1
+                // are dead from here -- the next candidate's geometry is
+                // loaded into them (no register copies at the end of the
+                // step), unconditionally with a clamped index (a conditional
+                // load becomes a pointer select that leaves LDS addressing)
+                if constexpr (!PARAMS) __asm__ volatile("" : "+v"(qx), "+v"(qy));
                 const int jp = jn >= 0 ? jn : j;
                 g0 = s_g0[jp];
                 g1 = s_g1[jp];
@@ -445,7 +489,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                         // partner's, so bit 4 is one swizzle and one add
                         pt[0] = swap_halves_add<32>(pt[0], pt[2]);
                         pt[1] = swap_halves_add<32>(pt[1], pt[3]);
-                        gx = (pt[0] + xor_lane<16>(pt[1])) + g[0];
+                        gx = pt[0] + xor_lane<16>(pt[1]);  // without the opacity channel (in Rg)
                     } else {
                         gx = fmaf(g[0], xs[0], fmaf(g[1], xs[1], fmaf(g[2], xs[2], fmaf(g[3], xs[AV * 4 - 1], g[4]))));
 #pragma unroll
@@ -457,13 +501,24 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     const float hm = (contrib && unc) ? dA : 0.0f;
                     const float h = hm * a;
                     float val[NBF];
-                    val[0] = h * qx;
-                    val[1] = h * qy;
-                    val[2] = h * dx * dx;
-                    val[3] = h * dx * dy;
-                    val[4] = h * dy * dy;
-                    if constexpr (PARAMS) val[5] = hm * G;
-                    else val[5] = g[3] * w;
+                    if constexpr (PARAMS) {
+                        // the moments h {1, u, v, u^2, u v, v^2} (u, v: the
+                        // pixel centre from the tile origin)
+                        const float hu = h * lu, hv = h * lv;
+                        val[0] = h;
+                        val[1] = hu;
+                        val[2] = hv;
+                        val[3] = hu * lu;
+                        val[4] = hu * lv;
+                        val[5] = hv * lv;
+                    } else {
+                        val[0] = h * qx;
+                        val[1] = h * qy;
+                        val[2] = h * dx * dx;
+                        val[3] = h * dx * dy;
+                        val[4] = h * dy * dy;
+                        val[5] = g[3] * w;
+                    }
                     if constexpr (PARAMS) {
                         float cv[NC];
                         geo6_bits54(val, cv[0], cv[1]);
@@ -476,7 +531,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 #pragma unroll
                         for (int m = 2 + NL; m < NC; ++m) cv[m] = 0.0f;
                         const float tot = Butterfly<NC, 1, 2 + NL>::reduce(cv, lane);
-                        if (cwriter) atomicAdd(&s_acc[j * AST + cslot], tot * cscale);
+                        if (cwriter) atomicAdd(&s_acc[j * AST + cslot], tot);
                     } else {
                         const float tot = geo6_reduce(val, lane);
                         if (writer) atomicAdd(&s_acc[j * AST + my_slot], tot * scale);
@@ -491,12 +546,12 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
         for (int k = tid; k < nb; k += NT) {
             float4* r4 = reinterpret_cast<float4*>(records + (size_t)inst[bstart + k] * RS);
             const float* a = s_acc + k * AST;
+            float r[RS];
 #pragma unroll
-            for (int q = 0; q < RS / 4; ++q) {
-                const int b = 4 * q;
-                r4[q] = make_float4(b < NREAL ? a[b] : 0.f, b + 1 < NREAL ? a[b + 1] : 0.f,
-                                    b + 2 < NREAL ? a[b + 2] : 0.f, b + 3 < NREAL ? a[b + 3] : 0.f);
-            }
+            for (int b = 0; b < RS; ++b) r[b] = b < NREAL ? a[b] : 0.0f;
+            if constexpr (PARAMS) moments_to_geometry(s_g0[k], s_g1[k], tile_x0, tile_y0, r);
+#pragma unroll
+            for (int q = 0; q < RS / 4; ++q) r4[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
         }
     }
 }
