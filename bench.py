@@ -254,6 +254,8 @@ def main():
     # ------------------------------------------- per-entry-point event times
     r = step.r
     names = ["project", "bin_sort", "render_fwd", "loss_grad", "render_bwd_records", "reduce_records", "project_bwd"]
+    if step.fuse_loss:
+        names.insert(4, "render_fwd_loss")
     if pose:
         names.append("pose_grad")
     evs = {k: [] for k in names}
@@ -270,6 +272,8 @@ def main():
         timed("bin_sort", r.bin_sort)
         timed("render_fwd", r.render_fwd)
         timed("loss_grad", lambda: r.loss_grad(rgb_t, dep_t, lab, W, w.weights))
+        if step.fuse_loss:
+            timed("render_fwd_loss", lambda: r.render_fwd_loss(rgb_t, dep_t, lab, W, w.weights))
         timed("render_bwd_records", lambda: r.render_bwd_records(g, r.grad_out, step.flags))
         timed("reduce_records", lambda: r.reduce_records(step.flags))
         if params:
@@ -333,7 +337,8 @@ def main():
                 "pixels_per_step": P, "instances": n_inst, "visible_pairs": n_vis,
                 "grad": ("params" if params else "") + ("+pose" if pose else ""), "mode": "batched hipGraph",
                 "tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
-                "lds_batch_bwd": cfg.lds_batch_bwd}
+                "lds_batch_bwd": cfg.lds_batch_bwd,
+                "loss": "in the forward kernel" if step.fuse_loss else "own kernel"}
     del step, r
     torch.cuda.empty_cache()
 
@@ -447,7 +452,8 @@ def secondary_bench(c, warmup, steps, no_cpu, no_perview, tune=True):
            "median_ms_per_step": round(med, 4), "value": round(mpix, 2), "unit": "Mpixel/s",
            "bytes_stream": int(strm), "hbm_frac_stream": round(strm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "launch": {"tile": cfg.tile, "lds_batch": cfg.lds_batch, "persistent": cfg.persistent,
-                      "lds_batch_bwd": cfg.lds_batch_bwd, "autotuned": bool(tune)}}
+                      "lds_batch_bwd": cfg.lds_batch_bwd, "autotuned": bool(tune),
+                      "loss": "in the forward kernel" if step.fuse_loss else "own kernel"}}
     del step
     torch.cuda.empty_cache()
     if not no_perview and len(w.views) > 1:

@@ -254,6 +254,28 @@ int gs_loss_grad(const float* out, int32_t n_feat, const float* rgb_target, cons
                  void* ws, size_t ws_bytes, gs_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * gs_render_fwd_loss -- gs_render_fwd and gs_loss_grad in one pass: the
+ * forward compositing of Eq. (4), (6), (7), (10) with the image-space loss
+ * of Sec. 3.3.4 / 3.4 evaluated in the same kernel while each pixel's
+ * rendered channels are still in registers, so the image is not read back.
+ * Arguments as for the two calls (out, T_final, last and grad_out are all
+ * written; loss[4] as for gs_loss_grad); grad_out holds the same values
+ * gs_loss_grad would write from this out, and loss the same terms up to
+ * the order of their FP64 sums (per tile here, per block of pixels there).
+ * ws: gs_render_fwd_loss_workspace bytes, 16-byte aligned (per-tile
+ * partial sums and the transposed decoder).  Supports n_feat <= 16 and
+ * n_classes <= 20 (the logits stay in registers); beyond that it returns
+ * GS_EUNSUPPORTED and the caller makes the two separate calls.
+ * --------------------------------------------------------------------------- */
+int gs_render_fwd_loss_workspace(const gs_view* views, int32_t n_views, int32_t tile, size_t* bytes);
+int gs_render_fwd_loss(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* inst,
+                       const int32_t* inst_gid, const int32_t* tile_ranges, const gs_view* views,
+                       const gs_view* views_dev, int32_t n_views, const gs_config* cfg, float* out, float* T_final,
+                       int32_t* last, int32_t* queue, const float* rgb_target, const float* depth_target,
+                       const int32_t* labels, const float* decoder, int32_t n_classes, const float* weights,
+                       float* grad_out, double* loss, void* ws, size_t ws_bytes, gs_stream stream);
+
+/* ---------------------------------------------------------------------------
  * gs_slam_loss -- the SLAM losses with their masks: the mapping colour term
  * of Sec. 3.3.4, Eq. (15) (L1 plus an SSIM term), the observed-region mask
  * of the tracking loss, Sec. 3.4, Eq. (21), and the unobserved-region mask

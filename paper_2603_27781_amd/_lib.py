@@ -22,7 +22,7 @@ GS_GRAD_PARAMS, GS_GRAD_POSE = 1, 2
 # symbols declared in include/sgs.h (checked by the ABI test)
 EXPORTS = [
     "gs_default_config", "gs_views_layout", "gs_views_check", "gs_app_stride", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
-    "gs_render_fwd", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
+    "gs_render_fwd", "gs_render_fwd_loss_workspace", "gs_render_fwd_loss", "gs_loss_grad_workspace", "gs_loss_grad", "gs_render_bwd_workspace", "gs_render_bwd",
     "gs_render_bwd_records", "gs_reduce_records", "gs_project_bwd", "gs_project_bwd_write",
     "gs_pose_grad_workspace",
     "gs_pose_grad", "gs_default_slam_loss_opts", "gs_slam_loss_workspace", "gs_slam_loss", "gs_expand_workspace",
@@ -31,6 +31,8 @@ EXPORTS = [
 ]
 GS_LOSS_OBS_MASK, GS_LOSS_BCE = 1, 2
 GS_NOALLOC_SCRATCH_BYTES = 8 << 20
+# gs_render_fwd_loss supports at most this many feature channels and classes
+GS_FUSED_MAX_FEAT, GS_FUSED_MAX_CLASSES = 16, 20
 
 
 class GsGaussians(ctypes.Structure):
@@ -104,6 +106,11 @@ def load() -> ctypes.CDLL:
                               c_void_p, c_void_p]
     L.gs_render_fwd.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, P(GsView),
                                 c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.gs_render_fwd_loss_workspace.argtypes = [P(GsView), c_int32, c_int32, P(c_size_t)]
+    L.gs_render_fwd_loss.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, P(GsView),
+                                     c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_int32, P(c_float), c_void_p,
+                                     c_void_p, c_void_p, c_size_t, c_void_p]
     L.gs_loss_grad_workspace.argtypes = [c_int64, P(c_size_t)]
     L.gs_loss_grad.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, P(c_float),
                                P(GsView), c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]

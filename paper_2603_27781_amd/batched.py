@@ -6,7 +6,9 @@ back-propagated together: one projection launch over all (view, Gaussian)
 pairs, one binning over all views (global tile ids carry the view), one
 forward and one backward compositing launch over every (view, tile) item
 (optionally persistent, pulling items from a device queue), the loss
-gradient kernel, and the projection backward summing the views' gradients
+gradient (in the forward kernel's epilogue where gs_render_fwd_loss
+supports the channel and class counts, else its own kernel), and the
+projection backward summing the views' gradients
 per Gaussian in registers.  The whole step is captured once in a HIP graph
 (torch.cuda.graph) and replayed; poses change between replays through
 Views.set_poses, parameters in place.
@@ -32,7 +34,8 @@ BENCH_CONFIG = {"tile": 16, "lds_batch": 256, "persistent": 0, "lds_batch_bwd": 
 class MappingStep:
     def __init__(self, g: Gaussians, views: Sequence, cfg: Config, rgb_t: torch.Tensor, depth_t: torch.Tensor,
                  labels: Optional[torch.Tensor], decoder: Optional[torch.Tensor], weights=(0.5, 1.0, 0.01),
-                 params: bool = True, pose: bool = False, capacity: Optional[int] = None):
+                 params: bool = True, pose: bool = False, capacity: Optional[int] = None,
+                 fuse_loss: bool = True):
         self.g = g
         self.cfg = cfg
         self.views = Views(views, cfg.tile)
@@ -42,6 +45,9 @@ class MappingStep:
         self.flags = (_lib.GS_GRAD_PARAMS if params else 0) | (_lib.GS_GRAD_POSE if pose else 0)
         self.grads = g.zeros_like() if params else None
         self.graph = None
+        self.fuse_loss = fuse_loss and self.r.fused_loss_supported(decoder)
+        if self.fuse_loss:
+            self.r.ensure_fused_ws()
 
     def ensure_capacity(self, slack: float = 1.25) -> int:
         return self.r.ensure_capacity(self.g, slack)
@@ -53,8 +59,11 @@ class MappingStep:
         r = self.r
         r.project(self.g)
         r.bin_sort()
-        r.render_fwd()
-        r.loss_grad(self.rgb_t, self.depth_t, self.labels, self.decoder, self.weights)
+        if self.fuse_loss:
+            r.render_fwd_loss(self.rgb_t, self.depth_t, self.labels, self.decoder, self.weights)
+        else:
+            r.render_fwd()
+            r.loss_grad(self.rgb_t, self.depth_t, self.labels, self.decoder, self.weights)
         r.render_bwd(self.g, r.grad_out, self.flags, self.grads, write=True)
         if self.flags & _lib.GS_GRAD_POSE:
             r.pose_grad(self.g)
@@ -91,7 +100,7 @@ class PerViewStep:
     """V plain single-view passes (no batching, no graph)."""
 
     def __init__(self, g: Gaussians, views: Sequence, cfg: Config, rgb_t, depth_t, labels, decoder,
-                 weights=(0.5, 1.0, 0.01), params: bool = True, pose: bool = False):
+                 weights=(0.5, 1.0, 0.01), params: bool = True, pose: bool = False, fuse_loss: bool = True):
         self.g = g
         self.steps = []
         off = 0
@@ -100,7 +109,7 @@ class PerViewStep:
             sl = slice(off, off + P)
             st = MappingStep(g, [v], cfg, rgb_t[:, sl].contiguous(), depth_t[sl].contiguous(),
                              labels[sl].contiguous() if labels is not None else None, decoder, weights,
-                             params=False, pose=pose)
+                             params=False, pose=pose, fuse_loss=fuse_loss)
             st.flags = (_lib.GS_GRAD_PARAMS if params else 0) | (_lib.GS_GRAD_POSE if pose else 0)
             self.steps.append(st)
             off += P
@@ -119,8 +128,11 @@ class PerViewStep:
             r = st.r
             r.project(self.g)
             r.bin_sort()
-            r.render_fwd()
-            r.loss_grad(st.rgb_t, st.depth_t, st.labels, st.decoder, st.weights)
+            if st.fuse_loss:
+                r.render_fwd_loss(st.rgb_t, st.depth_t, st.labels, st.decoder, st.weights)
+            else:
+                r.render_fwd()
+                r.loss_grad(st.rgb_t, st.depth_t, st.labels, st.decoder, st.weights)
             r.render_bwd(self.g, r.grad_out, st.flags, self.grads)
             if st.flags & _lib.GS_GRAD_POSE:
                 r.pose_grad(self.g)

@@ -14,6 +14,7 @@
 // More classes recompute z in the second pass.  The loss value is reduced
 // per block into a partial-sum array and then summed in a fixed order by
 // one block (no same-address atomics, deterministic).
+#include "fused_loss.h"
 #include "loss_common.h"
 
 namespace sgs {
@@ -143,6 +144,18 @@ __global__ void __launch_bounds__(kSumThreads) k_loss_final(const double* __rest
         }
         loss[3] = (r[0] + r[1]) + r[2];
     }
+}
+
+hipError_t launch_transpose_decoder(const float* W, int F, int K, float* Wt, hipStream_t s) {
+    if (F * K > 0) hipLaunchKernelGGL(k_transpose_decoder, dim3((unsigned)ceil_div(F * K, 256)), dim3(256), 0, s, W, F, K, Wt);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_sums(const double* partials, int n, double* stage, double* loss, hipStream_t s) {
+    const int nst = sum_stage_blocks(n);
+    hipLaunchKernelGGL(k_sum_stage, dim3((unsigned)nst), dim3(kSumThreads), 0, s, partials, n, 3, stage);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kSumThreads), 0, s, stage, nst, loss);
+    return hipGetLastError();
 }
 
 // workspace: per-block partials (3 doubles each), their first-stage sums,

@@ -202,29 +202,20 @@ struct Pow2<1> {
 
 // Geometry record values of one instance from its moments.  With h the
 // per-pixel factor dL/dalpha * alpha (zero where alpha is clamped or the
-// pixel does not contribute) and (u, v) a pixel centre from the tile origin
-// (x0, y0), the backward accumulates S = sum_p h {1, u, v, u^2, u v, v^2} in
-// slots 0-4 and 6.  With the staged g0 = (mx, my, A', B2'),
-// g1 = (C', o, ...), dx = u - mu, dy = v - mv (mu = mx - x0, mv = my - y0):
-//   sum h dx = Su - mu S1,  sum h dx^2 = Suu - 2 mu Su + mu^2 S1, ...
-// and the record holds -ln2 sum h dq'/ddx, -ln2 sum h dq'/ddy (mean),
-// -1/2 sum h dx^2, -sum h dx dy, -1/2 sum h dy^2 (conic), and
-// sum h / o = sum dL/dalpha * G (opacity, alpha = o G where unclamped).
-// The coordinates are bounded by the tile size: for a mean inside the tile
-// the expansion's terms exceed the per-pixel h dx^2 by at most about the
-// squared tile size (that many units in the last place of the sums, far
-// inside the gradient tolerance); for a mean outside, (u - mu)^2 is itself of
-// the order of the terms and nothing cancels.
-__device__ __forceinline__ void moments_to_geometry(const float4& g0, const float4& g1, float x0, float y0,
-                                                    float* r) {
-    const float s1 = r[0], su = r[1], sv = r[2], suu = r[3], suv = r[4], svv = r[6];
-    const float mu = g0.x - x0, mv = g0.y - y0;
-    const float sdx = fmaf(-mu, s1, su), sdy = fmaf(-mv, s1, sv);
-    const float sxx = fmaf(-mu, sdx, fmaf(-mu, su, suu));
-    const float sxy = fmaf(-mu, sdy, fmaf(-mv, su, suv));
-    const float syy = fmaf(-mv, sdy, fmaf(-mv, sv, svv));
-    r[0] = -kLn2 * fmaf(2.0f * g0.z, sdx, g0.w * sdy);
-    r[1] = -kLn2 * fmaf(g0.w, sdx, 2.0f * g1.x * sdy);
+// pixel does not contribute) and (dx, dy) a pixel centre from the projected
+// mean, the backward accumulates S = sum_p h {1, dx, dy, dx^2, dx dy, dy^2}
+// in slots 0-4 and 6; with the staged g0 = (mx, my, A', B2'),
+// g1 = (C', o, ...) the record holds
+//   -ln2 (2A' Sx + B2' Sy), -ln2 (B2' Sx + 2C' Sy)   (mean: -ln2 sum h dq'/ddx, ...)
+//   -Sxx / 2, -Sxy, -Syy / 2                          (conic)
+//   S1 / o = sum dL/dalpha G                           (opacity, alpha = o G where unclamped)
+// The derivatives of q' are linear in dx and dy, so their sums follow from
+// the first moments exactly; the step forms six products of h instead of
+// the derivatives and their products.
+__device__ __forceinline__ void moments_to_geometry(const float4& g0, const float4& g1, float* r) {
+    const float s1 = r[0], sx = r[1], sy = r[2], sxx = r[3], sxy = r[4], syy = r[6];
+    r[0] = -kLn2 * fmaf(2.0f * g0.z, sx, g0.w * sy);
+    r[1] = -kLn2 * fmaf(g0.w, sx, 2.0f * g1.x * sy);
     r[2] = -0.5f * sxx;
     r[3] = -sxy;
     r[4] = -0.5f * syy;
@@ -284,10 +275,6 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     // starts at -g_opacity instead: R + g_opacity is then the full R, and
     // g . x - R is unchanged.
     float Rg = PARAMS ? -g[0] : 0.0f;
-    // pixel centre relative to the tile origin: the coordinates of the
-    // moments that carry the geometry gradients with parameter gradients
-    const float lu = (float)(sbx + (lane & 7)) + 0.5f, lv = (float)(sby + (lane >> 3)) + 0.5f;
-    const float tile_x0 = (float)(tx * TS), tile_y0 = (float)(ty * TS);
     const float log2_amin = __log2f(c.alpha_min);
     const float amin = c.alpha_min, amax = c.alpha_max;
 
@@ -445,15 +432,17 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 float dx, dy, G, qx, qy;
                 bool unc;
                 const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc, qx, qy);
-                // Without parameter gradients qx, qy (the derivatives of q'
-                // along dx and dy, up to the factors the record scales apply)
-                // are kept here by an empty statement (no instruction): sunk
+                // The values the geometry sums need (dx, dy with parameter
+                // gradients; without, qx, qy: the derivatives of q' along dx
+                // and dy, up to the factors the record scales apply) are
+                // kept here by an empty statement (no instruction): sunk
                 // further down they would keep g0 and g1 alive.  g0 and g1
                 // are dead from here -- the next candidate's geometry is
                 // loaded into them (no register copies at the end of the
                 // step), unconditionally with a clamped index (a conditional
                 // load becomes a pointer select that leaves LDS addressing)
-                if constexpr (!PARAMS) __asm__ volatile("" : "+v"(qx), "+v"(qy));
+                if constexpr (PARAMS) __asm__ volatile("" : "+v"(dx), "+v"(dy));
+                else __asm__ volatile("" : "+v"(qx), "+v"(qy));
                 const int jp = jn >= 0 ? jn : j;
                 g0 = s_g0[jp];
                 g1 = s_g1[jp];
@@ -502,15 +491,14 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                     const float h = hm * a;
                     float val[NBF];
                     if constexpr (PARAMS) {
-                        // the moments h {1, u, v, u^2, u v, v^2} (u, v: the
-                        // pixel centre from the tile origin)
-                        const float hu = h * lu, hv = h * lv;
+                        // the moments h {1, dx, dy, dx^2, dx dy, dy^2}
+                        const float hx = h * dx, hy = h * dy;
                         val[0] = h;
-                        val[1] = hu;
-                        val[2] = hv;
-                        val[3] = hu * lu;
-                        val[4] = hu * lv;
-                        val[5] = hv * lv;
+                        val[1] = hx;
+                        val[2] = hy;
+                        val[3] = hx * dx;
+                        val[4] = hx * dy;
+                        val[5] = hy * dy;
                     } else {
                         val[0] = h * qx;
                         val[1] = h * qy;
@@ -549,7 +537,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             float r[RS];
 #pragma unroll
             for (int b = 0; b < RS; ++b) r[b] = b < NREAL ? a[b] : 0.0f;
-            if constexpr (PARAMS) moments_to_geometry(s_g0[k], s_g1[k], tile_x0, tile_y0, r);
+            if constexpr (PARAMS) moments_to_geometry(s_g0[k], s_g1[k], r);
 #pragma unroll
             for (int q = 0; q < RS / 4; ++q) r4[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
         }

@@ -7,6 +7,7 @@
 #include <mutex>
 
 #include "sgs_common.h"
+#include "fused_loss.h"
 #include "growth.h"
 #include "optim.h"
 
@@ -276,6 +277,47 @@ int gs_render_fwd(const float* rec, const float* app, int32_t n, int32_t n_feat,
     return hip_status(launch_render_fwd(rec, app, n, n_feat, inst, inst_gid, tile_ranges, views_dev, n_views,
                                         total_tiles, P, make_const(cfg), cfg->lds_batch, cfg->persistent, out,
                                         T_final, last, queue, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int gs_render_fwd_loss_workspace(const gs_view* views, int32_t n_views, int32_t tile, size_t* bytes) {
+    if (!bytes || !views || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+    if (tile != 8 && tile != 16 && tile != 32) return GS_EINVAL;
+    int64_t tl = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (views[v].width <= 0 || views[v].height <= 0) return GS_EINVAL;
+        tl += (int64_t)ceil_div(views[v].width, tile) * ceil_div(views[v].height, tile);
+    }
+    if (tl >= (1ll << 31)) return GS_EINVAL;
+    *bytes = fused_loss_workspace_bytes((int)tl);
+    return GS_OK;
+}
+
+int gs_render_fwd_loss(const float* rec, const float* app, int32_t n, int32_t n_feat, const int32_t* inst,
+                       const int32_t* inst_gid, const int32_t* tile_ranges, const gs_view* views,
+                       const gs_view* views_dev, int32_t n_views, const gs_config* cfg, float* out, float* T_final,
+                       int32_t* last, int32_t* queue, const float* rgb_target, const float* depth_target,
+                       const int32_t* labels, const float* decoder, int32_t n_classes, const float* weights,
+                       float* grad_out, double* loss, void* ws, size_t ws_bytes, gs_stream stream) {
+    int st = check_config(cfg);
+    if (st) return st;
+    int64_t P = 0;
+    int total_tiles = 0;
+    if ((st = check_views(views, views_dev, n_views, cfg->tile, &P, &total_tiles))) return st;
+    if (!feat_supported(n_feat)) return GS_EUNSUPPORTED;
+    if (n_feat > kFusedMaxFeat || n_classes > kFusedMaxClasses) return GS_EUNSUPPORTED;
+    if (n < 1 || !rec || !app || !inst || !inst_gid || !tile_ranges || !out || !T_final || !last) return GS_EINVAL;
+    if (cfg->persistent && !queue) return GS_EINVAL;
+    if (!aligned16(rec) || !aligned16(app)) return GS_EINVAL;
+    if (!rgb_target || !depth_target || !weights || !grad_out || !loss || !ws) return GS_EINVAL;
+    if (n_classes < 0) return GS_EINVAL;
+    if (n_classes > 0 && n_feat > 0 && (!labels || !decoder)) return GS_EINVAL;
+    if (ws_bytes < fused_loss_workspace_bytes(total_tiles)) return GS_ECAPACITY;
+    if ((reinterpret_cast<uintptr_t>(ws) & 15u) != 0) return GS_EINVAL;
+    return hip_status(launch_render_fwd_loss(rec, app, n, n_feat, inst, inst_gid, tile_ranges, views_dev, n_views,
+                                             total_tiles, P, make_const(cfg), cfg->lds_batch, cfg->persistent, out,
+                                             T_final, last, queue, rgb_target, depth_target, labels, decoder,
+                                             n_feat > 0 ? n_classes : 0, weights, grad_out, loss, ws,
+                                             reinterpret_cast<hipStream_t>(stream)));
 }
 
 int gs_loss_grad_workspace(int64_t total_pixels, size_t* bytes) {

@@ -269,6 +269,35 @@ class Rasterizer:
                                   _stream()), "gs_loss_grad")
         return self.grad_out
 
+    def fused_loss_supported(self, decoder=None) -> bool:
+        K = 0 if decoder is None else int(decoder.shape[1])
+        return self.F <= _lib.GS_FUSED_MAX_FEAT and K <= _lib.GS_FUSED_MAX_CLASSES
+
+    def ensure_fused_ws(self) -> None:
+        """Allocates the workspace of render_fwd_loss (before any graph capture)."""
+        if getattr(self, "fused_ws", None) is None:
+            b = ctypes.c_size_t(0)
+            check(self.L.gs_render_fwd_loss_workspace(self.views.host, self.views.n, self.cfg.tile, ctypes.byref(b)),
+                  "gs_render_fwd_loss_workspace")
+            self.fused_ws = torch.empty(b.value // 8 + 2, dtype=torch.float64, device=self.out.device)
+
+    def render_fwd_loss(self, rgb_t, depth_t, labels=None, decoder=None, weights=(0.5, 1.0, 0.0)) -> None:
+        """render_fwd and loss_grad in one pass (gs_render_fwd_loss): writes
+        self.out, T_final, last, self.grad_out and self.loss."""
+        L = self.L
+        self.ensure_fused_ws()
+        K = 0 if decoder is None else int(decoder.shape[1])
+        w = (ctypes.c_float * 3)(*[float(x) for x in weights])
+        check(L.gs_render_fwd_loss(self.rec.data_ptr(), self.app.data_ptr(), self.n, self.F, self.inst.data_ptr(),
+                                   self.inst_gid.data_ptr(), self.ranges.data_ptr(), self.views.host,
+                                   self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc), self.out.data_ptr(),
+                                   self.T_final.data_ptr(), self.last.data_ptr(), self.queue.data_ptr(),
+                                   rgb_t.data_ptr(), depth_t.data_ptr(),
+                                   labels.data_ptr() if labels is not None else None,
+                                   decoder.data_ptr() if decoder is not None else None, K, w,
+                                   self.grad_out.data_ptr(), self.loss.data_ptr(), self.fused_ws.data_ptr(),
+                                   self.fused_ws.numel() * 8, _stream()), "gs_render_fwd_loss")
+
     def slam_loss(self, rgb_t, depth_t, labels=None, decoder=None, opts=None,
                   out: Optional[torch.Tensor] = None, masks: bool = True, bias: Optional[torch.Tensor] = None,
                   decoder_grads: bool = False) -> torch.Tensor:

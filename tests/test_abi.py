@@ -188,3 +188,41 @@ def test_views_check_rejects_before_any_launch():
     assert L.gs_views_check(V, dummy, 2, 12, dummy, None) == _lib.GS_EINVAL
     V[1].tile_offset += 1
     assert L.gs_views_check(V, dummy, 2, 16, dummy, None) == _lib.GS_EINVAL
+
+
+def test_render_fwd_loss_workspace_and_refusals():
+    """gs_render_fwd_loss: the workspace query (per-tile partials, their
+    stage sums, the transposed decoder), and the host-side refusals made
+    before anything launches: more than 16 feature channels or 20 classes
+    (GS_EUNSUPPORTED: the caller makes the two separate calls), a short or
+    misaligned workspace, null targets (the dummy device pointers are never
+    dereferenced)."""
+    L = _lib.load()
+    V = (_lib.GsView * 2)()
+    for i, (w, h) in enumerate([(40, 30), (33, 17)]):
+        V[i].width, V[i].height, V[i].fx, V[i].fy = w, h, 50.0, 50.0
+    assert L.gs_views_layout(V, 2, 16, None, None) == 0
+    tiles = 3 * 2 + 3 * 2
+    b = ctypes.c_size_t()
+    assert L.gs_render_fwd_loss_workspace(V, 2, 16, ctypes.byref(b)) == 0
+    r256 = lambda x: (x + 255) // 256 * 256
+    assert b.value == r256(tiles * 3 * 8) + r256(1 * 3 * 8) + 16 * 20 * 4
+    assert L.gs_render_fwd_loss_workspace(V, 2, 12, ctypes.byref(b)) == _lib.GS_EINVAL
+    assert L.gs_render_fwd_loss_workspace(V, 0, 16, ctypes.byref(b)) == _lib.GS_EINVAL
+    assert L.gs_render_fwd_loss_workspace(V, 2, 16, None) == _lib.GS_EINVAL
+    L.gs_render_fwd_loss_workspace(V, 2, 16, ctypes.byref(b))
+    cfg = _lib.GsConfig()
+    L.gs_default_config(ctypes.byref(cfg))
+    d = 1 << 20
+    w = (ctypes.c_float * 3)(0.5, 1.0, 0.01)
+
+    def call(F=16, K=20, ws=d, ws_bytes=b.value, rgb=d):
+        return L.gs_render_fwd_loss(d, d, 100, F, d, d, d, V, d, 2, ctypes.byref(cfg), d, d, d, d, rgb, d, d, d, K,
+                                    w, d, d, ws, ws_bytes, None)
+
+    assert call(F=32, K=20) == _lib.GS_EUNSUPPORTED
+    assert call(F=16, K=21) == _lib.GS_EUNSUPPORTED
+    assert call(F=12) == _lib.GS_EUNSUPPORTED
+    assert call(ws_bytes=b.value - 1) == _lib.GS_ECAPACITY
+    assert call(ws=d + 8) == _lib.GS_EINVAL
+    assert call(rgb=None) == _lib.GS_EINVAL

@@ -108,3 +108,72 @@ def test_per_view_step_equals_batched_step(name):
         assert rel_err(t.cpu().numpy(), a["grads"][nm].astype(np.float64)) <= 1e-5, nm
     for vi, st in enumerate(pv.steps):
         assert rel_err(st.r.twist.cpu().numpy()[0], a["twist"][vi].astype(np.float64)) <= 1e-5, vi
+
+
+@pytest.mark.parametrize("name,persistent,tile,weights", [
+    ("tiny3views-F16", 0, 16, WEIGHTS), ("tiny3views-F16", 1, 16, WEIGHTS), ("40views-F8", 0, 8, WEIGHTS),
+    ("cfg2-160x120-20k-F16", 0, 32, WEIGHTS), ("empty-view-F8", 1, 16, WEIGHTS), ("tiny-F0", 0, 16, WEIGHTS),
+    ("tiny3views-F16", 0, 16, (0.5, 1.0, 0.0))])
+def test_fused_forward_loss_equals_separate_calls(name, persistent, tile, weights):
+    """gs_render_fwd_loss (the loss in the forward kernel's epilogue, what the
+    batched step runs) writes what gs_render_fwd followed by gs_loss_grad
+    writes: the render, T_final and last bit for bit, the loss gradient bit
+    for bit (the same per-pixel arithmetic on the same binary32 values), and
+    the loss terms up to the grouping of their FP64 sums (per tile against
+    per block of pixels).  Paper: Sec. 3.2.1-3.2.2 Eq. (4)-(8), Sec. 3.3.4."""
+    from paper_2603_27781_amd import batched, raster
+    scene, views = CASES[name]()
+    F = scene.n_feat
+    K = 20 if F else 0
+    rgb, dep, lab, W = _targets(views, F, K, 29)
+    cfg = raster.Config(**dict(batched.BENCH_CONFIG, tile=tile, persistent=persistent))
+    g = raster.Gaussians.from_numpy(scene)
+    step = batched.MappingStep(g, views, cfg, _dev(rgb), _dev(dep), _dev(lab), _dev(W), weights, params=True)
+    assert step.fuse_loss
+    step.ensure_capacity(slack=1.5)
+    r = step.r
+    _log(name, "tile", tile, "persistent", persistent, "weights", weights)
+    r.project(g)
+    r.bin_sort()
+    args = (step.rgb_t, step.depth_t, step.labels, step.decoder, weights)
+    r.out.fill_(float("nan"))
+    r.grad_out.fill_(float("nan"))
+    r.render_fwd_loss(*args)
+    torch.cuda.synchronize()
+    fused = {k: t.cpu().numpy().copy() for k, t in
+             (("out", r.out), ("T", r.T_final), ("last", r.last), ("grad_out", r.grad_out), ("loss", r.loss))}
+    r.out.fill_(float("nan"))
+    r.grad_out.fill_(float("nan"))
+    r.render_fwd()
+    r.loss_grad(*args)
+    torch.cuda.synchronize()
+    sep = {k: t.cpu().numpy().copy() for k, t in
+           (("out", r.out), ("T", r.T_final), ("last", r.last), ("grad_out", r.grad_out), ("loss", r.loss))}
+    for k in ("out", "T", "last", "grad_out"):
+        assert np.array_equal(fused[k], sep[k]), k
+    assert np.all(np.isfinite(fused["grad_out"]))
+    np.testing.assert_allclose(fused["loss"], sep["loss"], rtol=1e-12, atol=1e-300)
+    if weights[2] == 0.0 or K == 0:
+        assert fused["loss"][2] == 0.0
+
+
+def test_mapping_step_falls_back_beyond_the_fused_class_count():
+    """With more classes than the fused forward keeps in registers the step
+    makes the two separate calls, and its replay still matches the eager run
+    and the oracle."""
+    from paper_2603_27781_amd import batched, raster
+    scene, views = CASES["tiny3views-F16"]()
+    rgb, dep, lab, W = _targets(views, scene.n_feat, 21, 31)
+    cfg = raster.Config(**batched.BENCH_CONFIG)
+    g = raster.Gaussians.from_numpy(scene)
+    step = batched.MappingStep(g, views, cfg, _dev(rgb), _dev(dep), _dev(lab), _dev(W), WEIGHTS, params=True,
+                               pose=True)
+    assert not step.fuse_loss
+    step.ensure_capacity(slack=1.5)
+    step.capture()
+    step.replay()
+    a = step_snapshot(step)
+    step.run()
+    assert_same_step(a, step_snapshot(step))
+    step_oracle_parity(a, step.r, scene, views, cfg, rgb, dep, lab, W, WEIGHTS, flags=3,
+                       gpu_backward=gpu_backward_of(step))
