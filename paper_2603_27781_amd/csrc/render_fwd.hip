@@ -32,6 +32,15 @@
 
 namespace sgs {
 
+// A wavefront-uniform value copied into a vector register once (one
+// v_mov), so that its uses as an LDS address and as a select operand take
+// that register instead of a fresh copy each.
+__device__ __forceinline__ int to_vgpr(int s) {
+    int v;
+    __asm__("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
 template <int TS, int F, int B, int LK>
 __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, const float4* __restrict__ app, int n,
                                          const int32_t* __restrict__ inst, const int32_t* __restrict__ inst_gid,
@@ -117,18 +126,27 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                 cand[q] = __builtin_amdgcn_ballot_w64(ok);
             }
             bool wdone = false;
+            // byte offset, within the staged arrays (16 bytes per
+            // Gaussian in each), of the pixel's last contributor in this
+            // batch, or -1
+            int lastoff = -1;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 uint64_t m = cand[q];
                 if (m == 0 || wdone) continue;
                 int j = 64 * q + __builtin_ctzll(m);
                 float4 g0 = s_g0[j], g1 = s_g1[j];
+                // the candidate's byte offset in a vector register: the
+                // next candidate's, formed for its geometry prefetch, serves
+                // as the current one's on the following step
+                int joff = to_vgpr(16 * j);
                 for (;;) {
                     m &= m - 1;
                     const int jn = m ? 64 * q + __builtin_ctzll(m) : -1;
                     float4 av[AV];
 #pragma unroll
-                    for (int qq = 0; qq < AV; ++qq) av[qq] = s_app[qq * B + j];
+                    for (int qq = 0; qq < AV; ++qq)
+                        av[qq] = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_app + qq * B) + joff);
                     float dx, dy, G, qx, qy;
                     bool unc;
                     const float a = pair_alpha(g0, g1, px, py, amax, dx, dy, G, unc, qx, qy);
@@ -137,9 +155,9 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     // end of the step), unconditionally with a clamped index
                     // (a conditional load becomes a pointer select that
                     // leaves LDS addressing)
-                    const int jp = jn >= 0 ? jn : j;
-                    g0 = s_g0[jp];
-                    g1 = s_g1[jp];
+                    const int jpoff = to_vgpr(16 * (jn >= 0 ? jn : j));
+                    g0 = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_g0) + jpoff);
+                    g1 = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_g1) + jpoff);
                     // issue those loads here, half a step ahead of their use
                     // (left alone, the scheduler sinks them to the end of the
                     // step, next to their use)
@@ -161,7 +179,7 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
 #pragma unroll
                         for (int f = 0; f < F; ++f) acc[4 + f] = fmaf(w, ap[3 + f], acc[4 + f]);
                         T = mask_select(use, Tn, T);
-                        lastj = mask_select(use, b0 - rg.x + j + 1, lastj);
+                        lastoff = mask_select(use, joff, lastoff);
                     }
                     done_m |= ok & low;
                     if (done_m == ~0ull) {
@@ -170,8 +188,10 @@ __device__ __forceinline__ void fwd_tile(int t, const float4* __restrict__ rec, 
                     }
                     if (jn < 0) break;
                     j = jn;
+                    joff = jpoff;
                 }
             }
+            if (lastoff >= 0) lastj = b0 - rg.x + 1 + (lastoff >> 4);
         }
     }
     if (inside) {
