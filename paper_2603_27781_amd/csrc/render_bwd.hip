@@ -178,17 +178,21 @@ __device__ __forceinline__ float geo6_reduce(const float (&v)[6], int lane) {
     return t;
 }
 
-// The weights w of the four lanes that share this lane's bits 0-3.  W[x] is
-// w of the lane whose bits 4-5 are t = x ^ b4 (b4 = this lane's bit 4): one
-// permlane32 swap gives the lanes l & ~32 and l | 32, and a ds_swizzle (xor
-// 16, no VALU work) each of their bit-4 partners.
+// The weights w of the four lanes that share this lane's bits 0-3.  W[t] is
+// w of the lane whose bits 4-5 are t: a permlane32 swap of w with itself
+// gives the lanes l & ~32 and l | 32, a permlane16 swap of each of those
+// with itself their bit-4 pairs.  Register swaps only: the LDS crossbar
+// (ds_swizzle) would spare the three vector instructions, but the backward
+// is held by LDS issue as much as by vector issue.
 __device__ __forceinline__ void quad_row_weights(float w, float (&W)[4]) {
     const unsigned u = __float_as_uint(w);
     const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);  // w(l & ~32), w(l | 32)
-    W[0] = __uint_as_float(h[0]);
-    W[1] = xor_lane<16>(__uint_as_float(h[0]));
-    W[2] = __uint_as_float(h[1]);
-    W[3] = xor_lane<16>(__uint_as_float(h[1]));
+    const auto p0 = __builtin_amdgcn_permlane16_swap(h[0], h[0], false, false);
+    const auto p1 = __builtin_amdgcn_permlane16_swap(h[1], h[1], false, false);
+    W[0] = __uint_as_float(p0[0]);
+    W[1] = __uint_as_float(p0[1]);
+    W[2] = __uint_as_float(p1[0]);
+    W[3] = __uint_as_float(p1[1]);
 }
 
 template <int N>
@@ -311,16 +315,16 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     // Linear channels c (0 depth, 1-3 colour, 4+ feature): their gradient is
     // sum_p g_c(p) w(p) with g constant over the tile.  A lane owns the
     // channels c = 4 m + q (q = lane bits 4-5) and keeps, for them, g of the
-    // four lanes sharing its bits 0-3 (in the order of quad_row_weights);
-    // per Gaussian it takes those lanes' weights (one permlane swap, two
-    // swizzles), forms the four-lane sums with FMAs and finishes over the 16
-    // lanes of its row group with the ORD 1 butterfly.
+    // four lanes sharing its bits 0-3 (index t = the lane's bits 4-5, the
+    // order of quad_row_weights); per Gaussian it takes those lanes' weights
+    // (three permlane swaps), forms the four-lane sums with FMAs and finishes
+    // over the 16 lanes of its row group with the ORD 1 butterfly.
     const int q4 = (lane >> 4) & 3, b4 = q4 & 1;
     float gq[NL > 0 ? NL : 1][4];
     if constexpr (PARAMS) {
 #pragma unroll
         for (int t4 = 0; t4 < 4; ++t4) {
-            const int lp = (lane & 15) | ((t4 ^ b4) << 4);  // the order of quad_row_weights
+            const int lp = (lane & 15) | (t4 << 4);  // the order of quad_row_weights
             const int xx = tx * TS + sbx + (lp & 7), yy = ty * TS + sby + (lp >> 3);
             const bool in = xx < vw.width && yy < vw.height;
             const int64_t pp = vw.pixel_offset + (int64_t)yy * vw.width + xx;
@@ -473,12 +477,12 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                             for (int m = 1; m < NL; ++m) acc = fmaf(gq[m][t4], xs[m], acc);
                             pt[t4] = acc;
                         }
-                        // pt[x] is for the pixel t = x ^ b4: after bit 5, pt[0]
-                        // is this lane's own pixel and pt[1] its bit-4
-                        // partner's, so bit 4 is one swizzle and one add
-                        pt[0] = swap_halves_add<32>(pt[0], pt[2]);
-                        pt[1] = swap_halves_add<32>(pt[1], pt[3]);
-                        gx = pt[0] + xor_lane<16>(pt[1]);  // without the opacity channel (in Rg)
+                        // pt[t] is for the pixel of the lane with bits 4-5 = t:
+                        // bit 5 pairs pt[0] with pt[2] (bit-4 clear) and pt[1]
+                        // with pt[3], bit 4 the two results; the opacity
+                        // channel is not in gx (it is in Rg)
+                        gx = swap_halves_add<16>(swap_halves_add<32>(pt[0], pt[2]),
+                                                 swap_halves_add<32>(pt[1], pt[3]));
                     } else {
                         gx = fmaf(g[0], xs[0], fmaf(g[1], xs[1], fmaf(g[2], xs[2], fmaf(g[3], xs[AV * 4 - 1], g[4]))));
 #pragma unroll
