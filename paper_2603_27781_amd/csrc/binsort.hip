@@ -33,6 +33,51 @@ namespace sgs {
 
 namespace {
 
+// Value of v held by lane (lane ^ J), for wavefront sums and the
+// compare-exchanges of the bitonic network.  No LDS round trip where the hardware has a register
+// path: J = 1, 2 are DPP quad permutations, J = 8 a DPP row rotation (within
+// a row of 16 lanes that is lane ^ 8), J = 16, 32 permlane swaps of v with
+// itself (which give the values of the lanes with the bit clear and set);
+// J = 4 goes through the LDS crossbar (ds_swizzle, no address operand).
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor_u32(uint32_t v, int lane) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);  // row_ror:8
+    } else if constexpr (J == 4) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (4 << 10) | 0x1F);  // xor_mask 4
+    } else if constexpr (J == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);  // v(l & ~16), v(l | 16)
+        return (lane & 16) ? r[0] : r[1];
+    } else {
+        static_assert(J == 32, "lane_xor_u32: J is a power of two up to 32");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);  // v(l & ~32), v(l | 32)
+        return (lane & 32) ? r[0] : r[1];
+    }
+}
+
+// Value of v in lane l (l wavefront-uniform), read into scalar registers.
+__device__ __forceinline__ int64_t read_lane_i64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Sum of x over the 64 lanes, in every lane (integer: the order does not
+// matter), with one LDS crossbar step (J = 4) instead of six shuffles.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x, int lane) {
+    x += lane_xor_u32<1>(x, lane);
+    x += lane_xor_u32<2>(x, lane);
+    x += lane_xor_u32<4>(x, lane);
+    x += lane_xor_u32<8>(x, lane);
+    x += lane_xor_u32<16>(x, lane);
+    x += lane_xor_u32<32>(x, lane);
+    return x;
+}
+
 // Radix passes run on a fixed grid of at most RS_MAXBLK blocks; the device
 // side count is split into contiguous chunks (multiples of RS_THREADS), one
 // per block, so the digit histograms stay small whatever the capacity and
@@ -79,8 +124,7 @@ __device__ __forceinline__ uint32_t block_sum_before(const uint32_t* __restrict_
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     uint32_t x = 0;
     for (int i = tid; i < m; i += NT) x += a[i];
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    x = wave_sum_u32(x, lane);
     if (lane == 0) s_tmp[wave] = x;
     __syncthreads();
     uint32_t t = 0;
@@ -160,8 +204,7 @@ __device__ uint32_t lb_lookback(const uint64_t* status, int tile, LbGiveUp gu) {
         const uint64_t inc = __ballot((s >> 62) == 2);
         uint32_t v = (uint32_t)s;
         if (inc != 0 && lane > __builtin_ctzll(inc)) v = 0;  // stop at the nearest inclusive prefix
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+        v = wave_sum_u32(v, lane);
         prefix += v;
         if (inc != 0) return prefix;
     }
@@ -518,7 +561,7 @@ __global__ void __launch_bounds__(CV_THREADS) k_count_visible(const int32_t* __r
         const int64_t i = base + k * CV_THREADS + tid;
         c += (i < vn && touched[i] > 0) ? 1u : 0u;
     }
-    for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
+    c = wave_sum_u32(c, lane);
     if (lane == 0) s_w[wave] = c;
     __syncthreads();
     if (tid == 0) {
@@ -604,10 +647,10 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
                                         (uint32_t)ceil_div(views[v].width, tile));
         s_gid[wave][lane] = (int32_t)gid;
     }
-    const int64_t o_w = __shfl(o_i, 0, kWave);  // lane 0 is valid
+    const int64_t o_w = read_lane_i64(o_i, 0);  // lane 0 is valid
     s_start[wave][lane] = (uint32_t)(o_i - o_w);
     const int nvalid = (int)__popcll(__ballot(valid));
-    const int64_t total = __shfl(end_i, nvalid - 1, kWave) - o_w;
+    const int64_t total = read_lane_i64(end_i, nvalid - 1) - o_w;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -763,29 +806,34 @@ constexpr int TSS_THREADS = kWave;  // short lists: one wavefront per tile
 constexpr int TSL_THREADS = 256;    // long lists: one workgroup per tile
 constexpr uint64_t kNoKey = ~0ull;  // padding, above every real key
 
-// Lane-crossing exchange of a 64-bit key.
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, kWave);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
+template <int J>
+__device__ __forceinline__ uint64_t lane_xor_u64(uint64_t v, int lane) {
+    const uint32_t lo = lane_xor_u32<J>((uint32_t)v, lane);
+    const uint32_t hi = lane_xor_u32<J>((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
 }
 
 // Bitonic sort of one key per lane: afterwards lane l holds the l-th
-// smallest of the wavefront's 64 keys.  In each compare-exchange step the
-// lane with the bit clear keeps the smaller key inside an ascending block
-// (and the larger inside a descending one).
-__device__ __forceinline__ uint64_t wave_bitonic_u64(uint64_t x, int lane) {
-#pragma unroll
-    for (int size = 2; size <= kWave; size <<= 1) {
-#pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) {
-            const uint64_t y = shfl_xor_u64(x, j);
-            const bool keep_min = ((lane & j) == 0) == ((lane & size) == 0);
-            x = keep_min ? (y < x ? y : x) : (y > x ? y : x);
-        }
-    }
+// smallest of the wavefront's 64 keys.  Blocks of SIZE = 2, 4, ..., 64, each
+// merged by compare-exchanges at distances J = SIZE/2, ..., 1; in each, the
+// lane with bit J clear keeps the smaller key inside an ascending block (bit
+// SIZE clear) and the larger inside a descending one.
+template <int SIZE, int J>
+__device__ __forceinline__ uint64_t bitonic_merge(uint64_t x, int lane) {
+    const uint64_t y = lane_xor_u64<J>(x, lane);
+    const bool keep_min = ((lane & J) == 0) == ((lane & SIZE) == 0);
+    x = keep_min ? (y < x ? y : x) : (y > x ? y : x);
+    if constexpr (J > 1) x = bitonic_merge<SIZE, J / 2>(x, lane);
     return x;
 }
+
+template <int SIZE>
+__device__ __forceinline__ uint64_t bitonic_sort(uint64_t x, int lane) {
+    if constexpr (SIZE > 2) x = bitonic_sort<SIZE / 2>(x, lane);
+    return bitonic_merge<SIZE, SIZE / 2>(x, lane);
+}
+
+__device__ __forceinline__ uint64_t wave_bitonic_u64(uint64_t x, int lane) { return bitonic_sort<kWave>(x, lane); }
 
 // Number of keys of the sorted array a[0 .. 2^LOG) below `key`
 // (branch-free binary search; a is padded with kNoKey).
