@@ -195,6 +195,21 @@ __device__ __forceinline__ void quad_row_weights(float w, float (&W)[4]) {
     W[3] = __uint_as_float(p1[1]);
 }
 
+// Staged appearance records of the backward.  With parameter gradients a
+// lane reads only its channels c = 4 m + q (q = lane bits 4-5); with more
+// than five per lane (32 feature channels) each quarter q is staged
+// contiguously, QS floats 16-byte aligned, so a step reads its NL values with
+// ceil(NL / 4) wide loads instead of about NL / 2 paired ones.  Otherwise the
+// record is staged as the projection wrote it.
+template <int F, bool PARAMS>
+struct BwdApp {
+    static constexpr int AV = AppRec<F>::vec;
+    static constexpr int NL = PARAMS ? (4 + F) / 4 : 0;
+    static constexpr bool qmajor = PARAMS && NL > 5;
+    static constexpr int QS = (NL + 3) / 4 * 4;   // floats per quarter when quarter-major
+    static constexpr int vec = qmajor ? QS : AV;  // float4 per staged record
+};
+
 template <int N>
 struct Pow2 {
     static constexpr int value = N <= 1 ? 1 : 2 * Pow2<(N + 1) / 2>::value;
@@ -244,6 +259,7 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
     constexpr int RS = (NREAL + 3) / 4 * 4;  // record stride (floats), float4-aligned
     constexpr int AST = NREAL + 1;           // accumulator stride (odd: spreads LDS banks)
     constexpr int NQ = B / 64;               // 64-bit candidate masks per batch
+    using BA = BwdApp<F, PARAMS>;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     constexpr int WPR = TS / 8;
     const int sbx = (wave % WPR) * 8, sby = (wave / WPR) * 8;
@@ -379,10 +395,32 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
             stage_geometry(rec, vbase + gid, a0, a1);
             s_g0[k] = a0;
             s_g1[k] = a1;
+            if constexpr (BA::qmajor) {
+                // quarter q holds channels q, 4 + q, 8 + q, ... (channel 0 is
+                // the depth, channel c >= 1 the record's float c - 1)
+                float4 in[AV];
 #pragma unroll
-            for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
-            // the record's last float is padding (3 + F is 3 mod 4): depth goes there
-            reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
+                for (int q = 0; q < AV; ++q) in[q] = app[(size_t)gid * AV + q];
+                const float* f = reinterpret_cast<const float*>(in);
+#pragma unroll
+                for (int qd = 0; qd < 4; ++qd) {
+#pragma unroll
+                    for (int v4 = 0; v4 < BA::QS / 4; ++v4) {
+                        float e[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int m = 4 * v4 + u, ch = 4 * m + qd;
+                            e[u] = m < NL ? (ch == 0 ? a1.z : f[ch - 1]) : 0.0f;
+                        }
+                        s_app[k * BA::vec + qd * (BA::QS / 4) + v4] = make_float4(e[0], e[1], e[2], e[3]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < AV; ++q) s_app[k * AV + q] = app[(size_t)gid * AV + q];
+                // the record's last float is padding (3 + F is 3 mod 4): depth goes there
+                reinterpret_cast<float*>(s_app)[(k + 1) * AV * 4 - 1] = a1.z;
+            }
         }
         for (int k = tid; k < nb * AST; k += NT) s_acc[k] = 0.0f;
         __syncthreads();
@@ -414,7 +452,20 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
                 // appearance of Gaussian j: with parameter gradients only this
                 // lane's channels, else the whole record
                 float xs[PARAMS ? (NL > 0 ? NL : 1) : AV * 4];
-                if constexpr (PARAMS) {
+                if constexpr (BA::qmajor) {
+                    const float4* sq = s_app + j * BA::vec + q4 * (BA::QS / 4);
+#pragma unroll
+                    for (int v4 = 0; v4 < NL / 4; ++v4) {
+                        const float4 t = sq[v4];
+                        xs[4 * v4] = t.x;
+                        xs[4 * v4 + 1] = t.y;
+                        xs[4 * v4 + 2] = t.z;
+                        xs[4 * v4 + 3] = t.w;
+                    }
+#pragma unroll
+                    for (int m = NL / 4 * 4; m < NL; ++m) xs[m] = reinterpret_cast<const float*>(sq)[m];
+                    __builtin_amdgcn_sched_barrier(0);
+                } else if constexpr (PARAMS) {
                     const float* sa = reinterpret_cast<const float*>(s_app) + j * AV * 4;
 #pragma unroll
                     for (int m = 0; m < NL; ++m) xs[m] = sa[xidx[m]];
@@ -568,7 +619,7 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <
     constexpr int NREAL = PARAMS ? 10 + F : 6;
     __shared__ float4 s_g0[B];
     __shared__ float4 s_g1[B];
-    __shared__ float4 s_app[B * AV];
+    __shared__ float4 s_app[B * BwdApp<F, PARAMS>::vec];
     __shared__ float s_acc[B * (NREAL + 1)];
     __shared__ int s_tile;
     __shared__ int s_max;
