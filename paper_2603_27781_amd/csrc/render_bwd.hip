@@ -603,9 +603,14 @@ __device__ __forceinline__ void bwd_tile(int t, const float4* __restrict__ rec, 
 // every Gaussian), so the register budget is capped at five wavefronts per
 // SIMD with up to 16 feature channels and at four with 32 (with 64
 // Gaussians per LDS batch, which keeps the LDS from capping it at three):
-// the values fit without spills.
+// the values fit without spills.  Launch shapes whose LDS batch caps
+// residency below that anyway (tile 8, larger batches) get no cap.
+template <int TS, int F, int B>
+constexpr int bwd_waves_target() {
+    return TS < 16 ? 1 : (F <= 16 ? (B <= 128 ? 5 : 1) : (B <= 64 ? 4 : 1));
+}
 template <int TS, int F, int B, bool PARAMS>
-__global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <= 16 ? 5 : 4, 8))) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
+__global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(bwd_waves_target<TS, F, B>(), 8))) k_render_bwd(const float4* __restrict__ rec, const float4* __restrict__ app,
                                                        int n, const int32_t* __restrict__ inst,
                                                        const int32_t* __restrict__ inst_gid,
                                                        const int2* __restrict__ ranges,
@@ -615,7 +620,6 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(F <
                                                        const int32_t* __restrict__ last,
                                                        const float* __restrict__ grad_out,
                                                        float* __restrict__ records, int32_t* queue, int persistent) {
-    constexpr int AV = AppRec<F>::vec;
     constexpr int NREAL = PARAMS ? 10 + F : 6;
     __shared__ float4 s_g0[B];
     __shared__ float4 s_g1[B];
