@@ -651,14 +651,26 @@ __global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(bwd
 // than VP the lanes take views vl, vl + VP, ... in rounds.  Few
 // pairs are visible and their record counts vary widely, so a wavefront
 // flattens the records of its pairs (an exclusive scan of the counts) and
-// loads them 64 at a time, one record per lane (consecutive records of a
+// loads them STG at a time, one record per lane (consecutive records of a
 // pair are adjacent in memory), into LDS; each owner lane then adds its own
 // records from LDS in emission order.  grad_geo[V][n][8] <- (dmx, dmy, dA,
 // dB, dC, dd, 0, 0) for visible pairs (others are not written); the
 // appearance part is summed over the Gaussian's lanes by a fixed xor tree
 // and grad_app[n][4+F] written by its first lane (fixed order).
+//
+// Residency: the staged records take STG x 4 x RS bytes of LDS per
+// wavefront.  With 32 feature channels (176-byte records) a full wavefront
+// of them (45 KB per workgroup) and the 130 registers the kernel would take
+// both stop at three wavefronts per SIMD; staging 48 at a time (37 KB) and
+// capping the registers at 128 allow four.
 template <int F, bool PARAMS>
-__global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict__ records,
+struct ReduceShape {
+    static constexpr int STG = PARAMS && F > 16 ? 48 : kWave;  // records staged per pass
+    static constexpr int waves = PARAMS && F > 16 ? 4 : 1;     // occupancy target (1: none)
+};
+template <int F, bool PARAMS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ReduceShape<F, PARAMS>::waves, 8)))
+k_reduce_records(const float* __restrict__ records,
                                                         const int32_t* __restrict__ pair_first,
                                                         const int32_t* __restrict__ touched, int n, int n_views,
                                                         int vp_log2, int64_t capacity, float* __restrict__ grad_geo,
@@ -666,7 +678,8 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
     constexpr int NREAL = PARAMS ? 10 + F : 6;
     constexpr int RS = (NREAL + 3) / 4 * 4;
     constexpr int NA = PARAMS ? 4 + F : 1;
-    __shared__ float4 s_rec[256 / kWave][kWave][RS / 4];
+    constexpr int STG = ReduceShape<F, PARAMS>::STG;
+    __shared__ float4 s_rec[256 / kWave][STG][RS / 4];
     __shared__ int s_start[256 / kWave][kWave];
     __shared__ int s_first[256 / kWave][kWave];
     __shared__ int s_mark[256 / kWave][kWave];
@@ -705,7 +718,7 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
         // tiles adds many partials of both signs (float only at the end)
         double geo[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int carry = -1;  // owner of the last record before the current 64
-        for (int base = 0; base < total; base += kWave) {
+        for (int base = 0; base < total; base += STG) {
             // owner of record base + lane: the last lane with records whose
             // start is at or before it -- each such lane marks its start's
             // slot (starts of lanes with records are distinct) and a
@@ -714,14 +727,16 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (cnt > 0 && start >= base && start < base + kWave) s_mark[wave][start - base] = lane;
+            if (cnt > 0 && start >= base && start < base + STG) s_mark[wave][start - base] = lane;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int lo = max(wave_max_scan(s_mark[wave][lane]), carry);
             carry = __builtin_amdgcn_readlane(lo, kWave - 1);
+            // (lanes from STG on mark nothing, so the scan's last lane holds
+            // the owner of record base + STG - 1)
             const int idx = base + lane;
-            if (idx < total) {
+            if (lane < STG && idx < total) {
                 const int64_t e = (int64_t)s_first[wave][lo] + (idx - s_start[wave][lo]);
                 const float4* r4 = reinterpret_cast<const float4*>(records + (size_t)e * RS);
 #pragma unroll
@@ -731,7 +746,7 @@ __global__ void __launch_bounds__(256) k_reduce_records(const float* __restrict_
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int r0 = start > base ? start : base;
-            const int r1 = start + cnt < base + kWave ? start + cnt : base + kWave;
+            const int r1 = start + cnt < base + STG ? start + cnt : base + STG;
             for (int r = r0; r < r1; ++r) {
                 float rr[RS];
 #pragma unroll
