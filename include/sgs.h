@@ -160,7 +160,9 @@ int32_t gs_app_stride(int32_t n_feat);
  *                   (Sigma2D^-1, quadratic form A dx^2 + 2B dx dy + C dy^2),
  *                   opacity, camera depth, and r = the pixel box half-sizes
  *                   (rx, ry) as two binary16 rounded up.
- *   rect[V][n][2] = tile rectangle, (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
+ *   rect[V][n][4] = tile rectangle, (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive,
+ *                   then the bits of the camera depth d (as in rec) and 0
+ *                   (16-byte aligned; gs_bin_sort reads the depth here)
  *   tiles_touched[V][n] = number of tiles in rect, 0 if culled
  *                   (rec and rect are written only for pairs with
  *                   tiles_touched > 0; other entries are left as they were)
@@ -184,6 +186,7 @@ int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views
  * An instance is identified by its emission index e (pairs in (view, index)
  * order, each pair's tiles row by row), so the instances of one pair occupy the
  * contiguous range [pair_first[pair], pair_first[pair] + tiles_touched[pair]).
+ *   rect, tiles_touched     from gs_project (the depth key is read from rect)
  *   tile_keys[capacity]     global tile id of each sorted instance
  *   inst[capacity]          emission index of each sorted instance
  *   inst_gid[capacity]      Gaussian index of each emission index
@@ -210,7 +213,7 @@ int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views
  * 256-byte aligned.  Instance counts must stay below 2^31.
  * --------------------------------------------------------------------------- */
 int gs_bin_sort_workspace(int32_t n, int32_t n_views, int64_t capacity, size_t* bytes);
-int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float* rec, int32_t n,
+int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, int32_t n,
                 const gs_view* views, const gs_view* views_dev, int32_t n_views, const gs_config* cfg,
                 void* ws, size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* inst,
                 int32_t* inst_gid, int32_t* pair_first, int32_t* tile_ranges, int64_t* counts, gs_stream stream);

@@ -101,7 +101,7 @@ def load() -> ctypes.CDLL:
     L.gs_project.argtypes = [P(GsGaussians), P(GsView), c_void_p, c_int32, P(GsConfig), c_void_p, c_void_p,
                              c_void_p, c_void_p, c_void_p]
     L.gs_bin_sort_workspace.argtypes = [c_int32, c_int32, c_int64, P(c_size_t)]
-    L.gs_bin_sort.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, P(GsView), c_void_p, c_int32, P(GsConfig),
+    L.gs_bin_sort.argtypes = [c_void_p, c_void_p, c_int32, P(GsView), c_void_p, c_int32, P(GsConfig),
                               c_void_p, c_size_t, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]
     L.gs_render_fwd.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, P(GsView),

@@ -607,7 +607,12 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
 // per tile of its rectangle at emission indices offs[i] .. offs[i] + touched - 1
 // (row-major over the rectangle): key = global tile id (the first tile-sort
 // pass attaches the emission index as the value).  inst_gid[e] keeps the Gaussian of emission index e,
-// pair_first[pair] the first emission index of the pair, so that the
+// depth_e[e] the binary32 bits of its pair's camera depth (the per-tile sort
+// key, read there by emission index instead of through inst_gid and the
+// pair's projected record: one gather per instance instead of two dependent
+// ones; the projection stores the bits in the pair's rectangle entry, so
+// this kernel reads them with the rectangle), pair_first[pair] the first
+// emission index of the pair, so that the
 // instances of one (view, Gaussian) pair stay contiguous in emission space
 // after the tile sort has reordered them.
 // Each wavefront takes 64 consecutive pairs and its lanes stride over all of
@@ -618,13 +623,14 @@ __global__ void __launch_bounds__(CV_THREADS) k_compact_visible(const int32_t* _
 // wavefront (DPP) carries the latest mark to every later slot.
 __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_vals,
                                               const uint32_t* __restrict__ offs, const int64_t* n_vis,
-                                              const uint2* __restrict__ rect, const gs_view* __restrict__ views,
-                                              int n, int tile, int64_t capacity, uint32_t* __restrict__ keys,
-                                              int32_t* __restrict__ inst_gid,
-                                              int32_t* __restrict__ pair_first) {
+                                              const uint4* __restrict__ rect, const gs_view* __restrict__ views,
+                                              int n, int tile, int64_t capacity,
+                                              uint32_t* __restrict__ keys, int32_t* __restrict__ inst_gid,
+                                              uint32_t* __restrict__ depth_e, int32_t* __restrict__ pair_first) {
     __shared__ uint32_t s_start[4][kWave];
     __shared__ uint4 s_info[4][kWave];  // (x0 | y0 << 16, rect width, tile base, tiles per row)
     __shared__ int32_t s_gid[4][kWave];
+    __shared__ uint32_t s_depth[4][kWave];
     __shared__ int32_t s_mark[4][kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int64_t nv = *n_vis;
@@ -637,7 +643,7 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
         const uint32_t pair = vis_vals[i];
         const int v = (int)(pair / (uint32_t)n);
         const uint32_t gid = pair - (uint32_t)v * (uint32_t)n;
-        const uint2 r = rect[pair];
+        const uint4 r = rect[pair];
         const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
         const uint32_t wr = x1 - x0 + 1, hr = y1 - y0 + 1;
         o_i = offs[i];
@@ -646,6 +652,7 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
         s_info[wave][lane] = make_uint4(x0 | (y0 << 16), wr, (uint32_t)views[v].tile_offset,
                                         (uint32_t)ceil_div(views[v].width, tile));
         s_gid[wave][lane] = (int32_t)gid;
+        s_depth[wave][lane] = r.z;
     }
     const int64_t o_w = read_lane_i64(o_i, 0);  // lane 0 is valid
     s_start[wave][lane] = (uint32_t)(o_i - o_w);
@@ -690,6 +697,7 @@ __global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ vis_v
         if (o < capacity) {
             keys[o] = info.z + yy * info.w + xx;
             inst_gid[o] = s_gid[wave][lo];
+            depth_e[o] = s_depth[wave][lo];
         }
     }
 }
@@ -885,17 +893,13 @@ __device__ __forceinline__ void wave_sort_chunk_n(int n, uint64_t (&k)[8], int (
 }
 
 // Sort key of list position i of the tile: (depth bits << 32) | i.
-__device__ __forceinline__ uint64_t depth_key(const float4* __restrict__ rec, size_t vbase,
-                                              const int32_t* __restrict__ inst_gid, uint32_t e, int i) {
-    return ((uint64_t)__float_as_uint(rec[2 * (vbase + (size_t)inst_gid[e]) + 1].z) << 32) | (uint32_t)i;
+__device__ __forceinline__ uint64_t depth_key(const uint32_t* __restrict__ depth_e, uint32_t e, int i) {
+    return ((uint64_t)depth_e[e] << 32) | (uint32_t)i;
 }
 
-// Tiles in the XCD-aware order of the compositing launches (tile_of_block):
-// neighbouring lists gather the same Gaussians' ids and depths.
+// Tiles in the XCD-aware order of the compositing launches (tile_of_block).
 __global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __restrict__ ranges, int total_tiles,
-                                                                  int run, const gs_view* __restrict__ views,
-                                                                  int n_views, int n, const float4* __restrict__ rec,
-                                                                  const int32_t* __restrict__ inst_gid,
+                                                                  int run, const uint32_t* __restrict__ depth_e,
                                                                   int32_t* __restrict__ inst,
                                                                   uint32_t* __restrict__ long_list,
                                                                   uint32_t* __restrict__ long_count,
@@ -913,7 +917,6 @@ __global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __r
     }
     if (L <= 1) return;
     const int lane = threadIdx.x;
-    const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
     uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
     uint64_t k[8];
     int rank[8];
@@ -924,7 +927,7 @@ __global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __r
         if (i < L) {
             const uint32_t e = einst[i];
             s_e[i] = e;
-            k[r] = depth_key(rec, vbase, inst_gid, e, i);
+            k[r] = depth_key(depth_e, e, i);
         }
     }
     wave_sort_chunk_n(L, k, rank, s_run, lane);
@@ -936,16 +939,14 @@ __global__ void __launch_bounds__(TSS_THREADS) k_tile_sort_short(const int2* __r
 }
 
 // One long list (tile t, more than kTsShort instances), by the whole block.
-__device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_view* __restrict__ views,
-                               int n_views, int n, const float4* __restrict__ rec,
-                               const int32_t* __restrict__ inst_gid, uint32_t* __restrict__ tile_keys,
+__device__ void sort_long_list(int t, const int2* __restrict__ ranges, const uint32_t* __restrict__ depth_e,
+                               uint32_t* __restrict__ tile_keys,
                                int32_t* __restrict__ inst, uint32_t* __restrict__ gk, uint32_t* __restrict__ gv,
                                uint64_t (&s_sorted)[kTsLong], uint64_t (&s_run)[TSL_THREADS / kWave][kTsChunk],
                                uint32_t (&s_e)[kTsLong], SegSortLds<TSL_THREADS>& S) {
     constexpr int NW = TSL_THREADS / kWave;
     const int2 rg = ranges[t];
     const int L = rg.y - rg.x;
-    const size_t vbase = (size_t)view_of_tile(views, n_views, t) * (size_t)n;
     uint32_t* einst = reinterpret_cast<uint32_t*>(inst) + rg.x;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     if (L <= kTsLong) {
@@ -967,7 +968,7 @@ __device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_
                 if (r * kWave < CH && i < L) {
                     const uint32_t e = einst[i];
                     s_e[i] = e;
-                    k[r] = depth_key(rec, vbase, inst_gid, e, i);
+                    k[r] = depth_key(depth_e, e, i);
                 }
             }
             wave_sort_chunk_n(nc, k, rank, s_run[wave], lane);
@@ -1001,7 +1002,7 @@ __device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_
     uint32_t* ak = gk + rg.x;
     uint32_t* av = gv + rg.x;
     for (int i = threadIdx.x; i < L; i += TSL_THREADS)
-        bk[i] = __float_as_uint(rec[2 * (vbase + (size_t)inst_gid[einst[i]]) + 1].z);
+        bk[i] = depth_e[einst[i]];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         // the previous pass's global writes are complete and visible to the
@@ -1027,9 +1028,7 @@ __device__ void sort_long_list(int t, const int2* __restrict__ ranges, const gs_
 __global__ void __launch_bounds__(TSL_THREADS) k_tile_sort_long(const int2* __restrict__ ranges,
                                                                  const uint32_t* __restrict__ long_list,
                                                                  const uint32_t* __restrict__ long_count,
-                                                                 const gs_view* __restrict__ views, int n_views,
-                                                                 int n, const float4* __restrict__ rec,
-                                                                 const int32_t* __restrict__ inst_gid,
+                                                                 const uint32_t* __restrict__ depth_e,
                                                                  uint32_t* __restrict__ tile_keys,
                                                                  int32_t* __restrict__ inst,
                                                                  uint32_t* __restrict__ gk,
@@ -1040,15 +1039,14 @@ __global__ void __launch_bounds__(TSL_THREADS) k_tile_sort_long(const int2* __re
     __shared__ SegSortLds<TSL_THREADS> S;
     const uint32_t count = *long_count;
     for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        sort_long_list((int)long_list[idx], ranges, views, n_views, n, rec, inst_gid, tile_keys, inst, gk, gv,
-                       s_sorted, s_run, s_e, S);
+        sort_long_list((int)long_list[idx], ranges, depth_e, tile_keys, inst, gk, gv, s_sorted, s_run, s_e, S);
         __syncthreads();  // the LDS is reused by the next tile
     }
 }
 
 
 struct WsLayout {
-    size_t vis_k0, vis_v0, inst_k2, inst_v2, hist, sums, status, tickets, cnt, long_list, total;
+    size_t vis_k0, vis_v0, inst_k2, inst_v2, depth_e, hist, sums, status, tickets, cnt, long_list, total;
     int64_t spine_tiles, n_status;
 };
 
@@ -1074,6 +1072,7 @@ WsLayout ws_layout(int n, int n_views, int64_t capacity) {
     L.vis_v0 = o; o += al(4 * (size_t)(vn > 0 ? vn : 1));
     L.inst_k2 = o; o += al(4 * (size_t)cap);
     L.inst_v2 = o; o += al(4 * (size_t)cap);
+    L.depth_e = o; o += al(4 * (size_t)cap);
     L.hist = o; o += al(4 * (size_t)(256 * nblk + 1));
     L.sums = o; o += al(4 * (size_t)vt);
     L.status = o; o += al(8 * (size_t)L.n_status);
@@ -1098,7 +1097,7 @@ int lookback_spin_limit() {
     return x < 0 ? 0 : (x > LB_SPIN_MAX ? LB_SPIN_MAX : (int)x);
 }
 
-hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const float* rec, int n,
+hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, int n,
                           const gs_view* views_dev, int n_views, int total_tiles, int tile, void* ws,
                           int64_t capacity, uint32_t* tile_keys, int32_t* inst, int32_t* inst_gid,
                           int32_t* pair_first, int32_t* ranges, int64_t* counts, hipStream_t s) {
@@ -1108,6 +1107,7 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     uint32_t* vis_v0 = reinterpret_cast<uint32_t*>(w + L.vis_v0);
     uint32_t* ik2 = reinterpret_cast<uint32_t*>(w + L.inst_k2);
     uint32_t* iv2 = reinterpret_cast<uint32_t*>(w + L.inst_v2);
+    uint32_t* depth_e = reinterpret_cast<uint32_t*>(w + L.depth_e);
     uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
     uint32_t* sums = reinterpret_cast<uint32_t*>(w + L.sums);
     uint64_t* status = reinterpret_cast<uint64_t*>(w + L.status);
@@ -1145,7 +1145,7 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
     uint32_t* ov = (passes % 2 == 0) ? iv2 : reinterpret_cast<uint32_t*>(inst);
     if (vn > 0) {
         hipLaunchKernelGGL(k_emit, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, vis_v0, vis_k0, &cnt[0],
-                           reinterpret_cast<const uint2*>(rect), views_dev, n, tile, capacity, ek, inst_gid,
+                           reinterpret_cast<const uint4*>(rect), views_dev, n, tile, capacity, ek, inst_gid, depth_e,
                            pair_first);
     }
     // a look-back that waits past the spin limit (SGS_LOOKBACK_SPIN overrides
@@ -1164,17 +1164,15 @@ hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const fl
                            gu.flag);
         if (total_tiles > 0) {
             const int2* rg = reinterpret_cast<const int2*>(ranges);
-            const float4* rc = reinterpret_cast<const float4*>(rec);
             const int run = tile_run(tile);
             uint32_t* long_list = reinterpret_cast<uint32_t*>(w + L.long_list);
             uint32_t* long_count = tickets + kMaxPasses;
             hipLaunchKernelGGL(k_tile_sort_short, dim3(tile_grid(total_tiles, run)), dim3(TSS_THREADS), 0, s, rg,
-                               total_tiles, run, views_dev, n_views, n, rc, inst_gid, inst, long_list, long_count,
-                               gu.flag);
+                               total_tiles, run, depth_e, inst, long_list, long_count, gu.flag);
             const int64_t max_long = capacity / (kTsShort + 1) + 1;
             const unsigned lg = (unsigned)(max_long < 1024 ? max_long : 1024);
             hipLaunchKernelGGL(k_tile_sort_long, dim3(lg), dim3(TSL_THREADS), 0, s, rg, long_list, long_count,
-                               views_dev, n_views, n, rc, inst_gid, tile_keys, inst, ik2, iv2);
+                               depth_e, tile_keys, inst, ik2, iv2);
         }
     }
     return hipGetLastError();

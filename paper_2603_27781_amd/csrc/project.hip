@@ -42,10 +42,12 @@ __device__ __forceinline__ float guard_limit(float guard, int extent, float foca
 
 // The exact projection of one (view, Gaussian) pair (Eq. 3) and its tile
 // rectangle; writes the pair's record and rectangle when it is visible and
-// returns its tile count (0 when culled).
+// returns its tile count (0 when culled).  The rectangle entry also carries
+// the depth's bits, which the binning's emission reads from the same 16
+// bytes (the record itself is a 32-byte gather it would fetch only for them).
 __device__ __forceinline__ int32_t project_pair(const float* vw, const float* Mg, float op, float m0, float m1,
                                                 float m2, float kbox, const RasterConst& c, size_t o,
-                                                float4* __restrict__ rec, uint2* __restrict__ rect) {
+                                                float4* __restrict__ rec, uint4* __restrict__ rect) {
     const float* R = vw;
     const float fx = vw[12], fy = vw[13], cx = vw[14], cy = vw[15], limx = vw[16], limy = vw[17];
     const float txm1 = vw[18], tym1 = vw[19];
@@ -93,7 +95,8 @@ __device__ __forceinline__ int32_t project_pair(const float* vw, const float* Mg
     // the record and rectangle of a pair are only read when it is visible
     rec[2 * o] = make_float4(mx, my, cc / det, -b / det);
     rec[2 * o + 1] = make_float4(a / det, op, p2, pack_radii(rx, ry));
-    rect[o] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
+    rect[o] = make_uint4((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16),
+                         __float_as_uint(p2), 0u);
     return (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
 }
 
@@ -112,7 +115,7 @@ __device__ __forceinline__ int32_t project_pair(const float* vw, const float* Mg
 template <int F>
 __global__ void __launch_bounds__(kProjThreads) k_project(GaussPtrs g, const gs_view* __restrict__ views,
                                                           int n_views, RasterConst c, float4* __restrict__ rec,
-                                                          uint2* __restrict__ rect, int32_t* __restrict__ touched,
+                                                          uint4* __restrict__ rect, int32_t* __restrict__ touched,
                                                           float4* __restrict__ app) {
     constexpr int AS = ((3 + F) + 3) / 4 * 4;  // floats per appearance record
     __shared__ float4 s_vw4[GS_MAX_VIEWS * kViewFloats / 4];
@@ -273,7 +276,7 @@ hipError_t launch_project(const GaussPtrs& g, const gs_view* views_dev, int n_vi
         default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(g.n, kProjThreads)), dim3(kProjThreads), 0, s, g, views_dev,
-                       n_views, c, reinterpret_cast<float4*>(rec), reinterpret_cast<uint2*>(rect), touched,
+                       n_views, c, reinterpret_cast<float4*>(rec), reinterpret_cast<uint4*>(rect), touched,
                        reinterpret_cast<float4*>(app));
     return hipGetLastError();
 }

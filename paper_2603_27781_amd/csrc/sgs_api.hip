@@ -230,7 +230,7 @@ int gs_project(const gs_gaussians* g, const gs_view* views, const gs_view* views
     if ((st = check_config(cfg))) return st;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, nullptr))) return st;
     if (!rec || !rect || !tiles_touched) return GS_EINVAL;
-    if (!aligned16(rec) || (app && !aligned16(app))) return GS_EINVAL;
+    if (!aligned16(rec) || !aligned16(rect) || (app && !aligned16(app))) return GS_EINVAL;
     if ((int64_t)g->n * n_views >= (1ll << 31)) return GS_EINVAL;
     return hip_status(launch_project(gauss_ptrs(g), views_dev, n_views, make_const(cfg), rec, rect, tiles_touched,
                                      app, app_stride(g->n_feat), reinterpret_cast<hipStream_t>(stream)));
@@ -243,7 +243,7 @@ int gs_bin_sort_workspace(int32_t n, int32_t n_views, int64_t capacity, size_t* 
     return GS_OK;
 }
 
-int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float* rec, int32_t n,
+int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, int32_t n,
                 const gs_view* views, const gs_view* views_dev, int32_t n_views, const gs_config* cfg, void* ws,
                 size_t ws_bytes, int64_t capacity, uint32_t* tile_keys, int32_t* inst, int32_t* inst_gid,
                 int32_t* pair_first, int32_t* tile_ranges, int64_t* counts, gs_stream stream) {
@@ -251,12 +251,12 @@ int gs_bin_sort(const uint32_t* rect, const int32_t* tiles_touched, const float*
     if (st) return st;
     int total_tiles = 0;
     if ((st = check_views(views, views_dev, n_views, cfg->tile, nullptr, &total_tiles))) return st;
-    if (!rect || !tiles_touched || !rec || !ws || !tile_ranges || !counts || !pair_first) return GS_EINVAL;
+    if (!rect || !tiles_touched || !ws || !tile_ranges || !counts || !pair_first) return GS_EINVAL;
     if (capacity > 0 && (!tile_keys || !inst || !inst_gid)) return GS_EINVAL;
     if (n < 1 || capacity < 0 || capacity >= (1ll << 31) || (int64_t)n * n_views >= (1ll << 31)) return GS_EINVAL;
     if (ws_bytes < binsort_workspace_bytes(n, n_views, capacity)) return GS_ECAPACITY;
-    if (!aligned16(rec) || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return GS_EINVAL;
-    return hip_status(launch_binsort(rect, tiles_touched, rec, n, views_dev, n_views, total_tiles, cfg->tile, ws,
+    if (!aligned16(rect) || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return GS_EINVAL;
+    return hip_status(launch_binsort(rect, tiles_touched, n, views_dev, n_views, total_tiles, cfg->tile, ws,
                                      capacity, tile_keys, inst, inst_gid, pair_first, tile_ranges, counts,
                                      reinterpret_cast<hipStream_t>(stream)));
 }

@@ -161,7 +161,7 @@ hipError_t launch_project(const GaussPtrs& g, const gs_view* views_dev, int n_vi
                           hipStream_t s);
 
 size_t binsort_workspace_bytes(int n, int n_views, int64_t capacity);
-hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, const float* rec, int n,
+hipError_t launch_binsort(const uint32_t* rect, const int32_t* touched, int n,
                           const gs_view* views_dev, int n_views, int total_tiles, int tile, void* ws,
                           int64_t capacity, uint32_t* tile_keys, int32_t* inst, int32_t* inst_gid,
                           int32_t* pair_first, int32_t* ranges, int64_t* counts, hipStream_t s);

@@ -148,7 +148,7 @@ class Rasterizer:
         self.AS = int(L.gs_app_stride(n_feat))
         dev = dict(device=device)
         self.rec = torch.empty(V * n * 8, dtype=torch.float32, **dev)
-        self.rect = torch.empty(V * n * 2, dtype=torch.int32, **dev)
+        self.rect = torch.empty(V * n * 4, dtype=torch.int32, **dev)
         self.touched = torch.empty(V * n, dtype=torch.int32, **dev)
         self.app = torch.empty(n * self.AS, dtype=torch.float32, **dev)
         self.counts = torch.zeros(5, dtype=torch.int64, **dev)
@@ -236,7 +236,7 @@ class Rasterizer:
               "gs_project")
 
     def bin_sort(self) -> None:
-        check(self.L.gs_bin_sort(self.rect.data_ptr(), self.touched.data_ptr(), self.rec.data_ptr(), self.n,
+        check(self.L.gs_bin_sort(self.rect.data_ptr(), self.touched.data_ptr(), self.n,
                                  self.views.host, self.views.dev_ptr(), self.views.n, ctypes.byref(self.cc),
                                  self.ws_view.data_ptr(), self.ws_view.numel(), self.capacity, self.keys.data_ptr(),
                                  self.inst.data_ptr(), self.inst_gid.data_ptr(), self.pair_first.data_ptr(),

@@ -29,7 +29,7 @@ def test_project_bit_exact(name, tile):
     V, n = len(views), scene.n
     rec = r.rec.view(V, n, 8).cpu().numpy()
     touched = r.touched.view(V, n).cpu().numpy()
-    rect = r.rect.view(V, n, 2).cpu().numpy().view(np.uint32)
+    rect = r.rect.view(V, n, 4).cpu().numpy().view(np.uint32)
     assert np.array_equal(touched, dec["touched"])
     vis = touched > 0
     assert vis.sum() > 0
@@ -492,7 +492,7 @@ def test_abi_rejects_bad_arguments_without_launching():
     st = L.gs_project(ctypes.byref(g.c()), r.views.host, r.views.dev_ptr(), 1, ctypes.byref(r.cc), None,
                       r.rect.data_ptr(), r.touched.data_ptr(), r.app.data_ptr(), None)
     assert st == _lib.GS_EINVAL
-    st = L.gs_bin_sort(r.rect.data_ptr(), r.touched.data_ptr(), r.rec.data_ptr(), r.n, r.views.host,
+    st = L.gs_bin_sort(r.rect.data_ptr(), r.touched.data_ptr(), r.n, r.views.host,
                        r.views.dev_ptr(), 1, ctypes.byref(r.cc), r.ws_view.data_ptr(), 16, r.capacity,
                        r.keys.data_ptr(), r.inst.data_ptr(), r.inst_gid.data_ptr(), r.pair_first.data_ptr(),
                        r.ranges.data_ptr(), r.counts.data_ptr(), None)
